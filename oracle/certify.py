@@ -1,0 +1,46 @@
+"""KKT certificate of a primal-dual point (problem statement, eq. sdp-pd).
+
+For any returned (X, y, S) this measures, in FP64 on the CPU:
+primal infeasibility ||b - A(X)|| / (1 + ||b||), dual infeasibility
+||C - A^T(y) - S||_F / (1 + ||C||_F), the relative duality gap
+|<C,X> - b^T y| / (1 + |<C,X>| + |b^T y|), the smallest eigenvalues of X
+and S, mu = <X,S>/n and the centrality ||X^{1/2} S X^{1/2} / mu - I||
+(the quantity bounded by delta in Assumption 1).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import operators as ops
+from .notation import sym
+
+
+def certificate(problem, X, y, S):
+    n = problem["n"]
+    b, C = problem["b"], problem["C"]
+    X = sym(np.asarray(X, dtype=np.float64))
+    S = sym(np.asarray(S, dtype=np.float64))
+    y = np.asarray(y, dtype=np.float64)
+    rp = b - ops.a_op(problem, X)
+    Rd = C - ops.at_op(problem, y) - S
+    pobj = float(np.sum(C * X))
+    dobj = float(b @ y)
+    wx, Vx = np.linalg.eigh(X)
+    ws = np.linalg.eigvalsh(S)
+    mu = float(np.sum(X * S)) / n
+    Xh = (Vx * np.sqrt(np.clip(wx, 0.0, None))) @ Vx.T
+    if mu > 0:
+        delta = float(np.linalg.norm(Xh @ S @ Xh / mu - np.eye(n), 2))
+    else:
+        delta = float("inf")
+    return {
+        "pinf": float(np.linalg.norm(rp)) / (1.0 + float(np.linalg.norm(b))),
+        "dinf": float(np.linalg.norm(Rd)) / (1.0 + float(np.linalg.norm(C))),
+        "relgap": abs(pobj - dobj) / (1.0 + abs(pobj) + abs(dobj)),
+        "pobj": pobj,
+        "dobj": dobj,
+        "lmin_X": float(wx[0]),
+        "lmin_S": float(ws[0]),
+        "mu": mu,
+        "delta": delta,
+    }

@@ -1,0 +1,72 @@
+"""The constraint operator A: S^n -> R^m and its adjoint (Introduction, eq. sdp-pd).
+
+A(X)_i = <A_i, X> and A^T(y) = sum_i y_i A_i.  Two data forms:
+
+* dense : problem["A"] is (m, n*n), row i = vec(A_i).
+* entry : problem["jk"] is (m, 2), A_i = (e_j e_k^T + e_k e_j^T)/2, so
+          A(X)_i = X_jk and A^T(y) places y_i/2 at (j,k) and (k,j)
+          (y_i at (j,j) when j = k).
+
+The matrix form used by the paper, script-A = [svec(A_1) ... svec(A_m)]^T
+(Section 3), is built by ``amat`` for small instances.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .notation import svec, tri_len
+
+
+def a_op(problem, X: np.ndarray) -> np.ndarray:
+    n = problem["n"]
+    if problem["kind"] == "dense":
+        return problem["A"] @ X.reshape(n * n)
+    jk = problem["jk"]
+    Xs = 0.5 * (X + X.T)
+    return Xs[jk[:, 0], jk[:, 1]].copy()
+
+
+def at_op(problem, y: np.ndarray) -> np.ndarray:
+    n = problem["n"]
+    if problem["kind"] == "dense":
+        Y = (problem["A"].T @ y).reshape(n, n)
+        return 0.5 * (Y + Y.T)
+    jk = problem["jk"]
+    Y = np.zeros((n, n))
+    j = jk[:, 0]
+    k = jk[:, 1]
+    off = j != k
+    np.add.at(Y, (j[off], k[off]), 0.5 * y[off])
+    np.add.at(Y, (k[off], j[off]), 0.5 * y[off])
+    np.add.at(Y, (j[~off], j[~off]), y[~off])
+    return Y
+
+
+def a_matrix(problem, i: int) -> np.ndarray:
+    """The symmetric matrix A_i."""
+    n = problem["n"]
+    if problem["kind"] == "dense":
+        return problem["A"][i].reshape(n, n).copy()
+    j, k = problem["jk"][i]
+    M = np.zeros((n, n))
+    M[j, k] += 0.5
+    M[k, j] += 0.5
+    return M
+
+
+def amat(problem) -> np.ndarray:
+    """script-A = [svec(A_1), ..., svec(A_m)]^T, shape (m, n(n+1)/2)."""
+    n = problem["n"]
+    m = problem["m"]
+    out = np.empty((m, tri_len(n)))
+    for i in range(m):
+        out[i] = svec(a_matrix(problem, i))
+    return out
+
+
+def frob_norms(problem) -> np.ndarray:
+    """||A_i||_F for every constraint."""
+    if problem["kind"] == "dense":
+        return np.linalg.norm(problem["A"], axis=1)
+    jk = problem["jk"]
+    return np.where(jk[:, 0] == jk[:, 1], 1.0, np.sqrt(0.5))

@@ -1,0 +1,151 @@
+"""Seeded synthetic SDP instances shared by the oracle, the tests and the bench.
+
+This module only draws random numbers and assembles problem data
+(A, b, C and the planted solution).  It holds none of the solver's
+arithmetic, so both the CPU oracle and the GPU library can consume it
+without sharing any method code.
+
+Problem statement (Introduction, eq. sdp-pd): minimise <C, X> subject to
+A(X) = b, X PSD, with A: S^n -> R^m given either as dense symmetric
+matrices A_i or as sampled entries A_i = sym(e_j e_k^T).
+
+Layouts
+-------
+dense  : ``A`` is an (m, n*n) float64 array, row i = vec(A_i) (A_i is
+         symmetric, so row- and column-major vec coincide).
+entry  : ``jk`` is an (m, 2) int32 array of 0-based pairs with j <= k,
+         all distinct; A_i = (e_j e_k^T + e_k e_j^T) / 2 so <A_i, X> = X_jk.
+C      : (n, n) float64, symmetric.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "gaussian_sensing",
+    "matrix_completion",
+    "batched_sensing",
+    "random_pd_pair",
+    "config",
+    "CONFIGS",
+]
+
+
+def _packed_index_to_pair(p: np.ndarray, n: int):
+    """Map a column-major lower-triangle index p to the pair (j, k), j >= k.
+
+    Column k of the lower triangle holds rows k..n-1 and starts at
+    k*n - k*(k-1)/2.
+    """
+    p = np.asarray(p, dtype=np.int64)
+    starts = np.array([k * n - k * (k - 1) // 2 for k in range(n + 1)], dtype=np.int64)
+    k = np.searchsorted(starts, p, side="right") - 1
+    j = k + (p - starts[k])
+    return j, k
+
+
+def gaussian_sensing(n: int, r: int, m: int, seed: int):
+    """Gaussian matrix-sensing SDP with a planted rank-r solution.
+
+    A_i = (G_i + G_i^T)/2 with G_i iid N(0,1)/n, U iid N(0,1) of size n x r,
+    X* = U U^T, b = A(X*), C = I (trace minimisation).
+    """
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((m, n, n)) / n
+    A = 0.5 * (G + G.transpose(0, 2, 1))
+    del G
+    U = rng.standard_normal((n, r))
+    Xs = U @ U.T
+    A = A.reshape(m, n * n)
+    b = A @ Xs.reshape(n * n)
+    return {
+        "kind": "dense",
+        "n": n,
+        "m": m,
+        "r": r,
+        "A": np.ascontiguousarray(A),
+        "b": b,
+        "C": np.eye(n),
+        "U": U,
+        "seed": seed,
+    }
+
+
+def matrix_completion(n: int, r: int, m: int, seed: int):
+    """Matrix-completion SDP: observe m distinct entries (j <= k) of X* = U U^T.
+
+    Pairs are sampled uniformly without replacement from the n(n+1)/2
+    lower-triangle positions; A_i = sym(e_j e_k^T), b_i = X*_jk, C = I.
+    """
+    rng = np.random.default_rng(seed)
+    U = rng.standard_normal((n, r))
+    N2 = n * (n + 1) // 2
+    if m > N2:
+        raise ValueError("m exceeds the number of distinct entries")
+    p = np.sort(rng.choice(N2, size=m, replace=False))
+    jlo, khi = _packed_index_to_pair(p, n)  # jlo >= khi in lower-triangle terms
+    # store as (j, k) with j <= k
+    j = np.minimum(jlo, khi).astype(np.int32)
+    k = np.maximum(jlo, khi).astype(np.int32)
+    jk = np.stack([j, k], axis=1)
+    b = np.einsum("ir,ir->i", U[j], U[k])
+    return {
+        "kind": "entry",
+        "n": n,
+        "m": m,
+        "r": r,
+        "jk": np.ascontiguousarray(jk),
+        "b": b,
+        "C": np.eye(n),
+        "U": U,
+        "seed": seed,
+    }
+
+
+def batched_sensing(count: int, seed: int, n_lo: int = 16, n_hi: int = 128):
+    """Many small Gaussian sensing SDPs: n ~ U{n_lo..n_hi}, r ~ U{1,2,3}, m = 3 n r."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(n_lo, n_hi + 1, size=count)
+    rs = rng.integers(1, 4, size=count)
+    subseeds = rng.integers(0, 2**31 - 1, size=count)
+    out = []
+    for n, r, s in zip(ns, rs, subseeds):
+        n = int(n)
+        r = int(r)
+        out.append(gaussian_sensing(n, r, 3 * n * r, int(s)))
+    return out
+
+
+def random_pd_pair(n: int, seed: int, spread: float = 1.0):
+    """A random primal-dual point (X, S), both positive definite.
+
+    The eigenvalues are log-uniform over ``spread`` decades, which keeps the
+    spectrum of the resulting scaling matrix well separated.
+    """
+    rng = np.random.default_rng(seed)
+
+    def one():
+        Qm, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        ev = 10.0 ** rng.uniform(-spread, spread, size=n)
+        M = (Qm * ev) @ Qm.T
+        return 0.5 * (M + M.T)
+
+    X = one()
+    S = one()
+    return X, S
+
+
+# The five workloads the hot path is measured on.  Each entry is
+# (description, builder) and the builder takes no arguments.
+CONFIGS = {
+    0: ("gaussian sensing n=20 r=2 m=120", lambda: gaussian_sensing(20, 2, 120, seed=0)),
+    1: ("gaussian sensing n=200 r=3 m=2400", lambda: gaussian_sensing(200, 3, 2400, seed=1)),
+    2: ("matrix completion n=4000 r=4 m=160000", lambda: matrix_completion(4000, 4, 160000, seed=2)),
+    3: ("batched gaussian sensing x1024 n in [16,128]", lambda: batched_sensing(1024, seed=3)),
+    4: ("matrix completion n=1000 r=3 m=30000", lambda: matrix_completion(1000, 3, 30000, seed=4)),
+}
+
+
+def config(i: int):
+    """Build workload ``i`` (see ``CONFIGS``)."""
+    return CONFIGS[i][1]()
