@@ -1,0 +1,177 @@
+"""Benchmark: Newton-operator mat-vecs per second and IPM time to a 1e-8 gap.
+
+One step = one full FP64 interior-point solve (sdp_solve) of the dense
+Gaussian matrix-sensing workload n=200, r=3, m=2400 from the standard
+starting point to relative gap, primal and dual infeasibility <= 1e-8.  The
+constraint data is resident in HBM before timing starts (the setup upload
+and packing are outside the timed region).  value = augmented-operator
+applications performed by the timed solves / timed seconds.
+
+The JSON line also carries:
+  roofline      the dominant kernel (the packed A / A^T passes, HBM bound)
+                timed live with HIP events on the library's stream;
+  cpu_baseline  the CPU oracle's augmented operator on the same workload
+                (bounded sample, all host cores);
+  newton_apply  a tight loop of sdp_newton_apply at the final scaling point.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Newton-op matvecs/s and IPM time-to-1e-8 gap, FP64 vs mixed prec, 1 GPU"
+WORKLOAD = "gaussian sensing SDP n=200 r=3 m=2400 (dense A, FP64)"
+
+
+def cpu_baseline(p, budget_s=15.0):
+    """The oracle's Section 5 operator timed on the host cores."""
+    from oracle import nt, reform as rf
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    X, S = __import__("workloads").random_pd_pair(p["n"], seed=5, spread=1.0)
+    G, d, L = nt.nt_factor(X, S)
+    sp = rf.eig_split(G @ G.T)
+    E = rf.e_matrix(sp)
+    sig = rf.sigma_diag(sp)
+    m = p["m"]
+    N = m + rf.dim_d(p["n"], sp["r"])
+    x = np.random.default_rng(0).standard_normal(N)
+    rf.aug_apply(p, sp, E, sig, x[:m], x[m:])
+    calls = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        rf.aug_apply(p, sp, E, sig, x[:m], x[m:])
+        calls += 1
+    el = time.perf_counter() - t0
+    return {
+        "value": calls / el,
+        "unit": "matvec/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"{calls} applications of the oracle's augmented operator (eq. augsys via the Section 5 products) "
+                  f"on the same workload at a fixed scaling point, {el:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--apply-loop", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: every instance of this workload fits one MI355X, "
+              "and multi-GPU runs are not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads
+    from paper_2407_14013_amd import Context
+    from paper_2407_14013_amd import _lib as L
+
+    torch.cuda.set_device(0)
+    p = workloads.config(1)
+    ctx = Context(p)
+    X0, y0, S0 = (t.clone() for t in ctx.get_point())
+
+    def one_solve():
+        ctx.set_point(X0, y0, S0)
+        return ctx.solve()
+
+    for _ in range(args.warmup):
+        one_solve()
+    torch.cuda.synchronize()
+    ctx.profile_enable([L.SDP_K_A_APPLY, L.SDP_K_AT_APPLY])
+    results = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        results.append(one_solve())
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = {k: ctx.profile_get(k) for k in (L.SDP_K_A_APPLY, L.SDP_K_AT_APPLY, L.SDP_K_GEMM, L.SDP_K_NEWTON)}
+    ctx.profile_enable([])
+    matvecs = sum(r["newton_matvecs"] for r in results)
+    for r in results:
+        assert r["status"] == 0 and r["relgap"] <= 1e-8, r
+
+    # dominant kernel: the larger total time of the two packed passes over A
+    kcls = max((L.SDP_K_A_APPLY, L.SDP_K_AT_APPLY), key=lambda k: prof[k]["ms"])
+    kp = prof[kcls]
+    avg_ms = kp["ms"] / max(kp["launches"], 1)
+    bytes_per = kp["bytes"] / max(kp["launches"], 1)
+    achieved = bytes_per / (avg_ms * 1e-3) / 1e9
+
+    # tight loop of the operator at the final point
+    N = ctx.aug_dim()
+    xin = torch.randn(N, dtype=torch.float64, device="cuda")
+    xout = torch.empty_like(xin)
+    for _ in range(5):
+        ctx.newton_apply(xin, xout)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.apply_loop):
+        ctx.newton_apply(xin, xout)
+    torch.cuda.synchronize()
+    loop_rate = args.apply_loop / (time.perf_counter() - t1)
+
+    line = {
+        "metric": METRIC,
+        "value": matvecs / el,
+        "unit": "matvec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "precision": "fp64", "ipm_tol": 1e-8, "inner_tol": 1e-10},
+        "ipm": {
+            "time_to_gap_s": el / args.steps,
+            "iterations": [r["iterations"] for r in results],
+            "pcg_iterations": [r["pcg_iterations"] for r in results],
+            "newton_matvecs": [r["newton_matvecs"] for r in results],
+            "relgap": results[-1]["relgap"],
+            "pobj": results[-1]["pobj"],
+        },
+        "newton_apply_loop": {"matvec_per_s": loop_rate, "calls": args.apply_loop},
+        "roofline": {
+            "kernel": "gemv_rows (A(M))" if kcls == L.SDP_K_A_APPLY else "gemv_cols (A^T(u))",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_ms": avg_ms,
+            "launches": kp["launches"],
+            "bytes_per_launch": bytes_per,
+        },
+        "kernel_time_ms": {"A_apply": prof[L.SDP_K_A_APPLY]["ms"], "AT_apply": prof[L.SDP_K_AT_APPLY]["ms"],
+                           "gemm": prof[L.SDP_K_GEMM]["ms"], "newton_apply": prof[L.SDP_K_NEWTON]["ms"]},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(p)
+    ctx.close()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,243 @@
+/*
+ * wcsdp.h -- C ABI of the MI355X well-conditioned low-rank SDP solver.
+ *
+ * Solves the standard-form primal/dual pair (Introduction, eq. sdp-pd)
+ *     min <C, X>  s.t.  A(X) = b, X PSD;      max <b, y>  s.t.  A^T(y) + S = C, S PSD
+ * with a primal-dual interior-point method whose Newton systems (Section 3,
+ * eq. Newt-eps) are solved through the well-conditioned augmented system of
+ * eq. augsys by indefinite-preconditioned PCG (Corollary pcg, Section 6) and
+ * recovered with eq. recover.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Matrices are n x n, column-major, FP64.  Symmetric inputs must be
+ *    symmetric to within 1e-12 of their Frobenius norm.
+ *  - "device pointer" means memory the caller allocated on the GPU that
+ *    the context was set up on (hipMalloc, or a torch CUDA tensor); the
+ *    caller keeps ownership.  "host pointer" means ordinary CPU memory.
+ *  - Every GPU operation is issued on the stream given to sdp_setup (NULL =
+ *    the default stream) and is stream-ordered with the caller's work.  Entry
+ *    points that return scalars or statistics synchronise that stream.
+ *  - No C++ exception crosses this boundary.  On error the return value is
+ *    negative, sdp_last_error() describes it, and outputs are unspecified
+ *    unless stated otherwise.
+ *  - Augmented-system vectors have length sdp_aug_dim() = m + d with
+ *    d = n r - r (r - 1) / 2 (Proposition correct).  The first m entries are
+ *    u; the remaining d entries are v = [svec(B); vec(N)] with B an r x r
+ *    symmetric block (svec: column-major lower triangle, off-diagonal entries
+ *    times sqrt(2), Notations) and N an (n - r) x r block stored
+ *    column-major, both expressed in the eigenbasis [Q Qp] of the scaling
+ *    point W (eq. EQSigdef).  Eigenvalues are ordered decreasingly and every
+ *    eigenvector is signed so that its entry of largest magnitude is
+ *    positive (lowest index on ties).
+ */
+#ifndef WCSDP_H
+#define WCSDP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sdp_ctx sdp_ctx;
+typedef int32_t sdp_status;
+
+enum {
+    SDP_OK = 0,
+    SDP_EINVAL = -1,    /* invalid argument: shapes, indices, NaN/Inf, asymmetry */
+    SDP_ENOMEM = -2,    /* device allocation failed */
+    SDP_EDEVICE = -3,   /* a HIP call failed */
+    SDP_ENOTCONV = -4,  /* inner Krylov solve reached inner_maxit */
+    SDP_ENUMERIC = -5,  /* a factorisation met a non-positive pivot */
+    SDP_ESTALL = -6     /* the interior-point method hit max_ipm_iter or stalled */
+};
+
+enum { SDP_A_DENSE = 0, SDP_A_ENTRY = 1 };
+enum { SDP_SOLVER_PCG = 0, SDP_SOLVER_MINRES = 1 };
+enum { SDP_PREC_F64 = 0, SDP_PREC_F32 = 1, SDP_PREC_BF16 = 2 };
+
+/*
+ * Problem data (Introduction, eq. sdp-pd).
+ *  a_kind == SDP_A_DENSE: A holds m rows of n*n values, row i = vec(A_i); each
+ *      A_i must be symmetric.
+ *  a_kind == SDP_A_ENTRY: jk holds m pairs (j, k), 0-based, j <= k < n, all
+ *      distinct; A_i = (e_j e_k^T + e_k e_j^T)/2, so <A_i, X> = X_jk.
+ *  b has m entries; C is n x n symmetric.
+ *  on_device != 0 means A / jk / b / C are device pointers, else host
+ *  pointers.  Validation of values (NaN, symmetry, index range, duplicates)
+ *  is done for host inputs only; device inputs are checked for shape only.
+ *  sdp_setup copies everything it needs: the caller may free the inputs
+ *  afterwards.
+ */
+typedef struct sdp_problem {
+    int32_t n;
+    int32_t m;
+    int32_t a_kind;
+    const double* A;
+    const int32_t* jk;
+    const double* b;
+    const double* C;
+    int32_t on_device;
+} sdp_problem;
+
+/*
+ * Solver options.  sdp_default_options fills the defaults given in brackets.
+ *  rank_max     rhat of the rank rule r = argmax_{i <= rhat} lambda_i/lambda_{i+1}
+ *               (Experiments section) [10, clipped to n - 1]
+ *  rank_fixed   > 0 forces r [0]
+ *  beta         > 0 fixes the preconditioner's beta (Corollary pcg); <= 0 uses
+ *               (median eigenvalue of E)^2 * mean ||A_i||_F^2 [0]
+ *  solver       SDP_SOLVER_PCG (Corollary pcg) or SDP_SOLVER_MINRES (Corollary minres) [PCG]
+ *  inner_tol    PCG stops when ||r_u|| <= inner_tol * ||r_u(0)|| [1e-10]
+ *  inner_maxit  [500]
+ *  inner_prec   precision of the inner operator's GEMMs [SDP_PREC_F64]
+ *  max_refine   FP64 refinement sweeps around a low-precision inner solve [8]
+ *  gap_tol, feas_tol   stopping tolerances of the interior-point method [1e-8]
+ *  max_ipm_iter [100]
+ *  step_frac    fraction of the step to the boundary [0.98]
+ */
+typedef struct sdp_options {
+    int32_t rank_max;
+    int32_t rank_fixed;
+    double beta;
+    int32_t solver;
+    double inner_tol;
+    int32_t inner_maxit;
+    int32_t inner_prec;
+    int32_t max_refine;
+    double gap_tol;
+    double feas_tol;
+    int32_t max_ipm_iter;
+    double step_frac;
+    int32_t verbose;
+} sdp_options;
+
+typedef struct sdp_inner_stats {
+    int32_t iterations;     /* Krylov iterations (summed over refinement sweeps) */
+    int32_t refinements;    /* FP64 refinement sweeps (0 in FP64 mode) */
+    int32_t converged;      /* 1 if the tolerance was met */
+    int32_t r;              /* rank parameter of the split */
+    double tau;             /* lambda_{r+1}(W) / 2 */
+    double beta;            /* preconditioner beta */
+    double rel_res;         /* final ||r_u|| / ||r_u(0)|| */
+} sdp_inner_stats;
+
+typedef struct sdp_step_stats {
+    double mu, pobj, dobj, relgap, pinf, dinf;   /* at the start of the step */
+    double alpha_p, alpha_d, sigma;
+    int32_t r;
+    int32_t pcg_pred, pcg_corr;
+    int32_t converged;      /* 1 if the point already met the tolerances (no step taken) */
+    double t_scaling_ms, t_inner_ms, t_total_ms;
+} sdp_step_stats;
+
+typedef struct sdp_result {
+    int32_t status;
+    int32_t iterations;
+    int64_t pcg_iterations;
+    int64_t newton_matvecs;  /* applications of the augmented operator */
+    double pobj, dobj, relgap, pinf, dinf, mu;
+    double time_ms;
+} sdp_result;
+
+/* Fill *opt with the defaults listed above. */
+void sdp_default_options(sdp_options* opt);
+
+/*
+ * Create a context for one problem.  Validates and uploads the data, builds
+ * the device layout of A (dense: packed lower-triangle rows; entry: index
+ * pairs) and sets the starting point X = xi I, S = eta I, y = 0.
+ * hip_stream: a hipStream_t, or NULL.  *out receives the context; on error
+ * *out is NULL and the message is available from sdp_last_error(NULL).
+ */
+sdp_status sdp_setup(const sdp_problem* prob, const sdp_options* opt, void* hip_stream, sdp_ctx** out);
+
+/* Release every device buffer the context owns.  NULL is allowed. */
+void sdp_destroy(sdp_ctx* ctx);
+
+/* Message of the last error on ctx (or of the last failed sdp_setup when ctx is NULL). */
+const char* sdp_last_error(const sdp_ctx* ctx);
+
+/* m + d at the current scaling (d depends on the rank parameter r). */
+int64_t sdp_aug_dim(sdp_ctx* ctx);
+
+/*
+ * One application of the augmented operator of eq. augsys,
+ *   [u'; v'] = [A E A^T, A Q; Q^T A^T, -tau^2 Sigma] [u; v],
+ * evaluated with the Section 5 products at the scaling point of the current
+ * iterate (computed on first use after sdp_setup / sdp_set_point /
+ * sdp_ipm_step).  uv_in, uv_out: device pointers of sdp_aug_dim() doubles,
+ * not aliased.
+ */
+sdp_status sdp_newton_apply(sdp_ctx* ctx, const double* uv_in, double* uv_out);
+
+/*
+ * Solve eq. Newt-eps at the current scaling point: given b_tilde (m) and the
+ * symmetric C_tilde (n x n), return dX (n x n) and dy (m) with
+ *   dX = W (A^T(dy) - C_tilde) W,   A(dX) = b_tilde
+ * through eq. augsys (indefinite PCG, Corollary pcg) and eq. recover.
+ * All four arrays are device pointers.  stats may be NULL.  Returns
+ * SDP_ENOTCONV (with the last iterate's recovery written) when inner_maxit
+ * is reached.
+ */
+sdp_status sdp_inner_solve(sdp_ctx* ctx, const double* b_tilde, const double* C_tilde, double* dX, double* dy,
+                           sdp_inner_stats* stats);
+
+/*
+ * One Mehrotra predictor-corrector iteration with the Nesterov-Todd
+ * direction, both Newton systems solved by sdp_inner_solve.  stats may be NULL.
+ */
+sdp_status sdp_ipm_step(sdp_ctx* ctx, sdp_step_stats* stats);
+
+/*
+ * Iterate sdp_ipm_step until the relative gap and the primal and dual
+ * infeasibilities are all <= the tolerances.  Returns SDP_ESTALL after
+ * max_ipm_iter iterations.  res may be NULL.
+ */
+sdp_status sdp_solve(sdp_ctx* ctx, sdp_result* res);
+
+/* Copy the current iterate into device buffers (any may be NULL). */
+sdp_status sdp_get_point(sdp_ctx* ctx, double* X, double* y, double* S);
+
+/*
+ * Replace the current iterate with device buffers X (n x n), y (m),
+ * S (n x n); X and S must be positive definite (checked when the scaling is
+ * next computed, SDP_ENUMERIC otherwise).  Resets the iteration counter.
+ */
+sdp_status sdp_set_point(sdp_ctx* ctx, const double* X, const double* y, const double* S);
+
+/*
+ * The eigen-split of the scaling point (eq. EQSigdef) at the current
+ * iterate: lam (n, host, decreasing eigenvalues of W), V (n x n, device,
+ * eigenvectors with the sign convention above), and the scalars r, tau,
+ * beta (host).  Any pointer may be NULL.
+ */
+sdp_status sdp_get_scaling(sdp_ctx* ctx, double* lam, double* V, int32_t* r, double* tau, double* beta);
+
+/* Kernel classes whose launches can be timed with HIP events. */
+enum {
+    SDP_K_A_APPLY = 0,   /* A(M): packed dense rows times the weighted packed M */
+    SDP_K_AT_APPLY = 1,  /* A^T(u): column sums of the packed rows (both passes) */
+    SDP_K_GEMM = 2,      /* every FP64 GEMM launch */
+    SDP_K_NEWTON = 3,    /* a whole sdp_newton_apply */
+    SDP_K_COUNT = 4
+};
+
+/*
+ * Event timing of the kernel classes above: bit k of class_mask enables class
+ * k (0 disables all).  Resets the accumulated figures.
+ */
+sdp_status sdp_profile_enable(sdp_ctx* ctx, int32_t class_mask);
+
+/*
+ * Accumulated time (ms), launch count and algorithmic bytes moved for one
+ * kernel class since profiling was enabled.  Synchronises the stream.
+ */
+sdp_status sdp_profile_get(sdp_ctx* ctx, int32_t kernel_class, double* total_ms, int64_t* launches, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WCSDP_H */

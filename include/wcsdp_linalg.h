@@ -1,0 +1,67 @@
+/*
+ * wcsdp_linalg.h -- hand-written FP64 dense linear algebra on MI355X (gfx950).
+ *
+ * These are the building blocks the interior-point method uses to form the
+ * Nesterov-Todd scaling point (Introduction, eq. newt), its eigen-split
+ * (Section 3, eq. EQSigdef) and the Schur complement of the indefinite
+ * preconditioner (Section 6).  They are exported so they can be tested on
+ * their own.
+ *
+ * Conventions: column-major FP64, leading dimensions in elements, every
+ * matrix pointer is a device pointer, `stream` is a hipStream_t or NULL.
+ * Work is enqueued on `stream`; functions that return a count or a status
+ * computed on the GPU synchronise it.  Return value 0 = success, -1 = invalid
+ * argument, -3 = HIP error, -5 = numerical failure (see each function).
+ * Temporary device memory is allocated and freed internally.
+ */
+#ifndef WCSDP_LINALG_H
+#define WCSDP_LINALG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/*
+ * C = alpha op(A) op(B) + beta C with op(X) = X (trans 'N') or X^T ('T');
+ * op(A) is m x k, op(B) is k x n, C is m x n.  FP64 MFMA (16x16x4) tiles.
+ * When beta == 0, C is not read.
+ */
+int32_t wc_dgemm(void* stream, char transa, char transb, int32_t m, int32_t n, int32_t k, double alpha,
+                 const double* A, int32_t lda, const double* B, int32_t ldb, double beta, double* C, int32_t ldc);
+
+/*
+ * In-place Cholesky factorisation A = L L^T of the n x n symmetric positive
+ * definite A (lower triangle read and overwritten with L; the strict upper
+ * triangle is set to zero).  Returns 0, or -5 when a pivot is not positive;
+ * *info_host (may be NULL) receives 0 or the 1-based index of that pivot.
+ */
+int32_t wc_dpotrf(void* stream, int32_t n, double* A, int32_t lda, int32_t* info_host);
+
+/*
+ * Linv = L^{-1} for the n x n lower-triangular L (strict upper triangle of L
+ * ignored).  Linv's strict upper triangle is set to zero.  Linv must not
+ * alias L.
+ */
+int32_t wc_dtrtri(void* stream, int32_t n, const double* L, int32_t ldl, double* Linv, int32_t ldi);
+
+/*
+ * One-sided (Hestenes) block Jacobi on the n x n matrix A: rotates the
+ * columns of A in place until they are mutually orthogonal to within
+ * tol * ||a_i|| ||a_j|| (tol <= 0 selects n * 2^-53), so that on return
+ * A_in V = A_out.  Then sigma[k] (device, n) = ||A_out(:, k)|| in decreasing
+ * order, V (device, n x n, may be NULL) holds the matching right singular
+ * vectors with the sign convention "entry of largest magnitude positive"
+ * (the columns of A_out are permuted and signed to match).  The number of
+ * sweeps is returned through *sweeps_host (may be NULL).  Returns -5 if
+ * max_sweeps were not enough.
+ */
+int32_t wc_djacobi_svd(void* stream, int32_t n, double* A, int32_t lda, double* V, int32_t ldv, double* sigma,
+                       double tol, int32_t max_sweeps, int32_t* sweeps_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WCSDP_LINALG_H */

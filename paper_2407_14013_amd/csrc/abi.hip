@@ -1,0 +1,271 @@
+// extern "C" entry points of include/wcsdp.h and include/wcsdp_linalg.h.
+// Every call is wrapped so that no C++ exception crosses the boundary.
+#include <cstring>
+#include <new>
+
+#include "../../include/wcsdp.h"
+#include "../../include/wcsdp_linalg.h"
+#include "sdp_kernels.hpp"
+#include "solver.hpp"
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+template <class F>
+sdp_status guarded(sdp_ctx* c, F&& f) {
+    try {
+        return f();
+    } catch (const wc::Error& e) {
+        if (c) c->last_error = e.what();
+        else g_setup_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        if (c) c->last_error = "host allocation failed";
+        return SDP_ENOMEM;
+    } catch (const std::exception& e) {
+        if (c) c->last_error = e.what();
+        else g_setup_error = e.what();
+        return SDP_EDEVICE;
+    }
+}
+
+template <class F>
+int32_t guarded_la(F&& f) {
+    try {
+        return f();
+    } catch (const wc::Error& e) {
+        g_setup_error = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_setup_error = e.what();
+        return SDP_EDEVICE;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void sdp_default_options(sdp_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->rank_max = 10;
+    o->rank_fixed = 0;
+    o->beta = 0.0;
+    o->solver = SDP_SOLVER_PCG;
+    o->inner_tol = 1e-10;
+    o->inner_maxit = 500;
+    o->inner_prec = SDP_PREC_F64;
+    o->max_refine = 8;
+    o->gap_tol = 1e-8;
+    o->feas_tol = 1e-8;
+    o->max_ipm_iter = 100;
+    o->step_frac = 0.98;
+    o->verbose = 0;
+}
+
+sdp_status sdp_setup(const sdp_problem* prob, const sdp_options* opt, void* hip_stream, sdp_ctx** out) {
+    if (!out) {
+        g_setup_error = "out is NULL";
+        return SDP_EINVAL;
+    }
+    *out = nullptr;
+    sdp_ctx* c = nullptr;
+    try {
+        c = new sdp_ctx();
+    } catch (...) {
+        g_setup_error = "host allocation failed";
+        return SDP_ENOMEM;
+    }
+    sdp_status s = guarded(nullptr, [&]() {
+        if (opt) {
+            wc::require(opt->inner_tol > 0 && opt->gap_tol > 0 && opt->feas_tol > 0, "tolerances must be positive");
+            wc::require(opt->inner_maxit >= 1 && opt->max_ipm_iter >= 0, "iteration limits must be positive");
+            wc::require(opt->step_frac > 0 && opt->step_frac < 1, "step_frac must lie in (0, 1)");
+            wc::require(opt->solver == SDP_SOLVER_PCG, "only the PCG inner solver is available");
+            wc::require(opt->inner_prec == SDP_PREC_F64, "only FP64 inner precision is available");
+        }
+        wc::setup(c, prob, opt, static_cast<hipStream_t>(hip_stream));
+        return SDP_OK;
+    });
+    if (s != SDP_OK) {
+        delete c;
+        return s;
+    }
+    *out = c;
+    return SDP_OK;
+}
+
+void sdp_destroy(sdp_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->st);
+    delete ctx;
+}
+
+const char* sdp_last_error(const sdp_ctx* ctx) { return ctx ? ctx->last_error.c_str() : g_setup_error.c_str(); }
+
+int64_t sdp_aug_dim(sdp_ctx* ctx) {
+    if (!ctx) return -1;
+    int64_t out = -1;
+    sdp_status s = guarded(ctx, [&]() {
+        wc::ensure_scaling(ctx);
+        out = (int64_t)ctx->m + ctx->d;
+        return SDP_OK;
+    });
+    return s == SDP_OK ? out : (int64_t)s;
+}
+
+sdp_status sdp_newton_apply(sdp_ctx* ctx, const double* uv_in, double* uv_out) {
+    if (!ctx) return SDP_EINVAL;
+    return guarded(ctx, [&]() {
+        wc::require(uv_in && uv_out && uv_in != uv_out, "uv_in / uv_out must be distinct device pointers");
+        wc::newton_apply(ctx, uv_in, uv_out);
+        return SDP_OK;
+    });
+}
+
+sdp_status sdp_inner_solve(sdp_ctx* ctx, const double* b_tilde, const double* C_tilde, double* dX, double* dy,
+                           sdp_inner_stats* stats) {
+    if (!ctx) return SDP_EINVAL;
+    return guarded(ctx, [&]() {
+        wc::require(b_tilde && C_tilde && dX && dy, "inner_solve: NULL argument");
+        int rc = wc::inner_solve(ctx, b_tilde, C_tilde, dX, dy, stats);
+        WC_HIP(hipStreamSynchronize(ctx->st));
+        if (rc != 0) ctx->last_error = "inner solve reached inner_maxit";
+        return (sdp_status)rc;
+    });
+}
+
+sdp_status sdp_ipm_step(sdp_ctx* ctx, sdp_step_stats* stats) {
+    if (!ctx) return SDP_EINVAL;
+    return guarded(ctx, [&]() { return (sdp_status)wc::ipm_step(ctx, stats); });
+}
+
+sdp_status sdp_solve(sdp_ctx* ctx, sdp_result* res) {
+    if (!ctx) return SDP_EINVAL;
+    return guarded(ctx, [&]() {
+        int rc = wc::solve(ctx, res);
+        if (rc != 0) ctx->last_error = "the interior-point method reached max_ipm_iter";
+        return (sdp_status)rc;
+    });
+}
+
+sdp_status sdp_get_point(sdp_ctx* ctx, double* X, double* y, double* S) {
+    if (!ctx) return SDP_EINVAL;
+    return guarded(ctx, [&]() {
+        const long nn = (long)ctx->n * ctx->n;
+        if (X) wc::copy(ctx->st, nn, ctx->X, X);
+        if (y) wc::copy(ctx->st, ctx->m, ctx->y, y);
+        if (S) wc::copy(ctx->st, nn, ctx->S, S);
+        WC_HIP(hipStreamSynchronize(ctx->st));
+        return SDP_OK;
+    });
+}
+
+sdp_status sdp_set_point(sdp_ctx* ctx, const double* X, const double* y, const double* S) {
+    if (!ctx) return SDP_EINVAL;
+    return guarded(ctx, [&]() {
+        wc::require(X && y && S, "set_point: X, y and S are required");
+        wc::set_point(ctx, X, y, S);
+        return SDP_OK;
+    });
+}
+
+sdp_status sdp_get_scaling(sdp_ctx* ctx, double* lam, double* V, int32_t* r, double* tau, double* beta) {
+    if (!ctx) return SDP_EINVAL;
+    return guarded(ctx, [&]() {
+        wc::ensure_scaling(ctx);
+        if (lam) std::memcpy(lam, ctx->lam_h.data(), sizeof(double) * ctx->n);
+        if (V) wc::copy(ctx->st, (long)ctx->n * ctx->n, ctx->Gw, V);
+        if (r) *r = ctx->r;
+        if (tau) *tau = ctx->tau;
+        if (beta) *beta = ctx->beta;
+        WC_HIP(hipStreamSynchronize(ctx->st));
+        return SDP_OK;
+    });
+}
+
+sdp_status sdp_profile_enable(sdp_ctx* ctx, int32_t class_mask) {
+    if (!ctx) return SDP_EINVAL;
+    return guarded(ctx, [&]() {
+        wc::prof_collect(ctx);
+        for (auto& p : ctx->prof) {
+            p.ms = 0;
+            p.launches = 0;
+            p.bytes = 0;
+        }
+        ctx->prof_mask = class_mask;
+        return SDP_OK;
+    });
+}
+
+sdp_status sdp_profile_get(sdp_ctx* ctx, int32_t k, double* total_ms, int64_t* launches, double* bytes) {
+    if (!ctx) return SDP_EINVAL;
+    return guarded(ctx, [&]() {
+        wc::require(k >= 0 && k < SDP_K_COUNT, "unknown kernel class");
+        wc::prof_collect(ctx);
+        if (total_ms) *total_ms = ctx->prof[k].ms;
+        if (launches) *launches = ctx->prof[k].launches;
+        if (bytes) *bytes = ctx->prof[k].bytes;
+        return SDP_OK;
+    });
+}
+
+// ---- dense linear algebra building blocks ----------------------------------------------
+int32_t wc_dgemm(void* stream, char transa, char transb, int32_t m, int32_t n, int32_t k, double alpha,
+                 const double* A, int32_t lda, const double* B, int32_t ldb, double beta, double* C, int32_t ldc) {
+    return guarded_la([&]() {
+        const bool ta = (transa == 'T' || transa == 't'), tb = (transb == 'T' || transb == 't');
+        wc::require(ta || transa == 'N' || transa == 'n', "transa must be N or T");
+        wc::require(tb || transb == 'N' || transb == 'n', "transb must be N or T");
+        wc::require(m >= 0 && n >= 0 && k >= 0, "negative dimension");
+        wc::require(ldc >= std::max(1, m), "ldc too small");
+        wc::require(lda >= std::max(1, ta ? k : m), "lda too small");
+        wc::require(ldb >= std::max(1, tb ? n : k), "ldb too small");
+        wc::dgemm(static_cast<hipStream_t>(stream), ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+        return (int32_t)0;
+    });
+}
+
+int32_t wc_dpotrf(void* stream, int32_t n, double* A, int32_t lda, int32_t* info_host) {
+    return guarded_la([&]() {
+        wc::require(n >= 1 && lda >= n, "bad dimensions");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        wc::DevBuf<int> info(1);
+        wc::potrf(st, n, A, lda, info);
+        int h = 0;
+        WC_HIP(hipMemcpyAsync(&h, info.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+        WC_HIP(hipStreamSynchronize(st));
+        if (info_host) *info_host = h;
+        return (int32_t)(h ? -5 : 0);
+    });
+}
+
+int32_t wc_dtrtri(void* stream, int32_t n, const double* L, int32_t ldl, double* Linv, int32_t ldi) {
+    return guarded_la([&]() {
+        wc::require(n >= 1 && ldl >= n && ldi >= n, "bad dimensions");
+        wc::require(L != Linv, "Linv must not alias L");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        wc::DevBuf<double> work((size_t)n * n);
+        wc::trtri(st, n, L, ldl, Linv, ldi, work);
+        WC_HIP(hipStreamSynchronize(st));
+        return (int32_t)0;
+    });
+}
+
+int32_t wc_djacobi_svd(void* stream, int32_t n, double* A, int32_t lda, double* V, int32_t ldv, double* sigma,
+                       double tol, int32_t max_sweeps, int32_t* sweeps_host) {
+    return guarded_la([&]() {
+        wc::require(n >= 1 && lda >= n && (V == nullptr || ldv >= n) && sigma != nullptr && max_sweeps >= 1,
+                    "bad arguments");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        wc::JacobiWork w;
+        int sw = wc::jacobi_svd(st, n, A, lda, V, ldv, sigma, tol, max_sweeps, w, true);
+        WC_HIP(hipStreamSynchronize(st));
+        if (sweeps_host) *sweeps_host = sw;
+        return (int32_t)(sw < 0 ? -5 : 0);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,531 @@
+// FP64 dense kernels for gfx950: MFMA GEMM, HBM-streaming GEMVs over
+// row-major matrices, deterministic reductions and element-wise helpers.
+#include "common.hpp"
+
+namespace wc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+// ---------------------------------------------------------------------------
+// GEMM: 64 x 64 output tile per 256-thread workgroup, K step 16.  The four
+// waves form a 2 x 2 grid of 32 x 32 sub-tiles, each computed as 2 x 2
+// v_mfma_f64_16x16x4f64 tiles.  Operand layout of that instruction: lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator element v of
+// lane l is D[l / 16 + 4 v][l % 16].
+// ---------------------------------------------------------------------------
+constexpr int GBM = 64, GBN = 64, GBK = 16;
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void dgemm_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
+                                                    long lda, const double* __restrict__ B, long ldb, double beta,
+                                                    double* __restrict__ C, long ldc, int lower_only, long sA,
+                                                    long sB, long sC) {
+    const int tile_m = blockIdx.x * GBM;
+    const int tile_n = blockIdx.y * GBN;
+    if (lower_only && tile_n > tile_m + GBM - 1) return;
+    A += blockIdx.z * sA;
+    B += blockIdx.z * sB;
+    C += blockIdx.z * sC;
+
+    __shared__ double As[GBK][GBM + 1];
+    __shared__ double Bs[GBK][GBN + 1];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+
+    double ra[4], rb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int i, k;
+            if (!TA) { i = tid & 63; k = (tid >> 6) + 4 * q; }
+            else { k = tid & 15; i = (tid >> 4) + 16 * q; }
+            int gi = tile_m + i, gk = k0 + k;
+            double v = 0.0;
+            if (gi < M && gk < K) v = TA ? A[gk + (long)gi * lda] : A[gi + (long)gk * lda];
+            ra[q] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int j, k;
+            if (!TB) { k = tid & 15; j = (tid >> 4) + 16 * q; }
+            else { j = tid & 63; k = (tid >> 6) + 4 * q; }
+            int gj = tile_n + j, gk = k0 + k;
+            double v = 0.0;
+            if (gj < N && gk < K) v = TB ? B[gj + (long)gk * ldb] : B[gk + (long)gj * ldb];
+            rb[q] = v;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int i, k;
+            if (!TA) { i = tid & 63; k = (tid >> 6) + 4 * q; }
+            else { k = tid & 15; i = (tid >> 4) + 16 * q; }
+            As[k][i] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int j, k;
+            if (!TB) { k = tid & 15; j = (tid >> 4) + 16 * q; }
+            else { j = tid & 63; k = (tid >> 6) + 4 * q; }
+            Bs[k][j] = rb[q];
+        }
+    };
+
+    d4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+    load(0);
+    for (int k0 = 0; k0 < K; k0 += GBK) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (k0 + GBK < K) load(k0 + GBK);
+#pragma unroll
+        for (int kk = 0; kk < GBK; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            double a0 = As[kr][wm * 32 + (lane & 15)];
+            double a1 = As[kr][wm * 32 + 16 + (lane & 15)];
+            double b0 = Bs[kr][wn * 32 + (lane & 15)];
+            double b1 = Bs[kr][wn * 32 + 16 + (lane & 15)];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+    }
+
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int gi = tile_m + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
+                int gj = tile_n + wn * 32 + b * 16 + (lane & 15);
+                if (gi < M && gj < N && (!lower_only || gi >= gj)) {
+                    double* c = C + gi + (long)gj * ldc;
+                    double val = alpha * acc[a][b][v];
+                    *c = (beta == 0.0) ? val : val + beta * (*c);
+                }
+            }
+}
+
+void dgemm(hipStream_t st, bool ta, bool tb, int m, int n, int k, double alpha, const double* A, long lda,
+           const double* B, long ldb, double beta, double* C, long ldc, bool lower_only, int batch, long sA, long sB,
+           long sC) {
+    if (m <= 0 || n <= 0 || batch <= 0) return;
+    if (k <= 0) {
+        // C = beta C
+        for (int b = 0; b < batch; ++b) {
+            if (beta == 0.0) {
+                for (int j = 0; j < n; ++j) fill(st, m, C + b * sC + (long)j * ldc, 0.0);
+            } else if (beta != 1.0) {
+                for (int j = 0; j < n; ++j) scale(st, m, beta, C + b * sC + (long)j * ldc);
+            }
+        }
+        return;
+    }
+    dim3 grid(cdiv(m, GBM), cdiv(n, GBN), batch);
+    int lo = lower_only ? 1 : 0;
+    if (!ta && !tb)
+        hipLaunchKernelGGL((dgemm_kernel<false, false>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta,
+                           C, ldc, lo, sA, sB, sC);
+    else if (!ta && tb)
+        hipLaunchKernelGGL((dgemm_kernel<false, true>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta,
+                           C, ldc, lo, sA, sB, sC);
+    else if (ta && !tb)
+        hipLaunchKernelGGL((dgemm_kernel<true, false>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta,
+                           C, ldc, lo, sA, sB, sC);
+    else
+        hipLaunchKernelGGL((dgemm_kernel<true, true>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta, C,
+                           ldc, lo, sA, sB, sC);
+    WC_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Wave / block reductions.
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int NT>
+__device__ inline double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x < 64) {
+        r = (threadIdx.x < NT / 64) ? sh[threadIdx.x] : 0.0;
+        r = wave_sum(r);
+    }
+    __syncthreads();
+    return r;  // valid in thread 0
+}
+
+// ---------------------------------------------------------------------------
+// gemv_rows: y = alpha A x + beta y, A row-major.  ROWS rows per 256-thread
+// workgroup share every load of x; each thread streams 16-byte pairs.
+// ---------------------------------------------------------------------------
+constexpr int GV_ROWS = 4;
+
+__global__ __launch_bounds__(256) void gemv_rows_kernel(int m, int k2, const double* __restrict__ A, long lda,
+                                                        const double* __restrict__ x, double* __restrict__ y,
+                                                        double alpha, double beta) {
+    __shared__ double sh[8];
+    const int row0 = blockIdx.x * GV_ROWS;
+    double acc[GV_ROWS];
+#pragma unroll
+    for (int r = 0; r < GV_ROWS; ++r) acc[r] = 0.0;
+    const d2* x2 = reinterpret_cast<const d2*>(x);
+    const d2* arow[GV_ROWS];
+#pragma unroll
+    for (int r = 0; r < GV_ROWS; ++r) {
+        int row = row0 + r < m ? row0 + r : m - 1;
+        arow[r] = reinterpret_cast<const d2*>(A + (long)row * lda);
+    }
+    for (int c = threadIdx.x; c < k2; c += 256) {
+        d2 xv = x2[c];
+#pragma unroll
+        for (int r = 0; r < GV_ROWS; ++r) {
+            d2 av = __builtin_nontemporal_load(&arow[r][c]);
+            acc[r] += av.x * xv.x + av.y * xv.y;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < GV_ROWS; ++r) {
+        double s = block_sum<256>(acc[r], sh);
+        if (threadIdx.x == 0 && row0 + r < m) {
+            double v = alpha * s;
+            y[row0 + r] = (beta == 0.0) ? v : v + beta * y[row0 + r];
+        }
+    }
+}
+
+void gemv_rows(hipStream_t st, int m, int k, const double* A, long lda, const double* x, double* y, double alpha,
+               double beta) {
+    if (m <= 0) return;
+    int k2 = static_cast<int>(round_up(k, 2) / 2);
+    hipLaunchKernelGGL(gemv_rows_kernel, dim3(cdiv(m, GV_ROWS)), dim3(256), 0, st, m, k2, A, lda, x, y, alpha, beta);
+    WC_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// gemv_cols: y = alpha A^T x + beta y, A row-major.  Pass 1: workgroup
+// (column chunk of 512, row slab of GC_SLAB) accumulates its slab; pass 2
+// sums the slabs in a fixed order (deterministic).
+// ---------------------------------------------------------------------------
+constexpr int GC_SLAB = 64;
+
+int gemv_cols_parts(int m) { return cdiv(m, GC_SLAB); }
+
+__global__ __launch_bounds__(256) void gemv_cols_partial(int m, int k2, const double* __restrict__ A, long lda,
+                                                         const double* __restrict__ x, double* __restrict__ part,
+                                                         long pstride) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int i0 = blockIdx.y * GC_SLAB;
+    const int i1 = min(m, i0 + GC_SLAB);
+    if (c >= k2) return;
+    d2 acc = {0.0, 0.0};
+    int i = i0;
+    for (; i + 4 <= i1; i += 4) {
+        d2 a0 = __builtin_nontemporal_load(reinterpret_cast<const d2*>(A + (long)(i + 0) * lda) + c);
+        d2 a1 = __builtin_nontemporal_load(reinterpret_cast<const d2*>(A + (long)(i + 1) * lda) + c);
+        d2 a2 = __builtin_nontemporal_load(reinterpret_cast<const d2*>(A + (long)(i + 2) * lda) + c);
+        d2 a3 = __builtin_nontemporal_load(reinterpret_cast<const d2*>(A + (long)(i + 3) * lda) + c);
+        double x0 = x[i], x1 = x[i + 1], xx2 = x[i + 2], x3 = x[i + 3];
+        acc.x += a0.x * x0 + a1.x * x1 + a2.x * xx2 + a3.x * x3;
+        acc.y += a0.y * x0 + a1.y * x1 + a2.y * xx2 + a3.y * x3;
+    }
+    for (; i < i1; ++i) {
+        d2 a0 = reinterpret_cast<const d2*>(A + (long)i * lda)[c];
+        acc.x += a0.x * x[i];
+        acc.y += a0.y * x[i];
+    }
+    reinterpret_cast<d2*>(part + blockIdx.y * pstride)[c] = acc;
+}
+
+__global__ __launch_bounds__(256) void gemv_cols_reduce(int k, int nparts, const double* __restrict__ part,
+                                                        long pstride, double* __restrict__ y, double alpha,
+                                                        double beta) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= k) return;
+    double s = 0.0;
+    for (int p = 0; p < nparts; ++p) s += part[p * pstride + c];
+    double v = alpha * s;
+    y[c] = (beta == 0.0) ? v : v + beta * y[c];
+}
+
+void gemv_cols(hipStream_t st, int m, int k, const double* A, long lda, const double* x, double* y, double alpha,
+               double beta, double* part) {
+    if (k <= 0) return;
+    if (m <= 0) {
+        if (beta == 0.0) fill(st, k, y, 0.0);
+        else scale(st, k, beta, y);
+        return;
+    }
+    int k2 = static_cast<int>(round_up(k, 2) / 2);
+    long pstride = round_up(k, 2);
+    int nparts = gemv_cols_parts(m);
+    hipLaunchKernelGGL(gemv_cols_partial, dim3(cdiv(k2, 256), nparts), dim3(256), 0, st, m, k2, A, lda, x, part,
+                       pstride);
+    WC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(gemv_cols_reduce, dim3(cdiv(k, 256)), dim3(256), 0, st, k, nparts, part, pstride, y, alpha,
+                       beta);
+    WC_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic dot products: a fixed number of partial sums (depends on n
+// only), then one workgroup adds them in order.
+// ---------------------------------------------------------------------------
+constexpr int DOT_MAX_BLOCKS = 512;
+
+__global__ __launch_bounds__(256) void dot_partial(long n, const double* __restrict__ x, const double* __restrict__ y,
+                                                   double* __restrict__ part) {
+    __shared__ double sh[8];
+    double acc = 0.0;
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) acc += x[i] * y[i];
+    double s = block_sum<256>(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void dot_mat_partial(int rows, int cols, const double* __restrict__ X, long ldx,
+                                                       const double* __restrict__ Y, long ldy,
+                                                       double* __restrict__ part) {
+    __shared__ double sh[8];
+    double acc = 0.0;
+    long total = (long)rows * cols;
+    for (long t = blockIdx.x * 256L + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
+        int i = static_cast<int>(t % rows);
+        long j = t / rows;
+        acc += X[i + j * ldx] * Y[i + j * ldy];
+    }
+    double s = block_sum<256>(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void sum_parts(int np, const double* __restrict__ part, double* __restrict__ out,
+                                                 int take_sqrt) {
+    __shared__ double sh[8];
+    double acc = 0.0;
+    // fixed assignment of parts to threads keeps the order deterministic
+    for (int i = threadIdx.x; i < np; i += 256) acc += part[i];
+    double s = block_sum<256>(acc, sh);
+    if (threadIdx.x == 0) out[0] = take_sqrt ? sqrt(s) : s;
+}
+
+static int dot_blocks(long n) {
+    long b = (n + 2047) / 2048;
+    if (b < 1) b = 1;
+    if (b > DOT_MAX_BLOCKS) b = DOT_MAX_BLOCKS;
+    return static_cast<int>(b);
+}
+
+void dot(hipStream_t st, long n, const double* x, const double* y, double* out, double* part) {
+    int nb = dot_blocks(n);
+    hipLaunchKernelGGL(dot_partial, dim3(nb), dim3(256), 0, st, n, x, y, part);
+    WC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(sum_parts, dim3(1), dim3(256), 0, st, nb, part, out, 0);
+    WC_LAUNCH_CHECK();
+}
+
+void dot_mat(hipStream_t st, int rows, int cols, const double* X, long ldx, const double* Y, long ldy, double* out,
+             double* part) {
+    int nb = dot_blocks((long)rows * cols);
+    hipLaunchKernelGGL(dot_mat_partial, dim3(nb), dim3(256), 0, st, rows, cols, X, ldx, Y, ldy, part);
+    WC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(sum_parts, dim3(1), dim3(256), 0, st, nb, part, out, 0);
+    WC_LAUNCH_CHECK();
+}
+
+void frob_norm(hipStream_t st, int n, const double* A, long lda, double* out, double* part) {
+    int nb = dot_blocks((long)n * n);
+    hipLaunchKernelGGL(dot_mat_partial, dim3(nb), dim3(256), 0, st, n, n, A, lda, A, lda, part);
+    WC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(sum_parts, dim3(1), dim3(256), 0, st, nb, part, out, 1);
+    WC_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Element-wise kernels.
+// ---------------------------------------------------------------------------
+__global__ void fill_kernel(long n, double* x, double v) {
+    long i = blockIdx.x * 256L + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+__global__ void copy_kernel(long n, const double* __restrict__ x, double* __restrict__ y) {
+    long i = blockIdx.x * 256L + threadIdx.x;
+    if (i < n) y[i] = x[i];
+}
+__global__ void axpby_kernel(long n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+    long i = blockIdx.x * 256L + threadIdx.x;
+    if (i < n) y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
+}
+__global__ void axpbypcz_kernel(long n, double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+                                double c, double* __restrict__ z) {
+    long i = blockIdx.x * 256L + threadIdx.x;
+    if (i < n) z[i] = a * x[i] + b * y[i] + (c == 0.0 ? 0.0 : c * z[i]);
+}
+__global__ void scale_kernel(long n, double a, double* x) {
+    long i = blockIdx.x * 256L + threadIdx.x;
+    if (i < n) x[i] *= a;
+}
+
+static dim3 grid1(long n) { return dim3(static_cast<unsigned>((n + 255) / 256)); }
+
+void fill(hipStream_t st, long n, double* x, double v) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(fill_kernel, grid1(n), dim3(256), 0, st, n, x, v);
+    WC_LAUNCH_CHECK();
+}
+void copy(hipStream_t st, long n, const double* x, double* y) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(copy_kernel, grid1(n), dim3(256), 0, st, n, x, y);
+    WC_LAUNCH_CHECK();
+}
+void axpby(hipStream_t st, long n, double a, const double* x, double b, double* y) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(axpby_kernel, grid1(n), dim3(256), 0, st, n, a, x, b, y);
+    WC_LAUNCH_CHECK();
+}
+void axpbypcz(hipStream_t st, long n, double a, const double* x, double b, const double* y, double c, double* z) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(axpbypcz_kernel, grid1(n), dim3(256), 0, st, n, a, x, b, y, c, z);
+    WC_LAUNCH_CHECK();
+}
+void scale(hipStream_t st, long n, double a, double* x) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(scale_kernel, grid1(n), dim3(256), 0, st, n, a, x);
+    WC_LAUNCH_CHECK();
+}
+
+// 2-D helpers: one thread per element, rows fastest.
+__global__ void mat_copy_kernel(int rows, int cols, const double* __restrict__ A, long lda, double* __restrict__ B,
+                                long ldb) {
+    long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)rows * cols) return;
+    int i = static_cast<int>(t % rows);
+    long j = t / rows;
+    B[i + j * ldb] = A[i + j * lda];
+}
+__global__ void transpose_kernel(int rows, int cols, const double* __restrict__ A, long lda, double* __restrict__ B,
+                                 long ldb) {
+    __shared__ double tile[32][33];
+    int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
+    for (int k = ty; k < 32; k += 8) {
+        int i = bx + tx, j = by + k;
+        tile[k][tx] = (i < rows && j < cols) ? A[i + (long)j * lda] : 0.0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        int j = by + tx, i = bx + k;  // B(j, i) = A(i, j)
+        if (i < rows && j < cols) B[j + (long)i * ldb] = tile[tx][k];
+    }
+}
+__global__ void symmetrize_kernel(int n, double* A, long lda) {
+    long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)n * n) return;
+    int i = static_cast<int>(t % n);
+    int j = static_cast<int>(t / n);
+    if (i <= j) return;
+    double v = 0.5 * (A[i + (long)j * lda] + A[j + (long)i * lda]);
+    A[i + (long)j * lda] = v;
+    A[j + (long)i * lda] = v;
+}
+__global__ void zero_upper_kernel(int n, double* A, long lda) {
+    long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)n * n) return;
+    int i = static_cast<int>(t % n);
+    int j = static_cast<int>(t / n);
+    if (i < j) A[i + (long)j * lda] = 0.0;
+}
+__global__ void set_identity_kernel(int n, double* A, long lda, double diag) {
+    long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)n * n) return;
+    int i = static_cast<int>(t % n);
+    int j = static_cast<int>(t / n);
+    A[i + (long)j * lda] = (i == j) ? diag : 0.0;
+}
+__global__ void add_diag_kernel(int n, double* A, long lda, double v) {
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) A[i + (long)i * lda] += v;
+}
+__global__ void scale_cols_kernel(int rows, int cols, const double* __restrict__ A, long lda,
+                                  const double* __restrict__ s, double pw, double* __restrict__ B, long ldb) {
+    long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)rows * cols) return;
+    int i = static_cast<int>(t % rows);
+    long j = t / rows;
+    double f = (pw == 1.0) ? s[j] : (pw == -0.5 ? 1.0 / sqrt(s[j]) : (pw == 0.5 ? sqrt(s[j]) : pow(s[j], pw)));
+    B[i + j * ldb] = A[i + j * lda] * f;
+}
+__global__ void scale_rows_kernel(int rows, int cols, const double* __restrict__ A, long lda,
+                                  const double* __restrict__ s, double pw, double* __restrict__ B, long ldb) {
+    long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)rows * cols) return;
+    int i = static_cast<int>(t % rows);
+    long j = t / rows;
+    double f = (pw == 1.0) ? s[i] : (pw == -0.5 ? 1.0 / sqrt(s[i]) : (pw == 0.5 ? sqrt(s[i]) : pow(s[i], pw)));
+    B[i + j * ldb] = A[i + j * lda] * f;
+}
+
+void mat_copy(hipStream_t st, int rows, int cols, const double* A, long lda, double* B, long ldb) {
+    if ((long)rows * cols <= 0) return;
+    hipLaunchKernelGGL(mat_copy_kernel, grid1((long)rows * cols), dim3(256), 0, st, rows, cols, A, lda, B, ldb);
+    WC_LAUNCH_CHECK();
+}
+void transpose(hipStream_t st, int rows, int cols, const double* A, long lda, double* B, long ldb) {
+    if ((long)rows * cols <= 0) return;
+    hipLaunchKernelGGL(transpose_kernel, dim3(cdiv(rows, 32), cdiv(cols, 32)), dim3(256), 0, st, rows, cols, A, lda,
+                       B, ldb);
+    WC_LAUNCH_CHECK();
+}
+void symmetrize(hipStream_t st, int n, double* A, long lda) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(symmetrize_kernel, grid1((long)n * n), dim3(256), 0, st, n, A, lda);
+    WC_LAUNCH_CHECK();
+}
+void zero_upper(hipStream_t st, int n, double* A, long lda) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(zero_upper_kernel, grid1((long)n * n), dim3(256), 0, st, n, A, lda);
+    WC_LAUNCH_CHECK();
+}
+void set_identity(hipStream_t st, int n, double* A, long lda, double diag) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(set_identity_kernel, grid1((long)n * n), dim3(256), 0, st, n, A, lda, diag);
+    WC_LAUNCH_CHECK();
+}
+void add_diag(hipStream_t st, int n, double* A, long lda, double v) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(add_diag_kernel, grid1(n), dim3(256), 0, st, n, A, lda, v);
+    WC_LAUNCH_CHECK();
+}
+void scale_cols(hipStream_t st, int rows, int cols, const double* A, long lda, const double* s, double pw, double* B,
+                long ldb) {
+    if ((long)rows * cols <= 0) return;
+    hipLaunchKernelGGL(scale_cols_kernel, grid1((long)rows * cols), dim3(256), 0, st, rows, cols, A, lda, s, pw, B,
+                       ldb);
+    WC_LAUNCH_CHECK();
+}
+void scale_rows(hipStream_t st, int rows, int cols, const double* A, long lda, const double* s, double pw, double* B,
+                long ldb) {
+    if ((long)rows * cols <= 0) return;
+    hipLaunchKernelGGL(scale_rows_kernel, grid1((long)rows * cols), dim3(256), 0, st, rows, cols, A, lda, s, pw, B,
+                       ldb);
+    WC_LAUNCH_CHECK();
+}
+
+}  // namespace wc

@@ -1,0 +1,338 @@
+// One-sided (Hestenes) block Jacobi SVD for FP64 n x n matrices on gfx950.
+//
+// The columns are grouped into blocks of 16.  A sweep visits every pair of
+// blocks once through a round-robin tournament: in each round the nblk/2
+// disjoint block pairs are processed by one workgroup each.  A workgroup
+//   1. forms the 32 x 32 Gram matrix H of its two blocks with FP64 MFMA,
+//   2. diagonalises H in LDS with two-sided cyclic Jacobi (H = R D R^T),
+//   3. rotates the 32 columns of A (and of V) by R with FP64 MFMA.
+// A sweep in which every pair was already orthogonal to within
+// tol * ||a_i|| ||a_j|| ends the iteration.  Rotating only the columns of A
+// gives the singular values with high relative accuracy, which the small
+// eigenvalues of the scaling matrix need.
+#include "common.hpp"
+
+namespace wc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int JB = 16;  // block width
+constexpr int JW = 32;  // columns handled by one workgroup
+constexpr int JR = 64;  // rows staged per tile
+
+__device__ inline void tournament_pair(int round, int w, int N, int& a, int& b) {
+    // circle method: player N-1 is fixed, the others rotate
+    if (w == 0) {
+        a = round;
+        b = N - 1;
+    } else {
+        a = (round + w) % (N - 1);
+        b = (round - w + (N - 1)) % (N - 1);
+    }
+}
+
+__global__ __launch_bounds__(256) void jacobi_round_kernel(int n, int nblk, int round, double* __restrict__ A,
+                                                           long lda, double* __restrict__ V, long ldv, double tol,
+                                                           unsigned long long* offmax) {
+    __shared__ double P[JR][JW + 1];
+    __shared__ double H[JW][JW + 1];
+    __shared__ double R[JW][JW + 1];
+    __shared__ int cols[JW];
+    __shared__ double cs[JB], sn[JB];
+    __shared__ int pp[JB], qq[JB];
+    __shared__ double red[4];
+    __shared__ int rot_any;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    int bi, bj;
+    tournament_pair(round, blockIdx.x, nblk, bi, bj);
+    if (tid < JW) {
+        int c = (tid < JB) ? bi * JB + tid : bj * JB + (tid - JB);
+        cols[tid] = (c < n) ? c : -1;
+    }
+    __syncthreads();
+
+    // ---- 1. Gram matrix --------------------------------------------------
+    const int hi = wave >> 1, hj = wave & 1;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int r0 = 0; r0 < n; r0 += JR) {
+        const int row = r0 + lane;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            int c = wave + 4 * q;
+            int gc = cols[c];
+            P[lane][c] = (gc >= 0 && row < n) ? A[row + (long)gc * lda] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k4 = 0; k4 < JR; k4 += 4) {
+            double a = P[k4 + (lane >> 4)][hi * 16 + (lane & 15)];
+            double b = P[k4 + (lane >> 4)][hj * 16 + (lane & 15)];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) H[hi * 16 + (lane >> 4) + 4 * v][hj * 16 + (lane & 15)] = acc[v];
+    __syncthreads();
+
+    // ---- convergence measure of this pair ----------------------------------
+    double mx = 0.0;
+    for (int t = tid; t < JW * JW; t += 256) {
+        int i = t % JW, j = t / JW;
+        if (i < j) {
+            double hii = H[i][i], hjj = H[j][j];
+            if (hii > 0.0 && hjj > 0.0) mx = fmax(mx, fabs(H[i][j]) / sqrt(hii * hjj));
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if (lane == 0) red[wave] = mx;
+    __syncthreads();
+    const double off_pair = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (tid == 0) atomicMax(offmax, static_cast<unsigned long long>(__double_as_longlong(off_pair)));
+    if (off_pair <= tol) return;  // uniform across the workgroup
+
+    // ---- 2. inner two-sided Jacobi on H ------------------------------------
+    for (int t = tid; t < JW * JW; t += 256) {
+        int i = t % JW, j = t / JW;
+        R[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    const double eps_in = 2.220446049250313e-16;
+    for (int sweep = 0; sweep < 15; ++sweep) {
+        if (tid == 0) rot_any = 0;
+        __syncthreads();
+        for (int rr = 0; rr < JW - 1; ++rr) {
+            if (tid < JB) {
+                int p, q;
+                tournament_pair(rr, tid, JW, p, q);
+                double app = H[p][p], aqq = H[q][q], apq = H[p][q];
+                double c = 1.0, s = 0.0;
+                if (fabs(apq) > eps_in * sqrt(fabs(app * aqq)) && apq != 0.0) {
+                    double th = (aqq - app) / (2.0 * apq);
+                    double t;
+                    if (fabs(th) > 1e150) t = 0.5 / th;
+                    else t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    s = t * c;
+                    rot_any = 1;
+                }
+                cs[tid] = c;
+                sn[tid] = s;
+                pp[tid] = p;
+                qq[tid] = q;
+            }
+            __syncthreads();
+            for (int t = tid; t < JB * JW; t += 256) {
+                int k = t / JW, i = t % JW;
+                double c = cs[k], s = sn[k];
+                if (s != 0.0) {
+                    int p = pp[k], q = qq[k];
+                    double hp = H[i][p], hq = H[i][q];
+                    H[i][p] = c * hp - s * hq;
+                    H[i][q] = s * hp + c * hq;
+                    double rp = R[i][p], rq = R[i][q];
+                    R[i][p] = c * rp - s * rq;
+                    R[i][q] = s * rp + c * rq;
+                }
+            }
+            __syncthreads();
+            for (int t = tid; t < JB * JW; t += 256) {
+                int k = t / JW, i = t % JW;
+                double c = cs[k], s = sn[k];
+                if (s != 0.0) {
+                    int p = pp[k], q = qq[k];
+                    double hp = H[p][i], hq = H[q][i];
+                    H[p][i] = c * hp - s * hq;
+                    H[q][i] = s * hp + c * hq;
+                }
+            }
+            __syncthreads();
+        }
+        if (!rot_any) break;
+        __syncthreads();
+    }
+
+    // ---- 3. rotate the columns: [A_i A_j] <- [A_i A_j] R -----------------------
+    for (int pass = 0; pass < 2; ++pass) {
+        double* M = pass == 0 ? A : V;
+        const long ldm = pass == 0 ? lda : ldv;
+        if (M == nullptr) break;
+        for (int r0 = 0; r0 < n; r0 += JR) {
+            const int row = r0 + lane;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                int c = wave + 4 * q;
+                int gc = cols[c];
+                P[lane][c] = (gc >= 0 && row < n) ? M[row + (long)gc * ldm] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int jt = 0; jt < 2; ++jt) {
+                d4 o = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int k4 = 0; k4 < JW; k4 += 4) {
+                    double a = P[wave * 16 + (lane & 15)][k4 + (lane >> 4)];
+                    double b = R[k4 + (lane >> 4)][jt * 16 + (lane & 15)];
+                    o = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, o, 0, 0, 0);
+                }
+                const int gc = cols[jt * 16 + (lane & 15)];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int rrow = r0 + wave * 16 + (lane >> 4) + 4 * v;
+                    if (gc >= 0 && rrow < n) M[rrow + (long)gc * ldm] = o[v];
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// One wave per column: Euclidean norm of A(:, k) and the sign that makes the
+// largest-magnitude entry of V(:, k) positive (lowest row index on ties).
+__global__ __launch_bounds__(256) void col_norm_sign_kernel(int n, const double* __restrict__ A, long lda,
+                                                            const double* __restrict__ V, long ldv,
+                                                            double* __restrict__ norms, double* __restrict__ sign) {
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= n) return;
+    // scaled sum of squares avoids overflow / underflow
+    double amax = 0.0;
+    for (int i = lane; i < n; i += 64) amax = fmax(amax, fabs(A[i + (long)k * lda]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+    double ss = 0.0;
+    if (amax > 0.0) {
+        for (int i = lane; i < n; i += 64) {
+            double v = A[i + (long)k * lda] / amax;
+            ss += v * v;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    double best = -1.0;
+    int bidx = 0x7fffffff;
+    double bval = 1.0;
+    if (V != nullptr) {
+        for (int i = lane; i < n; i += 64) {
+            double v = V[i + (long)k * ldv];
+            double a = fabs(v);
+            if (a > best) {
+                best = a;
+                bidx = i;
+                bval = v;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            double ob = __shfl_xor(best, off, 64);
+            int oi = __shfl_xor(bidx, off, 64);
+            double ov = __shfl_xor(bval, off, 64);
+            if (ob > best || (ob == best && oi < bidx)) {
+                best = ob;
+                bidx = oi;
+                bval = ov;
+            }
+        }
+    }
+    if (lane == 0) {
+        norms[k] = amax * sqrt(ss);
+        sign[k] = (V != nullptr && bval < 0.0) ? -1.0 : 1.0;
+    }
+}
+
+// rank of each norm in decreasing order (ties by index): a permutation.
+__global__ __launch_bounds__(256) void rank_desc_kernel(int n, const double* __restrict__ v, int* __restrict__ rank) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const double x = v[k];
+    int r = 0;
+    for (int j = 0; j < n; ++j) {
+        double y = v[j];
+        r += (y > x) || (y == x && j < k);
+    }
+    rank[k] = r;
+}
+
+__global__ __launch_bounds__(256) void permute_cols_kernel(int n, const double* __restrict__ src, long lds,
+                                                           const int* __restrict__ rank,
+                                                           const double* __restrict__ sign, double* __restrict__ dst,
+                                                           long ldd) {
+    long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)n * n) return;
+    int i = static_cast<int>(t % n);
+    int k = static_cast<int>(t / n);
+    dst[i + (long)rank[k] * ldd] = sign[k] * src[i + (long)k * lds];
+}
+
+__global__ void permute_vec_kernel(int n, const double* __restrict__ src, const int* __restrict__ rank,
+                                   double* __restrict__ dst) {
+    int k = blockIdx.x * 256 + threadIdx.x;
+    if (k < n) dst[rank[k]] = src[k];
+}
+
+void JacobiWork::ensure(int n) {
+    if (n <= cap) return;
+    off.alloc(1);
+    norms.alloc(2 * (size_t)n);
+    perm.alloc(n);
+    tmpA.alloc((size_t)n * n);
+    tmpV.alloc((size_t)n * n);
+    if (!pinned) WC_HIP(hipHostMalloc(reinterpret_cast<void**>(&pinned), sizeof(double), hipHostMallocDefault));
+    cap = n;
+}
+
+JacobiWork::~JacobiWork() {
+    if (pinned) (void)hipHostFree(pinned);
+}
+
+int jacobi_svd(hipStream_t st, int n, double* A, long lda, double* V, long ldv, double* sigma, double tol,
+               int max_sweeps, JacobiWork& w, bool want_a) {
+    require(n >= 1, "jacobi_svd: n must be positive");
+    w.ensure(n);
+    if (tol <= 0.0) tol = std::max(n, 16) * 1.1102230246251565e-16;
+    if (V) set_identity(st, n, V, ldv, 1.0);
+    int nblk = cdiv(n, JB);
+    if (nblk < 2) nblk = 2;
+    if (nblk & 1) ++nblk;
+    int sweeps = -max_sweeps;
+    for (int s = 0; s < max_sweeps; ++s) {
+        fill(st, 1, w.off.get(), 0.0);
+        for (int round = 0; round < nblk - 1; ++round) {
+            hipLaunchKernelGGL(jacobi_round_kernel, dim3(nblk / 2), dim3(256), 0, st, n, nblk, round, A, lda, V, ldv,
+                               tol, reinterpret_cast<unsigned long long*>(w.off.get()));
+            WC_LAUNCH_CHECK();
+        }
+        WC_HIP(hipMemcpyAsync(w.pinned, w.off.get(), sizeof(double), hipMemcpyDeviceToHost, st));
+        WC_HIP(hipStreamSynchronize(st));
+        if (*w.pinned <= tol) {
+            sweeps = s + 1;
+            break;
+        }
+    }
+    double* norms = w.norms.get();
+    double* sgn = w.norms.get() + n;
+    hipLaunchKernelGGL(col_norm_sign_kernel, dim3(cdiv(n, 4)), dim3(256), 0, st, n, A, lda, V, ldv, norms, sgn);
+    WC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(rank_desc_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, n, norms, w.perm.get());
+    WC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(permute_vec_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, n, norms, w.perm.get(), sigma);
+    WC_LAUNCH_CHECK();
+    long nn = (long)n * n;
+    if (V) {
+        hipLaunchKernelGGL(permute_cols_kernel, dim3(cdiv(nn, 256)), dim3(256), 0, st, n, V, ldv, w.perm.get(), sgn,
+                           w.tmpV.get(), (long)n);
+        WC_LAUNCH_CHECK();
+        mat_copy(st, n, n, w.tmpV.get(), n, V, ldv);
+    }
+    if (want_a) {
+        hipLaunchKernelGGL(permute_cols_kernel, dim3(cdiv(nn, 256)), dim3(256), 0, st, n, A, lda, w.perm.get(), sgn,
+                           w.tmpA.get(), (long)n);
+        WC_LAUNCH_CHECK();
+        mat_copy(st, n, n, w.tmpA.get(), n, A, lda);
+    }
+    return sweeps;
+}
+
+}  // namespace wc

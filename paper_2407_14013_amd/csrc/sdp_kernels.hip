@@ -1,0 +1,427 @@
+// SDP-specific kernels: packing of the constraint data, the svec / v
+// coordinate maps of the reformulation (Section 3, eq. EQSigdef; Section 5
+// products), the Schur-complement blocks of the preconditioner (Section 6)
+// and the element-wise pieces of the interior-point step.
+#include "sdp_kernels.hpp"
+
+namespace wc {
+
+static dim3 g1(long n) { return dim3(static_cast<unsigned>((n + 255) / 256)); }
+constexpr double kSqrt2 = 1.4142135623730951;
+constexpr double kInvSqrt2 = 0.7071067811865476;
+
+// svec position c (0-based) of an r x r symmetric block -> (row i, column jj), i >= jj.
+__device__ inline void svec_pair(int c, int r, int& i, int& jj) {
+    jj = 0;
+    while (c >= r - jj) {
+        c -= r - jj;
+        ++jj;
+    }
+    i = jj + c;
+}
+
+// ---- packed lower-triangle index tables -------------------------------------
+__global__ void tri_tables_kernel(int n, int* __restrict__ pj, int* __restrict__ pk) {
+    long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)n * n) return;
+    int j = static_cast<int>(t % n);
+    int k = static_cast<int>(t / n);
+    if (j < k) return;
+    long p = (long)k * n - (long)k * (k - 1) / 2 + (j - k);
+    pj[p] = j;
+    pk[p] = k;
+}
+void tri_tables(hipStream_t st, int n, int* pj, int* pk) {
+    hipLaunchKernelGGL(tri_tables_kernel, g1((long)n * n), dim3(256), 0, st, n, pj, pk);
+    WC_LAUNCH_CHECK();
+}
+
+// P[i, p] = A_i[j, k] for the lower-triangle position p = (j, k); pad with zeros.
+__global__ void pack_dense_rows_kernel(int n, int m, long N2, long ldp, const double* __restrict__ A,
+                                       const int* __restrict__ pj, const int* __restrict__ pk,
+                                       double* __restrict__ P) {
+    long p = blockIdx.x * 256L + threadIdx.x;
+    int i = blockIdx.y;
+    if (p >= ldp) return;
+    double v = 0.0;
+    if (p < N2) {
+        int j = pj[p], k = pk[p];
+        const double* Ai = A + (long)i * n * n;
+        v = 0.5 * (Ai[j + (long)k * n] + Ai[k + (long)j * n]);
+    }
+    P[(long)i * ldp + p] = v;
+}
+void pack_dense_rows(hipStream_t st, int n, int m, long N2, long ldp, const double* A, const int* pj, const int* pk,
+                     double* P) {
+    // one y-block per constraint row; keep gridDim.y within the hardware limit
+    const int chunk = 65535;
+    for (int i0 = 0; i0 < m; i0 += chunk) {
+        int cnt = std::min(chunk, m - i0);
+        hipLaunchKernelGGL(pack_dense_rows_kernel, dim3(cdiv(ldp, 256), cnt), dim3(256), 0, st, n, cnt, N2, ldp,
+                           A + (long)i0 * n * n, pj, pk, P + (long)i0 * ldp);
+        WC_LAUNCH_CHECK();
+    }
+}
+
+// ||A_i||_F^2 from packed rows: diagonal entries once, off-diagonal twice.
+__global__ __launch_bounds__(256) void packed_row_norm2_kernel(int m, long N2, long ldp, const double* __restrict__ P,
+                                                               const int* __restrict__ pj,
+                                                               const int* __restrict__ pk, double* __restrict__ out) {
+    __shared__ double sh[4];
+    int i = blockIdx.x;
+    double acc = 0.0;
+    for (long p = threadIdx.x; p < N2; p += 256) {
+        double v = P[(long)i * ldp + p];
+        acc += (pj[p] == pk[p] ? 1.0 : 2.0) * v * v;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[i] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+void packed_row_norm2(hipStream_t st, int m, long N2, long ldp, const double* P, const int* pj, const int* pk,
+                      double* out) {
+    hipLaunchKernelGGL(packed_row_norm2_kernel, dim3(m), dim3(256), 0, st, m, N2, ldp, P, pj, pk, out);
+    WC_LAUNCH_CHECK();
+}
+
+// mw[p] = w_p (M_jk + M_kj)/2 with w = 1 on the diagonal and 2 off it, so that
+// A(M)_i = sum_p P[i,p] mw[p]; the pad [N2, ldp) is zero.
+__global__ void pack_weighted_kernel(int n, long N2, long ldp, const double* __restrict__ M, long ldm,
+                                     const int* __restrict__ pj, const int* __restrict__ pk,
+                                     double* __restrict__ mw) {
+    long p = blockIdx.x * 256L + threadIdx.x;
+    if (p >= ldp) return;
+    double v = 0.0;
+    if (p < N2) {
+        int j = pj[p], k = pk[p];
+        v = (j == k) ? M[j + (long)j * ldm] : (M[j + (long)k * ldm] + M[k + (long)j * ldm]);
+    }
+    mw[p] = v;
+}
+void pack_weighted(hipStream_t st, int n, long N2, long ldp, const double* M, long ldm, const int* pj, const int* pk,
+                   double* mw) {
+    hipLaunchKernelGGL(pack_weighted_kernel, g1(ldp), dim3(256), 0, st, n, N2, ldp, M, ldm, pj, pk, mw);
+    WC_LAUNCH_CHECK();
+}
+
+// Y[j,k] = Y[k,j] = yp[p]
+__global__ void unpack_sym_kernel(long N2, const double* __restrict__ yp, const int* __restrict__ pj,
+                                  const int* __restrict__ pk, double* __restrict__ Y, long ldy) {
+    long p = blockIdx.x * 256L + threadIdx.x;
+    if (p >= N2) return;
+    int j = pj[p], k = pk[p];
+    double v = yp[p];
+    Y[j + (long)k * ldy] = v;
+    Y[k + (long)j * ldy] = v;
+}
+void unpack_sym(hipStream_t st, long N2, const double* yp, const int* pj, const int* pk, double* Y, long ldy) {
+    hipLaunchKernelGGL(unpack_sym_kernel, g1(N2), dim3(256), 0, st, N2, yp, pj, pk, Y, ldy);
+    WC_LAUNCH_CHECK();
+}
+
+// ---- entry-sampling constraints ----------------------------------------------
+__global__ void entry_gather_kernel(int m, const int* __restrict__ jk, const double* __restrict__ M, long ldm,
+                                    double* __restrict__ out, double alpha, double beta) {
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    int j = jk[2 * i], k = jk[2 * i + 1];
+    double v = 0.5 * (M[j + (long)k * ldm] + M[k + (long)j * ldm]);
+    out[i] = (beta == 0.0) ? alpha * v : alpha * v + beta * out[i];
+}
+void entry_gather(hipStream_t st, int m, const int* jk, const double* M, long ldm, double* out, double alpha,
+                  double beta) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(entry_gather_kernel, g1(m), dim3(256), 0, st, m, jk, M, ldm, out, alpha, beta);
+    WC_LAUNCH_CHECK();
+}
+
+// Y (already zeroed) += sum_i u_i sym(e_j e_k^T); the pairs are distinct, so
+// every entry of Y is written by at most one thread.
+__global__ void entry_scatter_kernel(int m, const int* __restrict__ jk, const double* __restrict__ u,
+                                     double* __restrict__ Y, long ldy) {
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    int j = jk[2 * i], k = jk[2 * i + 1];
+    double v = u[i];
+    if (j == k) {
+        Y[j + (long)j * ldy] = v;
+    } else {
+        Y[j + (long)k * ldy] = 0.5 * v;
+        Y[k + (long)j * ldy] = 0.5 * v;
+    }
+}
+void entry_scatter(hipStream_t st, int m, const int* jk, const double* u, double* Y, long ldy) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(entry_scatter_kernel, g1(m), dim3(256), 0, st, m, jk, u, Y, ldy);
+    WC_LAUNCH_CHECK();
+}
+
+// ---- reformulation coordinates -------------------------------------------------
+// Sigma (eq. EQSigdef): 1/(l_i l_j - tau^2) on the svec(B) part, 1/((l_j - tau) lp_k) on vec(N).
+__global__ void sigma_kernel(int n, int r, const double* __restrict__ lam, double tau, double* __restrict__ sig) {
+    const int nb = r * (r + 1) / 2;
+    const int d = nb + (n - r) * r;
+    int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= d) return;
+    double v;
+    if (c < nb) {
+        int i, jj;
+        svec_pair(c, r, i, jj);
+        v = 1.0 / (lam[i] * lam[jj] - tau * tau);
+    } else {
+        int t = c - nb;
+        int k = t % (n - r), b = t / (n - r);
+        v = 1.0 / ((lam[b] - tau) * lam[r + k]);
+    }
+    sig[c] = v;
+}
+void sigma_diag(hipStream_t st, int n, int r, const double* lam, double tau, double* sig) {
+    int d = r * (r + 1) / 2 + (n - r) * r;
+    hipLaunchKernelGGL(sigma_kernel, g1(d), dim3(256), 0, st, n, r, lam, tau, sig);
+    WC_LAUNCH_CHECK();
+}
+
+// e_k = 1 for k < r and lam_k / tau otherwise (eigenvalues of E).
+__global__ void e_eig_kernel(int n, int r, const double* __restrict__ lam, double tau, double* __restrict__ e) {
+    int k = blockIdx.x * 256 + threadIdx.x;
+    if (k < n) e[k] = (k < r) ? 1.0 : lam[k] / tau;
+}
+void e_eigenvalues(hipStream_t st, int n, int r, const double* lam, double tau, double* e) {
+    hipLaunchKernelGGL(e_eig_kernel, g1(n), dim3(256), 0, st, n, r, lam, tau, e);
+    WC_LAUNCH_CHECK();
+}
+
+// Hm (n x r, ld n) = [B; sqrt(2) N] from v = [svec(B); vec(N)].
+__global__ void v_to_h_kernel(int n, int r, const double* __restrict__ v, double* __restrict__ Hm) {
+    long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)n * r) return;
+    int a = static_cast<int>(t % n), b = static_cast<int>(t / n);
+    const int nb = r * (r + 1) / 2;
+    double val;
+    if (a < r) {
+        int i = a > b ? a : b, jj = a > b ? b : a;
+        int c = jj * r - jj * (jj - 1) / 2 + (i - jj);
+        val = (i == jj) ? v[c] : v[c] * kInvSqrt2;
+    } else {
+        val = kSqrt2 * v[nb + (a - r) + (long)(n - r) * b];
+    }
+    Hm[a + (long)b * n] = val;
+}
+void v_to_h(hipStream_t st, int n, int r, const double* v, double* Hm) {
+    hipLaunchKernelGGL(v_to_h_kernel, g1((long)n * r), dim3(256), 0, st, n, r, v, Hm);
+    WC_LAUNCH_CHECK();
+}
+
+// out = [svec(sym F_top); sqrt(2) vec(F_bottom)] - t2 * sig .* vin  (F = G^T Y Q, n x r).
+__global__ void f_to_v_kernel(int n, int r, const double* __restrict__ F, long ldf, const double* __restrict__ vin,
+                              const double* __restrict__ sig, double t2, double* __restrict__ out) {
+    const int nb = r * (r + 1) / 2;
+    const int d = nb + (n - r) * r;
+    int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= d) return;
+    double val;
+    if (c < nb) {
+        int i, jj;
+        svec_pair(c, r, i, jj);
+        val = (i == jj) ? F[i + (long)i * ldf] : kSqrt2 * 0.5 * (F[i + (long)jj * ldf] + F[jj + (long)i * ldf]);
+    } else {
+        int t = c - nb;
+        int k = t % (n - r), b = t / (n - r);
+        val = kSqrt2 * F[(r + k) + (long)b * ldf];
+    }
+    if (vin != nullptr) val -= t2 * sig[c] * vin[c];
+    out[c] = val;
+}
+void f_to_v(hipStream_t st, int n, int r, const double* F, long ldf, const double* vin, const double* sig, double t2,
+            double* out) {
+    int d = r * (r + 1) / 2 + (n - r) * r;
+    hipLaunchKernelGGL(f_to_v_kernel, g1(d), dim3(256), 0, st, n, r, F, ldf, vin, sig, t2, out);
+    WC_LAUNCH_CHECK();
+}
+
+// M = (U Q^T + Q U^T) / 2 (+ beta M), U and Q n x r with leading dimension n.
+__global__ void symlr_kernel(int n, int r, const double* __restrict__ U, const double* __restrict__ Q, long ldq,
+                             double* __restrict__ M, long ldm, double beta) {
+    long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)n * n) return;
+    int i = static_cast<int>(t % n), j = static_cast<int>(t / n);
+    double s = 0.0;
+    for (int b = 0; b < r; ++b) s += U[i + (long)b * n] * Q[j + (long)b * ldq] + Q[i + (long)b * ldq] * U[j + (long)b * n];
+    double v = 0.5 * s;
+    M[i + (long)j * ldm] = (beta == 0.0) ? v : v + beta * M[i + (long)j * ldm];
+}
+void symlr(hipStream_t st, int n, int r, const double* U, const double* Q, long ldq, double* M, long ldm, double beta) {
+    hipLaunchKernelGGL(symlr_kernel, g1((long)n * n), dim3(256), 0, st, n, r, U, Q, ldq, M, ldm, beta);
+    WC_LAUNCH_CHECK();
+}
+
+// Phi[p, a + n b] = G[j,a] Q[k,b] + [j != k] G[k,a] Q[j,b], p = (j, k): then
+// (P Phi)[i, a + n b] = (G^T A_i Q)[a, b].
+__global__ void phi_kernel(int n, int r, long N2, const int* __restrict__ pj, const int* __restrict__ pk,
+                           const double* __restrict__ G, double* __restrict__ Phi, long ldphi) {
+    long p = blockIdx.x * 256L + threadIdx.x;
+    int col = blockIdx.y;  // a + n b
+    if (p >= N2) return;
+    int a = col % n, b = col / n;
+    int j = pj[p], k = pk[p];
+    double v = G[j + (long)a * n] * G[k + (long)b * n];
+    if (j != k) v += G[k + (long)a * n] * G[j + (long)b * n];
+    Phi[p + (long)col * ldphi] = v;
+}
+void phi_matrix(hipStream_t st, int n, int r, long N2, const int* pj, const int* pk, const double* G, double* Phi,
+                long ldphi) {
+    hipLaunchKernelGGL(phi_kernel, dim3(cdiv(N2, 256), n * r), dim3(256), 0, st, n, r, N2, pj, pk, G, Phi, ldphi);
+    WC_LAUNCH_CHECK();
+}
+
+// AQ[i, c] (row-major, pitch ldaq) from F = P Phi (column-major m x (n r)):
+// row i of script-A script-Q is script-Q^T svec(A_i) = [svec(F_top); sqrt2 vec(F_bot)].
+__global__ void f_to_aq_kernel(int m, int n, int r, const double* __restrict__ F, long ldf, double* __restrict__ AQ,
+                               long ldaq) {
+    const int nb = r * (r + 1) / 2;
+    const int d = nb + (n - r) * r;
+    long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)m * ldaq) return;
+    int c = static_cast<int>(t % ldaq);
+    int i = static_cast<int>(t / ldaq);
+    double val = 0.0;
+    if (c < nb) {
+        int a, b;
+        svec_pair(c, r, a, b);
+        double fab = F[i + (long)(a + n * b) * ldf], fba = F[i + (long)(b + n * a) * ldf];
+        val = (a == b) ? fab : kSqrt2 * 0.5 * (fab + fba);
+    } else if (c < d) {
+        int s = c - nb;
+        int k = s % (n - r), b = s / (n - r);
+        val = kSqrt2 * F[i + (long)((r + k) + n * b) * ldf];
+    }
+    AQ[(long)i * ldaq + c] = val;
+}
+void f_to_aq(hipStream_t st, int m, int n, int r, const double* F, long ldf, double* AQ, long ldaq) {
+    hipLaunchKernelGGL(f_to_aq_kernel, g1((long)m * ldaq), dim3(256), 0, st, m, n, r, F, ldf, AQ, ldaq);
+    WC_LAUNCH_CHECK();
+}
+
+// Entry-sampling rows of script-A script-Q: G^T A_i Q = (G_j^T Q_k + G_k^T Q_j) / 2.
+__global__ void aq_entry_kernel(int m, int n, int r, const int* __restrict__ jk, const double* __restrict__ G,
+                                double* __restrict__ AQ, long ldaq) {
+    const int nb = r * (r + 1) / 2;
+    const int d = nb + (n - r) * r;
+    long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)m * ldaq) return;
+    int c = static_cast<int>(t % ldaq);
+    int i = static_cast<int>(t / ldaq);
+    int j = jk[2 * i], k = jk[2 * i + 1];
+    double val = 0.0;
+    if (c < nb) {
+        int a, b;
+        svec_pair(c, r, a, b);
+        double f = 0.5 * (G[j + (long)a * n] * G[k + (long)b * n] + G[k + (long)a * n] * G[j + (long)b * n]);
+        val = (a == b) ? f : kSqrt2 * f;
+    } else if (c < d) {
+        int s = c - nb;
+        int kk = s % (n - r), b = s / (n - r);
+        int a = r + kk;
+        val = kSqrt2 * 0.5 * (G[j + (long)a * n] * G[k + (long)b * n] + G[k + (long)a * n] * G[j + (long)b * n]);
+    }
+    AQ[(long)i * ldaq + c] = val;
+}
+void aq_entry(hipStream_t st, int m, int n, int r, const int* jk, const double* G, double* AQ, long ldaq) {
+    hipLaunchKernelGGL(aq_entry_kernel, g1((long)m * ldaq), dim3(256), 0, st, m, n, r, jk, G, AQ, ldaq);
+    WC_LAUNCH_CHECK();
+}
+
+// A[c, c] += t2 * sig[c]
+__global__ void add_diag_vec_kernel(int d, double* A, long lda, const double* sig, double t2) {
+    int c = blockIdx.x * 256 + threadIdx.x;
+    if (c < d) A[c + (long)c * lda] += t2 * sig[c];
+}
+void add_diag_vec(hipStream_t st, int d, double* A, long lda, const double* sig, double t2) {
+    hipLaunchKernelGGL(add_diag_vec_kernel, g1(d), dim3(256), 0, st, d, A, lda, sig, t2);
+    WC_LAUNCH_CHECK();
+}
+
+// v0 = -qc ./ sig  (Corollary pcg starting point)
+__global__ void neg_div_kernel(int d, const double* qc, const double* sig, double* out) {
+    int c = blockIdx.x * 256 + threadIdx.x;
+    if (c < d) out[c] = -qc[c] / sig[c];
+}
+void neg_div(hipStream_t st, int d, const double* qc, const double* sig, double* out) {
+    hipLaunchKernelGGL(neg_div_kernel, g1(d), dim3(256), 0, st, d, qc, sig, out);
+    WC_LAUNCH_CHECK();
+}
+
+// Mehrotra corrector in NT-scaled coordinates:
+// H_ij = [2 (sigma mu - d_i^2) delta_ij - (Pm_ij + Pm_ji)] / (d_i + d_j), Pm = Dx Ds.
+__global__ void corrector_h_kernel(int n, const double* __restrict__ Pm, const double* __restrict__ dv, double smu,
+                                   double* __restrict__ H) {
+    long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)n * n) return;
+    int i = static_cast<int>(t % n), j = static_cast<int>(t / n);
+    double v = -(Pm[i + (long)j * n] + Pm[j + (long)i * n]);
+    if (i == j) v += 2.0 * (smu - dv[i] * dv[i]);
+    H[i + (long)j * n] = v / (dv[i] + dv[j]);
+}
+void corrector_h(hipStream_t st, int n, const double* Pm, const double* dv, double smu, double* H) {
+    hipLaunchKernelGGL(corrector_h_kernel, g1((long)n * n), dim3(256), 0, st, n, Pm, dv, smu, H);
+    WC_LAUNCH_CHECK();
+}
+
+// out = h - a + t2 * sig .* zv  (bottom block of the preconditioner residual)
+__global__ void rho_bottom_kernel(int d, const double* __restrict__ h, const double* __restrict__ a,
+                                  const double* __restrict__ sig, double t2, const double* __restrict__ zv,
+                                  double* __restrict__ out) {
+    int c = blockIdx.x * 256 + threadIdx.x;
+    if (c < d) out[c] = h[c] - a[c] + t2 * sig[c] * zv[c];
+}
+void rho_bottom(hipStream_t st, int d, const double* h, const double* a, const double* sig, double t2,
+                const double* zv, double* out) {
+    hipLaunchKernelGGL(rho_bottom_kernel, g1(d), dim3(256), 0, st, d, h, a, sig, t2, zv, out);
+    WC_LAUNCH_CHECK();
+}
+
+// ---- PCG scalars (device-resident) ------------------------------------------
+// sc[0] = <r,z>, sc[1] = <p,Kp>, sc[2] = alpha, sc[3] = beta, sc[4] = ||r_u||^2, sc[5] = <r,z>_new
+__global__ void pcg_alpha_kernel(double* sc) { sc[2] = sc[0] / sc[1]; }
+__global__ void pcg_beta_kernel(double* sc) {
+    sc[3] = sc[5] / sc[0];
+    sc[0] = sc[5];
+}
+// x += alpha p; r_u -= alpha (Kp)_u; r_v = 0.  The bottom block of the residual
+// is identically zero in exact arithmetic (Proposition indefpcg / Section 6);
+// keeping it at zero stops its rounding noise from entering <r, z>.
+__global__ void pcg_xr_kernel(long N, long m, double* __restrict__ x, double* __restrict__ r,
+                              const double* __restrict__ p, const double* __restrict__ Kp,
+                              const double* __restrict__ sc) {
+    long i = blockIdx.x * 256L + threadIdx.x;
+    if (i >= N) return;
+    double a = sc[2];
+    x[i] += a * p[i];
+    r[i] = (i < m) ? r[i] - a * Kp[i] : 0.0;
+}
+__global__ void pcg_p_kernel(long N, double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ sc) {
+    long i = blockIdx.x * 256L + threadIdx.x;
+    if (i >= N) return;
+    p[i] = z[i] + sc[3] * p[i];
+}
+void pcg_alpha(hipStream_t st, double* sc) {
+    hipLaunchKernelGGL(pcg_alpha_kernel, dim3(1), dim3(1), 0, st, sc);
+    WC_LAUNCH_CHECK();
+}
+void pcg_beta(hipStream_t st, double* sc) {
+    hipLaunchKernelGGL(pcg_beta_kernel, dim3(1), dim3(1), 0, st, sc);
+    WC_LAUNCH_CHECK();
+}
+void pcg_xr(hipStream_t st, long N, long m, double* x, double* r, const double* p, const double* Kp,
+            const double* sc) {
+    hipLaunchKernelGGL(pcg_xr_kernel, g1(N), dim3(256), 0, st, N, m, x, r, p, Kp, sc);
+    WC_LAUNCH_CHECK();
+}
+void pcg_p(hipStream_t st, long N, double* p, const double* z, const double* sc) {
+    hipLaunchKernelGGL(pcg_p_kernel, g1(N), dim3(256), 0, st, N, p, z, sc);
+    WC_LAUNCH_CHECK();
+}
+
+}  // namespace wc

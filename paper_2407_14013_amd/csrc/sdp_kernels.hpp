@@ -1,0 +1,40 @@
+// Launchers of the SDP-specific kernels (sdp_kernels.hip).
+#pragma once
+
+#include "common.hpp"
+
+namespace wc {
+
+void tri_tables(hipStream_t st, int n, int* pj, int* pk);
+void pack_dense_rows(hipStream_t st, int n, int m, long N2, long ldp, const double* A, const int* pj, const int* pk,
+                     double* P);
+void packed_row_norm2(hipStream_t st, int m, long N2, long ldp, const double* P, const int* pj, const int* pk,
+                      double* out);
+void pack_weighted(hipStream_t st, int n, long N2, long ldp, const double* M, long ldm, const int* pj, const int* pk,
+                   double* mw);
+void unpack_sym(hipStream_t st, long N2, const double* yp, const int* pj, const int* pk, double* Y, long ldy);
+void entry_gather(hipStream_t st, int m, const int* jk, const double* M, long ldm, double* out, double alpha,
+                  double beta);
+void entry_scatter(hipStream_t st, int m, const int* jk, const double* u, double* Y, long ldy);
+void sigma_diag(hipStream_t st, int n, int r, const double* lam, double tau, double* sig);
+void e_eigenvalues(hipStream_t st, int n, int r, const double* lam, double tau, double* e);
+void v_to_h(hipStream_t st, int n, int r, const double* v, double* Hm);
+void f_to_v(hipStream_t st, int n, int r, const double* F, long ldf, const double* vin, const double* sig, double t2,
+            double* out);
+void symlr(hipStream_t st, int n, int r, const double* U, const double* Q, long ldq, double* M, long ldm, double beta);
+void phi_matrix(hipStream_t st, int n, int r, long N2, const int* pj, const int* pk, const double* G, double* Phi,
+                long ldphi);
+void f_to_aq(hipStream_t st, int m, int n, int r, const double* F, long ldf, double* AQ, long ldaq);
+void aq_entry(hipStream_t st, int m, int n, int r, const int* jk, const double* G, double* AQ, long ldaq);
+void add_diag_vec(hipStream_t st, int d, double* A, long lda, const double* sig, double t2);
+void neg_div(hipStream_t st, int d, const double* qc, const double* sig, double* out);
+void corrector_h(hipStream_t st, int n, const double* Pm, const double* dv, double smu, double* H);
+void rho_bottom(hipStream_t st, int d, const double* h, const double* a, const double* sig, double t2,
+                const double* zv, double* out);
+void pcg_alpha(hipStream_t st, double* sc);
+void pcg_beta(hipStream_t st, double* sc);
+void pcg_xr(hipStream_t st, long N, long m, double* x, double* r, const double* p, const double* Kp,
+            const double* sc);
+void pcg_p(hipStream_t st, long N, double* p, const double* z, const double* sc);
+
+}  // namespace wc

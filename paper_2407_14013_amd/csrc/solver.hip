@@ -1,0 +1,721 @@
+// Host-side driver: problem setup, the Nesterov-Todd scaling and its
+// low-rank plus well-conditioned split (Section 3), the augmented operator
+// and its indefinite preconditioner (Sections 5 and 6), indefinite PCG
+// (Corollary pcg) with recovery (eq. recover), and the interior-point step.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <limits>
+
+#include "sdp_kernels.hpp"
+#include "solver.hpp"
+
+sdp_ctx::~sdp_ctx() {
+    if (pin) (void)hipHostFree(pin);
+    for (auto& p : prof)
+        for (auto e : p.ev) (void)hipEventDestroy(e);
+}
+
+namespace wc {
+
+static long dim_d(int n, int r) { return (long)n * r - (long)r * (r - 1) / 2; }
+
+static void fetch(sdp_ctx* c, const double* dev, int count) {
+    WC_HIP(hipMemcpyAsync(c->pin, dev, sizeof(double) * count, hipMemcpyDeviceToHost, c->st));
+    WC_HIP(hipStreamSynchronize(c->st));
+}
+
+// ---- profiling ---------------------------------------------------------------------
+void prof_begin(sdp_ctx* c, int k, hipEvent_t* e0) {
+    *e0 = nullptr;
+    if (!(c->prof_mask & (1 << k))) return;
+    WC_HIP(hipEventCreate(e0));
+    WC_HIP(hipEventRecord(*e0, c->st));
+}
+void prof_end(sdp_ctx* c, int k, hipEvent_t e0, double bytes) {
+    if (e0 == nullptr) return;
+    hipEvent_t e1;
+    WC_HIP(hipEventCreate(&e1));
+    WC_HIP(hipEventRecord(e1, c->st));
+    c->prof[k].ev.push_back(e0);
+    c->prof[k].ev.push_back(e1);
+    c->prof[k].launches += 1;
+    c->prof[k].bytes += bytes;
+}
+void prof_collect(sdp_ctx* c) {
+    WC_HIP(hipStreamSynchronize(c->st));
+    for (auto& p : c->prof) {
+        for (size_t i = 0; i + 1 < p.ev.size(); i += 2) {
+            float ms = 0.f;
+            WC_HIP(hipEventElapsedTime(&ms, p.ev[i], p.ev[i + 1]));
+            p.ms += ms;
+        }
+        for (auto e : p.ev) (void)hipEventDestroy(e);
+        p.ev.clear();
+    }
+}
+
+// ---- constraint operator (Introduction, eq. sdp-pd) ------------------------------------
+// out = alpha A(M) + beta out
+static void a_apply(sdp_ctx* c, const double* M, double* out, double alpha, double beta) {
+    if (c->kind == SDP_A_DENSE) {
+        pack_weighted(c->st, c->n, c->N2, c->ldP, M, c->n, c->pj, c->pk, c->mw);
+        hipEvent_t e;
+        prof_begin(c, SDP_K_A_APPLY, &e);
+        gemv_rows(c->st, c->m, static_cast<int>(c->N2), c->P, c->ldP, c->mw, out, alpha, beta);
+        prof_end(c, SDP_K_A_APPLY, e, 8.0 * c->m * c->N2 + 8.0 * c->N2 + 8.0 * c->m);
+    } else {
+        entry_gather(c->st, c->m, c->jk, M, c->n, out, alpha, beta);
+    }
+}
+
+// Y = A^T(u), full symmetric n x n
+static void at_apply(sdp_ctx* c, const double* u, double* Y) {
+    if (c->kind == SDP_A_DENSE) {
+        hipEvent_t e;
+        prof_begin(c, SDP_K_AT_APPLY, &e);
+        gemv_cols(c->st, c->m, static_cast<int>(c->N2), c->P, c->ldP, u, c->yp, 1.0, 0.0, c->gpart);
+        prof_end(c, SDP_K_AT_APPLY, e, 8.0 * c->m * c->N2 + 8.0 * c->N2 + 8.0 * c->m);
+        unpack_sym(c->st, c->N2, c->yp, c->pj, c->pk, Y, c->n);
+    } else {
+        fill(c->st, (long)c->n * c->n, Y, 0.0);
+        entry_scatter(c->st, c->m, c->jk, u, Y, c->n);
+    }
+}
+
+static void gemm(sdp_ctx* c, bool ta, bool tb, int m, int n, int k, double alpha, const double* A, long lda,
+                 const double* B, long ldb, double beta, double* C, long ldc) {
+    hipEvent_t e;
+    prof_begin(c, SDP_K_GEMM, &e);
+    dgemm(c->st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+    prof_end(c, SDP_K_GEMM, e, 8.0 * ((double)m * k + (double)k * n + 2.0 * (double)m * n));
+}
+
+// ---- setup ---------------------------------------------------------------------------------
+static void alloc_work(sdp_ctx* c) {
+    const int n = c->n, m = c->m;
+    const long nn = (long)n * n;
+    const long dmax = dim_d(n, c->rmax);
+    c->dmaxp = round_up(dmax + 1, 32);
+    const long Nmax = m + c->dmaxp + 32;
+    for (auto* b : {&c->L, &c->Rs, &c->Linv, &c->Rinv, &c->Mt, &c->Vs, &c->G, &c->Ginv, &c->Gt, &c->Gw, &c->E, &c->Y,
+                    &c->T1, &c->T2, &c->Mm, &c->dXa, &c->dSa, &c->dX, &c->dS, &c->Ct, &c->Rd, &c->Hc, &c->Dx, &c->Ds})
+        b->alloc(nn);
+    c->dnt.alloc(n);
+    c->lam.alloc(2 * (size_t)n);
+    c->evE.alloc(n);
+    c->sig.alloc(c->dmaxp);
+    c->Hm.alloc((long)n * c->rmax);
+    c->U.alloc((long)n * c->rmax);
+    c->YQ.alloc((long)n * c->rmax);
+    c->F.alloc((long)n * c->rmax);
+    c->AQ.alloc((long)m * c->dmaxp);
+    c->Cm.alloc(c->dmaxp * c->dmaxp);
+    c->Cinv.alloc(c->dmaxp * c->dmaxp);
+    c->Zw.alloc(c->dmaxp * c->dmaxp);
+    c->tm.alloc(m + 32);
+    c->td.alloc(c->dmaxp);
+    c->td2.alloc(c->dmaxp);
+    c->td3.alloc(c->dmaxp);
+    c->rho.alloc(m + c->dmaxp + 32);
+    c->dz.alloc(m + 32);
+    if (c->kind == SDP_A_DENSE) {
+        c->mw.alloc(c->ldP);
+        c->yp.alloc(c->ldP);
+        long N2p = round_up(c->N2, 32);
+        c->Phi.alloc(N2p * (long)n * c->rmax);
+        c->Fq.alloc((long)m * n * c->rmax);
+    }
+    long gp = (long)gemv_cols_parts(m) * std::max<long>(round_up(c->N2, 2), c->dmaxp);
+    c->gpart.alloc(gp);
+    c->part.alloc(1024);
+    for (auto* b : {&c->vx, &c->vr, &c->vz, &c->vp, &c->vKp, &c->vg, &c->vtmp}) {
+        b->alloc(Nmax);
+        fill(c->st, Nmax, b->get(), 0.0);
+    }
+    fill(c->st, c->dmaxp, c->td, 0.0);
+    fill(c->st, c->dmaxp, c->td2, 0.0);
+    fill(c->st, c->dmaxp, c->td3, 0.0);
+    c->dya.alloc(m + 32);
+    c->dy.alloc(m + 32);
+    c->rp.alloc(m + 32);
+    c->sc.alloc(64);
+    fill(c->st, 64, c->sc, 0.0);
+    c->info.alloc(4);
+    WC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->pin), 64 * sizeof(double), hipHostMallocDefault));
+}
+
+static void validate_host(const sdp_problem* p) {
+    const int n = p->n, m = p->m;
+    const long nn = (long)n * n;
+    auto finite = [](double v) { return std::isfinite(v); };
+    double cn = 0;
+    for (long t = 0; t < nn; ++t) {
+        require(finite(p->C[t]), "C has a non-finite entry");
+        cn += p->C[t] * p->C[t];
+    }
+    cn = std::sqrt(cn);
+    for (int j = 0; j < n; ++j)
+        for (int i = j + 1; i < n; ++i)
+            require(std::fabs(p->C[i + (long)j * n] - p->C[j + (long)i * n]) <= 1e-12 * std::max(cn, 1e-300),
+                    "C is not symmetric");
+    for (int i = 0; i < m; ++i) require(finite(p->b[i]), "b has a non-finite entry");
+    if (p->a_kind == SDP_A_DENSE) {
+        for (int i = 0; i < m; ++i) {
+            const double* Ai = p->A + (long)i * nn;
+            double an = 0;
+            for (long t = 0; t < nn; ++t) {
+                require(finite(Ai[t]), "A_" + std::to_string(i) + " has a non-finite entry");
+                an += Ai[t] * Ai[t];
+            }
+            an = std::sqrt(an);
+            for (int j = 0; j < n; ++j)
+                for (int k = j + 1; k < n; ++k)
+                    require(std::fabs(Ai[k + (long)j * n] - Ai[j + (long)k * n]) <= 1e-12 * std::max(an, 1e-300),
+                            "A_" + std::to_string(i) + " is not symmetric");
+        }
+    } else {
+        std::vector<long> keys(m);
+        for (int i = 0; i < m; ++i) {
+            int j = p->jk[2 * i], k = p->jk[2 * i + 1];
+            require(j >= 0 && k < n && j <= k, "entry pair " + std::to_string(i) + " must satisfy 0 <= j <= k < n");
+            keys[i] = (long)j * n + k;
+        }
+        std::sort(keys.begin(), keys.end());
+        for (int i = 1; i < m; ++i) require(keys[i] != keys[i - 1], "entry pairs must be distinct");
+    }
+}
+
+void setup(sdp_ctx* c, const sdp_problem* p, const sdp_options* o, hipStream_t st) {
+    require(p != nullptr, "problem is NULL");
+    require(p->n >= 2, "n must be at least 2");
+    require(p->m >= 1, "m must be at least 1");
+    require(p->a_kind == SDP_A_DENSE || p->a_kind == SDP_A_ENTRY, "unknown a_kind");
+    require(p->b && p->C, "b and C are required");
+    require(p->a_kind == SDP_A_DENSE ? p->A != nullptr : p->jk != nullptr, "constraint data is NULL");
+    const int n = p->n, m = p->m;
+    const long N2 = (long)n * (n + 1) / 2;
+    require(m <= N2, "m exceeds n(n+1)/2: the constraints cannot be linearly independent");
+    c->st = st;
+    c->n = n;
+    c->m = m;
+    c->kind = p->a_kind;
+    if (o) c->opt = *o;
+    else sdp_default_options(&c->opt);
+    c->rmax = std::max(1, std::min(c->opt.rank_max, n - 1));
+    if (c->opt.rank_fixed > 0) c->rmax = std::max(c->rmax, std::min(c->opt.rank_fixed, n - 1));
+    if (!p->on_device) validate_host(p);
+
+    c->N2 = N2;
+    c->ldP = round_up(N2, 32);
+    c->pj.alloc(N2);
+    c->pk.alloc(N2);
+    tri_tables(st, n, c->pj, c->pk);
+    const long nn = (long)n * n;
+    c->b.alloc(m + 32);
+    c->C.alloc(nn);
+    const hipMemcpyKind kind = p->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    WC_HIP(hipMemcpyAsync(c->b.get(), p->b, sizeof(double) * m, kind, st));
+    WC_HIP(hipMemcpyAsync(c->C.get(), p->C, sizeof(double) * nn, kind, st));
+    symmetrize(st, n, c->C, n);
+
+    std::vector<double> norms2(m);
+    if (c->kind == SDP_A_DENSE) {
+        c->P.alloc((long)m * c->ldP);
+        // stage the m x n^2 rows in blocks so the temporary stays bounded
+        const long rows_per = std::max<long>(1, std::min<long>(m, (256L << 20) / (8 * nn)));
+        DevBuf<double> stage;
+        if (!p->on_device) stage.alloc(rows_per * nn);
+        for (long i0 = 0; i0 < m; i0 += rows_per) {
+            long cnt = std::min<long>(rows_per, m - i0);
+            const double* src = p->A + i0 * nn;
+            if (!p->on_device) {
+                WC_HIP(hipMemcpyAsync(stage.get(), src, sizeof(double) * cnt * nn, hipMemcpyHostToDevice, st));
+                src = stage.get();
+            }
+            pack_dense_rows(st, n, static_cast<int>(cnt), N2, c->ldP, src, c->pj, c->pk, c->P + i0 * c->ldP);
+            if (!p->on_device) WC_HIP(hipStreamSynchronize(st));
+        }
+        DevBuf<double> nrm(m);
+        packed_row_norm2(st, m, N2, c->ldP, c->P, c->pj, c->pk, nrm);
+        WC_HIP(hipMemcpyAsync(norms2.data(), nrm.get(), sizeof(double) * m, hipMemcpyDeviceToHost, st));
+        WC_HIP(hipStreamSynchronize(st));
+    } else {
+        c->jk.alloc(2L * m);
+        WC_HIP(hipMemcpyAsync(c->jk.get(), p->jk, sizeof(int) * 2 * m, kind, st));
+        std::vector<int> hjk(2L * m);
+        WC_HIP(hipMemcpyAsync(hjk.data(), c->jk.get(), sizeof(int) * 2 * m, hipMemcpyDeviceToHost, st));
+        WC_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < m; ++i) {
+            require(hjk[2 * i] >= 0 && hjk[2 * i + 1] < n && hjk[2 * i] <= hjk[2 * i + 1], "bad entry pair");
+            norms2[i] = (hjk[2 * i] == hjk[2 * i + 1]) ? 1.0 : 0.5;
+        }
+    }
+    std::vector<double> hb(m), hC(nn);
+    WC_HIP(hipMemcpyAsync(hb.data(), c->b.get(), sizeof(double) * m, hipMemcpyDeviceToHost, st));
+    WC_HIP(hipMemcpyAsync(hC.data(), c->C.get(), sizeof(double) * nn, hipMemcpyDeviceToHost, st));
+    WC_HIP(hipStreamSynchronize(st));
+    double bn = 0, cn = 0, amax = 0, ratio = 0, a2 = 0;
+    for (int i = 0; i < m; ++i) {
+        bn += hb[i] * hb[i];
+        double an = std::sqrt(norms2[i]);
+        amax = std::max(amax, an);
+        a2 += norms2[i];
+        ratio = std::max(ratio, (1.0 + std::fabs(hb[i])) / (1.0 + an));
+    }
+    for (long t = 0; t < nn; ++t) cn += hC[t] * hC[t];
+    c->bnorm = std::sqrt(bn);
+    c->Cnorm = std::sqrt(cn);
+    c->mean_a2 = a2 / m;
+    // starting magnitudes X0 = xi I, S0 = eta I (SDPT3-style)
+    c->xi = std::max({10.0, std::sqrt((double)n), n * ratio});
+    c->eta = std::max({10.0, std::sqrt((double)n), 1.0 + std::max(amax, c->Cnorm)});
+
+    c->X.alloc(nn);
+    c->S.alloc(nn);
+    c->y.alloc(m + 32);
+    set_identity(st, n, c->X, n, c->xi);
+    set_identity(st, n, c->S, n, c->eta);
+    fill(st, m + 32, c->y, 0.0);
+    alloc_work(c);
+    WC_HIP(hipStreamSynchronize(st));
+}
+
+// ---- scaling point (Introduction eq. newt; Section 3 eq. EQSigdef; Section 6) ----------
+static int rank_rule(const std::vector<double>& lam, int rhat) {
+    int best = 1;
+    double bv = -1.0;
+    for (int i = 1; i <= rhat; ++i) {
+        double v = lam[i - 1] / lam[i];
+        if (v > bv) {
+            bv = v;
+            best = i;
+        }
+    }
+    return best;
+}
+
+void ensure_scaling(sdp_ctx* c) {
+    if (c->scaling_valid) return;
+    const int n = c->n, m = c->m;
+    const long nn = (long)n * n;
+    hipStream_t st = c->st;
+    // Cholesky factors X = L L^T, S = Rs Rs^T
+    copy(st, nn, c->X, c->L);
+    potrf(st, n, c->L, n, c->info.get());
+    copy(st, nn, c->S, c->Rs);
+    potrf(st, n, c->Rs, n, c->info.get() + 1);
+    int hinfo[2] = {0, 0};
+    WC_HIP(hipMemcpyAsync(hinfo, c->info.get(), 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    WC_HIP(hipStreamSynchronize(st));
+    if (hinfo[0]) throw Error(kENumeric, "X is not positive definite (pivot " + std::to_string(hinfo[0]) + ")");
+    if (hinfo[1]) throw Error(kENumeric, "S is not positive definite (pivot " + std::to_string(hinfo[1]) + ")");
+    trtri(st, n, c->L, n, c->Linv, n, c->T1);
+    trtri(st, n, c->Rs, n, c->Rinv, n, c->T1);
+    // NT factor: Rs^T L = U D V^T, G = L V D^{-1/2}, G^{-1} = D^{1/2} V^T L^{-1}
+    gemm(c, true, false, n, n, n, 1.0, c->Rs, n, c->L, n, 0.0, c->Mt, n);
+    int sw = jacobi_svd(st, n, c->Mt, n, c->Vs, n, c->dnt, 0.0, 60, c->jw, false);
+    if (sw < 0) throw Error(kENumeric, "Jacobi SVD of the NT factor did not converge");
+    gemm(c, false, false, n, n, n, 1.0, c->L, n, c->Vs, n, 0.0, c->T1, n);
+    scale_cols(st, n, n, c->T1, n, c->dnt, -0.5, c->G, n);
+    gemm(c, true, false, n, n, n, 1.0, c->Vs, n, c->Linv, n, 0.0, c->T1, n);
+    scale_rows(st, n, n, c->T1, n, c->dnt, 0.5, c->Ginv, n);
+    // eigen-decomposition of W = G G^T: one-sided Jacobi on G^T
+    transpose(st, n, n, c->G, n, c->Gt, n);
+    sw = jacobi_svd(st, n, c->Gt, n, c->Gw, n, c->lam, 0.0, 60, c->jw, false);
+    if (sw < 0) throw Error(kENumeric, "Jacobi eigen-decomposition of W did not converge");
+    c->lam_h.resize(n);
+    WC_HIP(hipMemcpyAsync(c->lam_h.data(), c->lam.get(), sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    WC_HIP(hipStreamSynchronize(st));
+    for (auto& v : c->lam_h) v = v * v;
+    WC_HIP(hipMemcpyAsync(c->lam.get(), c->lam_h.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    // rank rule and threshold (eq. EQSigdef, Experiments section)
+    int r = c->opt.rank_fixed > 0 ? std::min(c->opt.rank_fixed, n - 1) : rank_rule(c->lam_h, c->rmax);
+    c->r = r;
+    c->tau = 0.5 * c->lam_h[r];
+    c->d = static_cast<int>(dim_d(n, r));
+    std::vector<double> ev(n);
+    for (int k = 0; k < n; ++k) ev[k] = (k < r) ? 1.0 : c->lam_h[k] / c->tau;
+    std::sort(ev.begin(), ev.end());
+    double med = (n & 1) ? ev[n / 2] : 0.5 * (ev[n / 2 - 1] + ev[n / 2]);
+    c->beta = c->opt.beta > 0 ? c->opt.beta : med * med * c->mean_a2;
+    // E = G_w diag(e) G_w^T and Sigma
+    e_eigenvalues(st, n, r, c->lam, c->tau, c->evE);
+    scale_cols(st, n, n, c->Gw, n, c->evE, 1.0, c->T1, n);
+    gemm(c, false, true, n, n, n, 1.0, c->T1, n, c->Gw, n, 0.0, c->E, n);
+    symmetrize(st, n, c->E, n);
+    sigma_diag(st, n, r, c->lam, c->tau, c->sig);
+    // script-A script-Q, row i = script-Q^T svec(A_i)
+    const int d = c->d;
+    if (c->kind == SDP_A_DENSE) {
+        const long N2p = round_up(c->N2, 32);
+        phi_matrix(st, n, r, c->N2, c->pj, c->pk, c->Gw, c->Phi, N2p);
+        gemm(c, true, false, m, n * r, static_cast<int>(c->N2), 1.0, c->P, c->ldP, c->Phi, N2p, 0.0, c->Fq, m);
+        f_to_aq(st, m, n, r, c->Fq, m, c->AQ, c->dmaxp);
+    } else {
+        aq_entry(st, m, n, r, c->jk, c->Gw, c->AQ, c->dmaxp);
+    }
+    // Schur complement of the preconditioner: C = tau^2 Sigma + (AQ)^T (AQ) / beta, then C^{-1}
+    gemm(c, false, true, d, d, m, 1.0 / c->beta, c->AQ, c->dmaxp, c->AQ, c->dmaxp, 0.0, c->Cm, c->dmaxp);
+    add_diag_vec(st, d, c->Cm, c->dmaxp, c->sig, c->tau * c->tau);
+    potrf(st, d, c->Cm, c->dmaxp, c->info.get());
+    WC_HIP(hipMemcpyAsync(hinfo, c->info.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+    WC_HIP(hipStreamSynchronize(st));
+    if (hinfo[0]) throw Error(kENumeric, "the preconditioner's Schur complement is not positive definite");
+    // Z = L_C^{-1} (kept in Cm's buffer after inversion via Cinv as staging)
+    trtri(st, d, c->Cm, c->dmaxp, c->Cinv, c->dmaxp, c->Zw);
+    fill(st, c->dmaxp * c->dmaxp, c->Cm, 0.0);
+    gemm(c, true, false, d, d, d, 1.0, c->Cinv, c->dmaxp, c->Cinv, c->dmaxp, 0.0, c->Cm, c->dmaxp);
+    std::swap(c->Cm, c->Cinv);
+    c->scaling_valid = true;
+}
+
+// ---- augmented operator (eq. augsys via the Section 5 products) --------------------------
+void newton_apply(sdp_ctx* c, const double* in, double* out) {
+    ensure_scaling(c);
+    const int n = c->n, m = c->m, r = c->r;
+    hipStream_t st = c->st;
+    hipEvent_t e;
+    prof_begin(c, SDP_K_NEWTON, &e);
+    const double* u = in;
+    const double* v = in + m;
+    // Y = A^T(u)
+    at_apply(c, u, c->Y);
+    // U = [Q Qp][B; sqrt2 N];  Mm = sym(U Q^T) + E Y E
+    v_to_h(st, n, r, v, c->Hm);
+    gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
+    symlr(st, n, r, c->U, c->Gw, n, c->Mm, n, 0.0);
+    gemm(c, false, false, n, n, n, 1.0, c->Y, n, c->E, n, 0.0, c->T1, n);
+    gemm(c, false, false, n, n, n, 1.0, c->E, n, c->T1, n, 1.0, c->Mm, n);
+    // top = A(Mm)
+    a_apply(c, c->Mm, out, 1.0, 0.0);
+    // bottom = Q^T svec(Y) - tau^2 Sigma v, with Q^T svec(Y) read from F = G_w^T Y Q
+    gemm(c, false, false, n, r, n, 1.0, c->Y, n, c->Gw, n, 0.0, c->YQ, n);
+    gemm(c, true, false, n, r, n, 1.0, c->Gw, n, c->YQ, n, 0.0, c->F, n);
+    f_to_v(st, n, r, c->F, n, v, c->sig, c->tau * c->tau, out + m);
+    prof_end(c, SDP_K_NEWTON, e, 0.0);
+    c->matvecs += 1;
+}
+
+// Block elimination with P = [beta I, AQ; AQ^T, -tau^2 Sigma] (Section 6, with
+// beta^{-1} in both outer factors): zv = -C^{-1}(h - AQ^T f / beta) into the
+// aligned buffer zv, z1 = (f - AQ zv) / beta, and tm = AQ zv is left behind.
+// gemv_rows reads its vector in 16-byte pairs, so zv must be an aligned,
+// zero-padded buffer (z + m is not 16-byte aligned for odd m).
+static void precond_block(sdp_ctx* c, const double* f, const double* h, double* z1, double* zv) {
+    const int m = c->m, d = c->d;
+    hipStream_t st = c->st;
+    const double ib = 1.0 / c->beta;
+    gemv_cols(st, m, d, c->AQ, c->dmaxp, f, c->td, -ib, 0.0, c->gpart);   // td = -AQ^T f / beta
+    axpby(st, d, 1.0, h, 1.0, c->td);                                    // td += h
+    gemv_rows(st, d, d, c->Cinv, c->dmaxp, c->td, zv, -1.0, 0.0);        // zv = -C^{-1} td
+    gemv_rows(st, m, d, c->AQ, c->dmaxp, zv, c->tm, 1.0, 0.0);           // tm = AQ zv
+    axpbypcz(st, m, ib, f, -ib, c->tm, 0.0, z1);                          // z1 = (f - tm) / beta
+}
+
+// z = P^{-1} rv: block elimination followed by one step of iterative
+// refinement, z += P^{-1}(rv - P z).  As tau^2 Sigma -> 0 the elimination
+// computes the small z1 from the difference of two nearly equal vectors, and
+// the rounding error in its range(AQ) component breaks the identity
+// AQ^T z1 - tau^2 Sigma zv = h that keeps the bottom residual of indefinite
+// PCG at zero (Section 6); one refinement step restores it to O(eps^2).
+static void precond_apply(sdp_ctx* c, const double* rv, double* z) {
+    const int m = c->m, d = c->d;
+    hipStream_t st = c->st;
+    const double* f = rv;
+    const double* h = rv + m;
+    double* z1 = z;
+    precond_block(c, f, h, z1, c->td2);
+    // rho = rv - P z:  rho_u = f - tm - beta z1,  rho_v = h - AQ^T z1 + tau^2 Sigma zv
+    axpbypcz(st, m, 1.0, f, -1.0, c->tm, 0.0, c->rho);
+    axpby(st, m, -c->beta, z1, 1.0, c->rho);
+    gemv_cols(st, m, d, c->AQ, c->dmaxp, z1, c->td3, 1.0, 0.0, c->gpart);     // td3 = AQ^T z1
+    rho_bottom(st, d, h, c->td3, c->sig, c->tau * c->tau, c->td2, c->rho + m);
+    precond_block(c, c->rho, c->rho + m, c->dz, c->td3);
+    axpby(st, m, 1.0, c->dz, 1.0, z1);
+    axpbypcz(st, d, 1.0, c->td2, 1.0, c->td3, 0.0, z + m);
+}
+
+// [u; v] -> (dX, dy) by eq. recover: dy = u / tau^2, dX = E (A^T u - tau^2 C~) E + Q v.
+static void recover(sdp_ctx* c, const double* x, const double* Ct, double* dX, double* dy) {
+    const int n = c->n, m = c->m, r = c->r;
+    const long nn = (long)n * n;
+    hipStream_t st = c->st;
+    const double t2 = c->tau * c->tau;
+    axpby(st, m, 1.0 / t2, x, 0.0, dy);
+    at_apply(c, x, c->Y);
+    axpby(st, nn, -t2, Ct, 1.0, c->Y);
+    gemm(c, false, false, n, n, n, 1.0, c->Y, n, c->E, n, 0.0, c->T1, n);
+    v_to_h(st, n, r, x + m, c->Hm);
+    gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
+    symlr(st, n, r, c->U, c->Gw, n, dX, n, 0.0);
+    gemm(c, false, false, n, n, n, 1.0, c->E, n, c->T1, n, 1.0, dX, n);
+    symmetrize(st, n, dX, n);
+}
+
+// Indefinite PCG on eq. augsys (Corollary pcg) started at [0; -Sigma^{-1} Q^T c].
+int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, double* dy, sdp_inner_stats* stats) {
+    ensure_scaling(c);
+    const int n = c->n, m = c->m, r = c->r, d = c->d;
+    const long N = (long)m + d;
+    hipStream_t st = c->st;
+    const double t2 = c->tau * c->tau;
+    double* sc = c->sc;
+    // right-hand side g = [b~ + tau^2 A(E C~ E); tau^2 Q^T c]
+    gemm(c, false, false, n, n, n, 1.0, Ct, n, c->E, n, 0.0, c->T1, n);
+    gemm(c, false, false, n, n, n, 1.0, c->E, n, c->T1, n, 0.0, c->Mm, n);
+    a_apply(c, c->Mm, c->vg, t2, 0.0);
+    axpby(st, m, 1.0, bt, 1.0, c->vg);
+    gemm(c, false, false, n, r, n, 1.0, Ct, n, c->Gw, n, 0.0, c->YQ, n);
+    gemm(c, true, false, n, r, n, 1.0, c->Gw, n, c->YQ, n, 0.0, c->F, n);
+    f_to_v(st, n, r, c->F, n, nullptr, c->sig, 0.0, c->vtmp);              // vtmp = Q^T c
+    axpby(st, d, t2, c->vtmp, 0.0, c->vg + m);
+    fill(st, m, c->vx, 0.0);
+    neg_div(st, d, c->vtmp, c->sig, c->vx + m);
+    // r = g - K x, z = P^{-1} r, p = z
+    newton_apply(c, c->vx, c->vKp);
+    axpbypcz(st, N, 1.0, c->vg, -1.0, c->vKp, 0.0, c->vr);
+    fill(st, d, c->vr + m, 0.0);  // the bottom residual is zero at this start (Corollary pcg)
+    precond_apply(c, c->vr, c->vz);
+    copy(st, N, c->vz, c->vp);
+    dot(st, N, c->vr, c->vz, sc + 0, c->part);
+    dot(st, m, c->vr, c->vr, sc + 4, c->part);
+    fetch(c, sc + 4, 1);
+    const double ref = std::sqrt(c->pin[0]);
+    double rr = ref;
+    const double tol = c->opt.inner_tol * (ref > 0 ? ref : 1.0);
+    int it = 0;
+    bool conv = false;
+    while (true) {
+        if (!(rr > tol)) {
+            conv = std::isfinite(rr);
+            break;
+        }
+        if (it >= c->opt.inner_maxit) break;
+        newton_apply(c, c->vp, c->vKp);
+        dot(st, N, c->vp, c->vKp, sc + 1, c->part);
+        pcg_alpha(st, sc);
+        pcg_xr(st, N, m, c->vx, c->vr, c->vp, c->vKp, sc);
+        dot(st, m, c->vr, c->vr, sc + 4, c->part);
+        precond_apply(c, c->vr, c->vz);
+        dot(st, N, c->vr, c->vz, sc + 5, c->part);
+        pcg_beta(st, sc);
+        pcg_p(st, N, c->vp, c->vz, sc);
+        ++it;
+        if (c->opt.verbose >= 2) {
+            dot(st, d, c->vr + m, c->vr + m, sc + 6, c->part);
+            fetch(c, sc, 7);
+            fprintf(stderr, "[wcsdp]   pcg %d |r_u| %.3e |r_v| %.3e rz %.3e pKp %.3e alpha %.3e beta %.3e\n", it,
+                    std::sqrt(c->pin[4]), std::sqrt(c->pin[6]), c->pin[0], c->pin[1], c->pin[2], c->pin[3]);
+        }
+        fetch(c, sc + 4, 1);
+        rr = std::sqrt(c->pin[0]);
+    }
+    recover(c, c->vx, Ct, dX, dy);
+    c->pcg_total += it;
+    if (stats) {
+        stats->iterations = it;
+        stats->refinements = 0;
+        stats->converged = conv ? 1 : 0;
+        stats->r = r;
+        stats->tau = c->tau;
+        stats->beta = c->beta;
+        stats->rel_res = ref > 0 ? rr / ref : 0.0;
+    }
+    return conv ? 0 : kENotConv;
+}
+
+// ---- interior-point step --------------------------------------------------------------
+// Largest alpha with L L^T + alpha D PSD, from lambda_min(L^{-1} D L^{-T}).  The
+// shifted matrix T + c I is positive semidefinite, so its singular values from
+// the one-sided Jacobi SVD are its eigenvalues.
+static double max_step(sdp_ctx* c, const double* Linv, const double* D) {
+    const int n = c->n;
+    hipStream_t st = c->st;
+    gemm(c, false, false, n, n, n, 1.0, Linv, n, D, n, 0.0, c->T1, n);
+    gemm(c, false, true, n, n, n, 1.0, c->T1, n, Linv, n, 0.0, c->T2, n);
+    symmetrize(st, n, c->T2, n);
+    frob_norm(st, n, c->T2, n, c->sc + 8, c->part);
+    fetch(c, c->sc + 8, 1);
+    const double fn = c->pin[0];
+    if (!(fn > 0.0)) return std::numeric_limits<double>::infinity();
+    const double shift = 1.01 * fn;
+    add_diag(st, n, c->T2, n, shift);
+    double* sv = c->lam.get() + n;
+    int sw = jacobi_svd(st, n, c->T2, n, nullptr, n, sv, 0.0, 60, c->jw, false);
+    if (sw < 0) throw Error(kENumeric, "Jacobi eigenvalues for the step length did not converge");
+    fetch(c, sv + n - 1, 1);
+    const double lmin = c->pin[0] - shift;
+    return lmin >= 0.0 ? std::numeric_limits<double>::infinity() : -1.0 / lmin;
+}
+
+struct Resid {
+    double mu, pobj, dobj, relgap, pinf, dinf;
+};
+
+static Resid residuals(sdp_ctx* c) {
+    const int n = c->n, m = c->m;
+    const long nn = (long)n * n;
+    hipStream_t st = c->st;
+    a_apply(c, c->X, c->rp, -1.0, 0.0);
+    axpby(st, m, 1.0, c->b, 1.0, c->rp);
+    at_apply(c, c->y, c->Y);
+    axpbypcz(st, nn, 1.0, c->C, -1.0, c->Y, 0.0, c->Rd);
+    axpby(st, nn, -1.0, c->S, 1.0, c->Rd);
+    symmetrize(st, n, c->Rd, n);
+    double* sc = c->sc;
+    dot(st, nn, c->X, c->S, sc + 10, c->part);
+    dot(st, nn, c->C, c->X, sc + 11, c->part);
+    dot(st, m, c->b, c->y, sc + 12, c->part);
+    dot(st, m, c->rp, c->rp, sc + 13, c->part);
+    dot(st, nn, c->Rd, c->Rd, sc + 14, c->part);
+    fetch(c, sc + 10, 5);
+    Resid R;
+    R.mu = c->pin[0] / n;
+    R.pobj = c->pin[1];
+    R.dobj = c->pin[2];
+    R.relgap = std::fabs(R.pobj - R.dobj) / (1.0 + std::fabs(R.pobj) + std::fabs(R.dobj));
+    R.pinf = std::sqrt(c->pin[3]) / (1.0 + c->bnorm);
+    R.dinf = std::sqrt(c->pin[4]) / (1.0 + c->Cnorm);
+    return R;
+}
+
+int ipm_step(sdp_ctx* c, sdp_step_stats* stats) {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    const int n = c->n, m = c->m;
+    const long nn = (long)n * n;
+    hipStream_t st = c->st;
+    sdp_step_stats s{};
+    Resid R = residuals(c);
+    s.mu = R.mu;
+    s.pobj = R.pobj;
+    s.dobj = R.dobj;
+    s.relgap = R.relgap;
+    s.pinf = R.pinf;
+    s.dinf = R.dinf;
+    if (R.relgap <= c->opt.gap_tol && R.pinf <= c->opt.feas_tol && R.dinf <= c->opt.feas_tol) {
+        s.converged = 1;
+        if (stats) *stats = s;
+        return 0;
+    }
+    const auto t1 = clk::now();
+    ensure_scaling(c);
+    WC_HIP(hipStreamSynchronize(st));
+    const auto t2c = clk::now();
+    s.r = c->r;
+    // predictor: b~ = r_p, C~ = R_d + S
+    axpbypcz(st, nn, 1.0, c->Rd, 1.0, c->S, 0.0, c->Ct);
+    sdp_inner_stats is{};
+    int rc = inner_solve(c, c->rp, c->Ct, c->dXa, c->dya, &is);
+    if (rc != 0) throw Error(rc, "predictor inner solve did not converge");
+    s.pcg_pred = is.iterations;
+    at_apply(c, c->dya, c->Y);
+    axpbypcz(st, nn, 1.0, c->Rd, -1.0, c->Y, 0.0, c->dSa);
+    double ap = std::min(1.0, max_step(c, c->Linv, c->dXa));
+    double ad = std::min(1.0, max_step(c, c->Rinv, c->dSa));
+    double* sc = c->sc;
+    dot(st, nn, c->X, c->dSa, sc + 16, c->part);
+    dot(st, nn, c->dXa, c->S, sc + 17, c->part);
+    dot(st, nn, c->dXa, c->dSa, sc + 18, c->part);
+    fetch(c, sc + 16, 3);
+    const double mu_aff = (R.mu * n + ad * c->pin[0] + ap * c->pin[1] + ap * ad * c->pin[2]) / n;
+    double sig = std::min(1.0, std::max(0.0, mu_aff / R.mu));
+    sig = sig * sig * sig;
+    s.sigma = sig;
+    // corrector: H from Dx = G^{-1} dXa G^{-T}, Ds = G^T dSa G; C~ = R_d - G^{-T} H G^{-1}
+    gemm(c, false, false, n, n, n, 1.0, c->Ginv, n, c->dXa, n, 0.0, c->T1, n);
+    gemm(c, false, true, n, n, n, 1.0, c->T1, n, c->Ginv, n, 0.0, c->Dx, n);
+    gemm(c, true, false, n, n, n, 1.0, c->G, n, c->dSa, n, 0.0, c->T1, n);
+    gemm(c, false, false, n, n, n, 1.0, c->T1, n, c->G, n, 0.0, c->Ds, n);
+    gemm(c, false, false, n, n, n, 1.0, c->Dx, n, c->Ds, n, 0.0, c->T2, n);
+    corrector_h(st, n, c->T2, c->dnt, sig * R.mu, c->Hc);
+    gemm(c, true, false, n, n, n, 1.0, c->Ginv, n, c->Hc, n, 0.0, c->T1, n);
+    gemm(c, false, false, n, n, n, 1.0, c->T1, n, c->Ginv, n, 0.0, c->T2, n);
+    axpbypcz(st, nn, 1.0, c->Rd, -1.0, c->T2, 0.0, c->Ct);
+    symmetrize(st, n, c->Ct, n);
+    rc = inner_solve(c, c->rp, c->Ct, c->dX, c->dy, &is);
+    if (rc != 0) throw Error(rc, "corrector inner solve did not converge");
+    s.pcg_corr = is.iterations;
+    at_apply(c, c->dy, c->Y);
+    axpbypcz(st, nn, 1.0, c->Rd, -1.0, c->Y, 0.0, c->dS);
+    const double frac = c->opt.step_frac;
+    ap = std::min(1.0, frac * max_step(c, c->Linv, c->dX));
+    ad = std::min(1.0, frac * max_step(c, c->Rinv, c->dS));
+    axpby(st, nn, ap, c->dX, 1.0, c->X);
+    axpby(st, m, ad, c->dy, 1.0, c->y);
+    axpby(st, nn, ad, c->dS, 1.0, c->S);
+    symmetrize(st, n, c->X, n);
+    symmetrize(st, n, c->S, n);
+    WC_HIP(hipStreamSynchronize(st));
+    c->scaling_valid = false;
+    c->iter += 1;
+    const auto t3 = clk::now();
+    s.alpha_p = ap;
+    s.alpha_d = ad;
+    s.t_scaling_ms = std::chrono::duration<double, std::milli>(t2c - t1).count();
+    s.t_total_ms = std::chrono::duration<double, std::milli>(t3 - t0).count();
+    s.t_inner_ms = s.t_total_ms - s.t_scaling_ms;
+    if (c->opt.verbose)
+        fprintf(stderr, "[wcsdp] it %d mu %.3e relgap %.3e pinf %.3e dinf %.3e r %d pcg %d/%d ap %.3f ad %.3f\n",
+                c->iter, s.mu, s.relgap, s.pinf, s.dinf, s.r, s.pcg_pred, s.pcg_corr, ap, ad);
+    if (stats) *stats = s;
+    return 0;
+}
+
+int solve(sdp_ctx* c, sdp_result* res) {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    const int64_t mv0 = c->matvecs, pcg0 = c->pcg_total;
+    sdp_step_stats s{};
+    int status = kEStall;
+    int its = 0;
+    for (int k = 0; k <= c->opt.max_ipm_iter; ++k) {
+        ipm_step(c, &s);
+        if (s.converged) {
+            status = 0;
+            break;
+        }
+        ++its;
+        if (k == c->opt.max_ipm_iter) break;
+    }
+    if (status != 0) {
+        // report the final point
+        Resid R = residuals(c);
+        s.mu = R.mu;
+        s.pobj = R.pobj;
+        s.dobj = R.dobj;
+        s.relgap = R.relgap;
+        s.pinf = R.pinf;
+        s.dinf = R.dinf;
+    }
+    if (res) {
+        res->status = status;
+        res->iterations = its;
+        res->pcg_iterations = c->pcg_total - pcg0;
+        res->newton_matvecs = c->matvecs - mv0;
+        res->pobj = s.pobj;
+        res->dobj = s.dobj;
+        res->relgap = s.relgap;
+        res->pinf = s.pinf;
+        res->dinf = s.dinf;
+        res->mu = s.mu;
+        res->time_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    }
+    return status;
+}
+
+void set_point(sdp_ctx* c, const double* X, const double* y, const double* S) {
+    const int n = c->n, m = c->m;
+    const long nn = (long)n * n;
+    if (X) copy(c->st, nn, X, c->X);
+    if (y) copy(c->st, m, y, c->y);
+    if (S) copy(c->st, nn, S, c->S);
+    symmetrize(c->st, n, c->X, n);
+    symmetrize(c->st, n, c->S, n);
+    c->scaling_valid = false;
+    c->iter = 0;
+    WC_HIP(hipStreamSynchronize(c->st));
+}
+
+}  // namespace wc

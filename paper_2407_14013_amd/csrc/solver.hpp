@@ -1,0 +1,74 @@
+// The SDP context and the host-side driver of the interior-point method.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/wcsdp.h"
+#include "common.hpp"
+
+struct sdp_ctx {
+    hipStream_t st = nullptr;
+    int n = 0, m = 0, kind = SDP_A_DENSE;
+    sdp_options opt{};
+    std::string last_error;
+
+    // ---- problem data -------------------------------------------------------
+    long N2 = 0, ldP = 0;
+    wc::DevBuf<double> P;       // dense: m x ldP packed rows A_i[j,k], j >= k (row-major)
+    wc::DevBuf<int> pj, pk;     // packed index -> (j, k)
+    wc::DevBuf<int> jk;         // entry: 2 m pairs
+    wc::DevBuf<double> b, C;    // m, n x n
+    double bnorm = 0, Cnorm = 0, mean_a2 = 0, xi = 1, eta = 1;
+
+    // ---- iterate -------------------------------------------------------------
+    wc::DevBuf<double> X, y, S;
+    int iter = 0;
+
+    // ---- scaling point and its split (valid while scaling_valid) -------------
+    bool scaling_valid = false;
+    int rmax = 1, r = 1, d = 0;
+    long dmaxp = 0;             // padded row pitch for d-length rows
+    double tau = 0, beta = 0;
+    wc::DevBuf<double> L, Rs, Linv, Rinv, Mt, Vs, dnt, G, Ginv, Gt, Gw, lam, evE, E, sig;
+    std::vector<double> lam_h;
+    wc::DevBuf<double> Phi, Fq, AQ, Cm, Cinv, Zw;
+    wc::JacobiWork jw;
+
+    // ---- temporaries -------------------------------------------------------------
+    wc::DevBuf<double> Y, T1, T2, Mm, Hm, U, YQ, F, mw, yp, part, gpart, tm, td, td2, td3, rho, dz;
+    wc::DevBuf<double> vx, vr, vz, vp, vKp, vg, vtmp;   // Krylov vectors (m + dmax, padded)
+    wc::DevBuf<double> sc;      // device scalars
+    double* pin = nullptr;      // pinned host scalars
+    wc::DevBuf<int> info;
+
+    // ---- Newton direction buffers ----------------------------------------------
+    wc::DevBuf<double> dXa, dya, dSa, dX, dy, dS, Ct, Rd, rp, Hc, Dx, Ds;
+
+    // ---- counters / profiling ------------------------------------------------------
+    int64_t matvecs = 0, pcg_total = 0;
+    int prof_mask = 0;
+    struct Prof {
+        std::vector<hipEvent_t> ev;  // start/stop pairs
+        double ms = 0;
+        int64_t launches = 0;
+        double bytes = 0;
+    } prof[SDP_K_COUNT];
+
+    ~sdp_ctx();
+};
+
+namespace wc {
+
+void setup(sdp_ctx* c, const sdp_problem* p, const sdp_options* o, hipStream_t st);
+void ensure_scaling(sdp_ctx* c);
+void newton_apply(sdp_ctx* c, const double* in, double* out);
+int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, double* dy, sdp_inner_stats* stats);
+int ipm_step(sdp_ctx* c, sdp_step_stats* stats);
+int solve(sdp_ctx* c, sdp_result* res);
+void set_point(sdp_ctx* c, const double* X, const double* y, const double* S);
+void prof_begin(sdp_ctx* c, int k, hipEvent_t* e0);
+void prof_end(sdp_ctx* c, int k, hipEvent_t e0, double bytes);
+void prof_collect(sdp_ctx* c);
+
+}  // namespace wc

@@ -1,0 +1,75 @@
+"""Python binding of include/wcsdp_linalg.h (argument marshalling only).
+
+Matrices are exchanged as column-major device buffers: an m x k matrix A is
+held by a torch tensor of shape (k, m) whose rows are A's columns.  The
+helpers ``to_dev`` / ``from_dev`` convert numpy (row, column) arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .api import SdpError, _stream_ptr
+
+
+def to_dev(a: np.ndarray) -> torch.Tensor:
+    """Column-major device copy of a 2-D numpy array."""
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float64).T)).cuda()
+
+
+def from_dev(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().T.copy()
+
+
+def _p(t):
+    if t is None:
+        return C.c_void_p(0)
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+def _chk(st):
+    if st != 0:
+        raise SdpError(st, L.lib().sdp_last_error(None).decode())
+
+
+def dgemm(transa: str, transb: str, alpha, A: torch.Tensor, B: torch.Tensor, beta=0.0, Cm: torch.Tensor | None = None):
+    """C = alpha op(A) op(B) + beta C on column-major device buffers (shapes as in to_dev)."""
+    ka, ma = A.shape  # A is ma x ka column-major
+    kb, mb = B.shape
+    m = ka if transa == "T" else ma
+    k = ma if transa == "T" else ka
+    n = mb if transb == "T" else kb
+    kk = kb if transb == "T" else mb
+    assert k == kk, "inner dimensions differ"
+    if Cm is None:
+        Cm = torch.zeros((n, m), dtype=torch.float64, device=A.device)
+    _chk(L.lib().wc_dgemm(_stream_ptr(), transa.encode(), transb.encode(), m, n, k, alpha, _p(A), ma, _p(B), mb, beta,
+                          _p(Cm), m))
+    return Cm
+
+
+def dpotrf(A: torch.Tensor):
+    n = A.shape[0]
+    info = C.c_int32()
+    st = L.lib().wc_dpotrf(_stream_ptr(), n, _p(A), n, C.byref(info))
+    return st, info.value
+
+
+def dtrtri(Lm: torch.Tensor) -> torch.Tensor:
+    n = Lm.shape[0]
+    out = torch.empty_like(Lm)
+    _chk(L.lib().wc_dtrtri(_stream_ptr(), n, _p(Lm), n, _p(out), n))
+    return out
+
+
+def djacobi_svd(A: torch.Tensor, want_v: bool = True, tol: float = 0.0, max_sweeps: int = 60):
+    n = A.shape[0]
+    V = torch.empty_like(A) if want_v else None
+    s = torch.empty(n, dtype=torch.float64, device=A.device)
+    sw = C.c_int32()
+    _chk(L.lib().wc_djacobi_svd(_stream_ptr(), n, _p(A), n, _p(V), n, _p(s), tol, max_sweeps, C.byref(sw)))
+    return s, V, sw.value

@@ -1,0 +1,235 @@
+"""GPU parity of the SDP entry points (include/wcsdp.h) against the CPU oracle.
+
+* sdp_get_scaling: eigen-split of the NT scaling point (eq. EQSigdef).
+* sdp_newton_apply: the augmented operator of eq. augsys, compared element by
+  element with the oracle's Section 5 products in the same (canonically
+  signed) eigenbasis.  Bound: 1e-10 of the output's largest entry -- FP64
+  sums of length <= n(n+1)/2 contribute ~1e-12, the rest is the eigenvector
+  difference between the two eigensolvers, ~eps ||W|| / gap.
+* sdp_inner_solve: the Newton direction of eq. Newt-eps, by the residuals of
+  its two equations at every point (primal 1e-9 relative to the inner
+  tolerance 1e-10; the second in NT-scaled form, 1e-8, where the direct solve
+  itself reaches ~1e-9 at mu ~ 1e-5), and element by element against the direct Schur-complement solve
+  (relative 1e-7) where the KKT matrix is still well conditioned.
+* sdp_solve: objective relative error <= 1e-8 against the oracle, relative gap,
+  primal and dual infeasibility <= 1e-8 recomputed on the CPU, and recovery
+  of the planted X*.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import workloads  # noqa: E402
+from oracle import brute, certify, ipm, nt, operators as ops, reform as rf  # noqa: E402
+from paper_2407_14013_amd import Context, SdpError  # noqa: E402
+from paper_2407_14013_amd import _lib as L  # noqa: E402
+
+GOLDEN1 = os.path.join(os.path.dirname(__file__), "golden", "oracle_config1.json")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def oracle_split(X, S, rank_max=10, rank_fixed=0):
+    G, d, Lf = nt.nt_factor(X, S)
+    W = G @ G.T
+    return rf.eig_split(W, rank_max=rank_max, rank_fixed=rank_fixed)
+
+
+def small_entry():
+    return workloads.matrix_completion(16, 2, 100, seed=3)
+
+
+def points(p):
+    n = p["n"]
+    X, S = workloads.random_pd_pair(n, seed=n, spread=1.0)
+    out = [("random", X, np.zeros(p["m"]), S)]
+    res = ipm.solve(p, maxit=4)
+    out.append(("ipm4", res["X"], res["y"], res["S"]))
+    return out
+
+
+@pytest.mark.parametrize("which", ["cfg0", "entry"])
+def test_scaling_matches_oracle(which):
+    p = workloads.config(0) if which == "cfg0" else small_entry()
+    for name, X, y, S in points(p):
+        with Context(p) as ctx:
+            ctx.set_point(dev(X), dev(y), dev(S))
+            g = ctx.get_scaling()
+        sp = oracle_split(X, S)
+        assert g["r"] == sp["r"], name
+        assert np.allclose(g["lam"], sp["lam"], rtol=1e-11, atol=0), name
+        assert abs(g["tau"] - sp["tau"]) <= 1e-11 * sp["tau"]
+        assert abs(g["beta"] - rf.beta_rule(sp, p)) <= 1e-10 * g["beta"]
+        V = host(g["V"])
+        e_v = np.abs(V - sp["V"]).max()
+        assert e_v <= 1e-8, name
+
+
+@pytest.mark.parametrize("which,rank_fixed", [("cfg0", 0), ("cfg0", 19), ("cfg0", 1), ("entry", 0)])
+def test_newton_apply_matches_oracle(which, rank_fixed):
+    p = workloads.config(0) if which == "cfg0" else small_entry()
+    m = p["m"]
+    rng = np.random.default_rng(7)
+    for name, X, y, S in points(p):
+        with Context(p, rank_fixed=rank_fixed) as ctx:
+            ctx.set_point(dev(X), dev(y), dev(S))
+            N = ctx.aug_dim()
+            sp = oracle_split(X, S, rank_fixed=rank_fixed)
+            assert N == m + rf.dim_d(p["n"], sp["r"])
+            E = rf.e_matrix(sp)
+            sig = rf.sigma_diag(sp)
+            for trial in range(3):
+                x = rng.standard_normal(N)
+                if trial == 1:
+                    x[m:] = 0.0  # u only
+                if trial == 2:
+                    x[:m] = 0.0  # v only
+                got = host(ctx.newton_apply(dev(x)))
+                t, b = rf.aug_apply(p, sp, E, sig, x[:m], x[m:])
+                ref = np.concatenate([t, b])
+                err = np.abs(got - ref).max() / np.abs(ref).max()
+                assert err <= 1e-10, (name, trial)
+
+
+def test_newton_apply_config1_matches_oracle():
+    p = workloads.config(1)
+    m = p["m"]
+    X, S = workloads.random_pd_pair(p["n"], seed=5, spread=1.0)
+    y = np.zeros(m)
+    with Context(p) as ctx:
+        ctx.set_point(dev(X), dev(y), dev(S))
+        N = ctx.aug_dim()
+        sp = oracle_split(X, S)
+        E = rf.e_matrix(sp)
+        sig = rf.sigma_diag(sp)
+        x = np.random.default_rng(1).standard_normal(N)
+        got = host(ctx.newton_apply(dev(x)))
+    t, b = rf.aug_apply(p, sp, E, sig, x[:m], x[m:])
+    ref = np.concatenate([t, b])
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("which", ["cfg0", "entry"])
+@pytest.mark.parametrize("iters", [2, 6])
+def test_inner_solve_matches_direct(which, iters):
+    # eq. Newt-eps at an oracle iterate.  Its two equations are checked by
+    # their residuals at every point: A(dX) = b~ to the inner tolerance
+    # (Lemma smallres: the recovered step's primal residual is the augmented
+    # residual), and dX = W (A^T(dy) - C~) W to rounding.  Element-wise
+    # agreement with the direct Schur solve is required where the KKT matrix
+    # is still well conditioned (the first iterations).
+    p = workloads.config(0) if which == "cfg0" else small_entry()
+    res = ipm.solve(p, maxit=iters)
+    X, y, S = res["X"], res["y"], res["S"]
+    r = ipm.residuals(p, X, y, S)
+    Ct = r["Rd"] + S
+    bt = r["rp"]
+    G, d, Lf = nt.nt_factor(X, S)
+    W = G @ G.T
+    dX0, dy0, _ = ipm.newton_direct(p, G, ipm.schur_factor(p, G, W), bt, Ct, r["Rd"])
+    with Context(p) as ctx:
+        ctx.set_point(dev(X), dev(y), dev(S))
+        dX, dy, st = ctx.inner_solve(dev(bt), dev(Ct))
+    dX, dy = host(dX), host(dy)
+    assert st["converged"] == 1 and st["rel_res"] <= 1e-10
+    scale = np.linalg.norm(bt + ops.a_op(p, W @ Ct @ W))
+    e_primal = np.linalg.norm(ops.a_op(p, dX) - bt) / scale
+    assert e_primal <= 1e-9
+    # dX = W (A^T(dy) - C~) W compared in NT-scaled coordinates (W = G G^T):
+    # G^{-1} dX G^{-T} = G^T (A^T(dy) - C~) G; unscaled, the comparison would
+    # be dominated by rounding amplified by ||W||^2.
+    Gi = np.linalg.inv(G)
+    rhs = G.T @ (ops.at_op(p, dy) - Ct) @ G
+    e_second = np.linalg.norm(Gi @ dX @ Gi.T - rhs) / np.linalg.norm(rhs)
+    assert e_second <= 1e-8
+    if iters <= 2:
+        e_dx = np.abs(dX - dX0).max() / np.abs(dX0).max()
+        e_dy = np.abs(dy - dy0).max() / np.abs(dy0).max()
+        assert e_dx <= 1e-7 and e_dy <= 1e-7
+
+
+def check_solution(p, res, X, y, S, pobj_ref, tol=1e-8):
+    assert res["status"] == 0
+    c = certify.certificate(p, host(X), host(y), host(S))
+    assert c["pinf"] <= 1.01 * tol and c["dinf"] <= 1.01 * tol and c["relgap"] <= 1.01 * tol, c
+    assert c["lmin_X"] > 0 and c["lmin_S"] > 0
+    e_obj = abs(c["pobj"] - pobj_ref) / abs(pobj_ref)
+    assert e_obj <= tol, (c["pobj"], pobj_ref)
+    return c
+
+
+def test_solve_config0_matches_oracle():
+    p = workloads.config(0)
+    ref = ipm.solve(p)
+    with Context(p) as ctx:
+        res = ctx.solve()
+        X, y, S = ctx.get_point()
+    check_solution(p, res, X, y, S, ref["history"][-1]["pobj"])
+    Xs = p["U"] @ p["U"].T
+    e_rec = np.linalg.norm(host(X) - Xs) / np.linalg.norm(Xs)
+    assert e_rec <= 1e-6
+
+
+def test_solve_config1_matches_oracle():
+    with open(GOLDEN1) as f:
+        gold = json.load(f)
+    p = workloads.config(1)
+    with Context(p) as ctx:
+        res = ctx.solve()
+        X, y, S = ctx.get_point()
+    check_solution(p, res, X, y, S, gold["certificate"]["pobj"])
+    Xs = p["U"] @ p["U"].T
+    e_rec = np.linalg.norm(host(X) - Xs) / np.linalg.norm(Xs)
+    assert e_rec <= 1e-6
+    w, V = np.linalg.eigh(host(X))
+    assert np.allclose(np.sort(w)[::-1][:3], gold["X_top_eigenvalues"][:3], rtol=1e-7)
+
+
+def test_solve_entry_sampling_matches_oracle():
+    p = small_entry()
+    ref = ipm.solve(p)
+    with Context(p) as ctx:
+        res = ctx.solve()
+        X, y, S = ctx.get_point()
+    check_solution(p, res, X, y, S, ref["history"][-1]["pobj"])
+
+
+def test_solve_brute_force_cases():
+    q = brute.two_by_two_instance(1)
+    val, _ = brute.two_by_two_optimum(q)
+    with Context(q) as ctx:
+        res = ctx.solve()
+        X, y, S = ctx.get_point()
+    check_solution(q, res, X, y, S, val)
+    q = brute.lp_instance(5, 2, 1)
+    val, _ = brute.lp_optimum(*q["lp"])
+    with Context(q) as ctx:
+        res = ctx.solve()
+        X, y, S = ctx.get_point()
+    check_solution(q, res, X, y, S, val)
+
+
+def test_non_pd_point_is_reported():
+    p = workloads.config(0)
+    n = p["n"]
+    X = np.eye(n)
+    X[3, 3] = -1.0
+    with Context(p) as ctx:
+        ctx.set_point(dev(X), dev(np.zeros(p["m"])), dev(np.eye(n)))
+        with pytest.raises(SdpError) as ei:
+            ctx.aug_dim()
+        assert ei.value.status == L.SDP_ENUMERIC
+        assert "X is not positive definite" in str(ei.value)
