@@ -135,20 +135,22 @@ void trtri(hipStream_t st, int n, const double* L, long ldl, double* Linv, long 
 // ---------------------------------------------------------------------------
 struct JacobiWork {
     DevBuf<double> off;       // 1 double (max relative off-diagonal of a sweep)
+    DevBuf<int> flags;        // done flag and sweep counter
     DevBuf<double> norms;     // n
     DevBuf<int> perm;         // n
     DevBuf<double> tmpA;      // n * n (permutation staging)
     DevBuf<double> tmpV;      // n * n
-    DevBuf<double> host_off;  // unused placeholder (keeps layout simple)
-    double* pinned = nullptr; // 1 pinned host double
+    int* pinned = nullptr;    // 2 pinned host ints
     int cap = 0;
     void ensure(int n);
     ~JacobiWork();
 };
 // One-sided block Jacobi; see wcsdp_linalg.h.  V may be null.  If A_out is
-// requested (want_a), A is permuted/signed to match V.  Returns sweeps used
-// (negative if not converged).
+// requested (want_a), A is permuted/signed to match V.  With v_init the caller
+// has already multiplied A by an orthogonal V0 and stored V0 in V (warm start);
+// the rotations then accumulate onto V0.  Returns sweeps used (negative if not
+// converged).
 int jacobi_svd(hipStream_t st, int n, double* A, long lda, double* V, long ldv, double* sigma, double tol,
-               int max_sweeps, JacobiWork& w, bool want_a = true);
+               int max_sweeps, JacobiWork& w, bool want_a = true, bool v_init = false);
 
 }  // namespace wc

@@ -10,6 +10,8 @@
 // tol * ||a_i|| ||a_j|| ends the iteration.  Rotating only the columns of A
 // gives the singular values with high relative accuracy, which the small
 // eigenvalues of the scaling matrix need.
+#include <cstdlib>
+
 #include "common.hpp"
 
 namespace wc {
@@ -33,7 +35,9 @@ __device__ inline void tournament_pair(int round, int w, int N, int& a, int& b) 
 
 __global__ __launch_bounds__(256) void jacobi_round_kernel(int n, int nblk, int round, double* __restrict__ A,
                                                            long lda, double* __restrict__ V, long ldv, double tol,
-                                                           unsigned long long* offmax) {
+                                                           unsigned long long* offmax, const int* __restrict__ done,
+                                                           int inner_sweeps) {
+    if (*done) return;  // an earlier sweep already converged
     __shared__ double P[JR][JW + 1];
     __shared__ double H[JW][JW + 1];
     __shared__ double R[JW][JW + 1];
@@ -94,13 +98,15 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(int n, int nblk, int 
     if (tid == 0) atomicMax(offmax, static_cast<unsigned long long>(__double_as_longlong(off_pair)));
     if (off_pair <= tol) return;  // uniform across the workgroup
 
-    // ---- 2. inner two-sided Jacobi on H ------------------------------------
+    // ---- 2. two-sided Jacobi sweeps on H (at most inner_sweeps) ---------------
+    // The pair need not be diagonalised exactly: the outer sweeps revisit it,
+    // and convergence is judged only by the outer tolerance test above.
     for (int t = tid; t < JW * JW; t += 256) {
         int i = t % JW, j = t / JW;
         R[i][j] = (i == j) ? 1.0 : 0.0;
     }
     const double eps_in = 2.220446049250313e-16;
-    for (int sweep = 0; sweep < 15; ++sweep) {
+    for (int sweep = 0; sweep < inner_sweeps; ++sweep) {
         if (tid == 0) rot_any = 0;
         __syncthreads();
         for (int rr = 0; rr < JW - 1; ++rr) {
@@ -272,14 +278,40 @@ __global__ void permute_vec_kernel(int n, const double* __restrict__ src, const 
     if (k < n) dst[rank[k]] = src[k];
 }
 
+// End of a sweep: count it, mark convergence when no pair exceeded tol, and
+// reset the maximum for the next sweep.  flags[0] = done, flags[1] = sweeps.
+__global__ void sweep_end_kernel(unsigned long long* offmax, int* flags, double tol) {
+    if (flags[0]) return;
+    flags[1] += 1;
+    if (__longlong_as_double(static_cast<long long>(*offmax)) <= tol) flags[0] = 1;
+    *offmax = 0ull;
+}
+
+__global__ void sweep_reset_kernel(unsigned long long* offmax, int* flags) {
+    *offmax = 0ull;
+    flags[0] = 0;
+    flags[1] = 0;
+}
+
+// Inner sweeps per block-pair visit (WCSDP_JACOBI_INNER overrides; tuning only).
+static int jacobi_inner_sweeps() {
+    static int v = [] {
+        const char* e = getenv("WCSDP_JACOBI_INNER");
+        int x = e ? atoi(e) : 1;
+        return x < 1 ? 1 : (x > 15 ? 15 : x);
+    }();
+    return v;
+}
+
 void JacobiWork::ensure(int n) {
     if (n <= cap) return;
     off.alloc(1);
+    flags.alloc(2);
     norms.alloc(2 * (size_t)n);
     perm.alloc(n);
     tmpA.alloc((size_t)n * n);
     tmpV.alloc((size_t)n * n);
-    if (!pinned) WC_HIP(hipHostMalloc(reinterpret_cast<void**>(&pinned), sizeof(double), hipHostMallocDefault));
+    if (!pinned) WC_HIP(hipHostMalloc(reinterpret_cast<void**>(&pinned), 2 * sizeof(int), hipHostMallocDefault));
     cap = n;
 }
 
@@ -288,29 +320,36 @@ JacobiWork::~JacobiWork() {
 }
 
 int jacobi_svd(hipStream_t st, int n, double* A, long lda, double* V, long ldv, double* sigma, double tol,
-               int max_sweeps, JacobiWork& w, bool want_a) {
+               int max_sweeps, JacobiWork& w, bool want_a, bool v_init) {
     require(n >= 1, "jacobi_svd: n must be positive");
     w.ensure(n);
     if (tol <= 0.0) tol = std::max(n, 16) * 1.1102230246251565e-16;
-    if (V) set_identity(st, n, V, ldv, 1.0);
+    if (V && !v_init) set_identity(st, n, V, ldv, 1.0);
     int nblk = cdiv(n, JB);
     if (nblk < 2) nblk = 2;
     if (nblk & 1) ++nblk;
-    int sweeps = -max_sweeps;
-    for (int s = 0; s < max_sweeps; ++s) {
-        fill(st, 1, w.off.get(), 0.0);
+    auto* off = reinterpret_cast<unsigned long long*>(w.off.get());
+    int* flags = w.flags.get();
+    hipLaunchKernelGGL(sweep_reset_kernel, dim3(1), dim3(1), 0, st, off, flags);
+    WC_LAUNCH_CHECK();
+    // sweeps are launched in groups; rounds after convergence return at once
+    const int group = 3;
+    bool done = false;
+    for (int s = 0; s < max_sweeps && !done; ++s) {
         for (int round = 0; round < nblk - 1; ++round) {
             hipLaunchKernelGGL(jacobi_round_kernel, dim3(nblk / 2), dim3(256), 0, st, n, nblk, round, A, lda, V, ldv,
-                               tol, reinterpret_cast<unsigned long long*>(w.off.get()));
+                               tol, off, flags, jacobi_inner_sweeps());
             WC_LAUNCH_CHECK();
         }
-        WC_HIP(hipMemcpyAsync(w.pinned, w.off.get(), sizeof(double), hipMemcpyDeviceToHost, st));
-        WC_HIP(hipStreamSynchronize(st));
-        if (*w.pinned <= tol) {
-            sweeps = s + 1;
-            break;
+        hipLaunchKernelGGL(sweep_end_kernel, dim3(1), dim3(1), 0, st, off, flags, tol);
+        WC_LAUNCH_CHECK();
+        if ((s + 1) % group == 0 || s + 1 == max_sweeps) {
+            WC_HIP(hipMemcpyAsync(w.pinned, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+            WC_HIP(hipStreamSynchronize(st));
+            done = w.pinned[0] != 0;
         }
     }
+    const int sweeps = done ? w.pinned[1] : -max_sweeps;
     double* norms = w.norms.get();
     double* sgn = w.norms.get() + n;
     hipLaunchKernelGGL(col_norm_sign_kernel, dim3(cdiv(n, 4)), dim3(256), 0, st, n, A, lda, V, ldv, norms, sgn);

@@ -313,16 +313,31 @@ void ensure_scaling(sdp_ctx* c) {
     trtri(st, n, c->L, n, c->Linv, n, c->T1);
     trtri(st, n, c->Rs, n, c->Rinv, n, c->T1);
     // NT factor: Rs^T L = U D V^T, G = L V D^{-1/2}, G^{-1} = D^{1/2} V^T L^{-1}
-    gemm(c, true, false, n, n, n, 1.0, c->Rs, n, c->L, n, 0.0, c->Mt, n);
-    int sw = jacobi_svd(st, n, c->Mt, n, c->Vs, n, c->dnt, 0.0, 60, c->jw, false);
+    // Both Jacobi runs are warm-started from the previous iterate's vectors V0
+    // (Jacobi on A V0 with the rotations accumulated onto V0): consecutive
+    // scaling points are close, so few sweeps remain.
+    const bool warm = c->have_prev;
+    if (warm) {
+        gemm(c, true, false, n, n, n, 1.0, c->Rs, n, c->L, n, 0.0, c->T1, n);
+        gemm(c, false, false, n, n, n, 1.0, c->T1, n, c->Vs, n, 0.0, c->Mt, n);
+    } else {
+        gemm(c, true, false, n, n, n, 1.0, c->Rs, n, c->L, n, 0.0, c->Mt, n);
+    }
+    int sw = jacobi_svd(st, n, c->Mt, n, c->Vs, n, c->dnt, 0.0, 60, c->jw, false, warm);
     if (sw < 0) throw Error(kENumeric, "Jacobi SVD of the NT factor did not converge");
     gemm(c, false, false, n, n, n, 1.0, c->L, n, c->Vs, n, 0.0, c->T1, n);
     scale_cols(st, n, n, c->T1, n, c->dnt, -0.5, c->G, n);
     gemm(c, true, false, n, n, n, 1.0, c->Vs, n, c->Linv, n, 0.0, c->T1, n);
     scale_rows(st, n, n, c->T1, n, c->dnt, 0.5, c->Ginv, n);
     // eigen-decomposition of W = G G^T: one-sided Jacobi on G^T
-    transpose(st, n, n, c->G, n, c->Gt, n);
-    sw = jacobi_svd(st, n, c->Gt, n, c->Gw, n, c->lam, 0.0, 60, c->jw, false);
+    if (warm) {
+        transpose(st, n, n, c->G, n, c->T1, n);
+        gemm(c, false, false, n, n, n, 1.0, c->T1, n, c->Gw, n, 0.0, c->Gt, n);
+    } else {
+        transpose(st, n, n, c->G, n, c->Gt, n);
+    }
+    sw = jacobi_svd(st, n, c->Gt, n, c->Gw, n, c->lam, 0.0, 60, c->jw, false, warm);
+    c->have_prev = true;
     if (sw < 0) throw Error(kENumeric, "Jacobi eigen-decomposition of W did not converge");
     c->lam_h.resize(n);
     WC_HIP(hipMemcpyAsync(c->lam_h.data(), c->lam.get(), sizeof(double) * n, hipMemcpyDeviceToHost, st));

@@ -27,6 +27,7 @@ struct sdp_ctx {
 
     // ---- scaling point and its split (valid while scaling_valid) -------------
     bool scaling_valid = false;
+    bool have_prev = false;     // Vs / Gw hold the previous scaling's vectors (warm start)
     int rmax = 1, r = 1, d = 0;
     long dmaxp = 0;             // padded row pitch for d-length rows
     double tau = 0, beta = 0;
