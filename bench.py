@@ -153,7 +153,9 @@ def main():
         },
         "newton_apply_loop": {"matvec_per_s": loop_rate, "calls": args.apply_loop},
         "roofline": {
-            "kernel": "gemv_rows (A(M))" if kcls == L.SDP_K_A_APPLY else "gemv_cols (A^T(u))",
+            "kernel": ("packed_rows_kernel: A(M), one pass over the packed constraint rows"
+                       if kcls == L.SDP_K_A_APPLY else
+                       "packed_cols_partial_kernel: A^T(u), one pass over the packed constraint rows"),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -96,6 +96,14 @@ int gemv_cols_parts(int m);
 void gemv_cols(hipStream_t st, int m, int k, const double* A, long lda, const double* x, double* y, double alpha,
                double beta, double* part);
 
+// The two passes over the packed constraint rows P (m x ldp row-major):
+// packed_rows is y = alpha P x + beta y; packed_cols_partial writes the
+// gemv_cols_parts(m) slab partial sums of P^T x into `part` (row pitch
+// round_up(k, 2)), to be added in slab order by the caller.
+void packed_rows(hipStream_t st, int m, int k, const double* P, long ldp, const double* x, double* y, double alpha,
+                 double beta);
+void packed_cols_partial(hipStream_t st, int m, int k, const double* P, long ldp, const double* x, double* part);
+
 // Deterministic reductions into out[0] (device).  `part` holds >= 1024 doubles.
 void dot(hipStream_t st, long n, const double* x, const double* y, double* out, double* part);
 // sum of x[i] * y[i] over an n x n (column-major, ld) pair of matrices

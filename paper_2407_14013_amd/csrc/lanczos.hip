@@ -1,0 +1,171 @@
+// Smallest eigenvalue of a symmetric n x n matrix by the Lanczos process with
+// full reorthogonalisation, run by one 1024-thread workgroup (n <= 4096).
+//
+// Used for the interior-point step length: the largest alpha with
+// L L^T + alpha D PSD is 1 / max(0, -lambda_min(L^{-1} D L^{-T})).  The
+// Lanczos vectors and the tridiagonal coefficients stay on the device; the
+// host finds the smallest eigenvalue of the k x k tridiagonal by Sturm
+// bisection.  Ritz values lie inside the spectrum, so the estimate can only be
+// too large; the caller guards the final step with a Cholesky test.
+#include <cmath>
+
+#include "common.hpp"
+#include "lanczos.hpp"
+
+namespace wc {
+
+constexpr int LZ_THREADS = 1024;
+constexpr int LZ_WAVES = LZ_THREADS / 64;
+
+__device__ inline double lz_block_sum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < LZ_WAVES; ++i) s += red[i];
+    return s;
+}
+
+__global__ __launch_bounds__(LZ_THREADS) void lanczos_kernel(int n, const double* __restrict__ T, long ldt, int kmax,
+                                                             double* __restrict__ Q, long ldq,
+                                                             double* __restrict__ ab, int* __restrict__ kout) {
+    extern __shared__ double sm[];
+    double* q = sm;       // current Lanczos vector
+    double* w = sm + n;   // work vector
+    __shared__ double red[LZ_WAVES];
+    __shared__ double h[LZ_MAX_K + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+    // deterministic start vector with no special structure
+    double loc = 0.0;
+    for (int i = tid; i < n; i += LZ_THREADS) {
+        double v = 1.0 + 0.5 * sin(1.0 + 0.7071067811865476 * i) + 0.25 * cos(0.3 * i * i);
+        w[i] = v;
+        loc += v * v;
+    }
+    double nrm = sqrt(lz_block_sum(loc, red));
+    for (int i = tid; i < n; i += LZ_THREADS) {
+        q[i] = w[i] / nrm;
+        Q[i] = q[i];
+    }
+    __syncthreads();
+    double beta_prev = 0.0;
+    int k = 0;
+    for (int j = 0; j < kmax; ++j) {
+        // w = T q
+        for (int i = tid; i < n; i += LZ_THREADS) {
+            double acc = 0.0;
+            const double* Ti = T + i;
+#pragma unroll 8
+            for (int l = 0; l < n; ++l) acc += Ti[(long)l * ldt] * q[l];
+            w[i] = acc;
+        }
+        __syncthreads();
+        loc = 0.0;
+        for (int i = tid; i < n; i += LZ_THREADS) loc += q[i] * w[i];
+        const double alpha = lz_block_sum(loc, red);
+        for (int i = tid; i < n; i += LZ_THREADS) {
+            double v = w[i] - alpha * q[i];
+            if (j > 0) v -= beta_prev * Q[i + (long)(j - 1) * ldq];
+            w[i] = v;
+        }
+        __syncthreads();
+        // full reorthogonalisation against q_0..q_j, twice
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int l = wv; l <= j; l += LZ_WAVES) {
+                double s = 0.0;
+                for (int i = lane; i < n; i += 64) s += Q[i + (long)l * ldq] * w[i];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+                if (lane == 0) h[l] = s;
+            }
+            __syncthreads();
+            for (int i = tid; i < n; i += LZ_THREADS) {
+                double v = w[i];
+                for (int l = 0; l <= j; ++l) v -= h[l] * Q[i + (long)l * ldq];
+                w[i] = v;
+            }
+            __syncthreads();
+        }
+        loc = 0.0;
+        for (int i = tid; i < n; i += LZ_THREADS) loc += w[i] * w[i];
+        const double beta = sqrt(lz_block_sum(loc, red));
+        if (tid == 0) {
+            ab[j] = alpha;
+            ab[kmax + j] = beta;
+        }
+        k = j + 1;
+        if (!(beta > 1e-13 * (fabs(alpha) + beta_prev)) || j + 1 == kmax) break;  // invariant subspace or done
+        for (int i = tid; i < n; i += LZ_THREADS) {
+            double v = w[i] / beta;
+            q[i] = v;
+            Q[i + (long)(j + 1) * ldq] = v;
+        }
+        beta_prev = beta;
+        __syncthreads();
+    }
+    if (tid == 0) *kout = k;
+}
+
+void LanczosWork::ensure(int n) {
+    if (n <= cap) return;
+    Q.alloc((size_t)n * (LZ_MAX_K + 1));
+    ab.alloc(2 * LZ_MAX_K);
+    kout.alloc(1);
+    if (!pinned) WC_HIP(hipHostMalloc(reinterpret_cast<void**>(&pinned), (2 * LZ_MAX_K + 2) * sizeof(double),
+                                      hipHostMallocDefault));
+    cap = n;
+}
+
+LanczosWork::~LanczosWork() {
+    if (pinned) (void)hipHostFree(pinned);
+}
+
+// Number of eigenvalues of the symmetric tridiagonal (a, b) below x (Sturm count).
+static int sturm_count(const double* a, const double* b, int k, double x) {
+    int cnt = 0;
+    double d = 1.0;
+    for (int i = 0; i < k; ++i) {
+        double bb = (i > 0) ? b[i - 1] * b[i - 1] : 0.0;
+        d = a[i] - x - (i > 0 ? bb / d : 0.0);
+        if (d == 0.0) d = -1e-300;
+        if (d < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+double tridiag_min_eig(const double* a, const double* b, int k) {
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < k; ++i) {
+        double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(lo), std::fabs(hi)) + 1e-300; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (sturm_count(a, b, k, mid) >= 1) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+double lanczos_min_eig(hipStream_t st, int n, const double* T, long ldt, int kmax, LanczosWork& w) {
+    require(n >= 1 && n <= LZ_MAX_N, "lanczos: n out of range");
+    w.ensure(n);
+    kmax = std::max(1, std::min({kmax, n, LZ_MAX_K}));
+    size_t shm = 2 * (size_t)n * sizeof(double);
+    hipLaunchKernelGGL(lanczos_kernel, dim3(1), dim3(LZ_THREADS), shm, st, n, T, ldt, kmax, w.Q.get(), (long)n,
+                       w.ab.get(), w.kout.get());
+    WC_LAUNCH_CHECK();
+    WC_HIP(hipMemcpyAsync(w.pinned, w.ab.get(), 2 * kmax * sizeof(double), hipMemcpyDeviceToHost, st));
+    int k = 0;
+    WC_HIP(hipMemcpyAsync(&k, w.kout.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+    WC_HIP(hipStreamSynchronize(st));
+    return tridiag_min_eig(w.pinned, w.pinned + kmax, k);
+}
+
+}  // namespace wc

@@ -121,6 +121,25 @@ void unpack_sym(hipStream_t st, long N2, const double* yp, const int* pj, const 
     WC_LAUNCH_CHECK();
 }
 
+// Second half of the packed A^T(u) pass: add the slab partials of each packed
+// position in slab order and write the symmetric Y[j,k] = Y[k,j].
+__global__ void at_reduce_unpack_kernel(long N2, int nparts, const double* __restrict__ part, long pstride,
+                                        const int* __restrict__ pj, const int* __restrict__ pk,
+                                        double* __restrict__ Y, long ldy) {
+    long p = blockIdx.x * 256L + threadIdx.x;
+    if (p >= N2) return;
+    double s = 0.0;
+    for (int q = 0; q < nparts; ++q) s += part[q * pstride + p];
+    int j = pj[p], k = pk[p];
+    Y[j + (long)k * ldy] = s;
+    Y[k + (long)j * ldy] = s;
+}
+void at_reduce_unpack(hipStream_t st, long N2, int nparts, const double* part, long pstride, const int* pj,
+                      const int* pk, double* Y, long ldy) {
+    hipLaunchKernelGGL(at_reduce_unpack_kernel, g1(N2), dim3(256), 0, st, N2, nparts, part, pstride, pj, pk, Y, ldy);
+    WC_LAUNCH_CHECK();
+}
+
 // ---- entry-sampling constraints ----------------------------------------------
 __global__ void entry_gather_kernel(int m, const int* __restrict__ jk, const double* __restrict__ M, long ldm,
                                     double* __restrict__ out, double alpha, double beta) {

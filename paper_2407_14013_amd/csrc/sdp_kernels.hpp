@@ -13,6 +13,8 @@ void packed_row_norm2(hipStream_t st, int m, long N2, long ldp, const double* P,
 void pack_weighted(hipStream_t st, int n, long N2, long ldp, const double* M, long ldm, const int* pj, const int* pk,
                    double* mw);
 void unpack_sym(hipStream_t st, long N2, const double* yp, const int* pj, const int* pk, double* Y, long ldy);
+void at_reduce_unpack(hipStream_t st, long N2, int nparts, const double* part, long pstride, const int* pj,
+                      const int* pk, double* Y, long ldy);
 void entry_gather(hipStream_t st, int m, const int* jk, const double* M, long ldm, double* out, double alpha,
                   double beta);
 void entry_scatter(hipStream_t st, int m, const int* jk, const double* u, double* Y, long ldy);

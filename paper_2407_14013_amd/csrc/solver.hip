@@ -7,6 +7,7 @@
 #include <cmath>
 #include <limits>
 
+#include "lanczos.hpp"
 #include "sdp_kernels.hpp"
 #include "solver.hpp"
 
@@ -29,13 +30,14 @@ static void fetch(sdp_ctx* c, const double* dev, int count) {
 void prof_begin(sdp_ctx* c, int k, hipEvent_t* e0) {
     *e0 = nullptr;
     if (!(c->prof_mask & (1 << k))) return;
-    WC_HIP(hipEventCreate(e0));
+    // no system-scope fence: the timing events must not flush caches around the kernel
+    WC_HIP(hipEventCreateWithFlags(e0, hipEventDisableSystemFence));
     WC_HIP(hipEventRecord(*e0, c->st));
 }
 void prof_end(sdp_ctx* c, int k, hipEvent_t e0, double bytes) {
     if (e0 == nullptr) return;
     hipEvent_t e1;
-    WC_HIP(hipEventCreate(&e1));
+    WC_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
     WC_HIP(hipEventRecord(e1, c->st));
     c->prof[k].ev.push_back(e0);
     c->prof[k].ev.push_back(e1);
@@ -62,8 +64,8 @@ static void a_apply(sdp_ctx* c, const double* M, double* out, double alpha, doub
         pack_weighted(c->st, c->n, c->N2, c->ldP, M, c->n, c->pj, c->pk, c->mw);
         hipEvent_t e;
         prof_begin(c, SDP_K_A_APPLY, &e);
-        gemv_rows(c->st, c->m, static_cast<int>(c->N2), c->P, c->ldP, c->mw, out, alpha, beta);
-        prof_end(c, SDP_K_A_APPLY, e, 8.0 * c->m * c->N2 + 8.0 * c->N2 + 8.0 * c->m);
+        packed_rows(c->st, c->m, static_cast<int>(c->N2), c->P, c->ldP, c->mw, out, alpha, beta);
+        prof_end(c, SDP_K_A_APPLY, e, 8.0 * c->m * c->N2 + 8.0 * c->N2 + 8.0 * c->m);  // P, x, y
     } else {
         entry_gather(c->st, c->m, c->jk, M, c->n, out, alpha, beta);
     }
@@ -74,9 +76,9 @@ static void at_apply(sdp_ctx* c, const double* u, double* Y) {
     if (c->kind == SDP_A_DENSE) {
         hipEvent_t e;
         prof_begin(c, SDP_K_AT_APPLY, &e);
-        gemv_cols(c->st, c->m, static_cast<int>(c->N2), c->P, c->ldP, u, c->yp, 1.0, 0.0, c->gpart);
-        prof_end(c, SDP_K_AT_APPLY, e, 8.0 * c->m * c->N2 + 8.0 * c->N2 + 8.0 * c->m);
-        unpack_sym(c->st, c->N2, c->yp, c->pj, c->pk, Y, c->n);
+        packed_cols_partial(c->st, c->m, static_cast<int>(c->N2), c->P, c->ldP, u, c->gpart);
+        prof_end(c, SDP_K_AT_APPLY, e, 8.0 * c->m * c->N2 + 8.0 * c->m);
+        at_reduce_unpack(c->st, c->N2, gemv_cols_parts(c->m), c->gpart, round_up(c->N2, 2), c->pj, c->pk, Y, c->n);
     } else {
         fill(c->st, (long)c->n * c->n, Y, 0.0);
         entry_scatter(c->st, c->m, c->jk, u, Y, c->n);
@@ -128,6 +130,7 @@ static void alloc_work(sdp_ctx* c) {
     }
     long gp = (long)gemv_cols_parts(m) * std::max<long>(round_up(c->N2, 2), c->dmaxp);
     c->gpart.alloc(gp);
+
     c->part.alloc(1024);
     for (auto* b : {&c->vx, &c->vr, &c->vz, &c->vp, &c->vKp, &c->vg, &c->vtmp}) {
         b->alloc(Nmax);
@@ -541,27 +544,51 @@ int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, doub
 }
 
 // ---- interior-point step --------------------------------------------------------------
-// Largest alpha with L L^T + alpha D PSD, from lambda_min(L^{-1} D L^{-T}).  The
-// shifted matrix T + c I is positive semidefinite, so its singular values from
-// the one-sided Jacobi SVD are its eigenvalues.
+// Largest alpha with L L^T + alpha D PSD: 1 / max(0, -lambda_min(L^{-1} D L^{-T})).
+// lambda_min comes from Lanczos with full reorthogonalisation (exact once the
+// Krylov space is complete or the extreme Ritz value has converged); beyond
+// the Lanczos size limit it comes from the one-sided Jacobi SVD of the
+// shifted, positive semidefinite T + c I.
 static double max_step(sdp_ctx* c, const double* Linv, const double* D) {
     const int n = c->n;
     hipStream_t st = c->st;
     gemm(c, false, false, n, n, n, 1.0, Linv, n, D, n, 0.0, c->T1, n);
     gemm(c, false, true, n, n, n, 1.0, c->T1, n, Linv, n, 0.0, c->T2, n);
     symmetrize(st, n, c->T2, n);
-    frob_norm(st, n, c->T2, n, c->sc + 8, c->part);
-    fetch(c, c->sc + 8, 1);
-    const double fn = c->pin[0];
-    if (!(fn > 0.0)) return std::numeric_limits<double>::infinity();
-    const double shift = 1.01 * fn;
-    add_diag(st, n, c->T2, n, shift);
-    double* sv = c->lam.get() + n;
-    int sw = jacobi_svd(st, n, c->T2, n, nullptr, n, sv, 0.0, 60, c->jw, false);
-    if (sw < 0) throw Error(kENumeric, "Jacobi eigenvalues for the step length did not converge");
-    fetch(c, sv + n - 1, 1);
-    const double lmin = c->pin[0] - shift;
+    double lmin;
+    if (n <= LZ_MAX_N) {
+        lmin = lanczos_min_eig(st, n, c->T2, n, LZ_MAX_K, c->lw);
+    } else {
+        frob_norm(st, n, c->T2, n, c->sc + 8, c->part);
+        fetch(c, c->sc + 8, 1);
+        const double fn = c->pin[0];
+        if (!(fn > 0.0)) return std::numeric_limits<double>::infinity();
+        const double shift = 1.01 * fn;
+        add_diag(st, n, c->T2, n, shift);
+        double* sv = c->lam.get() + n;
+        int sw = jacobi_svd(st, n, c->T2, n, nullptr, n, sv, 0.0, 60, c->jw, false);
+        if (sw < 0) throw Error(kENumeric, "Jacobi eigenvalues for the step length did not converge");
+        fetch(c, sv + n - 1, 1);
+        lmin = c->pin[0] - shift;
+    }
     return lmin >= 0.0 ? std::numeric_limits<double>::infinity() : -1.0 / lmin;
+}
+
+// Shrink alpha until M + alpha D passes a Cholesky test (the Lanczos step
+// length is an upper estimate until converged).
+static double guard_step(sdp_ctx* c, const double* M, const double* D, double alpha) {
+    const int n = c->n;
+    const long nn = (long)n * n;
+    for (int t = 0; t < 40; ++t) {
+        axpbypcz(c->st, nn, 1.0, M, alpha, D, 0.0, c->T1);
+        potrf(c->st, n, c->T1, n, c->info.get() + 2);
+        int bad = 0;
+        WC_HIP(hipMemcpyAsync(&bad, c->info.get() + 2, sizeof(int), hipMemcpyDeviceToHost, c->st));
+        WC_HIP(hipStreamSynchronize(c->st));
+        if (!bad) return alpha;
+        alpha *= 0.9;
+    }
+    throw Error(kENumeric, "no positive definite step found along the Newton direction");
 }
 
 struct Resid {
@@ -655,8 +682,8 @@ int ipm_step(sdp_ctx* c, sdp_step_stats* stats) {
     at_apply(c, c->dy, c->Y);
     axpbypcz(st, nn, 1.0, c->Rd, -1.0, c->Y, 0.0, c->dS);
     const double frac = c->opt.step_frac;
-    ap = std::min(1.0, frac * max_step(c, c->Linv, c->dX));
-    ad = std::min(1.0, frac * max_step(c, c->Rinv, c->dS));
+    ap = guard_step(c, c->X, c->dX, std::min(1.0, frac * max_step(c, c->Linv, c->dX)));
+    ad = guard_step(c, c->S, c->dS, std::min(1.0, frac * max_step(c, c->Rinv, c->dS)));
     axpby(st, nn, ap, c->dX, 1.0, c->X);
     axpby(st, m, ad, c->dy, 1.0, c->y);
     axpby(st, nn, ad, c->dS, 1.0, c->S);

@@ -6,6 +6,7 @@
 
 #include "../../include/wcsdp.h"
 #include "common.hpp"
+#include "lanczos.hpp"
 
 struct sdp_ctx {
     hipStream_t st = nullptr;
@@ -35,6 +36,7 @@ struct sdp_ctx {
     std::vector<double> lam_h;
     wc::DevBuf<double> Phi, Fq, AQ, Cm, Cinv, Zw;
     wc::JacobiWork jw;
+    wc::LanczosWork lw;
 
     // ---- temporaries -------------------------------------------------------------
     wc::DevBuf<double> Y, T1, T2, Mm, Hm, U, YQ, F, mw, yp, part, gpart, tm, td, td2, td3, rho, dz;

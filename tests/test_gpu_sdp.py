@@ -233,3 +233,22 @@ def test_non_pd_point_is_reported():
             ctx.aug_dim()
         assert ei.value.status == L.SDP_ENUMERIC
         assert "X is not positive definite" in str(ei.value)
+
+
+@pytest.mark.parametrize("which", ["cfg0", "entry"])
+def test_ipm_step_matches_oracle_step(which):
+    # One predictor-corrector step from the same point: the step lengths to
+    # the PSD boundary (Lanczos on the GPU, exact eigenvalues in the oracle)
+    # and the centring parameter agree.
+    p = workloads.config(0) if which == "cfg0" else small_entry()
+    ref = ipm.solve(p, maxit=6)
+    hist = ref["history"]
+    for k in range(6):
+        o = ipm.solve(p, maxit=k)
+        X, y, S = o["X"], o["y"], o["S"]
+        with Context(p) as ctx:
+            ctx.set_point(dev(X), dev(y), dev(S))
+            st = ctx.ipm_step()
+        for key in ("alpha_p", "alpha_d", "sigma"):
+            e = abs(st[key] - hist[k][key]) / max(abs(hist[k][key]), 1e-300)
+            assert e <= 1e-6, (k, key, st[key], hist[k][key])
