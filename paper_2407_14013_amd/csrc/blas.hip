@@ -292,34 +292,38 @@ void gemv_cols(hipStream_t st, int m, int k, const double* A, long lda, const do
 //
 // packed_rows: y[i] = alpha P[i,:] x + beta y[i] (the A(M) pass).
 // packed_cols_partial: the streaming half of the A^T(u) pass; workgroup
-//   (column chunk of 512, row slab of 64) writes the slab's partial sums, which
+//   (column chunk of 512, row slab of 128) writes the slab's partial sums, which
 //   a second, small kernel adds in slab order (deterministic).
 // ---------------------------------------------------------------------------
+constexpr int PK_ROWS = 2;     // rows per workgroup of the A(M) pass
+constexpr int PK_SLAB = 128;   // row slab of the A^T(u) pass
+constexpr int PK_UNROLL = 8;   // rows in flight per thread in the A^T(u) pass
+
 __global__ __launch_bounds__(256) void packed_rows_kernel(int m, int k2, const double* __restrict__ P, long ldp,
                                                           const double* __restrict__ x, double* __restrict__ y,
                                                           double alpha, double beta) {
     __shared__ double sh[8];
-    const int row0 = blockIdx.x * GV_ROWS;
-    double acc[GV_ROWS];
+    const int row0 = blockIdx.x * PK_ROWS;
+    double acc[PK_ROWS];
 #pragma unroll
-    for (int r = 0; r < GV_ROWS; ++r) acc[r] = 0.0;
+    for (int r = 0; r < PK_ROWS; ++r) acc[r] = 0.0;
     const d2* x2 = reinterpret_cast<const d2*>(x);
-    const d2* arow[GV_ROWS];
+    const d2* arow[PK_ROWS];
 #pragma unroll
-    for (int r = 0; r < GV_ROWS; ++r) {
+    for (int r = 0; r < PK_ROWS; ++r) {
         int row = row0 + r < m ? row0 + r : m - 1;
         arow[r] = reinterpret_cast<const d2*>(P + (long)row * ldp);
     }
     for (int c = threadIdx.x; c < k2; c += 256) {
         d2 xv = x2[c];
 #pragma unroll
-        for (int r = 0; r < GV_ROWS; ++r) {
+        for (int r = 0; r < PK_ROWS; ++r) {
             d2 av = __builtin_nontemporal_load(&arow[r][c]);
             acc[r] += av.x * xv.x + av.y * xv.y;
         }
     }
 #pragma unroll
-    for (int r = 0; r < GV_ROWS; ++r) {
+    for (int r = 0; r < PK_ROWS; ++r) {
         double s2 = block_sum<256>(acc[r], sh);
         if (threadIdx.x == 0 && row0 + r < m) {
             double v = alpha * s2;
@@ -332,19 +336,22 @@ __global__ __launch_bounds__(256) void packed_cols_partial_kernel(int m, int k2,
                                                                   long ldp, const double* __restrict__ x,
                                                                   double* __restrict__ part, long pstride) {
     const int c = blockIdx.x * 256 + threadIdx.x;
-    const int i0 = blockIdx.y * GC_SLAB;
-    const int i1 = min(m, i0 + GC_SLAB);
+    const int i0 = blockIdx.y * PK_SLAB;
+    const int i1 = min(m, i0 + PK_SLAB);
     if (c >= k2) return;
     d2 acc = {0.0, 0.0};
     int i = i0;
-    for (; i + 4 <= i1; i += 4) {
-        d2 a0 = __builtin_nontemporal_load(reinterpret_cast<const d2*>(P + (long)(i + 0) * ldp) + c);
-        d2 a1 = __builtin_nontemporal_load(reinterpret_cast<const d2*>(P + (long)(i + 1) * ldp) + c);
-        d2 a2 = __builtin_nontemporal_load(reinterpret_cast<const d2*>(P + (long)(i + 2) * ldp) + c);
-        d2 a3 = __builtin_nontemporal_load(reinterpret_cast<const d2*>(P + (long)(i + 3) * ldp) + c);
-        double x0 = x[i], x1 = x[i + 1], xx2 = x[i + 2], x3 = x[i + 3];
-        acc.x += a0.x * x0 + a1.x * x1 + a2.x * xx2 + a3.x * x3;
-        acc.y += a0.y * x0 + a1.y * x1 + a2.y * xx2 + a3.y * x3;
+    for (; i + PK_UNROLL <= i1; i += PK_UNROLL) {
+        d2 a[PK_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PK_UNROLL; ++u)
+            a[u] = __builtin_nontemporal_load(reinterpret_cast<const d2*>(P + (long)(i + u) * ldp) + c);
+#pragma unroll
+        for (int u = 0; u < PK_UNROLL; ++u) {
+            const double xv = x[i + u];
+            acc.x += a[u].x * xv;
+            acc.y += a[u].y * xv;
+        }
     }
     for (; i < i1; ++i) {
         d2 a0 = reinterpret_cast<const d2*>(P + (long)i * ldp)[c];
@@ -358,16 +365,18 @@ void packed_rows(hipStream_t st, int m, int k, const double* P, long ldp, const 
                  double beta) {
     if (m <= 0) return;
     int k2 = static_cast<int>(round_up(k, 2) / 2);
-    hipLaunchKernelGGL(packed_rows_kernel, dim3(cdiv(m, GV_ROWS)), dim3(256), 0, st, m, k2, P, ldp, x, y, alpha,
+    hipLaunchKernelGGL(packed_rows_kernel, dim3(cdiv(m, PK_ROWS)), dim3(256), 0, st, m, k2, P, ldp, x, y, alpha,
                        beta);
     WC_LAUNCH_CHECK();
 }
 
+int packed_cols_parts(int m) { return cdiv(m, PK_SLAB); }
+
 void packed_cols_partial(hipStream_t st, int m, int k, const double* P, long ldp, const double* x, double* part) {
     if (k <= 0 || m <= 0) return;
     int k2 = static_cast<int>(round_up(k, 2) / 2);
-    hipLaunchKernelGGL(packed_cols_partial_kernel, dim3(cdiv(k2, 256), gemv_cols_parts(m)), dim3(256), 0, st, m, k2,
-                       P, ldp, x, part, round_up(k, 2));
+    hipLaunchKernelGGL(packed_cols_partial_kernel, dim3(cdiv(k2, 256), packed_cols_parts(m)), dim3(256), 0, st, m,
+                       k2, P, ldp, x, part, round_up(k, 2));
     WC_LAUNCH_CHECK();
 }
 

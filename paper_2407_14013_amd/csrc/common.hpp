@@ -98,8 +98,9 @@ void gemv_cols(hipStream_t st, int m, int k, const double* A, long lda, const do
 
 // The two passes over the packed constraint rows P (m x ldp row-major):
 // packed_rows is y = alpha P x + beta y; packed_cols_partial writes the
-// gemv_cols_parts(m) slab partial sums of P^T x into `part` (row pitch
+// packed_cols_parts(m) slab partial sums of P^T x into `part` (row pitch
 // round_up(k, 2)), to be added in slab order by the caller.
+int packed_cols_parts(int m);
 void packed_rows(hipStream_t st, int m, int k, const double* P, long ldp, const double* x, double* y, double alpha,
                  double beta);
 void packed_cols_partial(hipStream_t st, int m, int k, const double* P, long ldp, const double* x, double* part);

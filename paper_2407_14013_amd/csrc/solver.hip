@@ -78,7 +78,7 @@ static void at_apply(sdp_ctx* c, const double* u, double* Y) {
         prof_begin(c, SDP_K_AT_APPLY, &e);
         packed_cols_partial(c->st, c->m, static_cast<int>(c->N2), c->P, c->ldP, u, c->gpart);
         prof_end(c, SDP_K_AT_APPLY, e, 8.0 * c->m * c->N2 + 8.0 * c->m);
-        at_reduce_unpack(c->st, c->N2, gemv_cols_parts(c->m), c->gpart, round_up(c->N2, 2), c->pj, c->pk, Y, c->n);
+        at_reduce_unpack(c->st, c->N2, packed_cols_parts(c->m), c->gpart, round_up(c->N2, 2), c->pj, c->pk, Y, c->n);
     } else {
         fill(c->st, (long)c->n * c->n, Y, 0.0);
         entry_scatter(c->st, c->m, c->jk, u, Y, c->n);
