@@ -26,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "packed_passes_gaussian_n200_m2400_hbm_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2407_14013_amd", "csrc", "blas.hip")
 METRIC = "Newton-op matvecs/s and IPM time-to-1e-8 gap, FP64 vs mixed prec, 1 GPU"
 WORKLOAD = "gaussian sensing SDP n=200 r=3 m=2400 (dense A, FP64)"
 
@@ -65,6 +67,57 @@ def cpu_baseline(p, budget_s=15.0):
     }
 
 
+def packed_source_digest():
+    """SHA-256 of the source text of the two packed-pass kernels and their launchers."""
+    import hashlib
+
+    src = open(KERNEL_SOURCE).read()
+    a = src.index("constexpr int PK_ROWS")
+    b = src.index("void packed_cols_partial(")
+    b = src.index("\n}\n", b) + 3
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter runs.
+
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are each divided by what the
+    same counter read per byte for a device copy of known size in the same run.
+    None when no record exists or the kernel source changed since it was taken.
+    """
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != packed_source_digest() or kernel not in rec.get("kernels", {}):
+        return None
+    k = rec["kernels"][kernel]
+    return 1024.0 * (k["fetch_kib"] / rec["copy"]["fetch_factor"] + k["write_kib"] / rec["copy"]["write_factor"])
+
+
+def pmc_pass():
+    """Short run for the rocprofv3 counter passes: operator applications plus a copy of known size."""
+    import torch
+
+    import workloads
+    from paper_2407_14013_amd import Context
+
+    torch.cuda.set_device(0)
+    ctx = Context(workloads.config(1))
+    N = ctx.aug_dim()
+    xin = torch.randn(N, dtype=torch.float64, device="cuda")
+    xout = torch.empty_like(xin)
+    for _ in range(10):
+        ctx.newton_apply(xin, xout)
+    src = torch.randn(64 << 20, dtype=torch.float64, device="cuda")  # 512 MiB
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ctx.close()
+    print(f"pmc pass: 10 operator applications, 3 copies of {src.numel() * 8} bytes", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,11 +125,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-loop", type=int, default=200)
+    ap.add_argument("--pmc-pass", action="store_true", help="only the short run profiled for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every instance of this workload fits one MI355X, "
               "and multi-GPU runs are not part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.pmc_pass:
+        pmc_pass()
+        return
 
     import torch
 
@@ -115,6 +172,8 @@ def main():
     avg_ms = kp["ms"] / max(kp["launches"], 1)
     bytes_per = kp["bytes"] / max(kp["launches"], 1)
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9
+    kname = "packed_rows_kernel" if kcls == L.SDP_K_A_APPLY else "packed_cols_partial_kernel"
+    traffic = measured_traffic(kname)
 
     # tight loop of the operator at the final point
     N = ctx.aug_dim()
@@ -161,7 +220,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "avg_launch_ms": avg_ms,
             "launches": kp["launches"],
             "bytes_per_launch": bytes_per,

@@ -215,10 +215,15 @@ sdp_status sdp_set_point(sdp_ctx* ctx, const double* X, const double* y, const d
  */
 sdp_status sdp_get_scaling(sdp_ctx* ctx, double* lam, double* V, int32_t* r, double* tau, double* beta);
 
-/* Kernel classes whose launches can be timed with HIP events. */
+/*
+ * Kernel classes whose launches can be timed with HIP events.  The two dense
+ * constraint passes are timed from the kernel's own start and end timestamps
+ * (events handed to the launch); GEMM and NEWTON are bracketed by events
+ * recorded on the stream, which adds a few microseconds of dispatch per launch.
+ */
 enum {
     SDP_K_A_APPLY = 0,   /* A(M): packed dense rows times the weighted packed M */
-    SDP_K_AT_APPLY = 1,  /* A^T(u): column sums of the packed rows (both passes) */
+    SDP_K_AT_APPLY = 1,  /* A^T(u): slab partial column sums of the packed rows */
     SDP_K_GEMM = 2,      /* every FP64 GEMM launch */
     SDP_K_NEWTON = 3,    /* a whole sdp_newton_apply */
     SDP_K_COUNT = 4

@@ -1,5 +1,7 @@
 // FP64 dense kernels for gfx950: MFMA GEMM, HBM-streaming GEMVs over
 // row-major matrices, deterministic reductions and element-wise helpers.
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 
 namespace wc {
@@ -362,21 +364,22 @@ __global__ __launch_bounds__(256) void packed_cols_partial_kernel(int m, int k2,
 }
 
 void packed_rows(hipStream_t st, int m, int k, const double* P, long ldp, const double* x, double* y, double alpha,
-                 double beta) {
+                 double beta, hipEvent_t t0, hipEvent_t t1) {
     if (m <= 0) return;
     int k2 = static_cast<int>(round_up(k, 2) / 2);
-    hipLaunchKernelGGL(packed_rows_kernel, dim3(cdiv(m, PK_ROWS)), dim3(256), 0, st, m, k2, P, ldp, x, y, alpha,
-                       beta);
+    hipExtLaunchKernelGGL(packed_rows_kernel, dim3(cdiv(m, PK_ROWS)), dim3(256), 0, st, t0, t1, 0, m, k2, P, ldp, x,
+                          y, alpha, beta);
     WC_LAUNCH_CHECK();
 }
 
 int packed_cols_parts(int m) { return cdiv(m, PK_SLAB); }
 
-void packed_cols_partial(hipStream_t st, int m, int k, const double* P, long ldp, const double* x, double* part) {
+void packed_cols_partial(hipStream_t st, int m, int k, const double* P, long ldp, const double* x, double* part,
+                         hipEvent_t t0, hipEvent_t t1) {
     if (k <= 0 || m <= 0) return;
     int k2 = static_cast<int>(round_up(k, 2) / 2);
-    hipLaunchKernelGGL(packed_cols_partial_kernel, dim3(cdiv(k2, 256), packed_cols_parts(m)), dim3(256), 0, st, m,
-                       k2, P, ldp, x, part, round_up(k, 2));
+    hipExtLaunchKernelGGL(packed_cols_partial_kernel, dim3(cdiv(k2, 256), packed_cols_parts(m)), dim3(256), 0, st,
+                          t0, t1, 0, m, k2, P, ldp, x, part, round_up(k, 2));
     WC_LAUNCH_CHECK();
 }
 

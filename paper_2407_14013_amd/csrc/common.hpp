@@ -99,11 +99,13 @@ void gemv_cols(hipStream_t st, int m, int k, const double* A, long lda, const do
 // The two passes over the packed constraint rows P (m x ldp row-major):
 // packed_rows is y = alpha P x + beta y; packed_cols_partial writes the
 // packed_cols_parts(m) slab partial sums of P^T x into `part` (row pitch
-// round_up(k, 2)), to be added in slab order by the caller.
+// round_up(k, 2)), to be added in slab order by the caller.  Non-null events
+// t0 / t1 receive the kernel's own start and end timestamps.
 int packed_cols_parts(int m);
 void packed_rows(hipStream_t st, int m, int k, const double* P, long ldp, const double* x, double* y, double alpha,
-                 double beta);
-void packed_cols_partial(hipStream_t st, int m, int k, const double* P, long ldp, const double* x, double* part);
+                 double beta, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+void packed_cols_partial(hipStream_t st, int m, int k, const double* P, long ldp, const double* x, double* part,
+                         hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 // Deterministic reductions into out[0] (device).  `part` holds >= 1024 doubles.
 void dot(hipStream_t st, long n, const double* x, const double* y, double* out, double* part);

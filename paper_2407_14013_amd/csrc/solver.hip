@@ -44,6 +44,20 @@ void prof_end(sdp_ctx* c, int k, hipEvent_t e0, double bytes) {
     c->prof[k].launches += 1;
     c->prof[k].bytes += bytes;
 }
+// Event pair that a launch fills with the kernel's own start / end timestamps.
+static void prof_kernel_events(sdp_ctx* c, int k, hipEvent_t* e0, hipEvent_t* e1) {
+    *e0 = *e1 = nullptr;
+    if (!(c->prof_mask & (1 << k))) return;
+    WC_HIP(hipEventCreateWithFlags(e0, hipEventDisableSystemFence));
+    WC_HIP(hipEventCreateWithFlags(e1, hipEventDisableSystemFence));
+}
+static void prof_kernel_done(sdp_ctx* c, int k, hipEvent_t e0, hipEvent_t e1, double bytes) {
+    if (e0 == nullptr) return;
+    c->prof[k].ev.push_back(e0);
+    c->prof[k].ev.push_back(e1);
+    c->prof[k].launches += 1;
+    c->prof[k].bytes += bytes;
+}
 void prof_collect(sdp_ctx* c) {
     WC_HIP(hipStreamSynchronize(c->st));
     for (auto& p : c->prof) {
@@ -62,10 +76,10 @@ void prof_collect(sdp_ctx* c) {
 static void a_apply(sdp_ctx* c, const double* M, double* out, double alpha, double beta) {
     if (c->kind == SDP_A_DENSE) {
         pack_weighted(c->st, c->n, c->N2, c->ldP, M, c->n, c->pj, c->pk, c->mw);
-        hipEvent_t e;
-        prof_begin(c, SDP_K_A_APPLY, &e);
-        packed_rows(c->st, c->m, static_cast<int>(c->N2), c->P, c->ldP, c->mw, out, alpha, beta);
-        prof_end(c, SDP_K_A_APPLY, e, 8.0 * c->m * c->N2 + 8.0 * c->N2 + 8.0 * c->m);  // P, x, y
+        hipEvent_t e0, e1;
+        prof_kernel_events(c, SDP_K_A_APPLY, &e0, &e1);
+        packed_rows(c->st, c->m, static_cast<int>(c->N2), c->P, c->ldP, c->mw, out, alpha, beta, e0, e1);
+        prof_kernel_done(c, SDP_K_A_APPLY, e0, e1, 8.0 * c->m * c->N2 + 8.0 * c->N2 + 8.0 * c->m);  // P, x, y
     } else {
         entry_gather(c->st, c->m, c->jk, M, c->n, out, alpha, beta);
     }
@@ -74,10 +88,10 @@ static void a_apply(sdp_ctx* c, const double* M, double* out, double alpha, doub
 // Y = A^T(u), full symmetric n x n
 static void at_apply(sdp_ctx* c, const double* u, double* Y) {
     if (c->kind == SDP_A_DENSE) {
-        hipEvent_t e;
-        prof_begin(c, SDP_K_AT_APPLY, &e);
-        packed_cols_partial(c->st, c->m, static_cast<int>(c->N2), c->P, c->ldP, u, c->gpart);
-        prof_end(c, SDP_K_AT_APPLY, e, 8.0 * c->m * c->N2 + 8.0 * c->m);
+        hipEvent_t e0, e1;
+        prof_kernel_events(c, SDP_K_AT_APPLY, &e0, &e1);
+        packed_cols_partial(c->st, c->m, static_cast<int>(c->N2), c->P, c->ldP, u, c->gpart, e0, e1);
+        prof_kernel_done(c, SDP_K_AT_APPLY, e0, e1, 8.0 * c->m * c->N2 + 8.0 * c->m);
         at_reduce_unpack(c->st, c->N2, packed_cols_parts(c->m), c->gpart, round_up(c->N2, 2), c->pj, c->pk, Y, c->n);
     } else {
         fill(c->st, (long)c->n * c->n, Y, 0.0);
