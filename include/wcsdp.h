@@ -91,11 +91,24 @@ typedef struct sdp_problem {
  *  solver       SDP_SOLVER_PCG (Corollary pcg) or SDP_SOLVER_MINRES (Corollary minres) [PCG]
  *  inner_tol    PCG stops when ||r_u|| <= inner_tol * ||r_u(0)|| [1e-10]
  *  inner_maxit  [500]
- *  inner_prec   precision of the inner operator's GEMMs [SDP_PREC_F64]
+ *  inner_prec   precision of the inner operator [SDP_PREC_F64].  SDP_PREC_F32:
+ *               the A E A^T block of the augmented operator with E Y E on the
+ *               FP32 matrix cores and, for dense A, the two constraint passes
+ *               over an FP32 copy of the packed rows (FP64 accumulation);
+ *               SDP_PREC_BF16: the same with the GEMM operands in BF16 (FP32
+ *               accumulation; the constraint data stays FP32).  The
+ *               off-diagonal and bottom blocks stay FP64.  The Newton step is
+ *               brought to inner_tol by FP64 iterative refinement; the scaling
+ *               point, its eigen-decomposition, the preconditioner, residuals
+ *               and step lengths stay FP64.
  *  max_refine   FP64 refinement sweeps around a low-precision inner solve [8]
+ *  refine_tol   relative residual reduction asked of each low-precision PCG
+ *               run inside a refinement sweep [1e-4]
  *  gap_tol, feas_tol   stopping tolerances of the interior-point method [1e-8]
  *  max_ipm_iter [100]
  *  step_frac    fraction of the step to the boundary [0.98]
+ *  verbose      0 silent, 1 one line per interior-point iteration, 2 also one
+ *               line per Krylov iteration (stderr) [0]
  */
 typedef struct sdp_options {
     int32_t rank_max;
@@ -111,6 +124,7 @@ typedef struct sdp_options {
     int32_t max_ipm_iter;
     double step_frac;
     int32_t verbose;
+    double refine_tol;
 } sdp_options;
 
 typedef struct sdp_inner_stats {
@@ -136,9 +150,10 @@ typedef struct sdp_result {
     int32_t status;
     int32_t iterations;
     int64_t pcg_iterations;
-    int64_t newton_matvecs;  /* applications of the augmented operator */
+    int64_t newton_matvecs;  /* FP64 applications of the augmented operator */
     double pobj, dobj, relgap, pinf, dinf, mu;
     double time_ms;
+    int64_t lp_matvecs;      /* applications of its low-precision form (mixed mode) */
 } sdp_result;
 
 /* Fill *opt with the defaults listed above. */
@@ -171,6 +186,14 @@ int64_t sdp_aug_dim(sdp_ctx* ctx);
  * not aliased.
  */
 sdp_status sdp_newton_apply(sdp_ctx* ctx, const double* uv_in, double* uv_out);
+
+/*
+ * The same product in a chosen precision: SDP_PREC_F64 is sdp_newton_apply;
+ * otherwise prec must equal the inner_prec the context was set up with, and
+ * the product is the low-precision form used inside the refinement sweeps
+ * (see sdp_options.inner_prec).  Returns SDP_EINVAL for any other prec.
+ */
+sdp_status sdp_newton_apply_prec(sdp_ctx* ctx, int32_t prec, const double* uv_in, double* uv_out);
 
 /*
  * Solve eq. Newt-eps at the current scaling point: given b_tilde (m) and the

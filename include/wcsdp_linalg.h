@@ -60,6 +60,24 @@ int32_t wc_dtrtri(void* stream, int32_t n, const double* L, int32_t ldl, double*
 int32_t wc_djacobi_svd(void* stream, int32_t n, double* A, int32_t lda, double* V, int32_t ldv, double* sigma,
                        double tol, int32_t max_sweeps, int32_t* sweeps_host);
 
+/*
+ * Low-precision GEMM of the mixed-precision inner operator: C = A B for
+ * column-major A (m x k) and B (k x n) given in FP32 (prec_in = 1) or as BF16
+ * bit patterns (prec_in = 2, uint16 per element), multiplied on the matrix
+ * cores with FP32 accumulation.  out_kind 0 writes C as FP32, 1 as BF16
+ * (round to nearest even), 2 adds the result to an FP64 C (C += A B), 3
+ * writes C as FP64.
+ */
+int32_t wc_gemm_lp(void* stream, int32_t prec_in, int32_t out_kind, int32_t m, int32_t n, int32_t k, const void* A,
+                   int32_t lda, const void* B, int32_t ldb, void* C, int32_t ldc);
+
+/*
+ * B = A rounded to FP32 (prec = 1, round to nearest) or to BF16 (prec = 2,
+ * round to FP32 then to nearest even), column-major rows x cols.
+ */
+int32_t wc_to_lowp(void* stream, int32_t prec, int32_t rows, int32_t cols, const double* A, int32_t lda, void* B,
+                   int32_t ldb);
+
 #ifdef __cplusplus
 }
 #endif

@@ -56,6 +56,7 @@ class SdpOptions(C.Structure):
         ("max_ipm_iter", C.c_int32),
         ("step_frac", C.c_double),
         ("verbose", C.c_int32),
+        ("refine_tol", C.c_double),
     ]
 
 
@@ -105,6 +106,7 @@ class SdpResult(C.Structure):
         ("dinf", C.c_double),
         ("mu", C.c_double),
         ("time_ms", C.c_double),
+        ("lp_matvecs", C.c_int64),
     ]
 
 
@@ -122,6 +124,7 @@ _SIGNATURES = [
     ("sdp_last_error", C.c_char_p, [C.c_void_p]),
     ("sdp_aug_dim", C.c_int64, [C.c_void_p]),
     ("sdp_newton_apply", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("sdp_newton_apply_prec", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     ("sdp_inner_solve", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SdpInnerStats)]),
     ("sdp_ipm_step", C.c_int32, [C.c_void_p, C.POINTER(SdpStepStats)]),
     ("sdp_solve", C.c_int32, [C.c_void_p, C.POINTER(SdpResult)]),
@@ -138,6 +141,10 @@ _SIGNATURES = [
     ("wc_dtrtri", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
     ("wc_djacobi_svd", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                    C.c_double, C.c_int32, C.POINTER(C.c_int32)]),
+    ("wc_gemm_lp", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                               C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
+    ("wc_to_lowp", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                               C.c_int32]),
 ]
 
 

@@ -129,11 +129,17 @@ class Context:
             self._check(int(v))
         return int(v)
 
-    def newton_apply(self, uv_in: torch.Tensor, uv_out: torch.Tensor | None = None) -> torch.Tensor:
+    def newton_apply(self, uv_in: torch.Tensor, uv_out: torch.Tensor | None = None, prec: int | None = None):
+        """K [u; v] (eq. augsys); prec selects FP64 (default) or the context's low-precision form."""
         N = self.aug_dim()
         if uv_out is None:
             uv_out = torch.empty(N, dtype=torch.float64, device=uv_in.device)
-        self._check(self._lib.sdp_newton_apply(self._ctx, _dptr(uv_in, "uv_in", N), _dptr(uv_out, "uv_out", N)))
+        if prec is None:
+            st = self._lib.sdp_newton_apply(self._ctx, _dptr(uv_in, "uv_in", N), _dptr(uv_out, "uv_out", N))
+        else:
+            st = self._lib.sdp_newton_apply_prec(self._ctx, int(prec), _dptr(uv_in, "uv_in", N),
+                                                 _dptr(uv_out, "uv_out", N))
+        self._check(st)
         return uv_out
 
     def inner_solve(self, b_tilde: torch.Tensor, C_tilde: torch.Tensor, raise_on_notconv: bool = True):

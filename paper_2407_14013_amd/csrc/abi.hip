@@ -6,6 +6,7 @@
 #include "../../include/wcsdp.h"
 #include "../../include/wcsdp_linalg.h"
 #include "sdp_kernels.hpp"
+#include "lowprec.hpp"
 #include "solver.hpp"
 
 namespace {
@@ -63,6 +64,7 @@ void sdp_default_options(sdp_options* o) {
     o->max_ipm_iter = 100;
     o->step_frac = 0.98;
     o->verbose = 0;
+    o->refine_tol = 1e-4;
 }
 
 sdp_status sdp_setup(const sdp_problem* prob, const sdp_options* opt, void* hip_stream, sdp_ctx** out) {
@@ -84,7 +86,11 @@ sdp_status sdp_setup(const sdp_problem* prob, const sdp_options* opt, void* hip_
             wc::require(opt->inner_maxit >= 1 && opt->max_ipm_iter >= 0, "iteration limits must be positive");
             wc::require(opt->step_frac > 0 && opt->step_frac < 1, "step_frac must lie in (0, 1)");
             wc::require(opt->solver == SDP_SOLVER_PCG, "only the PCG inner solver is available");
-            wc::require(opt->inner_prec == SDP_PREC_F64, "only FP64 inner precision is available");
+            wc::require(opt->inner_prec == SDP_PREC_F64 || opt->inner_prec == SDP_PREC_F32 ||
+                            opt->inner_prec == SDP_PREC_BF16,
+                        "inner_prec must be SDP_PREC_F64, SDP_PREC_F32 or SDP_PREC_BF16");
+            wc::require(opt->max_refine >= 0, "max_refine must be non-negative");
+            wc::require(opt->refine_tol >= 0 && opt->refine_tol < 1, "refine_tol must lie in [0, 1)");
         }
         wc::setup(c, prob, opt, static_cast<hipStream_t>(hip_stream));
         return SDP_OK;
@@ -121,6 +127,20 @@ sdp_status sdp_newton_apply(sdp_ctx* ctx, const double* uv_in, double* uv_out) {
     return guarded(ctx, [&]() {
         wc::require(uv_in && uv_out && uv_in != uv_out, "uv_in / uv_out must be distinct device pointers");
         wc::newton_apply(ctx, uv_in, uv_out);
+        return SDP_OK;
+    });
+}
+
+sdp_status sdp_newton_apply_prec(sdp_ctx* ctx, int32_t prec, const double* uv_in, double* uv_out) {
+    if (!ctx) return SDP_EINVAL;
+    return guarded(ctx, [&]() {
+        wc::require(uv_in && uv_out && uv_in != uv_out, "uv_in / uv_out must be distinct device pointers");
+        if (prec == SDP_PREC_F64) {
+            wc::newton_apply(ctx, uv_in, uv_out);
+        } else {
+            wc::require(prec == ctx->opt.inner_prec, "prec must be SDP_PREC_F64 or the context's inner_prec");
+            wc::newton_apply_lowp(ctx, uv_in, uv_out);
+        }
         return SDP_OK;
     });
 }
@@ -224,6 +244,33 @@ int32_t wc_dgemm(void* stream, char transa, char transb, int32_t m, int32_t n, i
         wc::require(lda >= std::max(1, ta ? k : m), "lda too small");
         wc::require(ldb >= std::max(1, tb ? n : k), "ldb too small");
         wc::dgemm(static_cast<hipStream_t>(stream), ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+        return (int32_t)0;
+    });
+}
+
+int32_t wc_gemm_lp(void* stream, int32_t prec_in, int32_t out_kind, int32_t m, int32_t n, int32_t k, const void* A,
+                   int32_t lda, const void* B, int32_t ldb, void* C, int32_t ldc) {
+    return guarded_la([&]() {
+        wc::require(prec_in == 1 || prec_in == 2, "prec_in must be 1 (FP32) or 2 (BF16)");
+        wc::require(out_kind >= 0 && out_kind <= 3, "out_kind must be 0, 1, 2 or 3");
+        const wc::LpOut out = out_kind == 0   ? wc::LpOut::F32
+                              : out_kind == 1 ? wc::LpOut::BF16
+                              : out_kind == 2 ? wc::LpOut::ADD_F64
+                                              : wc::LpOut::F64;
+        wc::lp_gemm_nn(static_cast<hipStream_t>(stream), prec_in == 1 ? wc::Lp::F32 : wc::Lp::BF16, out, m, n, k, A,
+                       lda, B, ldb, C, ldc);
+        return (int32_t)0;
+    });
+}
+
+int32_t wc_to_lowp(void* stream, int32_t prec, int32_t rows, int32_t cols, const double* A, int32_t lda, void* B,
+                   int32_t ldb) {
+    return guarded_la([&]() {
+        wc::require(prec == 1 || prec == 2, "prec must be 1 (FP32) or 2 (BF16)");
+        wc::require(rows >= 0 && cols >= 0 && lda >= std::max(1, rows) && ldb >= std::max(1, rows),
+                    "bad shape or leading dimension");
+        wc::to_lowp(static_cast<hipStream_t>(stream), prec == 1 ? wc::Lp::F32 : wc::Lp::BF16, rows, cols, A, lda, B,
+                    ldb);
         return (int32_t)0;
     });
 }

@@ -1,0 +1,388 @@
+// Low-precision pieces of the inner operator for the mixed-precision mode.
+//
+// The W-sandwich products E Y E of the augmented operator (Section 5) run on
+// the gfx950 matrix cores in FP32 (v_mfma_f32_16x16x4_f32) or BF16
+// (v_mfma_f32_16x16x32_bf16), both accumulating in FP32; the dense constraint
+// passes read an FP32 copy of the packed rows and accumulate in FP64.  The
+// outer refinement that restores FP64 accuracy lives in the solver.
+//
+// MFMA 16x16 lane layout (both instructions, verified on gfx950): lane l
+// supplies row l % 16 of A and column l % 16 of B at k-group l / 16; output
+// element v of lane l is D[4 (l / 16) + v][l % 16].
+#include "lowprec.hpp"
+
+namespace wc {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned short v8us __attribute__((ext_vector_type(8)));
+typedef double ld2 __attribute__((ext_vector_type(2)));
+typedef float lf4 __attribute__((ext_vector_type(4)));
+typedef float lf2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<unsigned short>((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<unsigned short>(u >> 16);
+}
+
+template <int BS>
+__device__ __forceinline__ double lp_block_sum(double v, double* sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < BS / 64; ++i) s += sh[i];
+    return s;
+}
+
+// ---- GEMM epilogue -----------------------------------------------------------------
+template <LpOut OUT>
+__device__ __forceinline__ void lp_store(void* C, long ldc, int M, int N, int r0, int c0, const v4f& acc) {
+    const int lane = threadIdx.x & 63;
+    const int col = c0 + (lane & 15);
+    if (col >= N) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = r0 + 4 * (lane >> 4) + v;
+        if (row >= M) continue;
+        const long o = row + (long)col * ldc;
+        if constexpr (OUT == LpOut::F32) static_cast<float*>(C)[o] = acc[v];
+        else if constexpr (OUT == LpOut::BF16) static_cast<unsigned short*>(C)[o] = bf16_rne(acc[v]);
+        else if constexpr (OUT == LpOut::F64) static_cast<double*>(C)[o] = static_cast<double>(acc[v]);
+        else static_cast<double*>(C)[o] += static_cast<double>(acc[v]);
+    }
+}
+
+// 64 x 64 output tile per workgroup, four waves in a 2 x 2 grid, each wave a
+// 2 x 2 block of 16 x 16 MFMA tiles; K staged through LDS 32 at a time.
+constexpr int LT = 64;
+constexpr int LK = 32;
+
+template <LpOut OUT>
+__global__ __launch_bounds__(256) void sgemm_nn_kernel(int M, int N, int K, const float* __restrict__ A, long lda,
+                                                       const float* __restrict__ B, long ldb, void* __restrict__ C,
+                                                       long ldc) {
+    __shared__ float As[LT][LK + 1];  // [row][k]
+    __shared__ float Bs[LT][LK + 1];  // [col][k]
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv & 1, wn = wv >> 1;
+    const int row0 = blockIdx.x * LT, col0 = blockIdx.y * LT;
+    v4f acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += LK) {
+        {
+            const int i = tid & 63, gi = row0 + i;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int kk = (tid >> 6) + 4 * t, gk = k0 + kk;
+                As[i][kk] = (gi < M && gk < K) ? A[gi + (long)gk * lda] : 0.f;
+            }
+        }
+        {
+            const int kk = tid & 31, gk = k0 + kk;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int j = (tid >> 5) + 8 * t, gj = col0 + j;
+                Bs[j][kk] = (gk < K && gj < N) ? B[gk + (long)gj * ldb] : 0.f;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < LK / 4; ++s) {
+            const int kk = 4 * s + (lane >> 4);
+            float a[2], b[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) a[x] = As[wm * 32 + x * 16 + (lane & 15)][kk];
+#pragma unroll
+            for (int y = 0; y < 2; ++y) b[y] = Bs[wn * 32 + y * 16 + (lane & 15)][kk];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x], b[y], acc[x][y], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+            lp_store<OUT>(C, ldc, M, N, row0 + wm * 32 + x * 16, col0 + wn * 32 + y * 16, acc[x][y]);
+}
+
+template <LpOut OUT>
+__global__ __launch_bounds__(256) void bgemm_nn_kernel(int M, int N, int K, const unsigned short* __restrict__ A,
+                                                       long lda, const unsigned short* __restrict__ B, long ldb,
+                                                       void* __restrict__ C, long ldc) {
+    // rows padded to 40 halves (80 bytes) so each lane's 8-element k-group is a 16-byte aligned read
+    __shared__ __attribute__((aligned(16))) unsigned short As[LT][LK + 8];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[LT][LK + 8];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv & 1, wn = wv >> 1;
+    const int row0 = blockIdx.x * LT, col0 = blockIdx.y * LT;
+    v4f acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += LK) {
+        {
+            const int i = tid & 63, gi = row0 + i;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int kk = (tid >> 6) + 4 * t, gk = k0 + kk;
+                As[i][kk] = (gi < M && gk < K) ? A[gi + (long)gk * lda] : static_cast<unsigned short>(0);
+            }
+        }
+        {
+            const int kk = tid & 31, gk = k0 + kk;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int j = (tid >> 5) + 8 * t, gj = col0 + j;
+                Bs[j][kk] = (gk < K && gj < N) ? B[gk + (long)gj * ldb] : static_cast<unsigned short>(0);
+            }
+        }
+        __syncthreads();
+        const int kg = 8 * (lane >> 4);
+        v8us a[2], b[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) a[x] = *reinterpret_cast<const v8us*>(&As[wm * 32 + x * 16 + (lane & 15)][kg]);
+#pragma unroll
+        for (int y = 0; y < 2; ++y) b[y] = *reinterpret_cast<const v8us*>(&Bs[wn * 32 + y * 16 + (lane & 15)][kg]);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a[x]),
+                                                                    __builtin_bit_cast(v8bf, b[y]), acc[x][y], 0, 0,
+                                                                    0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+            lp_store<OUT>(C, ldc, M, N, row0 + wm * 32 + x * 16, col0 + wn * 32 + y * 16, acc[x][y]);
+}
+
+template <LpOut OUT>
+static void lp_gemm_launch(hipStream_t st, Lp in, int M, int N, int K, const void* A, long lda, const void* B,
+                           long ldb, void* C, long ldc) {
+    dim3 grid(cdiv(M, LT), cdiv(N, LT));
+    if (in == Lp::F32)
+        hipLaunchKernelGGL(sgemm_nn_kernel<OUT>, grid, dim3(256), 0, st, M, N, K, static_cast<const float*>(A), lda,
+                           static_cast<const float*>(B), ldb, C, ldc);
+    else
+        hipLaunchKernelGGL(bgemm_nn_kernel<OUT>, grid, dim3(256), 0, st, M, N, K,
+                           static_cast<const unsigned short*>(A), lda, static_cast<const unsigned short*>(B), ldb, C,
+                           ldc);
+    WC_LAUNCH_CHECK();
+}
+
+void lp_gemm_nn(hipStream_t st, Lp in, LpOut out, int M, int N, int K, const void* A, long lda, const void* B,
+                long ldb, void* C, long ldc) {
+    require(M >= 0 && N >= 0 && K >= 0, "lp_gemm: negative size");
+    require(lda >= std::max(1, M) && ldb >= std::max(1, K) && ldc >= std::max(1, M), "lp_gemm: bad leading dimension");
+    if (M == 0 || N == 0) return;
+    require(cdiv(N, LT) <= 65535, "lp_gemm: N too large for the grid");
+    switch (out) {
+        case LpOut::F32: lp_gemm_launch<LpOut::F32>(st, in, M, N, K, A, lda, B, ldb, C, ldc); break;
+        case LpOut::BF16: lp_gemm_launch<LpOut::BF16>(st, in, M, N, K, A, lda, B, ldb, C, ldc); break;
+        case LpOut::F64: lp_gemm_launch<LpOut::F64>(st, in, M, N, K, A, lda, B, ldb, C, ldc); break;
+        case LpOut::ADD_F64: lp_gemm_launch<LpOut::ADD_F64>(st, in, M, N, K, A, lda, B, ldb, C, ldc); break;
+    }
+}
+
+// ---- conversions ---------------------------------------------------------------------
+template <Lp P>
+__global__ void to_lowp_kernel(int rows, int cols, const double* __restrict__ A, long lda, void* __restrict__ B,
+                               long ldb) {
+    const long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)rows * cols) return;
+    const int i = static_cast<int>(t % rows), j = static_cast<int>(t / rows);
+    const double v = A[i + (long)j * lda];
+    if constexpr (P == Lp::F32) static_cast<float*>(B)[i + (long)j * ldb] = static_cast<float>(v);
+    else static_cast<unsigned short*>(B)[i + (long)j * ldb] = bf16_rne(static_cast<float>(v));
+}
+void to_lowp(hipStream_t st, Lp p, int rows, int cols, const double* A, long lda, void* B, long ldb) {
+    const long cnt = (long)rows * cols;
+    if (cnt <= 0) return;
+    // double -> float rounds to nearest; float -> bf16 rounds to nearest even.
+    // (The two-step rounding to BF16 can differ from a direct one only on
+    // exact float ties, which does not matter for an approximate operator.)
+    if (p == Lp::F32)
+        hipLaunchKernelGGL(to_lowp_kernel<Lp::F32>, dim3(cdiv(cnt, 256)), dim3(256), 0, st, rows, cols, A, lda, B, ldb);
+    else
+        hipLaunchKernelGGL(to_lowp_kernel<Lp::BF16>, dim3(cdiv(cnt, 256)), dim3(256), 0, st, rows, cols, A, lda, B,
+                           ldb);
+    WC_LAUNCH_CHECK();
+}
+
+__global__ void to_f32_kernel(long n, const double* __restrict__ x, float* __restrict__ y) {
+    const long t = blockIdx.x * 256L + threadIdx.x;
+    if (t < n) y[t] = static_cast<float>(x[t]);
+}
+void to_f32(hipStream_t st, long count, const double* x, float* y) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(count, 256)), dim3(256), 0, st, count, x, y);
+    WC_LAUNCH_CHECK();
+}
+
+// ---- packed constraint passes over FP32 rows ---------------------------------------------
+constexpr int PF_ROWS = 4;     // rows per workgroup of the A(M) pass
+constexpr int PF_SLAB = 64;    // row slab of the A^T(u) pass
+constexpr int PF_UNROLL = 8;   // rows in flight per thread in the A^T(u) pass
+
+__global__ __launch_bounds__(256) void packed_rows_f32_kernel(int m, int k4, const float* __restrict__ P, long ldp,
+                                                              const float* __restrict__ x, double* __restrict__ y,
+                                                              double alpha, double beta) {
+    __shared__ double sh[4];
+    const int row0 = blockIdx.x * PF_ROWS;
+    double acc[PF_ROWS];
+#pragma unroll
+    for (int r = 0; r < PF_ROWS; ++r) acc[r] = 0.0;
+    const lf4* x4 = reinterpret_cast<const lf4*>(x);
+    const lf4* arow[PF_ROWS];
+#pragma unroll
+    for (int r = 0; r < PF_ROWS; ++r) {
+        const int row = row0 + r < m ? row0 + r : m - 1;
+        arow[r] = reinterpret_cast<const lf4*>(P + (long)row * ldp);
+    }
+    for (int c = threadIdx.x; c < k4; c += 256) {
+        const lf4 xv = x4[c];
+#pragma unroll
+        for (int r = 0; r < PF_ROWS; ++r) {
+            const lf4 av = __builtin_nontemporal_load(&arow[r][c]);
+            acc[r] += (double)av.x * xv.x + (double)av.y * xv.y + (double)av.z * xv.z + (double)av.w * xv.w;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < PF_ROWS; ++r) {
+        const double s = lp_block_sum<256>(acc[r], sh);
+        if (threadIdx.x == 0 && row0 + r < m) {
+            const double v = alpha * s;
+            y[row0 + r] = (beta == 0.0) ? v : v + beta * y[row0 + r];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void packed_cols_partial_f32_kernel(int m, int k4, const float* __restrict__ P,
+                                                                      long ldp, const double* __restrict__ x,
+                                                                      double* __restrict__ part, long pstride) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int i0 = blockIdx.y * PF_SLAB;
+    const int i1 = min(m, i0 + PF_SLAB);
+    if (c >= k4) return;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = i0;
+    for (; i + PF_UNROLL <= i1; i += PF_UNROLL) {
+        lf4 a[PF_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PF_UNROLL; ++u)
+            a[u] = __builtin_nontemporal_load(reinterpret_cast<const lf4*>(P + (long)(i + u) * ldp) + c);
+#pragma unroll
+        for (int u = 0; u < PF_UNROLL; ++u) {
+            const double xv = x[i + u];
+            a0 += a[u].x * xv;
+            a1 += a[u].y * xv;
+            a2 += a[u].z * xv;
+            a3 += a[u].w * xv;
+        }
+    }
+    for (; i < i1; ++i) {
+        const lf4 a = reinterpret_cast<const lf4*>(P + (long)i * ldp)[c];
+        const double xv = x[i];
+        a0 += a.x * xv;
+        a1 += a.y * xv;
+        a2 += a.z * xv;
+        a3 += a.w * xv;
+    }
+    ld2* out = reinterpret_cast<ld2*>(part + blockIdx.y * pstride + 4L * c);
+    out[0] = ld2{a0, a1};
+    out[1] = ld2{a2, a3};
+}
+
+int packed_cols_parts_f32(int m) { return cdiv(m, PF_SLAB); }
+
+void packed_rows_f32(hipStream_t st, int m, int k, const float* P, long ldp, const float* x, double* y,
+                     double alpha, double beta) {
+    if (m <= 0) return;
+    require(ldp % 4 == 0, "packed_rows_f32: row pitch must be a multiple of 4");
+    const int k4 = static_cast<int>(round_up(k, 4) / 4);
+    hipLaunchKernelGGL(packed_rows_f32_kernel, dim3(cdiv(m, PF_ROWS)), dim3(256), 0, st, m, k4, P, ldp, x, y, alpha,
+                       beta);
+    WC_LAUNCH_CHECK();
+}
+
+void packed_cols_partial_f32(hipStream_t st, int m, int k, const float* P, long ldp, const double* x, double* part) {
+    if (k <= 0 || m <= 0) return;
+    require(ldp % 4 == 0, "packed_cols_partial_f32: row pitch must be a multiple of 4");
+    const int k4 = static_cast<int>(round_up(k, 4) / 4);
+    hipLaunchKernelGGL(packed_cols_partial_f32_kernel, dim3(cdiv(k4, 256), packed_cols_parts_f32(m)), dim3(256), 0,
+                       st, m, k4, P, ldp, x, part, round_up(k, 4));
+    WC_LAUNCH_CHECK();
+}
+
+__global__ void pack_weighted_f32_kernel(long N2, long ldp, const double* __restrict__ M, long ldm,
+                                         const int* __restrict__ pj, const int* __restrict__ pk,
+                                         float* __restrict__ mw) {
+    const long p = blockIdx.x * 256L + threadIdx.x;
+    if (p >= ldp) return;
+    double v = 0.0;
+    if (p < N2) {
+        const int j = pj[p], k = pk[p];
+        v = (j == k) ? M[j + (long)j * ldm] : (M[j + (long)k * ldm] + M[k + (long)j * ldm]);
+    }
+    mw[p] = static_cast<float>(v);
+}
+void pack_weighted_f32(hipStream_t st, long N2, long ldp, const double* M, long ldm, const int* pj, const int* pk,
+                       float* mw) {
+    hipLaunchKernelGGL(pack_weighted_f32_kernel, dim3(cdiv(ldp, 256)), dim3(256), 0, st, N2, ldp, M, ldm, pj, pk, mw);
+    WC_LAUNCH_CHECK();
+}
+
+template <Lp P>
+__global__ void at_reduce_unpack_lp_kernel(long N2, int nparts, const double* __restrict__ part, long pstride,
+                                           const int* __restrict__ pj, const int* __restrict__ pk,
+                                           double* __restrict__ Y, long ldy, void* __restrict__ Ylp) {
+    const long p = blockIdx.x * 256L + threadIdx.x;
+    if (p >= N2) return;
+    double s = 0.0;
+    for (int q = 0; q < nparts; ++q) s += part[q * pstride + p];
+    const int j = pj[p], k = pk[p];
+    const long o1 = j + (long)k * ldy, o2 = k + (long)j * ldy;
+    if (Y) {
+        Y[o1] = s;
+        Y[o2] = s;
+    }
+    if constexpr (P == Lp::F32) {
+        static_cast<float*>(Ylp)[o1] = static_cast<float>(s);
+        static_cast<float*>(Ylp)[o2] = static_cast<float>(s);
+    } else {
+        const unsigned short h = bf16_rne(static_cast<float>(s));
+        static_cast<unsigned short*>(Ylp)[o1] = h;
+        static_cast<unsigned short*>(Ylp)[o2] = h;
+    }
+}
+void at_reduce_unpack_lp(hipStream_t st, Lp p, long N2, int nparts, const double* part, long pstride, const int* pj,
+                         const int* pk, double* Y, long ldy, void* Ylp) {
+    if (N2 <= 0) return;
+    if (p == Lp::F32)
+        hipLaunchKernelGGL(at_reduce_unpack_lp_kernel<Lp::F32>, dim3(cdiv(N2, 256)), dim3(256), 0, st, N2, nparts,
+                           part, pstride, pj, pk, Y, ldy, Ylp);
+    else
+        hipLaunchKernelGGL(at_reduce_unpack_lp_kernel<Lp::BF16>, dim3(cdiv(N2, 256)), dim3(256), 0, st, N2, nparts,
+                           part, pstride, pj, pk, Y, ldy, Ylp);
+    WC_LAUNCH_CHECK();
+}
+
+}  // namespace wc

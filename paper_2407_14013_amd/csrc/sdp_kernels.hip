@@ -401,6 +401,19 @@ void rho_bottom(hipStream_t st, int d, const double* h, const double* a, const d
     WC_LAUNCH_CHECK();
 }
 
+// Bottom block of the augmented operator from the explicit script-A script-Q:
+// out = a - tau^2 Sigma v with a = (AQ)^T u.
+__global__ void aq_bottom_kernel(int d, const double* __restrict__ a, const double* __restrict__ sig, double t2,
+                                 const double* __restrict__ v, double* __restrict__ out) {
+    int c = blockIdx.x * 256 + threadIdx.x;
+    if (c < d) out[c] = a[c] - t2 * sig[c] * v[c];
+}
+void aq_bottom(hipStream_t st, int d, const double* a, const double* sig, double t2, const double* v, double* out) {
+    if (d <= 0) return;
+    hipLaunchKernelGGL(aq_bottom_kernel, g1(d), dim3(256), 0, st, d, a, sig, t2, v, out);
+    WC_LAUNCH_CHECK();
+}
+
 // ---- PCG scalars (device-resident) ------------------------------------------
 // sc[0] = <r,z>, sc[1] = <p,Kp>, sc[2] = alpha, sc[3] = beta, sc[4] = ||r_u||^2, sc[5] = <r,z>_new
 __global__ void pcg_alpha_kernel(double* sc) { sc[2] = sc[0] / sc[1]; }

@@ -33,6 +33,7 @@ void neg_div(hipStream_t st, int d, const double* qc, const double* sig, double*
 void corrector_h(hipStream_t st, int n, const double* Pm, const double* dv, double smu, double* H);
 void rho_bottom(hipStream_t st, int d, const double* h, const double* a, const double* sig, double t2,
                 const double* zv, double* out);
+void aq_bottom(hipStream_t st, int d, const double* a, const double* sig, double t2, const double* v, double* out);
 void pcg_alpha(hipStream_t st, double* sc);
 void pcg_beta(hipStream_t st, double* sc);
 void pcg_xr(hipStream_t st, long N, long m, double* x, double* r, const double* p, const double* Kp,

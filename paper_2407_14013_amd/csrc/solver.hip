@@ -143,10 +143,21 @@ static void alloc_work(sdp_ctx* c) {
         c->Fq.alloc((long)m * n * c->rmax);
     }
     long gp = (long)gemv_cols_parts(m) * std::max<long>(round_up(c->N2, 2), c->dmaxp);
+    gp = std::max(gp, (long)packed_cols_parts_f32(m) * round_up(c->N2, 4));
     c->gpart.alloc(gp);
+    if (c->lowp) {
+        c->Elp.alloc(nn);
+        c->Ylp.alloc(nn);
+        c->Tlp.alloc(nn);
+        if (c->kind == SDP_A_DENSE) {
+            c->P32.alloc((long)m * c->ldP);
+            to_f32(c->st, (long)m * c->ldP, c->P, c->P32);
+            c->mw32.alloc(c->ldP);
+        }
+    }
 
     c->part.alloc(1024);
-    for (auto* b : {&c->vx, &c->vr, &c->vz, &c->vp, &c->vKp, &c->vg, &c->vtmp}) {
+    for (auto* b : {&c->vx, &c->vr, &c->vz, &c->vp, &c->vKp, &c->vg, &c->vtmp, &c->vres, &c->vdx}) {
         b->alloc(Nmax);
         fill(c->st, Nmax, b->get(), 0.0);
     }
@@ -219,6 +230,8 @@ void setup(sdp_ctx* c, const sdp_problem* p, const sdp_options* o, hipStream_t s
     c->kind = p->a_kind;
     if (o) c->opt = *o;
     else sdp_default_options(&c->opt);
+    c->lowp = c->opt.inner_prec != SDP_PREC_F64;
+    c->lp = c->opt.inner_prec == SDP_PREC_BF16 ? Lp::BF16 : Lp::F32;
     c->rmax = std::max(1, std::min(c->opt.rank_max, n - 1));
     if (c->opt.rank_fixed > 0) c->rmax = std::max(c->rmax, std::min(c->opt.rank_fixed, n - 1));
     if (!p->on_device) validate_host(p);
@@ -376,6 +389,7 @@ void ensure_scaling(sdp_ctx* c) {
     scale_cols(st, n, n, c->Gw, n, c->evE, 1.0, c->T1, n);
     gemm(c, false, true, n, n, n, 1.0, c->T1, n, c->Gw, n, 0.0, c->E, n);
     symmetrize(st, n, c->E, n);
+    if (c->lowp) to_lowp(st, c->lp, n, n, c->E, n, c->Elp, n);
     sigma_diag(st, n, r, c->lam, c->tau, c->sig);
     // script-A script-Q, row i = script-Q^T svec(A_i)
     const int d = c->d;
@@ -427,6 +441,53 @@ void newton_apply(sdp_ctx* c, const double* in, double* out) {
     f_to_v(st, n, r, c->F, n, v, c->sig, c->tau * c->tau, out + m);
     prof_end(c, SDP_K_NEWTON, e, 0.0);
     c->matvecs += 1;
+}
+
+// The augmented operator with its A E A^T block in low precision (the
+// refinement sweeps' inner operator).  E Y E runs on the matrix cores in FP32
+// or BF16 with FP32 accumulation.  Dense A: Y = A^T(u) and A(E Y E) read the
+// FP32 copy of the packed rows (FP64 accumulation), and the off-diagonal
+// blocks are FP64 products with the explicit script-A script-Q that the
+// preconditioner also uses, so the operator differs from the FP64 one only in
+// its top-left block.  Entry-sampling A: the gathers and scatters are exact,
+// and only E Y E is rounded.  Either way the bottom block is the FP64 one,
+// which keeps the identities that indefinite PCG relies on (Section 6).
+void newton_apply_lowp(sdp_ctx* c, const double* in, double* out) {
+    ensure_scaling(c);
+    require(c->lowp, "the context was set up with FP64 inner precision");
+    const int n = c->n, m = c->m, r = c->r, d = c->d;
+    hipStream_t st = c->st;
+    const double* u = in;
+    const double* v = in + m;
+    const LpOut tout = c->lp == Lp::F32 ? LpOut::F32 : LpOut::BF16;
+    if (c->kind == SDP_A_DENSE) {
+        packed_cols_partial_f32(st, m, static_cast<int>(c->N2), c->P32, c->ldP, u, c->gpart);
+        at_reduce_unpack_lp(st, c->lp, c->N2, packed_cols_parts_f32(m), c->gpart, round_up(c->N2, 4), c->pj, c->pk,
+                            nullptr, n, c->Ylp);
+        lp_gemm_nn(st, c->lp, tout, n, n, n, c->Ylp, n, c->Elp, n, c->Tlp, n);
+        lp_gemm_nn(st, c->lp, LpOut::F64, n, n, n, c->Elp, n, c->Tlp, n, c->Mm, n);
+        pack_weighted_f32(st, c->N2, c->ldP, c->Mm, n, c->pj, c->pk, c->mw32);
+        packed_rows_f32(st, m, static_cast<int>(c->N2), c->P32, c->ldP, c->mw32, out, 1.0, 0.0);
+        // top += AQ v (v staged in an aligned, zero-padded buffer); bottom = AQ^T u - tau^2 Sigma v
+        copy(st, d, v, c->td2);
+        gemv_rows(st, m, d, c->AQ, c->dmaxp, c->td2, out, 1.0, 1.0);
+        gemv_cols(st, m, d, c->AQ, c->dmaxp, u, c->td3, 1.0, 0.0, c->gpart);
+        aq_bottom(st, d, c->td3, c->sig, c->tau * c->tau, v, out + m);
+    } else {
+        fill(st, (long)n * n, c->Y, 0.0);
+        entry_scatter(st, m, c->jk, u, c->Y, n);
+        to_lowp(st, c->lp, n, n, c->Y, n, c->Ylp, n);
+        v_to_h(st, n, r, v, c->Hm);
+        gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
+        symlr(st, n, r, c->U, c->Gw, n, c->Mm, n, 0.0);
+        lp_gemm_nn(st, c->lp, tout, n, n, n, c->Ylp, n, c->Elp, n, c->Tlp, n);
+        lp_gemm_nn(st, c->lp, LpOut::ADD_F64, n, n, n, c->Elp, n, c->Tlp, n, c->Mm, n);
+        entry_gather(st, m, c->jk, c->Mm, n, out, 1.0, 0.0);
+        gemm(c, false, false, n, r, n, 1.0, c->Y, n, c->Gw, n, 0.0, c->YQ, n);
+        gemm(c, true, false, n, r, n, 1.0, c->Gw, n, c->YQ, n, 0.0, c->F, n);
+        f_to_v(st, n, r, c->F, n, v, c->sig, c->tau * c->tau, out + m);
+    }
+    c->lp_matvecs += 1;
 }
 
 // Block elimination with P = [beta I, AQ; AQ^T, -tau^2 Sigma] (Section 6, with
@@ -485,7 +546,76 @@ static void recover(sdp_ctx* c, const double* x, const double* Ct, double* dX, d
     symmetrize(st, n, dX, n);
 }
 
-// Indefinite PCG on eq. augsys (Corollary pcg) started at [0; -Sigma^{-1} Q^T c].
+// Indefinite PCG (Definition pcg, Corollary pcg) on K x = g from the iterate
+// already in x, preconditioned as in Section 6, with the FP64 operator or its
+// low-precision form.  Stops when ||r_u|| <= tol_rel ||r_u(0)|| or after maxit
+// iterations.  Uses vr, vz, vp, vKp.
+struct PcgOut {
+    int it = 0;
+    double ref = 0, rr = 0;
+    bool conv = false;
+};
+static PcgOut pcg_loop(sdp_ctx* c, bool lowp, const double* g, double* x, double tol_rel, int maxit) {
+    const int m = c->m, d = c->d;
+    const long N = (long)m + d;
+    hipStream_t st = c->st;
+    double* sc = c->sc;
+    auto K = [&](const double* in, double* out) {
+        if (lowp) newton_apply_lowp(c, in, out);
+        else newton_apply(c, in, out);
+    };
+    // r = g - K x with its bottom block zero (Corollary pcg), z = P^{-1} r, p = z
+    K(x, c->vKp);
+    axpbypcz(st, N, 1.0, g, -1.0, c->vKp, 0.0, c->vr);
+    fill(st, d, c->vr + m, 0.0);
+    precond_apply(c, c->vr, c->vz);
+    copy(st, N, c->vz, c->vp);
+    dot(st, N, c->vr, c->vz, sc + 0, c->part);
+    dot(st, m, c->vr, c->vr, sc + 4, c->part);
+    fetch(c, sc + 4, 1);
+    PcgOut o;
+    o.ref = std::sqrt(c->pin[0]);
+    o.rr = o.ref;
+    const double tol = tol_rel * (o.ref > 0 ? o.ref : 1.0);
+    while (true) {
+        if (!(o.rr > tol)) {
+            o.conv = std::isfinite(o.rr);
+            break;
+        }
+        if (o.it >= maxit) break;
+        K(c->vp, c->vKp);
+        dot(st, N, c->vp, c->vKp, sc + 1, c->part);
+        pcg_alpha(st, sc);
+        pcg_xr(st, N, m, x, c->vr, c->vp, c->vKp, sc);
+        dot(st, m, c->vr, c->vr, sc + 4, c->part);
+        precond_apply(c, c->vr, c->vz);
+        dot(st, N, c->vr, c->vz, sc + 5, c->part);
+        pcg_beta(st, sc);
+        pcg_p(st, N, c->vp, c->vz, sc);
+        ++o.it;
+        if (c->opt.verbose >= 2) {
+            dot(st, d, c->vr + m, c->vr + m, sc + 6, c->part);
+            fetch(c, sc, 7);
+            fprintf(stderr, "[wcsdp]   pcg%s %d |r_u| %.3e |r_v| %.3e rz %.3e pKp %.3e alpha %.3e beta %.3e\n",
+                    lowp ? "(lp)" : "", o.it, std::sqrt(c->pin[4]), std::sqrt(c->pin[6]), c->pin[0], c->pin[1],
+                    c->pin[2], c->pin[3]);
+        }
+        fetch(c, sc + 4, 1);
+        o.rr = std::sqrt(c->pin[0]);
+    }
+    return o;
+}
+
+// Solve eq. augsys for the right-hand side of eq. Newt-eps and recover the
+// Newton direction (eq. recover).  FP64 mode: one indefinite PCG run started at
+// [0; -Sigma^{-1} Q^T c] (Corollary pcg).  Mixed mode: iterative refinement --
+// the FP64 residual rho = g - K x is computed, the correction K delta = rho is
+// solved from delta = 0 by indefinite PCG with the low-precision operator to
+// refine_tol, and x += delta, until the FP64 residual meets inner_tol.  The
+// bottom block of rho is set to zero: the low-precision operator shares its
+// bottom block with the FP64 one, so that residual is rounding noise, which
+// the tiny tau^2 Sigma block would amplify (indefinite PCG likewise keeps its
+// bottom residual at zero).
 int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, double* dy, sdp_inner_stats* stats) {
     ensure_scaling(c);
     const int n = c->n, m = c->m, r = c->r, d = c->d;
@@ -504,50 +634,45 @@ int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, doub
     axpby(st, d, t2, c->vtmp, 0.0, c->vg + m);
     fill(st, m, c->vx, 0.0);
     neg_div(st, d, c->vtmp, c->sig, c->vx + m);
-    // r = g - K x, z = P^{-1} r, p = z
-    newton_apply(c, c->vx, c->vKp);
-    axpbypcz(st, N, 1.0, c->vg, -1.0, c->vKp, 0.0, c->vr);
-    fill(st, d, c->vr + m, 0.0);  // the bottom residual is zero at this start (Corollary pcg)
-    precond_apply(c, c->vr, c->vz);
-    copy(st, N, c->vz, c->vp);
-    dot(st, N, c->vr, c->vz, sc + 0, c->part);
-    dot(st, m, c->vr, c->vr, sc + 4, c->part);
-    fetch(c, sc + 4, 1);
-    const double ref = std::sqrt(c->pin[0]);
-    double rr = ref;
-    const double tol = c->opt.inner_tol * (ref > 0 ? ref : 1.0);
-    int it = 0;
+    int its = 0, sweeps = 0;
+    double ref = 0, rr = 0;
     bool conv = false;
-    while (true) {
-        if (!(rr > tol)) {
-            conv = std::isfinite(rr);
-            break;
+    if (!c->lowp) {
+        PcgOut o = pcg_loop(c, false, c->vg, c->vx, c->opt.inner_tol, c->opt.inner_maxit);
+        its = o.it;
+        ref = o.ref;
+        rr = o.rr;
+        conv = o.conv;
+    } else {
+        const double rtol = c->opt.refine_tol > 0 ? c->opt.refine_tol : 1e-4;
+        while (true) {
+            newton_apply(c, c->vx, c->vKp);
+            axpbypcz(st, N, 1.0, c->vg, -1.0, c->vKp, 0.0, c->vres);          // rho = g - K x (FP64)
+            dot(st, m, c->vres, c->vres, sc + 4, c->part);
+            fetch(c, sc + 4, 1);
+            rr = std::sqrt(c->pin[0]);
+            if (sweeps == 0) ref = rr;
+            if (c->opt.verbose >= 2)
+                fprintf(stderr, "[wcsdp]   refine %d |rho_u| / |rho_u(0)| %.3e\n", sweeps, ref > 0 ? rr / ref : 0.0);
+            if (!(rr > c->opt.inner_tol * (ref > 0 ? ref : 1.0))) {
+                conv = std::isfinite(rr);
+                break;
+            }
+            if (!std::isfinite(rr) || sweeps >= c->opt.max_refine || its >= c->opt.inner_maxit) break;
+            fill(st, d, c->vres + m, 0.0);
+            fill(st, N, c->vdx, 0.0);
+            PcgOut o = pcg_loop(c, true, c->vres, c->vdx, rtol, c->opt.inner_maxit - its);
+            its += o.it;
+            ++sweeps;
+            if (!std::isfinite(o.rr)) break;
+            axpby(st, N, 1.0, c->vdx, 1.0, c->vx);
         }
-        if (it >= c->opt.inner_maxit) break;
-        newton_apply(c, c->vp, c->vKp);
-        dot(st, N, c->vp, c->vKp, sc + 1, c->part);
-        pcg_alpha(st, sc);
-        pcg_xr(st, N, m, c->vx, c->vr, c->vp, c->vKp, sc);
-        dot(st, m, c->vr, c->vr, sc + 4, c->part);
-        precond_apply(c, c->vr, c->vz);
-        dot(st, N, c->vr, c->vz, sc + 5, c->part);
-        pcg_beta(st, sc);
-        pcg_p(st, N, c->vp, c->vz, sc);
-        ++it;
-        if (c->opt.verbose >= 2) {
-            dot(st, d, c->vr + m, c->vr + m, sc + 6, c->part);
-            fetch(c, sc, 7);
-            fprintf(stderr, "[wcsdp]   pcg %d |r_u| %.3e |r_v| %.3e rz %.3e pKp %.3e alpha %.3e beta %.3e\n", it,
-                    std::sqrt(c->pin[4]), std::sqrt(c->pin[6]), c->pin[0], c->pin[1], c->pin[2], c->pin[3]);
-        }
-        fetch(c, sc + 4, 1);
-        rr = std::sqrt(c->pin[0]);
     }
     recover(c, c->vx, Ct, dX, dy);
-    c->pcg_total += it;
+    c->pcg_total += its;
     if (stats) {
-        stats->iterations = it;
-        stats->refinements = 0;
+        stats->iterations = its;
+        stats->refinements = sweeps;
         stats->converged = conv ? 1 : 0;
         stats->r = r;
         stats->tau = c->tau;
@@ -722,7 +847,7 @@ int ipm_step(sdp_ctx* c, sdp_step_stats* stats) {
 int solve(sdp_ctx* c, sdp_result* res) {
     using clk = std::chrono::steady_clock;
     const auto t0 = clk::now();
-    const int64_t mv0 = c->matvecs, pcg0 = c->pcg_total;
+    const int64_t mv0 = c->matvecs, pcg0 = c->pcg_total, lmv0 = c->lp_matvecs;
     sdp_step_stats s{};
     int status = kEStall;
     int its = 0;
@@ -750,6 +875,7 @@ int solve(sdp_ctx* c, sdp_result* res) {
         res->iterations = its;
         res->pcg_iterations = c->pcg_total - pcg0;
         res->newton_matvecs = c->matvecs - mv0;
+        res->lp_matvecs = c->lp_matvecs - lmv0;
         res->pobj = s.pobj;
         res->dobj = s.dobj;
         res->relgap = s.relgap;

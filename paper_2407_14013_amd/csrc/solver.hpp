@@ -7,6 +7,7 @@
 #include "../../include/wcsdp.h"
 #include "common.hpp"
 #include "lanczos.hpp"
+#include "lowprec.hpp"
 
 struct sdp_ctx {
     hipStream_t st = nullptr;
@@ -41,15 +42,23 @@ struct sdp_ctx {
     // ---- temporaries -------------------------------------------------------------
     wc::DevBuf<double> Y, T1, T2, Mm, Hm, U, YQ, F, mw, yp, part, gpart, tm, td, td2, td3, rho, dz;
     wc::DevBuf<double> vx, vr, vz, vp, vKp, vg, vtmp;   // Krylov vectors (m + dmax, padded)
+    wc::DevBuf<double> vres, vdx;                       // refinement residual and correction
+
     wc::DevBuf<double> sc;      // device scalars
     double* pin = nullptr;      // pinned host scalars
     wc::DevBuf<int> info;
+
+    // ---- mixed precision (inner_prec != SDP_PREC_F64) ------------------------------
+    bool lowp = false;
+    wc::Lp lp = wc::Lp::F32;
+    wc::DevBuf<float> P32, mw32;   // dense: FP32 packed rows and packed weights
+    wc::DevBuf<float> Elp, Ylp, Tlp;  // n x n in FP32, or BF16 bit patterns in the first half
 
     // ---- Newton direction buffers ----------------------------------------------
     wc::DevBuf<double> dXa, dya, dSa, dX, dy, dS, Ct, Rd, rp, Hc, Dx, Ds;
 
     // ---- counters / profiling ------------------------------------------------------
-    int64_t matvecs = 0, pcg_total = 0;
+    int64_t matvecs = 0, pcg_total = 0, lp_matvecs = 0;
     int prof_mask = 0;
     struct Prof {
         std::vector<hipEvent_t> ev;  // start/stop pairs
@@ -66,6 +75,7 @@ namespace wc {
 void setup(sdp_ctx* c, const sdp_problem* p, const sdp_options* o, hipStream_t st);
 void ensure_scaling(sdp_ctx* c);
 void newton_apply(sdp_ctx* c, const double* in, double* out);
+void newton_apply_lowp(sdp_ctx* c, const double* in, double* out);
 int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, double* dy, sdp_inner_stats* stats);
 int ipm_step(sdp_ctx* c, sdp_step_stats* stats);
 int solve(sdp_ctx* c, sdp_result* res);

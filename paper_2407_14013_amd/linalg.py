@@ -73,3 +73,31 @@ def djacobi_svd(A: torch.Tensor, want_v: bool = True, tol: float = 0.0, max_swee
     sw = C.c_int32()
     _chk(L.lib().wc_djacobi_svd(_stream_ptr(), n, _p(A), n, _p(V), n, _p(s), tol, max_sweeps, C.byref(sw)))
     return s, V, sw.value
+
+
+def _praw(t):
+    assert t.is_cuda and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+_LP_DTYPE = {1: torch.float32, 2: torch.int16}  # BF16 is carried as raw 16-bit patterns
+
+
+def to_lowp(A: torch.Tensor, prec: int) -> torch.Tensor:
+    """Column-major FP64 device matrix rounded to FP32 (prec 1) or BF16 bit patterns (prec 2)."""
+    cols, rows = A.shape
+    out = torch.empty((cols, rows), dtype=_LP_DTYPE[prec], device=A.device)
+    _chk(L.lib().wc_to_lowp(_stream_ptr(), prec, rows, cols, _p(A), rows, _praw(out), rows))
+    return out
+
+
+def gemm_lp(prec: int, out_kind: int, A: torch.Tensor, B: torch.Tensor, Cm: torch.Tensor | None = None):
+    """C = A B with low-precision column-major operands (as from to_lowp); out_kind 0 FP32, 1 BF16, 2 FP64 +=."""
+    k, m = A.shape
+    n, kb = B.shape
+    assert k == kb, "inner dimensions differ"
+    if Cm is None:
+        dt = {0: torch.float32, 1: torch.int16, 2: torch.float64}[out_kind]
+        Cm = torch.zeros((n, m), dtype=dt, device=A.device)
+    _chk(L.lib().wc_gemm_lp(_stream_ptr(), prec, out_kind, m, n, k, _praw(A), m, _praw(B), k, _praw(Cm), m))
+    return Cm

@@ -37,9 +37,10 @@ def test_default_options():
     L.lib().sdp_default_options(C.byref(o))
     assert o.rank_max == 10 and o.inner_tol == 1e-10 and o.gap_tol == 1e-8 and o.step_frac == 0.98
     assert o.solver == L.SDP_SOLVER_PCG and o.inner_prec == L.SDP_PREC_F64
+    assert o.max_refine == 8 and o.refine_tol == 1e-4
 
 
-def _setup_status(problem):
+def _setup_status(problem, opts=None):
     lib = L.lib()
     keep = []
 
@@ -59,7 +60,7 @@ def _setup_status(problem):
         p.jk = host(problem["jk"], np.int32)
     p.on_device = 0
     ctx = C.c_void_p()
-    st = lib.sdp_setup(C.byref(p), None, None, C.byref(ctx))
+    st = lib.sdp_setup(C.byref(p), C.byref(opts) if opts is not None else None, None, C.byref(ctx))
     return st, lib.sdp_last_error(None).decode(), ctx
 
 
@@ -117,3 +118,21 @@ def test_setup_rejects_bad_options():
     ctx = C.c_void_p()
     st = lib.sdp_setup(C.byref(p), C.byref(o), None, C.byref(ctx))
     assert st == L.SDP_EINVAL and "step_frac" in lib.sdp_last_error(None).decode()
+
+
+@pytest.mark.parametrize(
+    "field,value,needle",
+    [
+        ("inner_prec", 3, "inner_prec must be"),
+        ("refine_tol", 1.5, "refine_tol must lie"),
+        ("max_refine", -1, "max_refine must be"),
+        ("step_frac", 1.0, "step_frac must lie"),
+    ],
+)
+def test_setup_rejects_invalid_options(field, value, needle):
+    # option checks run before any device work, so they are testable without a GPU
+    o = L.SdpOptions()
+    L.lib().sdp_default_options(C.byref(o))
+    setattr(o, field, value)
+    st, msg, ctx = _setup_status(workloads.gaussian_sensing(5, 1, 6, seed=0), o)
+    assert st == L.SDP_EINVAL and needle in msg and not ctx.value
