@@ -126,6 +126,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-loop", type=int, default=200)
     ap.add_argument("--pmc-pass", action="store_true", help="only the short run profiled for HBM counters")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solves")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every instance of this workload fits one MI355X, "
@@ -165,6 +166,39 @@ def main():
     matvecs = sum(r["newton_matvecs"] for r in results)
     for r in results:
         assert r["status"] == 0 and r["relgap"] <= 1e-8, r
+
+    # the same solves with the mixed-precision inner operator
+    mixed = {}
+    if not args.no_mixed:
+        for name, prec in (("f32", L.SDP_PREC_F32), ("bf16", L.SDP_PREC_BF16)):
+            mctx = Context(p, inner_prec=prec)
+            mctx.set_point(X0, y0, S0)
+
+            def msolve():
+                mctx.set_point(X0, y0, S0)
+                return mctx.solve()
+
+            for _ in range(args.warmup):
+                msolve()
+            torch.cuda.synchronize()
+            mres = []
+            tm0 = time.perf_counter()
+            for _ in range(args.steps):
+                mres.append(msolve())
+            torch.cuda.synchronize()
+            mel = time.perf_counter() - tm0
+            mctx.close()
+            for r in mres:
+                assert r["status"] == 0 and r["relgap"] <= 1e-8, r
+            mixed[name] = {
+                "time_to_gap_s": mel / args.steps,
+                "speedup_vs_fp64": (el / args.steps) / (mel / args.steps),
+                "iterations": mres[-1]["iterations"],
+                "fp64_matvecs": mres[-1]["newton_matvecs"],
+                "lowp_matvecs": mres[-1]["lp_matvecs"],
+                "relgap": mres[-1]["relgap"],
+                "pobj_rel_diff_vs_fp64": abs(mres[-1]["pobj"] - results[-1]["pobj"]) / abs(results[-1]["pobj"]),
+            }
 
     # dominant kernel: the larger total time of the two packed passes over A
     kcls = max((L.SDP_K_A_APPLY, L.SDP_K_AT_APPLY), key=lambda k: prof[k]["ms"])
@@ -211,6 +245,7 @@ def main():
             "pobj": results[-1]["pobj"],
         },
         "newton_apply_loop": {"matvec_per_s": loop_rate, "calls": args.apply_loop},
+        "mixed": mixed,
         "roofline": {
             "kernel": ("packed_rows_kernel: A(M), one pass over the packed constraint rows"
                        if kcls == L.SDP_K_A_APPLY else

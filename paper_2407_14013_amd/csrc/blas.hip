@@ -135,6 +135,13 @@ void dgemm(hipStream_t st, bool ta, bool tb, int m, int n, int k, double alpha, 
         }
         return;
     }
+    if (batch > 65535) {
+        // keep gridDim.z within the hardware limit
+        for (int b0 = 0; b0 < batch; b0 += 65535)
+            dgemm(st, ta, tb, m, n, k, alpha, A + b0 * sA, lda, B + b0 * sB, ldb, beta, C + b0 * sC, ldc, lower_only,
+                  std::min(65535, batch - b0), sA, sB, sC);
+        return;
+    }
     dim3 grid(cdiv(m, GBM), cdiv(n, GBN), batch);
     int lo = lower_only ? 1 : 0;
     if (!ta && !tb)
@@ -430,7 +437,24 @@ static int dot_blocks(long n) {
     return static_cast<int>(b);
 }
 
+// Short vectors: one 1024-thread workgroup reads both and writes the sum
+// (one launch instead of partial sums plus their reduction).
+constexpr long DOT_SINGLE_MAX = 1L << 15;
+__global__ __launch_bounds__(1024) void dot_single(long n, const double* __restrict__ x, const double* __restrict__ y,
+                                                   double* __restrict__ out) {
+    __shared__ double sh[16];
+    double acc = 0.0;
+    for (long i = threadIdx.x; i < n; i += 1024) acc += x[i] * y[i];
+    double s = block_sum<1024>(acc, sh);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
 void dot(hipStream_t st, long n, const double* x, const double* y, double* out, double* part) {
+    if (n <= DOT_SINGLE_MAX) {
+        hipLaunchKernelGGL(dot_single, dim3(1), dim3(1024), 0, st, n, x, y, out);
+        WC_LAUNCH_CHECK();
+        return;
+    }
     int nb = dot_blocks(n);
     hipLaunchKernelGGL(dot_partial, dim3(nb), dim3(256), 0, st, n, x, y, part);
     WC_LAUNCH_CHECK();

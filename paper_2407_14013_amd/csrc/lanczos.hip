@@ -1,5 +1,6 @@
 // Smallest eigenvalue of a symmetric n x n matrix by the Lanczos process with
-// full reorthogonalisation, run by one 1024-thread workgroup (n <= 4096).
+// full reorthogonalisation, run by one 1024-thread workgroup (n <= 4096; the
+// basis is kept in LDS for n up to about 240).
 //
 // Used for the interior-point step length: the largest alpha with
 // L L^T + alpha D PSD is 1 / max(0, -lambda_min(L^{-1} D L^{-T})).  The
@@ -30,15 +31,28 @@ __device__ inline double lz_block_sum(double v, double* red) {
     return s;
 }
 
+// Dynamic LDS layout: q (n), w (n), partial products of the matrix-vector
+// product (LZ_THREADS, only when rows are split into chunks), and, when it
+// fits (qlds != 0), the Lanczos basis (n x (kmax + 1)).  Otherwise the basis
+// lives in the global buffer Qg.
+//
+// The product w = T q splits each row into `nch` column chunks so that all
+// threads take part: thread t < n * nch forms the partial sum of row t % n
+// over chunk t / n, and the partials are added in chunk order.
 __global__ __launch_bounds__(LZ_THREADS) void lanczos_kernel(int n, const double* __restrict__ T, long ldt, int kmax,
-                                                             double* __restrict__ Q, long ldq,
+                                                             double* __restrict__ Qg, int qlds,
                                                              double* __restrict__ ab, int* __restrict__ kout) {
     extern __shared__ double sm[];
-    double* q = sm;       // current Lanczos vector
-    double* w = sm + n;   // work vector
+    double* q = sm;                 // current Lanczos vector
+    double* w = sm + n;             // work vector
+    const int nch = n > LZ_THREADS / 2 ? 1 : LZ_THREADS / n;
+    double* pp = sm + 2 * n;        // partial products (nch > 1 only)
+    double* Q = qlds ? sm + 2 * n + (nch > 1 ? LZ_THREADS : 0) : Qg;
+    const long ldq = n;
     __shared__ double red[LZ_WAVES];
     __shared__ double h[LZ_MAX_K + 1];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int clen = (n + nch - 1) / nch;
 
     // deterministic start vector with no special structure
     double loc = 0.0;
@@ -57,12 +71,30 @@ __global__ __launch_bounds__(LZ_THREADS) void lanczos_kernel(int n, const double
     int k = 0;
     for (int j = 0; j < kmax; ++j) {
         // w = T q
-        for (int i = tid; i < n; i += LZ_THREADS) {
-            double acc = 0.0;
-            const double* Ti = T + i;
+        if (nch > 1) {
+            if (tid < n * nch) {
+                const int i = tid % n, c = tid / n;
+                const int l0 = c * clen, l1 = min(n, l0 + clen);
+                const double* Ti = T + i;
+                double acc = 0.0;
 #pragma unroll 8
-            for (int l = 0; l < n; ++l) acc += Ti[(long)l * ldt] * q[l];
-            w[i] = acc;
+                for (int l = l0; l < l1; ++l) acc += Ti[(long)l * ldt] * q[l];
+                pp[tid] = acc;
+            }
+            __syncthreads();
+            for (int i = tid; i < n; i += LZ_THREADS) {
+                double acc = 0.0;
+                for (int c = 0; c < nch; ++c) acc += pp[i + c * n];
+                w[i] = acc;
+            }
+        } else {
+            for (int i = tid; i < n; i += LZ_THREADS) {
+                double acc = 0.0;
+                const double* Ti = T + i;
+#pragma unroll 8
+                for (int l = 0; l < n; ++l) acc += Ti[(long)l * ldt] * q[l];
+                w[i] = acc;
+            }
         }
         __syncthreads();
         loc = 0.0;
@@ -157,8 +189,22 @@ double lanczos_min_eig(hipStream_t st, int n, const double* T, long ldt, int kma
     require(n >= 1 && n <= LZ_MAX_N, "lanczos: n out of range");
     w.ensure(n);
     kmax = std::max(1, std::min({kmax, n, LZ_MAX_K}));
-    size_t shm = 2 * (size_t)n * sizeof(double);
-    hipLaunchKernelGGL(lanczos_kernel, dim3(1), dim3(LZ_THREADS), shm, st, n, T, ldt, kmax, w.Q.get(), (long)n,
+    // keep the basis in LDS when it fits beside the vectors
+    static const size_t lds_max = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 64 << 10;
+        return static_cast<size_t>(v);
+    }();
+    const bool split = n <= LZ_THREADS / 2;
+    size_t shm = (2 * (size_t)n + (split ? LZ_THREADS : 0)) * sizeof(double);
+    const size_t qbytes = (size_t)n * (kmax + 1) * sizeof(double);
+    const size_t static_lds = (LZ_WAVES + LZ_MAX_K + 1) * sizeof(double) + 1024;  // red, h, slack
+    const int qlds = shm + qbytes + static_lds <= lds_max ? 1 : 0;
+    if (qlds) shm += qbytes;
+    require(shm + static_lds <= lds_max, "lanczos: n too large for the workgroup's LDS");
+    hipLaunchKernelGGL(lanczos_kernel, dim3(1), dim3(LZ_THREADS), shm, st, n, T, ldt, kmax, w.Q.get(), qlds,
                        w.ab.get(), w.kout.get());
     WC_LAUNCH_CHECK();
     WC_HIP(hipMemcpyAsync(w.pinned, w.ab.get(), 2 * kmax * sizeof(double), hipMemcpyDeviceToHost, st));

@@ -63,6 +63,30 @@ void pack_dense_rows(hipStream_t st, int n, int m, long N2, long ldp, const doub
     }
 }
 
+// Full symmetric n x n matrices (column-major, one after another) from the
+// packed rows: A_i[j,k] = A_i[k,j] = P[i, p].
+__global__ void unpack_rows_kernel(long N2, long ldp, const double* __restrict__ P, const int* __restrict__ pj,
+                                   const int* __restrict__ pk, int n, double* __restrict__ A) {
+    const long p = blockIdx.x * 256L + threadIdx.x;
+    const long i = blockIdx.y;
+    if (p >= N2) return;
+    const int j = pj[p], k = pk[p];
+    const double v = P[i * ldp + p];
+    double* Ai = A + i * (long)n * n;
+    Ai[j + (long)k * n] = v;
+    Ai[k + (long)j * n] = v;
+}
+void unpack_rows(hipStream_t st, int m, long N2, long ldp, const double* P, const int* pj, const int* pk, int n,
+                 double* A) {
+    const int chunk = 65535;
+    for (int i0 = 0; i0 < m; i0 += chunk) {
+        const int cnt = std::min(chunk, m - i0);
+        hipLaunchKernelGGL(unpack_rows_kernel, dim3(cdiv(N2, 256), cnt), dim3(256), 0, st, N2, ldp,
+                           P + (long)i0 * ldp, pj, pk, n, A + (long)i0 * n * n);
+        WC_LAUNCH_CHECK();
+    }
+}
+
 // ||A_i||_F^2 from packed rows: diagonal entries once, off-diagonal twice.
 __global__ __launch_bounds__(256) void packed_row_norm2_kernel(int m, long N2, long ldp, const double* __restrict__ P,
                                                                const int* __restrict__ pj,
@@ -276,29 +300,10 @@ void symlr(hipStream_t st, int n, int r, const double* U, const double* Q, long 
     WC_LAUNCH_CHECK();
 }
 
-// Phi[p, a + n b] = G[j,a] Q[k,b] + [j != k] G[k,a] Q[j,b], p = (j, k): then
-// (P Phi)[i, a + n b] = (G^T A_i Q)[a, b].
-__global__ void phi_kernel(int n, int r, long N2, const int* __restrict__ pj, const int* __restrict__ pk,
-                           const double* __restrict__ G, double* __restrict__ Phi, long ldphi) {
-    long p = blockIdx.x * 256L + threadIdx.x;
-    int col = blockIdx.y;  // a + n b
-    if (p >= N2) return;
-    int a = col % n, b = col / n;
-    int j = pj[p], k = pk[p];
-    double v = G[j + (long)a * n] * G[k + (long)b * n];
-    if (j != k) v += G[k + (long)a * n] * G[j + (long)b * n];
-    Phi[p + (long)col * ldphi] = v;
-}
-void phi_matrix(hipStream_t st, int n, int r, long N2, const int* pj, const int* pk, const double* G, double* Phi,
-                long ldphi) {
-    hipLaunchKernelGGL(phi_kernel, dim3(cdiv(N2, 256), n * r), dim3(256), 0, st, n, r, N2, pj, pk, G, Phi, ldphi);
-    WC_LAUNCH_CHECK();
-}
-
-// AQ[i, c] (row-major, pitch ldaq) from F = P Phi (column-major m x (n r)):
+// AQ[i, c] (row-major, pitch ldaq) from F_i = G_w^T A_i Q (n x r, read with strides):
 // row i of script-A script-Q is script-Q^T svec(A_i) = [svec(F_top); sqrt2 vec(F_bot)].
-__global__ void f_to_aq_kernel(int m, int n, int r, const double* __restrict__ F, long ldf, double* __restrict__ AQ,
-                               long ldaq) {
+__global__ void f_to_aq_kernel(int m, int n, int r, const double* __restrict__ F, long si, long sab,
+                               double* __restrict__ AQ, long ldaq) {
     const int nb = r * (r + 1) / 2;
     const int d = nb + (n - r) * r;
     long t = blockIdx.x * 256L + threadIdx.x;
@@ -309,17 +314,17 @@ __global__ void f_to_aq_kernel(int m, int n, int r, const double* __restrict__ F
     if (c < nb) {
         int a, b;
         svec_pair(c, r, a, b);
-        double fab = F[i + (long)(a + n * b) * ldf], fba = F[i + (long)(b + n * a) * ldf];
+        double fab = F[i * si + (long)(a + n * b) * sab], fba = F[i * si + (long)(b + n * a) * sab];
         val = (a == b) ? fab : kSqrt2 * 0.5 * (fab + fba);
     } else if (c < d) {
         int s = c - nb;
         int k = s % (n - r), b = s / (n - r);
-        val = kSqrt2 * F[i + (long)((r + k) + n * b) * ldf];
+        val = kSqrt2 * F[i * si + (long)((r + k) + n * b) * sab];
     }
     AQ[(long)i * ldaq + c] = val;
 }
-void f_to_aq(hipStream_t st, int m, int n, int r, const double* F, long ldf, double* AQ, long ldaq) {
-    hipLaunchKernelGGL(f_to_aq_kernel, g1((long)m * ldaq), dim3(256), 0, st, m, n, r, F, ldf, AQ, ldaq);
+void f_to_aq(hipStream_t st, int m, int n, int r, const double* F, long si, long sab, double* AQ, long ldaq) {
+    hipLaunchKernelGGL(f_to_aq_kernel, g1((long)m * ldaq), dim3(256), 0, st, m, n, r, F, si, sab, AQ, ldaq);
     WC_LAUNCH_CHECK();
 }
 

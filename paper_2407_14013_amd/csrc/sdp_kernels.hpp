@@ -8,6 +8,8 @@ namespace wc {
 void tri_tables(hipStream_t st, int n, int* pj, int* pk);
 void pack_dense_rows(hipStream_t st, int n, int m, long N2, long ldp, const double* A, const int* pj, const int* pk,
                      double* P);
+void unpack_rows(hipStream_t st, int m, long N2, long ldp, const double* P, const int* pj, const int* pk, int n,
+                 double* A);
 void packed_row_norm2(hipStream_t st, int m, long N2, long ldp, const double* P, const int* pj, const int* pk,
                       double* out);
 void pack_weighted(hipStream_t st, int n, long N2, long ldp, const double* M, long ldm, const int* pj, const int* pk,
@@ -24,9 +26,8 @@ void v_to_h(hipStream_t st, int n, int r, const double* v, double* Hm);
 void f_to_v(hipStream_t st, int n, int r, const double* F, long ldf, const double* vin, const double* sig, double t2,
             double* out);
 void symlr(hipStream_t st, int n, int r, const double* U, const double* Q, long ldq, double* M, long ldm, double beta);
-void phi_matrix(hipStream_t st, int n, int r, long N2, const int* pj, const int* pk, const double* G, double* Phi,
-                long ldphi);
-void f_to_aq(hipStream_t st, int m, int n, int r, const double* F, long ldf, double* AQ, long ldaq);
+// AQ rows from F_i = G_w^T A_i Q stored at F[i * si + (a + n b) * sab].
+void f_to_aq(hipStream_t st, int m, int n, int r, const double* F, long si, long sab, double* AQ, long ldaq);
 void aq_entry(hipStream_t st, int m, int n, int r, const int* jk, const double* G, double* AQ, long ldaq);
 void add_diag_vec(hipStream_t st, int d, double* A, long lda, const double* sig, double t2);
 void neg_div(hipStream_t st, int d, const double* qc, const double* sig, double* out);

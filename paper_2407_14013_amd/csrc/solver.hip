@@ -126,6 +126,9 @@ static void alloc_work(sdp_ctx* c) {
     c->YQ.alloc((long)n * c->rmax);
     c->F.alloc((long)n * c->rmax);
     c->AQ.alloc((long)m * c->dmaxp);
+    c->ldAQt = round_up(m, 32);
+    c->AQt.alloc(c->ldAQt * c->dmaxp);
+    fill(c->st, c->ldAQt * c->dmaxp, c->AQt, 0.0);
     c->Cm.alloc(c->dmaxp * c->dmaxp);
     c->Cinv.alloc(c->dmaxp * c->dmaxp);
     c->Zw.alloc(c->dmaxp * c->dmaxp);
@@ -135,12 +138,15 @@ static void alloc_work(sdp_ctx* c) {
     c->td3.alloc(c->dmaxp);
     c->rho.alloc(m + c->dmaxp + 32);
     c->dz.alloc(m + 32);
+    fill(c->st, m + c->dmaxp + 32, c->rho, 0.0);
+    fill(c->st, m + 32, c->dz, 0.0);
     if (c->kind == SDP_A_DENSE) {
         c->mw.alloc(c->ldP);
         c->yp.alloc(c->ldP);
-        long N2p = round_up(c->N2, 32);
-        c->Phi.alloc(N2p * (long)n * c->rmax);
-        c->Fq.alloc((long)m * n * c->rmax);
+        c->Tcat.alloc((long)m * n * c->rmax);
+        c->Fcat.alloc((long)m * n * c->rmax);
+        c->Afull.alloc((long)m * n * n);
+        unpack_rows(c->st, m, c->N2, c->ldP, c->P, c->pj, c->pk, n, c->Afull);
     }
     long gp = (long)gemv_cols_parts(m) * std::max<long>(round_up(c->N2, 2), c->dmaxp);
     gp = std::max(gp, (long)packed_cols_parts_f32(m) * round_up(c->N2, 4));
@@ -355,6 +361,7 @@ void ensure_scaling(sdp_ctx* c) {
     }
     int sw = jacobi_svd(st, n, c->Mt, n, c->Vs, n, c->dnt, 0.0, 60, c->jw, false, warm);
     if (sw < 0) throw Error(kENumeric, "Jacobi SVD of the NT factor did not converge");
+    c->sweeps_nt = sw;
     gemm(c, false, false, n, n, n, 1.0, c->L, n, c->Vs, n, 0.0, c->T1, n);
     scale_cols(st, n, n, c->T1, n, c->dnt, -0.5, c->G, n);
     gemm(c, true, false, n, n, n, 1.0, c->Vs, n, c->Linv, n, 0.0, c->T1, n);
@@ -367,6 +374,7 @@ void ensure_scaling(sdp_ctx* c) {
         transpose(st, n, n, c->G, n, c->Gt, n);
     }
     sw = jacobi_svd(st, n, c->Gt, n, c->Gw, n, c->lam, 0.0, 60, c->jw, false, warm);
+    c->sweeps_w = sw;
     c->have_prev = true;
     if (sw < 0) throw Error(kENumeric, "Jacobi eigen-decomposition of W did not converge");
     c->lam_h.resize(n);
@@ -394,13 +402,17 @@ void ensure_scaling(sdp_ctx* c) {
     // script-A script-Q, row i = script-Q^T svec(A_i)
     const int d = c->d;
     if (c->kind == SDP_A_DENSE) {
-        const long N2p = round_up(c->N2, 32);
-        phi_matrix(st, n, r, c->N2, c->pj, c->pk, c->Gw, c->Phi, N2p);
-        gemm(c, true, false, m, n * r, static_cast<int>(c->N2), 1.0, c->P, c->ldP, c->Phi, N2p, 0.0, c->Fq, m);
-        f_to_aq(st, m, n, r, c->Fq, m, c->AQ, c->dmaxp);
+        // T_i = A_i Q for every constraint (one batched GEMM), then
+        // F = G_w^T [T_1 ... T_m] (one GEMM), so F_i = G_w^T A_i Q
+        dgemm(st, false, false, n, r, n, 1.0, c->Afull, n, c->Gw, n, 0.0, c->Tcat, n, false, m, (long)n * n, 0,
+              (long)n * r);
+        gemm(c, true, false, n, m * r, n, 1.0, c->Gw, n, c->Tcat, n, 0.0, c->Fcat, n);
+        f_to_aq(st, m, n, r, c->Fcat, (long)n * r, 1, c->AQ, c->dmaxp);
     } else {
         aq_entry(st, m, n, r, c->jk, c->Gw, c->AQ, c->dmaxp);
     }
+    // row-major copy of (AQ)^T: the products (AQ)^T f become row passes
+    transpose(st, d, m, c->AQ, c->dmaxp, c->AQt, c->ldAQt);
     // Schur complement of the preconditioner: C = tau^2 Sigma + (AQ)^T (AQ) / beta, then C^{-1}
     gemm(c, false, true, d, d, m, 1.0 / c->beta, c->AQ, c->dmaxp, c->AQ, c->dmaxp, 0.0, c->Cm, c->dmaxp);
     add_diag_vec(st, d, c->Cm, c->dmaxp, c->sig, c->tau * c->tau);
@@ -471,7 +483,7 @@ void newton_apply_lowp(sdp_ctx* c, const double* in, double* out) {
         // top += AQ v (v staged in an aligned, zero-padded buffer); bottom = AQ^T u - tau^2 Sigma v
         copy(st, d, v, c->td2);
         gemv_rows(st, m, d, c->AQ, c->dmaxp, c->td2, out, 1.0, 1.0);
-        gemv_cols(st, m, d, c->AQ, c->dmaxp, u, c->td3, 1.0, 0.0, c->gpart);
+        gemv_rows(st, d, m, c->AQt, c->ldAQt, u, c->td3, 1.0, 0.0);
         aq_bottom(st, d, c->td3, c->sig, c->tau * c->tau, v, out + m);
     } else {
         fill(st, (long)n * n, c->Y, 0.0);
@@ -499,7 +511,7 @@ static void precond_block(sdp_ctx* c, const double* f, const double* h, double* 
     const int m = c->m, d = c->d;
     hipStream_t st = c->st;
     const double ib = 1.0 / c->beta;
-    gemv_cols(st, m, d, c->AQ, c->dmaxp, f, c->td, -ib, 0.0, c->gpart);   // td = -AQ^T f / beta
+    gemv_rows(st, d, m, c->AQt, c->ldAQt, f, c->td, -ib, 0.0);           // td = -AQ^T f / beta
     axpby(st, d, 1.0, h, 1.0, c->td);                                    // td += h
     gemv_rows(st, d, d, c->Cinv, c->dmaxp, c->td, zv, -1.0, 0.0);        // zv = -C^{-1} td
     gemv_rows(st, m, d, c->AQ, c->dmaxp, zv, c->tm, 1.0, 0.0);           // tm = AQ zv
@@ -522,7 +534,7 @@ static void precond_apply(sdp_ctx* c, const double* rv, double* z) {
     // rho = rv - P z:  rho_u = f - tm - beta z1,  rho_v = h - AQ^T z1 + tau^2 Sigma zv
     axpbypcz(st, m, 1.0, f, -1.0, c->tm, 0.0, c->rho);
     axpby(st, m, -c->beta, z1, 1.0, c->rho);
-    gemv_cols(st, m, d, c->AQ, c->dmaxp, z1, c->td3, 1.0, 0.0, c->gpart);     // td3 = AQ^T z1
+    gemv_rows(st, d, m, c->AQt, c->ldAQt, z1, c->td3, 1.0, 0.0);           // td3 = AQ^T z1
     rho_bottom(st, d, h, c->td3, c->sig, c->tau * c->tau, c->td2, c->rho + m);
     precond_block(c, c->rho, c->rho + m, c->dz, c->td3);
     axpby(st, m, 1.0, c->dz, 1.0, z1);
@@ -838,8 +850,11 @@ int ipm_step(sdp_ctx* c, sdp_step_stats* stats) {
     s.t_total_ms = std::chrono::duration<double, std::milli>(t3 - t0).count();
     s.t_inner_ms = s.t_total_ms - s.t_scaling_ms;
     if (c->opt.verbose)
-        fprintf(stderr, "[wcsdp] it %d mu %.3e relgap %.3e pinf %.3e dinf %.3e r %d pcg %d/%d ap %.3f ad %.3f\n",
-                c->iter, s.mu, s.relgap, s.pinf, s.dinf, s.r, s.pcg_pred, s.pcg_corr, ap, ad);
+        fprintf(stderr,
+                "[wcsdp] it %d mu %.3e relgap %.3e pinf %.3e dinf %.3e r %d pcg %d/%d ap %.3f ad %.3f "
+                "sweeps %d/%d t_scaling %.2f t_total %.2f ms\n",
+                c->iter, s.mu, s.relgap, s.pinf, s.dinf, s.r, s.pcg_pred, s.pcg_corr, ap, ad, c->sweeps_nt,
+                c->sweeps_w, s.t_scaling_ms, s.t_total_ms);
     if (stats) *stats = s;
     return 0;
 }

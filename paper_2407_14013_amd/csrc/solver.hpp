@@ -18,6 +18,7 @@ struct sdp_ctx {
     // ---- problem data -------------------------------------------------------
     long N2 = 0, ldP = 0;
     wc::DevBuf<double> P;       // dense: m x ldP packed rows A_i[j,k], j >= k (row-major)
+    wc::DevBuf<double> Afull;   // dense: the m symmetric A_i, n x n column-major each
     wc::DevBuf<int> pj, pk;     // packed index -> (j, k)
     wc::DevBuf<int> jk;         // entry: 2 m pairs
     wc::DevBuf<double> b, C;    // m, n x n
@@ -31,11 +32,13 @@ struct sdp_ctx {
     bool scaling_valid = false;
     bool have_prev = false;     // Vs / Gw hold the previous scaling's vectors (warm start)
     int rmax = 1, r = 1, d = 0;
+    int sweeps_nt = 0, sweeps_w = 0;  // Jacobi sweeps of the last NT SVD and eigen-decomposition of W
     long dmaxp = 0;             // padded row pitch for d-length rows
     double tau = 0, beta = 0;
     wc::DevBuf<double> L, Rs, Linv, Rinv, Mt, Vs, dnt, G, Ginv, Gt, Gw, lam, evE, E, sig;
     std::vector<double> lam_h;
-    wc::DevBuf<double> Phi, Fq, AQ, Cm, Cinv, Zw;
+    wc::DevBuf<double> Tcat, Fcat, AQ, AQt, Cm, Cinv, Zw;
+    long ldAQt = 0;             // AQt: (script-A script-Q)^T, d x m row-major, zero padded
     wc::JacobiWork jw;
     wc::LanczosWork lw;
 
