@@ -195,6 +195,184 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(int n, int nblk, int 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Small-n round kernel: the 32 columns of A (and of V) that a workgroup owns
+// stay in LDS for the whole round -- loaded once, used for the Gram matrix
+// and for the rotation -- and the inner two-sided Jacobi applies each
+// rotation round to H in one pass (H' = J^T H J element by element, ping-pong
+// buffers), so a rotation round costs one barrier pair instead of three
+// barriers.  Used when 2 * 32 * (n + 1) doubles plus the 32 x 32 work arrays
+// fit in the workgroup's LDS.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int jl_ld(int n) { return ((n + 15) / 16) * 16 + 1; }  // odd pitch: fewer bank conflicts
+
+__global__ __launch_bounds__(256) void jacobi_round_lds_kernel(int n, int nblk, int round, double* __restrict__ A,
+                                                               long lda, double* __restrict__ V, long ldv, double tol,
+                                                               unsigned long long* offmax,
+                                                               const int* __restrict__ done, int inner_sweeps) {
+    if (*done) return;
+    extern __shared__ double jl[];
+    const int ldb = jl_ld(n);
+    const int nr = ldb - 1;                    // rows rounded up to 16, zero padded
+    double* Ab = jl;                           // [32][ldb]: column c at Ab + c * ldb
+    double* Vb = jl + JW * ldb;                // same for V (when V != nullptr)
+    __shared__ double H0[JW][JW + 1], H1[JW][JW + 1], R[JW][JW + 1];
+    __shared__ int cols[JW];
+    __shared__ int ia1[JW], ia2[JW];
+    __shared__ double w1[JW], w2[JW];
+    __shared__ double red[4];
+    __shared__ int rot_any;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    int bi, bj;
+    tournament_pair(round, blockIdx.x, nblk, bi, bj);
+    if (tid < JW) {
+        int c = (tid < JB) ? bi * JB + tid : bj * JB + (tid - JB);
+        cols[tid] = (c < n) ? c : -1;
+    }
+    __syncthreads();
+    // ---- load both column blocks: thread `row` holds 16 loads in flight ------
+    // (nr <= 256 whenever this kernel is selected, so one row per thread)
+    if (tid < nr) {
+        const int row = tid;
+        for (int pass = 0; pass < 2; ++pass) {
+            const double* M = pass == 0 ? A : V;
+            double* Mb = pass == 0 ? Ab : Vb;
+            const long ldm = pass == 0 ? lda : ldv;
+            if (M == nullptr) break;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                double t[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int gc = cols[h * 16 + u];
+                    t[u] = (gc >= 0 && row < n) ? M[row + (long)gc * ldm] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u) Mb[(h * 16 + u) * ldb + row] = t[u];
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- 1. Gram matrix from LDS ----------------------------------------------
+    {
+        const int hi = wave >> 1, hj = wave & 1;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        const double* ca = Ab + (hi * 16 + (lane & 15)) * ldb + (lane >> 4);
+        const double* cb = Ab + (hj * 16 + (lane & 15)) * ldb + (lane >> 4);
+        for (int k4 = 0; k4 < nr; k4 += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[k4], cb[k4], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) H0[hi * 16 + (lane >> 4) + 4 * v][hj * 16 + (lane & 15)] = acc[v];
+    }
+    __syncthreads();
+
+    // ---- convergence measure of this pair ----------------------------------
+    double mx = 0.0;
+    for (int t = tid; t < JW * JW; t += 256) {
+        const int i = t % JW, j = t / JW;
+        if (i < j) {
+            const double hii = H0[i][i], hjj = H0[j][j];
+            if (hii > 0.0 && hjj > 0.0) mx = fmax(mx, fabs(H0[i][j]) / sqrt(hii * hjj));
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if (lane == 0) red[wave] = mx;
+    __syncthreads();
+    const double off_pair = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (tid == 0) atomicMax(offmax, static_cast<unsigned long long>(__double_as_longlong(off_pair)));
+    if (off_pair <= tol) return;  // uniform across the workgroup; A and V unchanged
+
+    // ---- 2. two-sided Jacobi on H (at most inner_sweeps sweeps) --------------
+    for (int t = tid; t < JW * JW; t += 256) {
+        const int i = t % JW, j = t / JW;
+        R[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    const double eps_in = 2.220446049250313e-16;
+    double (*Hc)[JW + 1] = H0;
+    double (*Hn)[JW + 1] = H1;
+    for (int sweep = 0; sweep < inner_sweeps; ++sweep) {
+        if (tid == 0) rot_any = 0;
+        __syncthreads();
+        for (int rr = 0; rr < JW - 1; ++rr) {
+            // rotation of pair (p, q): J[p][p] = J[q][q] = c, J[p][q] = s, J[q][p] = -s;
+            // column i of J has two entries: (a1[i], w1[i]) and (a2[i], w2[i])
+            if (tid < JB) {
+                int p, q;
+                tournament_pair(rr, tid, JW, p, q);
+                const double app = Hc[p][p], aqq = Hc[q][q], apq = Hc[p][q];
+                double c = 1.0, s = 0.0;
+                if (fabs(apq) > eps_in * sqrt(fabs(app * aqq)) && apq != 0.0) {
+                    const double th = (aqq - app) / (2.0 * apq);
+                    double t;
+                    if (fabs(th) > 1e150) t = 0.5 / th;
+                    else t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    s = t * c;
+                    rot_any = 1;
+                }
+                ia1[p] = p; w1[p] = c; ia2[p] = q; w2[p] = -s;
+                ia1[q] = p; w1[q] = s; ia2[q] = q; w2[q] = c;
+            }
+            __syncthreads();
+            // H' = J^T H J and R' = R J, element by element
+            for (int t = tid; t < JW * JW; t += 256) {
+                const int i = t % JW, j = t / JW;
+                const int ai = ia1[i], bi2 = ia2[i], aj = ia1[j], bj2 = ia2[j];
+                const double ui = w1[i], vi = w2[i], uj = w1[j], vj = w2[j];
+                Hn[i][j] = ui * (uj * Hc[ai][aj] + vj * Hc[ai][bj2]) + vi * (uj * Hc[bi2][aj] + vj * Hc[bi2][bj2]);
+            }
+            // R is updated in place column-pair by column-pair: each thread owns
+            // both columns of a pair for its rows
+            for (int t = tid; t < JB * JW; t += 256) {
+                const int k = t / JW, i = t % JW;
+                int p, q;
+                tournament_pair(rr, k, JW, p, q);
+                const double c = w1[p], s = w1[q];
+                const double rp = R[i][p], rq = R[i][q];
+                R[i][p] = c * rp - s * rq;
+                R[i][q] = s * rp + c * rq;
+            }
+            __syncthreads();
+            double (*tmp)[JW + 1] = Hc;
+            Hc = Hn;
+            Hn = tmp;
+        }
+        if (!rot_any) break;
+        __syncthreads();
+    }
+
+    // ---- 3. [A_i A_j] <- [A_i A_j] R and likewise V, from LDS to global -------
+    for (int pass = 0; pass < 2; ++pass) {
+        double* M = pass == 0 ? A : V;
+        const double* Mb = pass == 0 ? Ab : Vb;
+        const long ldm = pass == 0 ? lda : ldv;
+        if (M == nullptr) break;
+        for (int rt = wave; rt < nr / 16; rt += 4) {
+            const int r0 = rt * 16;
+#pragma unroll
+            for (int jt = 0; jt < 2; ++jt) {
+                d4 o = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int k4 = 0; k4 < JW; k4 += 4) {
+                    const int k = k4 + (lane >> 4);
+                    const double a = Mb[k * ldb + r0 + (lane & 15)];
+                    const double b = R[k][jt * 16 + (lane & 15)];
+                    o = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, o, 0, 0, 0);
+                }
+                const int gc = cols[jt * 16 + (lane & 15)];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = r0 + (lane >> 4) + 4 * v;
+                    if (gc >= 0 && row < n) M[row + (long)gc * ldm] = o[v];
+                }
+            }
+        }
+    }
+}
+
 // One wave per column: Euclidean norm of A(:, k) and the sign that makes the
 // largest-magnitude entry of V(:, k) positive (lowest row index on ties).
 __global__ __launch_bounds__(256) void col_norm_sign_kernel(int n, const double* __restrict__ A, long lda,
@@ -303,6 +481,15 @@ static int jacobi_inner_sweeps() {
     return v;
 }
 
+// The LDS-resident round kernel can be switched off (WCSDP_JACOBI_LDS=0; tuning only).
+static bool jacobi_lds_enabled() {
+    static bool v = [] {
+        const char* e = getenv("WCSDP_JACOBI_LDS");
+        return !(e && e[0] == '0');
+    }();
+    return v;
+}
+
 void JacobiWork::ensure(int n) {
     if (n <= cap) return;
     off.alloc(1);
@@ -332,13 +519,28 @@ int jacobi_svd(hipStream_t st, int n, double* A, long lda, double* V, long ldv, 
     int* flags = w.flags.get();
     hipLaunchKernelGGL(sweep_reset_kernel, dim3(1), dim3(1), 0, st, off, flags);
     WC_LAUNCH_CHECK();
+    // the LDS-resident round kernel when both column blocks fit
+    static const size_t lds_max = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 64 << 10;
+        return static_cast<size_t>(v);
+    }();
+    const size_t lds_dyn = (V ? 2 : 1) * (size_t)JW * jl_ld(n) * sizeof(double);
+    const size_t lds_static = 3 * JW * (JW + 1) * sizeof(double) + 4 * JW * sizeof(double) + 1024;
+    const bool use_lds = jl_ld(n) - 1 <= 256 && lds_dyn + lds_static <= lds_max && jacobi_lds_enabled();
     // sweeps are launched in groups; rounds after convergence return at once
     const int group = 3;
     bool done = false;
     for (int s = 0; s < max_sweeps && !done; ++s) {
         for (int round = 0; round < nblk - 1; ++round) {
-            hipLaunchKernelGGL(jacobi_round_kernel, dim3(nblk / 2), dim3(256), 0, st, n, nblk, round, A, lda, V, ldv,
-                               tol, off, flags, jacobi_inner_sweeps());
+            if (use_lds)
+                hipLaunchKernelGGL(jacobi_round_lds_kernel, dim3(nblk / 2), dim3(256), lds_dyn, st, n, nblk, round, A,
+                                   lda, V, ldv, tol, off, flags, jacobi_inner_sweeps());
+            else
+                hipLaunchKernelGGL(jacobi_round_kernel, dim3(nblk / 2), dim3(256), 0, st, n, nblk, round, A, lda, V,
+                                   ldv, tol, off, flags, jacobi_inner_sweeps());
             WC_LAUNCH_CHECK();
         }
         hipLaunchKernelGGL(sweep_end_kernel, dim3(1), dim3(1), 0, st, off, flags, tol);
