@@ -71,6 +71,53 @@ def gaussian_sensing(n: int, r: int, m: int, seed: int):
     }
 
 
+def generic_sensing(n: int, m: int, seed: int):
+    """A generic dense SDP: unique, nondegenerate and strictly complementary solution.
+
+    A_i as in gaussian_sensing; b = A(X0) for a random positive definite X0
+    (a strictly feasible primal point); C = B B^T / n + I/2 with B iid N(0,1)
+    (so y = 0, S = C is strictly dual feasible).  Nothing is planted, which
+    keeps the data generic (for the derivative of the solution map).
+    """
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((m, n, n)) / n
+    A = (0.5 * (G + G.transpose(0, 2, 1))).reshape(m, n * n)
+    F = rng.standard_normal((n, n))
+    X0 = F @ F.T / n + 0.5 * np.eye(n)
+    B = rng.standard_normal((n, n))
+    return {
+        "kind": "dense",
+        "n": n,
+        "m": m,
+        "A": np.ascontiguousarray(A),
+        "b": A @ X0.reshape(n * n),
+        "C": B @ B.T / n + 0.5 * np.eye(n),
+        "seed": seed,
+    }
+
+
+def generic_completion(n: int, m: int, seed: int):
+    """Entry-sampling SDP with generic data: observed entries of a random positive definite X0, random PD C."""
+    rng = np.random.default_rng(seed)
+    N2 = n * (n + 1) // 2
+    p = np.sort(rng.choice(N2, size=m, replace=False))
+    jlo, khi = _packed_index_to_pair(p, n)
+    j = np.minimum(jlo, khi).astype(np.int32)
+    k = np.maximum(jlo, khi).astype(np.int32)
+    F = rng.standard_normal((n, n))
+    X0 = F @ F.T / n + 0.5 * np.eye(n)
+    B = rng.standard_normal((n, n))
+    return {
+        "kind": "entry",
+        "n": n,
+        "m": m,
+        "jk": np.stack([j, k], axis=1).astype(np.int32),
+        "b": X0[j, k],
+        "C": B @ B.T / n + 0.5 * np.eye(n),
+        "seed": seed,
+    }
+
+
 def matrix_completion(n: int, r: int, m: int, seed: int):
     """Matrix-completion SDP: observe m distinct entries (j <= k) of X* = U U^T.
 
