@@ -220,6 +220,35 @@ sdp_status sdp_ipm_step(sdp_ctx* ctx, sdp_step_stats* stats);
  */
 sdp_status sdp_solve(sdp_ctx* ctx, sdp_result* res);
 
+typedef struct sdp_adjoint_stats {
+    int32_t centring_steps;   /* Newton centring steps that led to the point used */
+    int32_t inner_iterations; /* Krylov iterations, centring and gradient solves together */
+    int32_t converged;        /* 1 if the gradient solve met inner_tol */
+    double centrality;        /* max(||X S / mu - I||_F, pinf, dinf) at that point */
+    double mu;                /* the mu of the central-path point aimed at */
+} sdp_adjoint_stats;
+
+/*
+ * Gradient of a loss L(X) of the solution with respect to the data b and C
+ * (the paper does not treat derivatives; this follows from eq. Newt-eps).
+ * The Newton KKT operator [dX; dy] -> [-W^{-1} dX W^{-1} + A^T(dy); A(dX)] is
+ * self-adjoint and, on the central path, is exactly the linearisation of the
+ * path point in the data; so (dL/dC, dL/db) is the Newton direction with
+ * C~ = dL/dX, b~ = 0.  The current iterate (normally the output of sdp_solve)
+ * is first moved onto the central path at its own mu by pure centring Newton
+ * steps, to a distance of 1e-8 or until they stall (at most 12; the closest
+ * point is kept and becomes the context's iterate), and the gradient is that
+ * of the central-path point, which tends to the solution map's derivative as
+ * mu -> 0 when that derivative exists (nondegenerate, strictly complementary
+ * problems).  Without a strictly feasible point there is no central path and
+ * stats->centrality stays large: the result is then the Newton-system
+ * gradient at the iterate, not a derivative of the solution.  dL_dX (n x n symmetric, read), dL_db (m, written), dL_dC
+ * (n x n symmetric, written): device pointers.  stats may be NULL.  The inner
+ * solves use the context's inner precision.  Returns SDP_ENOTCONV if the
+ * gradient solve reached inner_maxit.
+ */
+sdp_status sdp_adjoint(sdp_ctx* ctx, const double* dL_dX, double* dL_db, double* dL_dC, sdp_adjoint_stats* stats);
+
 /* Copy the current iterate into device buffers (any may be NULL). */
 sdp_status sdp_get_point(sdp_ctx* ctx, double* X, double* y, double* S);
 

@@ -49,21 +49,31 @@ def kkt_gradient(problem, X, S, GX):
     return dX, dy
 
 
-def center(problem, X, y, S, mu=None, tol=1e-5, maxit=8):
+def center(problem, X, y, S, mu=None, tol=1e-8, maxit=12):
     """Newton steps towards the central-path point (A(X) = b, A^T(y) + S = C, XS = mu I).
 
     NT direction of eq. Newt-eps with b~ = r_p and C~ = R_d - G^{-T} H G^{-1},
     H = diag((mu - d_i^2) / d_i) (the corrector's H with sigma mu = mu and no
-    second-order term); step min(1, 0.95 alpha_max) for both X and S.  Stops
-    when ||d^2 / mu - 1|| <= tol (d^2 are the eigenvalues of XS).
+    second-order term); step min(1, 0.95 alpha_max) for both X and S.  The
+    distance to the point is max(||d^2 / mu - 1||, pinf, dinf) (d^2 are the
+    eigenvalues of XS; pinf, dinf the relative infeasibilities).  Stops when it
+    is <= tol, or when two steps in a row fail to reduce it by 10% (rounding
+    floor, or no central path: without a strictly feasible point the iterates
+    drift off instead); returns the closest point seen.
     """
     n = problem["n"]
     if mu is None:
         mu = float(np.sum(X * S)) / n
+    best = (np.inf, X, y, S)
+    stall = 0
     for _ in range(maxit):
         r = ipm.residuals(problem, X, y, S)
         G, d, _ = nt_factor(X, S)
-        if np.linalg.norm(d ** 2 / mu - 1.0) <= tol:
+        dev = max(np.linalg.norm(d ** 2 / mu - 1.0), r["pinf"], r["dinf"])
+        stall = stall + 1 if dev > 0.9 * best[0] else 0
+        if dev < best[0]:
+            best = (dev, X, y, S)
+        if dev <= tol or stall >= 2:
             break
         W = G @ G.T
         Gi = np.linalg.inv(G)
@@ -71,8 +81,21 @@ def center(problem, X, y, S, mu=None, tol=1e-5, maxit=8):
         Ct = r["Rd"] - Gi.T @ H @ Gi
         dX, dy, dS = ipm.newton_direct(problem, G, ipm.schur_factor(problem, G, W), r["rp"], Ct, r["Rd"])
         a = min(1.0, 0.95 * ipm.max_step(np.linalg.cholesky(X), dX), 0.95 * ipm.max_step(np.linalg.cholesky(S), dS))
+        while True:  # the eigenvalue bound is exact only up to rounding: confirm both stay PD
+            try:
+                np.linalg.cholesky(sym(X + a * dX))
+                np.linalg.cholesky(sym(S + a * dS))
+                break
+            except np.linalg.LinAlgError:
+                a *= 0.5
         X, y, S = sym(X + a * dX), y + a * dy, sym(S + a * dS)
-    return X, y, S
+    else:
+        r = ipm.residuals(problem, X, y, S)
+        G, d, _ = nt_factor(X, S)
+        dev = max(np.linalg.norm(d ** 2 / mu - 1.0), r["pinf"], r["dinf"])
+        if dev < best[0]:
+            best = (dev, X, y, S)
+    return best[1], best[2], best[3]
 
 
 def solution_gradient(problem, X, y, S, GX):

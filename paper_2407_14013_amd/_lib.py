@@ -93,6 +93,16 @@ class SdpStepStats(C.Structure):
     ]
 
 
+class SdpAdjointStats(C.Structure):
+    _fields_ = [
+        ("centring_steps", C.c_int32),
+        ("inner_iterations", C.c_int32),
+        ("converged", C.c_int32),
+        ("centrality", C.c_double),
+        ("mu", C.c_double),
+    ]
+
+
 class SdpResult(C.Structure):
     _fields_ = [
         ("status", C.c_int32),
@@ -127,6 +137,7 @@ _SIGNATURES = [
     ("sdp_newton_apply_prec", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     ("sdp_inner_solve", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SdpInnerStats)]),
     ("sdp_ipm_step", C.c_int32, [C.c_void_p, C.POINTER(SdpStepStats)]),
+    ("sdp_adjoint", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SdpAdjointStats)]),
     ("sdp_solve", C.c_int32, [C.c_void_p, C.POINTER(SdpResult)]),
     ("sdp_get_point", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("sdp_set_point", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

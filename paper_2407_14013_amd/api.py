@@ -153,6 +153,17 @@ class Context:
             self._check(st)
         return dX, dy, L.struct_dict(s)
 
+    def adjoint(self, dL_dX: torch.Tensor):
+        """(dL/db, dL/dC, stats) for a loss gradient dL/dX at the current (re-centred) iterate."""
+        n, m = self.n, self.m
+        G = dL_dX.detach().to(dtype=torch.float64).contiguous()
+        gb = torch.empty(m, dtype=torch.float64, device=G.device)
+        gC = torch.empty((n, n), dtype=torch.float64, device=G.device)
+        s = L.SdpAdjointStats()
+        self._check(self._lib.sdp_adjoint(self._ctx, _dptr(G, "dL_dX", n * n), _dptr(gb, "dL_db"), _dptr(gC, "dL_dC"),
+                                          C.byref(s)))
+        return gb, gC, L.struct_dict(s)
+
     def ipm_step(self) -> dict:
         s = L.SdpStepStats()
         self._check(self._lib.sdp_ipm_step(self._ctx, C.byref(s)))

@@ -157,6 +157,17 @@ sdp_status sdp_inner_solve(sdp_ctx* ctx, const double* b_tilde, const double* C_
     });
 }
 
+sdp_status sdp_adjoint(sdp_ctx* ctx, const double* dL_dX, double* dL_db, double* dL_dC, sdp_adjoint_stats* stats) {
+    if (!ctx) return SDP_EINVAL;
+    return guarded(ctx, [&]() {
+        wc::require(dL_dX && dL_db && dL_dC, "adjoint: NULL argument");
+        wc::require(dL_dX != dL_dC, "adjoint: dL_dX and dL_dC must not alias");
+        int rc = wc::adjoint(ctx, dL_dX, dL_db, dL_dC, stats);
+        if (rc != 0) ctx->last_error = "adjoint solve reached inner_maxit";
+        return (sdp_status)rc;
+    });
+}
+
 sdp_status sdp_ipm_step(sdp_ctx* ctx, sdp_step_stats* stats) {
     if (!ctx) return SDP_EINVAL;
     return guarded(ctx, [&]() { return (sdp_status)wc::ipm_step(ctx, stats); });

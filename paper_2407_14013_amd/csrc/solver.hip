@@ -859,6 +859,95 @@ int ipm_step(sdp_ctx* c, sdp_step_stats* stats) {
     return 0;
 }
 
+// ---- adjoint (derivative of the solution with respect to b and C) -------------------
+// The Newton KKT operator of eq. Newt-eps is self-adjoint, and on the central
+// path the NT linearisation is exactly the derivative of the path point with
+// respect to the data; so the gradient of a loss L(X) is the Newton direction
+// with C~ = dL/dX and b~ = 0 at the central-path point of the current mu.  The
+// iterate is first moved onto that point by pure centring Newton steps
+// (sigma = 1, no second-order term), each an inner solve as in ipm_step.
+int adjoint(sdp_ctx* c, const double* GX, double* gb, double* gC, sdp_adjoint_stats* stats) {
+    const int n = c->n, m = c->m;
+    const long nn = (long)n * n;
+    hipStream_t st = c->st;
+    Resid R = residuals(c);
+    const double mu = R.mu;
+    std::vector<double> dh(n);
+    // distance to the central-path point: max(||XS/mu - I||_F, pinf, dinf); the
+    // closest point seen is kept in (dXa, dya, dSa)
+    double best = std::numeric_limits<double>::infinity();
+    int best_step = -1, stall = 0, steps = 0, inner_its = 0;
+    const int max_center = 12;
+    const double tol_center = 1e-8;
+    for (;; ++steps) {
+        ensure_scaling(c);
+        WC_HIP(hipMemcpyAsync(dh.data(), c->dnt.get(), sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        WC_HIP(hipStreamSynchronize(st));
+        double dev = 0.0;
+        for (double di : dh) dev += (di * di / mu - 1.0) * (di * di / mu - 1.0);
+        dev = std::max({std::sqrt(dev), R.pinf, R.dinf});
+        stall = dev > 0.9 * best ? stall + 1 : 0;
+        if (dev < best) {
+            best = dev;
+            best_step = steps;
+            copy(st, nn, c->X, c->dXa);
+            copy(st, m, c->y, c->dya);
+            copy(st, nn, c->S, c->dSa);
+        }
+        if (c->opt.verbose)
+            fprintf(stderr, "[wcsdp] adjoint centring %d: distance to the central point %.3e\n", steps, dev);
+        // stop at the tolerance, at a stall (rounding floor, or no strictly
+        // feasible point: then the iterates drift away) or after max_center steps
+        if (dev <= tol_center || stall >= 2 || steps >= max_center) break;
+        // C~ = R_d - G^{-T} H G^{-1} with H = diag((mu - d_i^2) / d_i)
+        fill(st, nn, c->T2, 0.0);
+        corrector_h(st, n, c->T2, c->dnt, mu, c->Hc);
+        gemm(c, true, false, n, n, n, 1.0, c->Ginv, n, c->Hc, n, 0.0, c->T1, n);
+        gemm(c, false, false, n, n, n, 1.0, c->T1, n, c->Ginv, n, 0.0, c->T2, n);
+        axpbypcz(st, nn, 1.0, c->Rd, -1.0, c->T2, 0.0, c->Ct);
+        symmetrize(st, n, c->Ct, n);
+        sdp_inner_stats is{};
+        int rc = inner_solve(c, c->rp, c->Ct, c->dX, c->dy, &is);
+        inner_its += is.iterations;
+        if (rc != 0) break;  // keep the closest point so far
+        at_apply(c, c->dy, c->Y);
+        axpbypcz(st, nn, 1.0, c->Rd, -1.0, c->Y, 0.0, c->dS);
+        double a = std::min({1.0, 0.95 * max_step(c, c->Linv, c->dX), 0.95 * max_step(c, c->Rinv, c->dS)});
+        a = guard_step(c, c->X, c->dX, a);
+        a = guard_step(c, c->S, c->dS, a);
+        axpby(st, nn, a, c->dX, 1.0, c->X);
+        axpby(st, m, a, c->dy, 1.0, c->y);
+        axpby(st, nn, a, c->dS, 1.0, c->S);
+        symmetrize(st, n, c->X, n);
+        symmetrize(st, n, c->S, n);
+        c->scaling_valid = false;
+        R = residuals(c);
+    }
+    if (best_step != steps) {
+        copy(st, nn, c->dXa, c->X);
+        copy(st, m, c->dya, c->y);
+        copy(st, nn, c->dSa, c->S);
+        c->scaling_valid = false;
+    }
+    const double dev = best;
+    // gradient: Newton direction with C~ = sym(dL/dX), b~ = 0
+    copy(st, nn, GX, c->Ct);
+    symmetrize(st, n, c->Ct, n);
+    fill(st, m, c->dya, 0.0);
+    sdp_inner_stats is{};
+    int rc = inner_solve(c, c->dya, c->Ct, gC, gb, &is);
+    inner_its += is.iterations;
+    WC_HIP(hipStreamSynchronize(st));
+    if (stats) {
+        stats->centring_steps = best_step;
+        stats->centrality = dev;
+        stats->mu = mu;
+        stats->inner_iterations = inner_its;
+        stats->converged = rc == 0 ? 1 : 0;
+    }
+    return rc;
+}
+
 int solve(sdp_ctx* c, sdp_result* res) {
     using clk = std::chrono::steady_clock;
     const auto t0 = clk::now();

@@ -82,6 +82,7 @@ void newton_apply_lowp(sdp_ctx* c, const double* in, double* out);
 int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, double* dy, sdp_inner_stats* stats);
 int ipm_step(sdp_ctx* c, sdp_step_stats* stats);
 int solve(sdp_ctx* c, sdp_result* res);
+int adjoint(sdp_ctx* c, const double* GX, double* gb, double* gC, sdp_adjoint_stats* stats);
 void set_point(sdp_ctx* c, const double* X, const double* y, const double* S);
 void prof_begin(sdp_ctx* c, int k, hipEvent_t* e0);
 void prof_end(sdp_ctx* c, int k, hipEvent_t e0, double bytes);

@@ -10,6 +10,9 @@
   optimal value's sensitivity gives dL/db = y* and dL/dC = 0.
 * Central finite differences (step 1e-6) of full solves to a 1e-11 gap, in
   random joint (db, dC) directions.
+* Central finite differences (step 1e-7) of central-path points at a fixed
+  mu, which exist whenever both problems are strictly feasible -- also for
+  the planted, primal-degenerate sensing workload (config 0).
 
 The last two need a differentiable solution map, i.e. a nondegenerate,
 strictly complementary problem: generic data (workloads.generic_*).  The
@@ -79,3 +82,29 @@ def test_kkt_gradient_matches_finite_differences(which):
         # the central-path derivative at mu ~ 1e-9 vs the solution map's:
         # measured differences 1e-5 .. 2e-4 relative on these instances
         assert abs(an - fd) <= 5e-4 * max(abs(fd), 1e-8), (k, an, fd)
+
+
+def test_kkt_gradient_is_the_central_path_derivative():
+    p = workloads.config(0)
+    n, m = p["n"], p["m"]
+    res = ipm.solve(p, tol=1e-2)
+    mu = float(np.sum(res["X"] * res["S"])) / n
+    Xc, yc, Sc = adjoint.center(p, res["X"], res["y"], res["S"], mu=mu, tol=1e-13, maxit=40)
+    target = np.random.default_rng(11).standard_normal((n, 2))
+    target = target @ target.T
+
+    def loss(X):
+        return float(np.sum((X - target) ** 2))
+
+    gC, gb = adjoint.kkt_gradient(p, Xc, Sc, 2.0 * (Xc - target))
+    rng = np.random.default_rng(3)
+    h = 1e-7
+    for k in range(2):
+        db = rng.standard_normal(m)
+        M = rng.standard_normal((n, n))
+        dC = 0.5 * (M + M.T)
+        Xp = adjoint.center(adjoint.perturbed(p, db, dC, h), Xc, yc, Sc, mu=mu, tol=1e-13, maxit=40)[0]
+        Xm = adjoint.center(adjoint.perturbed(p, db, dC, -h), Xc, yc, Sc, mu=mu, tol=1e-13, maxit=40)[0]
+        fd = (loss(Xp) - loss(Xm)) / (2 * h)
+        an = float(gb @ db + np.sum(gC * dC))
+        assert abs(an - fd) <= 1e-5 * abs(fd), (k, an, fd)

@@ -118,6 +118,44 @@ def generic_completion(n: int, m: int, seed: int):
     }
 
 
+def planted_pair(n: int, r: int, m: int, seed: int, kind: str = "dense"):
+    """An SDP with a planted strictly complementary primal-dual solution.
+
+    X* = U U^T (rank r), S* = V V^T with V an orthonormal basis of the
+    complement of range(U) scaled by uniform(0.5, 2) weights, y* iid N(0,1);
+    then b = A(X*) and C = A^T(y*) + S*, so (X*, y*, S*) is optimal.  With
+    m = n r - r(r-1)/2 (the dimension of the tangent space at X*) and generic
+    A the solution is unique and nondegenerate, so the solution map is
+    differentiable.  kind "dense": A_i as in gaussian_sensing; "entry":
+    distinct sampled entries (j <= k), A_i = sym(e_j e_k^T).
+    """
+    rng = np.random.default_rng(seed)
+    U = rng.standard_normal((n, r))
+    Qf, _ = np.linalg.qr(np.concatenate([U, rng.standard_normal((n, n - r))], axis=1))
+    Vc = Qf[:, r:] * np.sqrt(rng.uniform(0.5, 2.0, n - r))
+    Ss = Vc @ Vc.T
+    ys = rng.standard_normal(m)
+    Xs = U @ U.T
+    out = {"n": n, "m": m, "r": r, "U": U, "y_star": ys, "S_star": Ss, "seed": seed}
+    if kind == "dense":
+        G = rng.standard_normal((m, n, n)) / n
+        A = (0.5 * (G + G.transpose(0, 2, 1))).reshape(m, n * n)
+        out.update(kind="dense", A=np.ascontiguousarray(A), b=A @ Xs.reshape(n * n),
+                   C=(A.T @ ys).reshape(n, n) + Ss)
+    else:
+        N2 = n * (n + 1) // 2
+        pidx = np.sort(rng.choice(N2, size=m, replace=False))
+        jlo, khi = _packed_index_to_pair(pidx, n)
+        j = np.minimum(jlo, khi).astype(np.int32)
+        k = np.maximum(jlo, khi).astype(np.int32)
+        Aty = np.zeros((n, n))
+        np.add.at(Aty, (j, k), 0.5 * ys)
+        np.add.at(Aty, (k, j), 0.5 * ys)
+        out.update(kind="entry", jk=np.stack([j, k], axis=1), b=Xs[j, k], C=Aty + Ss)
+    out["C"] = 0.5 * (out["C"] + out["C"].T)
+    return out
+
+
 def matrix_completion(n: int, r: int, m: int, seed: int):
     """Matrix-completion SDP: observe m distinct entries (j <= k) of X* = U U^T.
 
