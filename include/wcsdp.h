@@ -249,6 +249,44 @@ typedef struct sdp_adjoint_stats {
  */
 sdp_status sdp_adjoint(sdp_ctx* ctx, const double* dL_dX, double* dL_db, double* dL_dC, sdp_adjoint_stats* stats);
 
+/*
+ * Pass configuration of the batched solver, chosen per size bucket by
+ * sdp_autotune_batched: packed constraint rows each wave streams at once in
+ * the A(M) pass (1, 2 or 4) and constraints per group when script-A script-Q
+ * is formed (4, 8 or 16).
+ */
+typedef struct sdp_batch_tune {
+    int32_t rows_per_wave;
+    int32_t aq_group;
+} sdp_batch_tune;
+
+/*
+ * Solve `count` independent problems in one persistent launch: each
+ * workgroup takes instances from a queue (largest first) and runs the whole
+ * interior-point method of sdp_solve (FP64, PCG) for one instance at a time.
+ * Dense constraint data only (a_kind SDP_A_DENSE), host inputs (on_device 0),
+ * n_i <= 128 recommended (every workgroup keeps O(n^2 + m d + d^2) doubles of
+ * scratch).  results: count entries (time_ms is the whole launch).  X_out,
+ * y_out: NULL or host arrays of `count` device pointers (NULL entries
+ * allowed) receiving X_i (n_i x n_i) and y_i (m_i).  tune: NULL (defaults) or
+ * `count` configurations.  Uses opt's rank_max, inner_tol, inner_maxit,
+ * gap_tol, feas_tol, max_ipm_iter and step_frac; status per instance in
+ * results[i].status.
+ */
+sdp_status sdp_solve_batched(const sdp_problem* probs, int32_t count, const sdp_options* opt, void* hip_stream,
+                             sdp_result* results, double* const* X_out, double* const* y_out,
+                             const sdp_batch_tune* tune);
+
+/*
+ * Autotuner of the batched solver: for each size bucket (n < 48, n < 96,
+ * larger) times every candidate configuration on up to 8 of the bucket's
+ * instances for two interior-point iterations and writes the fastest to
+ * tune_out[i] for every instance; bucket_ms (3 entries, may be NULL) receives
+ * the winning times.
+ */
+sdp_status sdp_autotune_batched(const sdp_problem* probs, int32_t count, const sdp_options* opt, void* hip_stream,
+                                sdp_batch_tune* tune_out, double* bucket_ms);
+
 /* Copy the current iterate into device buffers (any may be NULL). */
 sdp_status sdp_get_point(sdp_ctx* ctx, double* X, double* y, double* S);
 

@@ -103,6 +103,13 @@ class SdpAdjointStats(C.Structure):
     ]
 
 
+class SdpBatchTune(C.Structure):
+    _fields_ = [
+        ("rows_per_wave", C.c_int32),
+        ("aq_group", C.c_int32),
+    ]
+
+
 class SdpResult(C.Structure):
     _fields_ = [
         ("status", C.c_int32),
@@ -137,6 +144,10 @@ _SIGNATURES = [
     ("sdp_newton_apply_prec", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     ("sdp_inner_solve", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SdpInnerStats)]),
     ("sdp_ipm_step", C.c_int32, [C.c_void_p, C.POINTER(SdpStepStats)]),
+    ("sdp_solve_batched", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(SdpOptions), C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("sdp_autotune_batched", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(SdpOptions), C.c_void_p, C.c_void_p,
+                                         C.POINTER(C.c_double)]),
     ("sdp_adjoint", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SdpAdjointStats)]),
     ("sdp_solve", C.c_int32, [C.c_void_p, C.POINTER(SdpResult)]),
     ("sdp_get_point", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -7,6 +7,7 @@
 #include "../../include/wcsdp_linalg.h"
 #include "sdp_kernels.hpp"
 #include "lowprec.hpp"
+#include "batched.hpp"
 #include "solver.hpp"
 
 namespace {
@@ -166,6 +167,37 @@ sdp_status sdp_adjoint(sdp_ctx* ctx, const double* dL_dX, double* dL_db, double*
         if (rc != 0) ctx->last_error = "adjoint solve reached inner_maxit";
         return (sdp_status)rc;
     });
+}
+
+sdp_status sdp_solve_batched(const sdp_problem* probs, int32_t count, const sdp_options* opt, void* hip_stream,
+                             sdp_result* results, double* const* X_out, double* const* y_out,
+                             const sdp_batch_tune* tune) {
+    try {
+        wc::require(probs && results && count >= 1, "solve_batched: NULL argument or count < 1");
+        wc::solve_batched(probs, count, opt, static_cast<hipStream_t>(hip_stream), results, X_out, y_out, tune);
+        return SDP_OK;
+    } catch (const wc::Error& e) {
+        g_setup_error = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_setup_error = e.what();
+        return SDP_EDEVICE;
+    }
+}
+
+sdp_status sdp_autotune_batched(const sdp_problem* probs, int32_t count, const sdp_options* opt, void* hip_stream,
+                                sdp_batch_tune* tune_out, double* bucket_ms) {
+    try {
+        wc::require(probs && tune_out && count >= 1, "autotune_batched: NULL argument or count < 1");
+        wc::autotune_batched(probs, count, opt, static_cast<hipStream_t>(hip_stream), tune_out, bucket_ms);
+        return SDP_OK;
+    } catch (const wc::Error& e) {
+        g_setup_error = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_setup_error = e.what();
+        return SDP_EDEVICE;
+    }
 }
 
 sdp_status sdp_ipm_step(sdp_ctx* ctx, sdp_step_stats* stats) {

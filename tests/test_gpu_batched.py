@@ -1,0 +1,67 @@
+"""GPU checks of the batched persistent solver (sdp_solve_batched, sdp_autotune_batched).
+
+An uneven batch of Gaussian sensing problems (n from 18 to 30, r in {1,2,3},
+m = 3 n r, the generator of the batched workload at sizes the oracle solves
+in seconds) is solved in one launch and every instance is checked like the
+single-instance solver: objective within 1e-8 of the oracle's, relative gap
+and primal infeasibility <= 1e-8 recomputed on the CPU from the returned X
+and y, X positive definite and C - A^T(y) PSD to rounding, and the planted
+low-rank solution recovered.  The autotuner's choice must give the same
+answers, and instances solved alone must agree with the batch.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import workloads  # noqa: E402
+from oracle import ipm, operators as ops  # noqa: E402
+from paper_2407_14013_amd.batched import autotune, solve_batched  # noqa: E402
+
+
+def batch(count=10, seed=7):
+    return workloads.batched_sensing(count, seed=seed, n_lo=18, n_hi=30)
+
+
+def check_instance(p, res, X, y, pobj_ref):
+    assert res["status"] == 0, res
+    X = X.detach().cpu().numpy()
+    y = y.detach().cpu().numpy()
+    rp = p["b"] - ops.a_op(p, X)
+    pinf = np.linalg.norm(rp) / (1.0 + np.linalg.norm(p["b"]))
+    pobj = float(np.sum(p["C"] * X))
+    dobj = float(p["b"] @ y)
+    relgap = abs(pobj - dobj) / (1.0 + abs(pobj) + abs(dobj))
+    assert pinf <= 1.01e-8 and relgap <= 1.01e-8, (pinf, relgap)
+    assert np.linalg.eigvalsh(X)[0] > 0
+    S = p["C"] - ops.at_op(p, y)
+    assert np.linalg.eigvalsh(S)[0] >= -1e-6 * np.linalg.norm(p["C"])
+    e_obj = abs(pobj - pobj_ref) / abs(pobj_ref)
+    assert e_obj <= 1e-8, (pobj, pobj_ref)
+    Xs = p["U"] @ p["U"].T
+    return e_obj, np.linalg.norm(X - Xs) / np.linalg.norm(Xs)
+
+
+def test_batched_matches_oracle():
+    probs = batch()
+    refs = [ipm.solve(p)["history"][-1]["pobj"] for p in probs]
+    results, Xs, ys = solve_batched(probs, want_y=True)
+    for i, p in enumerate(probs):
+        e_obj, e_rec = check_instance(p, results[i], Xs[i], ys[i], refs[i])
+        print(f"instance {i}: n {p['n']} r {p['r']} m {p['m']} its {results[i]['iterations']} "
+              f"pcg {results[i]['pcg_iterations']} objective error {e_obj:.1e} recovery {e_rec:.1e}")
+        assert e_rec <= 1e-6
+
+
+def test_batched_autotune_and_single_instances_agree():
+    probs = batch(count=6, seed=8)
+    tune, ms = autotune(probs)
+    assert all(t.rows_per_wave in (1, 2, 4) and t.aq_group in (4, 8, 16) for t in tune)
+    r_all, X_all, _ = solve_batched(probs, tune=tune)
+    for i, p in enumerate(probs):
+        r_one, X_one, _ = solve_batched([p])
+        assert r_all[i]["status"] == 0 and r_one[0]["status"] == 0
+        e = abs(r_all[i]["pobj"] - r_one[0]["pobj"]) / abs(r_one[0]["pobj"])
+        assert e <= 1e-10
