@@ -118,6 +118,118 @@ def pmc_pass():
     print(f"pmc pass: 10 operator applications, 3 copies of {src.numel() * 8} bytes", flush=True)
 
 
+def bench_batched(args):
+    """Config 3: 1024 Gaussian sensing SDPs (n in [16,128], r in {1,2,3}, m = 3nr) in one persistent launch."""
+    import torch
+
+    import workloads
+    from paper_2407_14013_amd.batched import autotune, solve_batched
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    probs = workloads.config(3)
+    gen_s = time.perf_counter() - t0
+    print(f"generated {len(probs)} instances in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    tune, bucket_ms = autotune(probs)
+    tune_s = time.perf_counter() - t0
+    print(f"autotuned in {tune_s:.1f} s", file=sys.stderr, flush=True)
+    results, Xs, _ = solve_batched(probs, tune=tune)
+    torch.cuda.synchronize()
+    launch_ms = results[0]["time_ms"]
+    ok = sum(r["status"] == 0 for r in results)
+    # algorithmic bytes of the packed constraint passes: two passes per PCG iteration
+    nbytes = 0.0
+    for p, r in zip(probs, results):
+        ldp = (p["n"] * (p["n"] + 1) // 2 + 1) // 2 * 2
+        nbytes += 2.0 * r["pcg_iterations"] * p["m"] * ldp * 8
+    line = {
+        "metric": "IPM time-to-1e-8 gap, batched",
+        "value": len(probs) / (launch_ms * 1e-3),
+        "unit": "instances/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "1024 gaussian sensing SDPs, n in [16,128], r in {1,2,3}, m = 3nr (dense A, FP64)"},
+        "launch_ms": launch_ms,
+        "solved": ok,
+        "ipm_iterations_total": int(sum(r["iterations"] for r in results)),
+        "pcg_iterations_total": int(sum(r["pcg_iterations"] for r in results)),
+        "autotune": {"bucket_ms": bucket_ms, "configs": sorted({(t.rows_per_wave, t.aq_group) for t in tune})},
+        "a_pass_bytes": nbytes,
+        "a_pass_gbs_lower_bound": nbytes / (launch_ms * 1e-3) / 1e9,
+        "generate_s": gen_s,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import ipm
+
+        try:
+            from threadpoolctl import threadpool_info
+
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        except Exception:
+            threads = os.cpu_count()
+        sample = sorted(range(len(probs)), key=lambda i: probs[i]["m"] * probs[i]["n"] ** 2)[::128][:6]
+        t0 = time.perf_counter()
+        for i in sample:
+            ipm.solve(probs[i])
+        el = time.perf_counter() - t0
+        work = sum(probs[i]["m"] * probs[i]["n"] ** 2 for i in sample)
+        total = sum(p["m"] * p["n"] ** 2 for p in probs)
+        line["cpu_baseline"] = {
+            "value": len(probs) / (el * total / work),
+            "unit": "instances/s",
+            "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{len(sample)} instances spread over the size range solved by the oracle in {el:.1f} s, "
+                      f"scaled to the whole batch by sum(m n^2)",
+        }
+    print(json.dumps(line))
+
+
+def bench_adjoint(args):
+    """Config 4: FP64 solve of the n=1000 completion SDP, then the KKT adjoint with the FP32 inner operator."""
+    import torch
+
+    import workloads
+    from paper_2407_14013_amd import Context
+    from paper_2407_14013_amd import _lib as L
+
+    torch.cuda.set_device(0)
+    p = workloads.config(4)
+    n = p["n"]
+    V = np.random.default_rng(1).standard_normal((n, 3))
+    target = torch.from_numpy(V @ V.T).cuda()
+    with Context(p) as fwd:
+        t0 = time.perf_counter()
+        res = fwd.solve()
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        X, y, S = fwd.get_point()
+    with Context(p, inner_prec=L.SDP_PREC_F32) as bwd:
+        bwd.set_point(X, y, S)
+        t0 = time.perf_counter()
+        gb, gC, st = bwd.adjoint(2.0 * (X - target))
+        torch.cuda.synchronize()
+        t_bwd = time.perf_counter() - t0
+    line = {
+        "metric": "SDP layer forward (FP64 solve) and backward (FP32-inner KKT adjoint) time",
+        "value": t_fwd + t_bwd,
+        "unit": "s",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "matrix completion SDP n=1000 r=3 m=30000, loss ||X - X_target||_F^2"},
+        "forward": {"time_s": t_fwd, "iterations": res["iterations"], "pcg_iterations": res["pcg_iterations"],
+                    "relgap": res["relgap"]},
+        "backward": {"time_s": t_bwd, **st},
+        "grad_norms": {"dL_db": float(gb.norm()), "dL_dC": float(gC.norm())},
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +239,9 @@ def main():
     ap.add_argument("--apply-loop", type=int, default=200)
     ap.add_argument("--pmc-pass", action="store_true", help="only the short run profiled for HBM counters")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solves")
+    ap.add_argument("--workload", choices=["sensing", "batched", "adjoint"], default="sensing",
+                    help="sensing: the headline line (n=200 dense); batched: 1024 small SDPs in one launch; "
+                         "adjoint: n=1000 completion forward + backward")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every instance of this workload fits one MI355X, "
@@ -134,6 +249,12 @@ def main():
         sys.exit(2)
     if args.pmc_pass:
         pmc_pass()
+        return
+    if args.workload == "batched":
+        bench_batched(args)
+        return
+    if args.workload == "adjoint":
+        bench_adjoint(args)
         return
 
     import torch

@@ -90,7 +90,7 @@ typedef struct sdp_problem {
  *               (median eigenvalue of E)^2 * mean ||A_i||_F^2 [0]
  *  solver       SDP_SOLVER_PCG (Corollary pcg) or SDP_SOLVER_MINRES (Corollary minres) [PCG]
  *  inner_tol    PCG stops when ||r_u|| <= inner_tol * ||r_u(0)|| [1e-10]
- *  inner_maxit  [500]
+ *  inner_maxit  [2000]
  *  inner_prec   precision of the inner operator [SDP_PREC_F64].  SDP_PREC_F32:
  *               the A E A^T block of the augmented operator with E Y E on the
  *               FP32 matrix cores and, for dense A, the two constraint passes
@@ -252,8 +252,8 @@ sdp_status sdp_adjoint(sdp_ctx* ctx, const double* dL_dX, double* dL_db, double*
 /*
  * Pass configuration of the batched solver, chosen per size bucket by
  * sdp_autotune_batched: packed constraint rows each wave streams at once in
- * the A(M) pass (1, 2 or 4) and constraints per group when script-A script-Q
- * is formed (4, 8 or 16).
+ * the A(M) pass (1 to 4) and constraints per group when script-A script-Q is
+ * formed (1 to 16).
  */
 typedef struct sdp_batch_tune {
     int32_t rows_per_wave;

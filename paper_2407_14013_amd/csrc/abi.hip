@@ -57,7 +57,7 @@ void sdp_default_options(sdp_options* o) {
     o->beta = 0.0;
     o->solver = SDP_SOLVER_PCG;
     o->inner_tol = 1e-10;
-    o->inner_maxit = 500;
+    o->inner_maxit = 2000;
     o->inner_prec = SDP_PREC_F64;
     o->max_refine = 8;
     o->gap_tol = 1e-8;

@@ -1240,6 +1240,8 @@ void stage(const sdp_problem* probs, int count, const sdp_options& o, hipStream_
         I.rmax = std::max(1, std::min(o.rank_max, n - 1));
         I.rows_per_wave = tune ? tune[i].rows_per_wave : 2;
         I.aq_group = tune ? tune[i].aq_group : 8;
+        require(I.rows_per_wave >= 1 && I.rows_per_wave <= 4 && I.aq_group >= 1 && I.aq_group <= 16,
+                "batch tune out of range (rows_per_wave 1..4, aq_group 1..16)");
         I.N2 = N2;
         I.ldp = ldp;
         I.P = S.data.get() + off;

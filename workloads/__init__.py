@@ -188,7 +188,11 @@ def matrix_completion(n: int, r: int, m: int, seed: int):
 
 
 def batched_sensing(count: int, seed: int, n_lo: int = 16, n_hi: int = 128):
-    """Many small Gaussian sensing SDPs: n ~ U{n_lo..n_hi}, r ~ U{1,2,3}, m = 3 n r."""
+    """Many small Gaussian sensing SDPs: n ~ U{n_lo..n_hi}, r ~ U{1,2,3}, m = 3 n r.
+
+    m is capped at n(n+1)/2, the number of independent constraints on a
+    symmetric n x n matrix (3 n r exceeds it only for n = 16, r = 3).
+    """
     rng = np.random.default_rng(seed)
     ns = rng.integers(n_lo, n_hi + 1, size=count)
     rs = rng.integers(1, 4, size=count)
@@ -197,7 +201,7 @@ def batched_sensing(count: int, seed: int, n_lo: int = 16, n_hi: int = 128):
     for n, r, s in zip(ns, rs, subseeds):
         n = int(n)
         r = int(r)
-        out.append(gaussian_sensing(n, r, 3 * n * r, int(s)))
+        out.append(gaussian_sensing(n, r, min(3 * n * r, n * (n + 1) // 2), int(s)))
     return out
 
 
