@@ -286,7 +286,9 @@ int32_t wc_dgemm(void* stream, char transa, char transb, int32_t m, int32_t n, i
         wc::require(ldc >= std::max(1, m), "ldc too small");
         wc::require(lda >= std::max(1, ta ? k : m), "lda too small");
         wc::require(ldb >= std::max(1, tb ? n : k), "ldb too small");
-        wc::dgemm(static_cast<hipStream_t>(stream), ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (tb || !wc::dgemm_thin(st, ta, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc))
+            wc::dgemm(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
         return (int32_t)0;
     });
 }

@@ -160,6 +160,100 @@ void dgemm(hipStream_t st, bool ta, bool tb, int m, int n, int k, double alpha, 
 }
 
 // ---------------------------------------------------------------------------
+// Thin GEMM, N <= 16 (the n x r products of the augmented operator): the
+// MFMA tiles above would leave most of a 64-wide tile idle and walk K in a
+// serial chain.  op(A) = A: one thread per output row, B staged in LDS.
+// op(A) = A^T: one wave per output row (a contiguous column of A), lanes
+// over K, wave reduction.
+// ---------------------------------------------------------------------------
+constexpr int THIN_N = 16;
+constexpr int THIN_LDS = 4096;  // doubles of B staged in LDS
+
+// 64 rows per workgroup; the four waves split K and their partial sums are
+// added in LDS in wave order.
+__global__ __launch_bounds__(256) void dgemm_thin_n_kernel(int M, int N, int K, double alpha,
+                                                           const double* __restrict__ A, long lda,
+                                                           const double* __restrict__ B, long ldb, double beta,
+                                                           double* __restrict__ C, long ldc) {
+    __shared__ double Bs[THIN_LDS];
+    __shared__ double part[4][THIN_N][64];
+    for (int t = threadIdx.x; t < K * N; t += 256) Bs[t] = B[(t % K) + (long)(t / K) * ldb];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
+    const int kc = (K + 3) / 4;
+    const int k0 = wv * kc, k1 = min(K, k0 + kc);
+    double acc[THIN_N];
+#pragma unroll
+    for (int j = 0; j < THIN_N; ++j) acc[j] = 0.0;
+    if (i < M) {
+#pragma unroll 8
+        for (int k = k0; k < k1; ++k) {
+            const double a = A[i + (long)k * lda];
+#pragma unroll
+            for (int j = 0; j < THIN_N; ++j)
+                if (j < N) acc[j] += a * Bs[k + j * K];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < THIN_N; ++j)
+        if (j < N) part[wv][j][lane] = acc[j];
+    __syncthreads();
+    if (wv == 0 && i < M) {
+        for (int j = 0; j < N; ++j) {
+            const double v = ((part[0][j][lane] + part[1][j][lane]) + part[2][j][lane]) + part[3][j][lane];
+            double* c = C + i + (long)j * ldc;
+            *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void dgemm_thin_t_kernel(int M, int N, int K, double alpha,
+                                                           const double* __restrict__ A, long lda,
+                                                           const double* __restrict__ B, long ldb, double beta,
+                                                           double* __restrict__ C, long ldc) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= M) return;  // whole waves leave together
+    const double* a = A + (long)i * lda;
+    double acc[THIN_N];
+#pragma unroll
+    for (int j = 0; j < THIN_N; ++j) acc[j] = 0.0;
+    for (int k = lane; k < K; k += 64) {
+        const double av = a[k];
+#pragma unroll
+        for (int j = 0; j < THIN_N; ++j)
+            if (j < N) acc[j] += av * B[k + (long)j * ldb];
+    }
+#pragma unroll
+    for (int j = 0; j < THIN_N; ++j) {
+        if (j >= N) break;
+        double v = acc[j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) {
+            double* c = C + i + (long)j * ldc;
+            *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
+        }
+    }
+}
+
+bool dgemm_thin(hipStream_t st, bool ta, int m, int n, int k, double alpha, const double* A, long lda,
+                const double* B, long ldb, double beta, double* C, long ldc) {
+    if (n < 1 || n > THIN_N || m < 1 || k < 1) return false;
+    if (!ta) {
+        if ((long)k * n > THIN_LDS) return false;
+        hipLaunchKernelGGL(dgemm_thin_n_kernel, dim3(cdiv(m, 64)), dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb,
+                           beta, C, ldc);
+    } else {
+        hipLaunchKernelGGL(dgemm_thin_t_kernel, dim3(cdiv(m, 4)), dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb,
+                           beta, C, ldc);
+    }
+    WC_LAUNCH_CHECK();
+    return true;
+}
+
+// ---------------------------------------------------------------------------
 // Wave / block reductions.
 // ---------------------------------------------------------------------------
 __device__ inline double wave_sum(double v) {

@@ -84,6 +84,11 @@ void dgemm(hipStream_t st, bool ta, bool tb, int m, int n, int k, double alpha, 
            const double* B, long ldb, double beta, double* C, long ldc, bool lower_only = false, int batch = 1,
            long sA = 0, long sB = 0, long sC = 0);
 
+// C = alpha op(A) B + beta C for a thin B (n <= 16 columns); returns false
+// (nothing launched) when the shape is not handled.
+bool dgemm_thin(hipStream_t st, bool ta, int m, int n, int k, double alpha, const double* A, long lda,
+                const double* B, long ldb, double beta, double* C, long ldc);
+
 // y = alpha A x + beta y for row-major A (m rows, k used columns, row pitch
 // lda, lda even, 16-byte aligned rows); x must be readable up to
 // round_up(k, 2) with a zero pad.

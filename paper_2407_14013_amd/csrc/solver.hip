@@ -103,7 +103,8 @@ static void gemm(sdp_ctx* c, bool ta, bool tb, int m, int n, int k, double alpha
                  const double* B, long ldb, double beta, double* C, long ldc) {
     hipEvent_t e;
     prof_begin(c, SDP_K_GEMM, &e);
-    dgemm(c->st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+    if (tb || !dgemm_thin(c->st, ta, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc))
+        dgemm(c->st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
     prof_end(c, SDP_K_GEMM, e, 8.0 * ((double)m * k + (double)k * n + 2.0 * (double)m * n));
 }
 
