@@ -103,7 +103,9 @@ typedef struct sdp_problem {
  *               and step lengths stay FP64.
  *  max_refine   FP64 refinement sweeps around a low-precision inner solve [8]
  *  refine_tol   relative residual reduction asked of each low-precision PCG
- *               run inside a refinement sweep [1e-4]
+ *               run inside a refinement sweep (0: 1e-6 for FP32, 1e-3 for
+ *               BF16); later sweeps ask only for the reduction still missing
+ *               to inner_tol when that is larger [0]
  *  gap_tol, feas_tol   stopping tolerances of the interior-point method [1e-8]
  *  max_ipm_iter [100]
  *  step_frac    fraction of the step to the boundary [0.98]

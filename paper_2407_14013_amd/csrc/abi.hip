@@ -65,7 +65,7 @@ void sdp_default_options(sdp_options* o) {
     o->max_ipm_iter = 100;
     o->step_frac = 0.98;
     o->verbose = 0;
-    o->refine_tol = 1e-4;
+    o->refine_tol = 0.0;
 }
 
 sdp_status sdp_setup(const sdp_problem* prob, const sdp_options* opt, void* hip_stream, sdp_ctx** out) {

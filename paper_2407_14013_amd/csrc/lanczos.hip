@@ -51,7 +51,10 @@ __global__ __launch_bounds__(LZ_THREADS) void lanczos_kernel(int n, const double
     const long ldq = n;
     __shared__ double red[LZ_WAVES];
     __shared__ double h[LZ_MAX_K + 1];
+    __shared__ double ta[LZ_MAX_K], tb[LZ_MAX_K];  // the tridiagonal so far
+    __shared__ int first_hit;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double theta_prev = 0.0, tnorm = 0.0;
     const int clen = (n + nch - 1) / nch;
 
     // deterministic start vector with no special structure
@@ -129,9 +132,50 @@ __global__ __launch_bounds__(LZ_THREADS) void lanczos_kernel(int n, const double
         if (tid == 0) {
             ab[j] = alpha;
             ab[kmax + j] = beta;
+            ta[j] = alpha;
+            tb[j] = beta;
         }
         k = j + 1;
         if (!(beta > 1e-13 * (fabs(alpha) + beta_prev)) || j + 1 == kmax) break;  // invariant subspace or done
+        tnorm = fmax(tnorm, fabs(alpha) + beta + beta_prev);
+        // every 8 steps: smallest eigenvalue of the tridiagonal so far by
+        // multisection (every thread tests one point per round); stop once it
+        // has settled -- the Ritz values only move down towards lambda_min,
+        // and the caller confirms the resulting step with a Cholesky test
+        if (k >= 16 && (k & 7) == 0) {
+            __syncthreads();
+            double lo = ta[0], hi = ta[0];
+            for (int i = 0; i < k; ++i) {
+                const double rr = (i > 0 ? fabs(tb[i - 1]) : 0.0) + (i + 1 < k ? fabs(tb[i]) : 0.0);
+                lo = fmin(lo, ta[i] - rr);
+                hi = fmax(hi, ta[i] + rr);
+            }
+            for (int round = 0; round < 6; ++round) {
+                const double step = (hi - lo) / (LZ_THREADS + 1);
+                const double x = lo + (tid + 1) * step;
+                int cnt = 0;
+                double dd = 1.0;
+                for (int i = 0; i < k; ++i) {
+                    const double bb = i > 0 ? tb[i - 1] * tb[i - 1] : 0.0;
+                    dd = ta[i] - x - (i > 0 ? bb / dd : 0.0);
+                    if (dd == 0.0) dd = -1e-300;
+                    if (dd < 0.0) ++cnt;
+                }
+                if (tid == 0) first_hit = LZ_THREADS;
+                __syncthreads();
+                if (cnt >= 1) atomicMin(&first_hit, tid);
+                __syncthreads();
+                const int t = first_hit;
+                __syncthreads();
+                const double nlo = lo + t * step, nhi = (t < LZ_THREADS) ? lo + (t + 1) * step : hi;
+                lo = nlo;
+                hi = nhi;
+            }
+            const double theta = 0.5 * (lo + hi);
+            const bool settled = k >= 24 && fabs(theta - theta_prev) <= 1e-10 * tnorm;
+            theta_prev = theta;
+            if (settled) break;
+        }
         for (int i = tid; i < n; i += LZ_THREADS) {
             double v = w[i] / beta;
             q[i] = v;

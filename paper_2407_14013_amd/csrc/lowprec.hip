@@ -78,24 +78,28 @@ __global__ __launch_bounds__(256) void sgemm_nn_kernel(int M, int N, int K, cons
     for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) acc[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += LK) {
-        {
-            const int i = tid & 63, gi = row0 + i;
+    // the next K slice is fetched into registers while the current one is multiplied
+    float ra[8], rb[8];
+    const int ai = tid & 63, bk = tid & 31;
+    auto fetch = [&](int k0) {
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int kk = (tid >> 6) + 4 * t, gk = k0 + kk;
-                As[i][kk] = (gi < M && gk < K) ? A[gi + (long)gk * lda] : 0.f;
-            }
+        for (int t = 0; t < 8; ++t) {
+            const int kk = (tid >> 6) + 4 * t, gk = k0 + kk, gi = row0 + ai;
+            ra[t] = (gi < M && gk < K) ? A[gi + (long)gk * lda] : 0.f;
+            const int j = (tid >> 5) + 8 * t, gj = col0 + j, gkb = k0 + bk;
+            rb[t] = (gkb < K && gj < N) ? B[gkb + (long)gj * ldb] : 0.f;
         }
-        {
-            const int kk = tid & 31, gk = k0 + kk;
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += LK) {
+        __syncthreads();
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int j = (tid >> 5) + 8 * t, gj = col0 + j;
-                Bs[j][kk] = (gk < K && gj < N) ? B[gk + (long)gj * ldb] : 0.f;
-            }
+        for (int t = 0; t < 8; ++t) {
+            As[ai][(tid >> 6) + 4 * t] = ra[t];
+            Bs[(tid >> 5) + 8 * t][bk] = rb[t];
         }
         __syncthreads();
+        if (k0 + LK < K) fetch(k0 + LK);
 #pragma unroll
         for (int s = 0; s < LK / 4; ++s) {
             const int kk = 4 * s + (lane >> 4);
@@ -110,7 +114,6 @@ __global__ __launch_bounds__(256) void sgemm_nn_kernel(int M, int N, int K, cons
                 for (int y = 0; y < 2; ++y)
                     acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x], b[y], acc[x][y], 0, 0, 0);
         }
-        __syncthreads();
     }
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -134,24 +137,27 @@ __global__ __launch_bounds__(256) void bgemm_nn_kernel(int M, int N, int K, cons
     for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) acc[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += LK) {
-        {
-            const int i = tid & 63, gi = row0 + i;
+    unsigned short ra[8], rb[8];
+    const int ai = tid & 63, bk = tid & 31;
+    auto fetch = [&](int k0) {
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int kk = (tid >> 6) + 4 * t, gk = k0 + kk;
-                As[i][kk] = (gi < M && gk < K) ? A[gi + (long)gk * lda] : static_cast<unsigned short>(0);
-            }
+        for (int t = 0; t < 8; ++t) {
+            const int kk = (tid >> 6) + 4 * t, gk = k0 + kk, gi = row0 + ai;
+            ra[t] = (gi < M && gk < K) ? A[gi + (long)gk * lda] : static_cast<unsigned short>(0);
+            const int j = (tid >> 5) + 8 * t, gj = col0 + j, gkb = k0 + bk;
+            rb[t] = (gkb < K && gj < N) ? B[gkb + (long)gj * ldb] : static_cast<unsigned short>(0);
         }
-        {
-            const int kk = tid & 31, gk = k0 + kk;
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += LK) {
+        __syncthreads();
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int j = (tid >> 5) + 8 * t, gj = col0 + j;
-                Bs[j][kk] = (gk < K && gj < N) ? B[gk + (long)gj * ldb] : static_cast<unsigned short>(0);
-            }
+        for (int t = 0; t < 8; ++t) {
+            As[ai][(tid >> 6) + 4 * t] = ra[t];
+            Bs[(tid >> 5) + 8 * t][bk] = rb[t];
         }
         __syncthreads();
+        if (k0 + LK < K) fetch(k0 + LK);
         const int kg = 8 * (lane >> 4);
         v8us a[2], b[2];
 #pragma unroll
@@ -165,7 +171,6 @@ __global__ __launch_bounds__(256) void bgemm_nn_kernel(int M, int N, int K, cons
                 acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a[x]),
                                                                     __builtin_bit_cast(v8bf, b[y]), acc[x][y], 0, 0,
                                                                     0);
-        __syncthreads();
     }
 #pragma unroll
     for (int x = 0; x < 2; ++x)

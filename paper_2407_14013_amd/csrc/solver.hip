@@ -624,7 +624,8 @@ static PcgOut pcg_loop(sdp_ctx* c, bool lowp, const double* g, double* x, double
 // [0; -Sigma^{-1} Q^T c] (Corollary pcg).  Mixed mode: iterative refinement --
 // the FP64 residual rho = g - K x is computed, the correction K delta = rho is
 // solved from delta = 0 by indefinite PCG with the low-precision operator to
-// refine_tol, and x += delta, until the FP64 residual meets inner_tol.  The
+// max(refine_tol, the reduction still missing to inner_tol), and x += delta,
+// until the FP64 residual meets inner_tol.  The
 // bottom block of rho is set to zero: the low-precision operator shares its
 // bottom block with the FP64 one, so that residual is rounding noise, which
 // the tiny tau^2 Sigma block would amplify (indefinite PCG likewise keeps its
@@ -657,7 +658,9 @@ int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, doub
         rr = o.rr;
         conv = o.conv;
     } else {
-        const double rtol = c->opt.refine_tol > 0 ? c->opt.refine_tol : 1e-4;
+        // 0 selects the reduction that suits the precision: BF16 GEMM operands
+        // (u = 2^-8) make each sweep's correction accurate to ~1e-3 only
+        const double rtol = c->opt.refine_tol > 0 ? c->opt.refine_tol : (c->lp == Lp::BF16 ? 1e-3 : 1e-6);
         while (true) {
             newton_apply(c, c->vx, c->vKp);
             axpbypcz(st, N, 1.0, c->vg, -1.0, c->vKp, 0.0, c->vres);          // rho = g - K x (FP64)
@@ -674,7 +677,10 @@ int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, doub
             if (!std::isfinite(rr) || sweeps >= c->opt.max_refine || its >= c->opt.inner_maxit) break;
             fill(st, d, c->vres + m, 0.0);
             fill(st, N, c->vdx, 0.0);
-            PcgOut o = pcg_loop(c, true, c->vres, c->vdx, rtol, c->opt.inner_maxit - its);
+            // ask each sweep only for the reduction still needed (with a factor 2
+            // of slack), but never less than refine_tol
+            const double need = 0.5 * c->opt.inner_tol * ref / (rr > 0 ? rr : 1.0);
+            PcgOut o = pcg_loop(c, true, c->vres, c->vdx, std::max(rtol, need), c->opt.inner_maxit - its);
             its += o.it;
             ++sweeps;
             if (!std::isfinite(o.rr)) break;
