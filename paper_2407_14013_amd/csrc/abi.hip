@@ -86,7 +86,10 @@ sdp_status sdp_setup(const sdp_problem* prob, const sdp_options* opt, void* hip_
             wc::require(opt->inner_tol > 0 && opt->gap_tol > 0 && opt->feas_tol > 0, "tolerances must be positive");
             wc::require(opt->inner_maxit >= 1 && opt->max_ipm_iter >= 0, "iteration limits must be positive");
             wc::require(opt->step_frac > 0 && opt->step_frac < 1, "step_frac must lie in (0, 1)");
-            wc::require(opt->solver == SDP_SOLVER_PCG, "only the PCG inner solver is available");
+            wc::require(opt->solver == SDP_SOLVER_PCG || opt->solver == SDP_SOLVER_MINRES,
+                        "solver must be SDP_SOLVER_PCG or SDP_SOLVER_MINRES");
+            wc::require(opt->solver == SDP_SOLVER_PCG || opt->inner_prec == SDP_PREC_F64,
+                        "MINRES runs with the FP64 operator only");
             wc::require(opt->inner_prec == SDP_PREC_F64 || opt->inner_prec == SDP_PREC_F32 ||
                             opt->inner_prec == SDP_PREC_BF16,
                         "inner_prec must be SDP_PREC_F64, SDP_PREC_F32 or SDP_PREC_BF16");

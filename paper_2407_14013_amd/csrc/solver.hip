@@ -619,6 +619,78 @@ static PcgOut pcg_loop(sdp_ctx* c, bool lowp, const double* g, double* x, double
     return o;
 }
 
+// MINRES (Corollary minres: identity preconditioner, start at 0) on K x = g,
+// by the Lanczos three-term recurrence and Givens rotations of the
+// tridiagonal (the Paige-Saunders form of the method).  Stops when the
+// residual norm estimate |phibar| <= tol_rel ||g|| or after maxit steps.
+static PcgOut minres_loop(sdp_ctx* c, const double* g, double* x, double tol_rel, int maxit) {
+    const int m = c->m, d = c->d;
+    const long N = (long)m + d;
+    hipStream_t st = c->st;
+    double* sc = c->sc;
+    // buffers: r1 = vr, r2 = vz, y = vKp, v = vp, directions w = vtmp, w2 = vres
+    double *r1 = c->vr, *r2 = c->vz, *y = c->vKp, *v = c->vp, *w = c->vtmp, *w2 = c->vres;
+    fill(st, N, x, 0.0);
+    copy(st, N, g, r1);
+    copy(st, N, g, r2);
+    copy(st, N, g, y);
+    fill(st, N, w, 0.0);
+    fill(st, N, w2, 0.0);
+    dot(st, N, g, g, sc + 4, c->part);
+    fetch(c, sc + 4, 1);
+    PcgOut o;
+    const double beta1 = std::sqrt(c->pin[0]);
+    o.ref = beta1;
+    o.rr = beta1;
+    if (!(beta1 > 0)) {
+        o.conv = true;
+        return o;
+    }
+    double oldb = 0.0, beta = beta1, dbar = 0.0, epsln = 0.0, phibar = beta1, cs = -1.0, sn = 0.0;
+    const double tol = tol_rel * beta1;
+    while (o.it < maxit) {
+        axpby(st, N, 1.0 / beta, y, 0.0, v);                 // v = y / beta
+        newton_apply(c, v, y);                               // y = K v
+        if (o.it > 0) axpby(st, N, -beta / oldb, r1, 1.0, y);
+        dot(st, N, v, y, sc + 4, c->part);
+        fetch(c, sc + 4, 1);
+        const double alfa = c->pin[0];
+        axpby(st, N, -alfa / beta, r2, 1.0, y);
+        std::swap(r1, r2);                                   // r1 <- r2
+        copy(st, N, y, r2);                                  // r2 <- y
+        dot(st, N, r2, r2, sc + 4, c->part);
+        fetch(c, sc + 4, 1);
+        oldb = beta;
+        beta = std::sqrt(c->pin[0]);
+        // next Givens rotation of the tridiagonal
+        const double oldeps = epsln;
+        const double delta = cs * dbar + sn * alfa;
+        const double gbar = sn * dbar - cs * alfa;
+        epsln = sn * beta;
+        dbar = -cs * beta;
+        const double gamma = std::max(std::hypot(gbar, beta), 1e-300);
+        cs = gbar / gamma;
+        sn = beta / gamma;
+        const double phi = cs * phibar;
+        phibar = sn * phibar;
+        // new direction (v - oldeps w_{k-2} - delta w_{k-1}) / gamma, written over
+        // w_{k-2} (held in w2), then w <- new, w2 <- w_{k-1}
+        axpbypcz(st, N, 1.0 / gamma, v, -delta / gamma, w, -oldeps / gamma, w2);
+        std::swap(w, w2);
+        axpby(st, N, phi, w, 1.0, x);
+        ++o.it;
+        o.rr = std::fabs(phibar);
+        if (c->opt.verbose >= 2)
+            fprintf(stderr, "[wcsdp]   minres %d |r| %.3e alpha %.3e beta %.3e\n", o.it, o.rr, alfa, beta);
+        if (!(o.rr > tol)) {
+            o.conv = std::isfinite(o.rr);
+            break;
+        }
+        if (!(beta > 0)) break;  // invariant subspace: x solves the projected system
+    }
+    return o;
+}
+
 // Solve eq. augsys for the right-hand side of eq. Newt-eps and recover the
 // Newton direction (eq. recover).  FP64 mode: one indefinite PCG run started at
 // [0; -Sigma^{-1} Q^T c] (Corollary pcg).  Mixed mode: iterative refinement --
@@ -651,7 +723,13 @@ int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, doub
     int its = 0, sweeps = 0;
     double ref = 0, rr = 0;
     bool conv = false;
-    if (!c->lowp) {
+    if (c->opt.solver == SDP_SOLVER_MINRES) {
+        PcgOut o = minres_loop(c, c->vg, c->vx, c->opt.inner_tol, c->opt.inner_maxit);
+        its = o.it;
+        ref = o.ref;
+        rr = o.rr;
+        conv = o.conv;
+    } else if (!c->lowp) {
         PcgOut o = pcg_loop(c, false, c->vg, c->vx, c->opt.inner_tol, c->opt.inner_maxit);
         its = o.it;
         ref = o.ref;

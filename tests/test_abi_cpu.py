@@ -127,6 +127,7 @@ def test_setup_rejects_bad_options():
         ("refine_tol", 1.5, "refine_tol must lie"),
         ("max_refine", -1, "max_refine must be"),
         ("step_frac", 1.0, "step_frac must lie"),
+        ("solver", 7, "solver must be"),
     ],
 )
 def test_setup_rejects_invalid_options(field, value, needle):
@@ -136,3 +137,12 @@ def test_setup_rejects_invalid_options(field, value, needle):
     setattr(o, field, value)
     st, msg, ctx = _setup_status(workloads.gaussian_sensing(5, 1, 6, seed=0), o)
     assert st == L.SDP_EINVAL and needle in msg and not ctx.value
+
+
+def test_minres_requires_fp64_operator():
+    o = L.SdpOptions()
+    L.lib().sdp_default_options(C.byref(o))
+    o.solver = L.SDP_SOLVER_MINRES
+    o.inner_prec = L.SDP_PREC_F32
+    st, msg, ctx = _setup_status(workloads.gaussian_sensing(5, 1, 6, seed=0), o)
+    assert st == L.SDP_EINVAL and "MINRES runs with the FP64 operator" in msg and not ctx.value

@@ -252,3 +252,44 @@ def test_ipm_step_matches_oracle_step(which):
         for key in ("alpha_p", "alpha_d", "sigma"):
             e = abs(st[key] - hist[k][key]) / max(abs(hist[k][key]), 1e-300)
             assert e <= 1e-6, (k, key, st[key], hist[k][key])
+
+
+@pytest.mark.parametrize("which", ["cfg0", "entry"])
+@pytest.mark.parametrize("iters", [2, 6])
+def test_inner_solve_minres(which, iters):
+    # Corollary minres: MINRES (identity preconditioner, zero start) on eq.
+    # augsys with the same recovery.  Unlike indefinite PCG it leaves a
+    # nonzero bottom residual, which the recovery amplifies by up to 1/tau^2
+    # in the second equation (measured: 4.6e-7 at inner_tol 1e-10 on the
+    # entry instance), so it runs at inner_tol 1e-13 here.
+    p = workloads.config(0) if which == "cfg0" else small_entry()
+    res = ipm.solve(p, maxit=iters)
+    X, y, S = res["X"], res["y"], res["S"]
+    r = ipm.residuals(p, X, y, S)
+    Ct = r["Rd"] + S
+    bt = r["rp"]
+    G, d, Lf = nt.nt_factor(X, S)
+    W = G @ G.T
+    with Context(p, solver=L.SDP_SOLVER_MINRES, inner_tol=1e-13) as ctx:
+        ctx.set_point(dev(X), dev(y), dev(S))
+        dX, dy, st = ctx.inner_solve(dev(bt), dev(Ct))
+    dX, dy = host(dX), host(dy)
+    assert st["converged"] == 1 and st["rel_res"] <= 1e-13
+    scale = np.linalg.norm(bt + ops.a_op(p, W @ Ct @ W))
+    e_primal = np.linalg.norm(ops.a_op(p, dX) - bt) / scale
+    Gi = np.linalg.inv(G)
+    rhs = G.T @ (ops.at_op(p, dy) - Ct) @ G
+    e_second = np.linalg.norm(Gi @ dX @ Gi.T - rhs) / np.linalg.norm(rhs)
+    print(f"{which} it {iters}: minres its {st['iterations']} primal {e_primal:.1e} second {e_second:.1e}")
+    assert e_primal <= 1e-8
+    assert e_second <= 1e-8
+
+
+def test_solve_minres_config0_matches_oracle():
+    p = workloads.config(0)
+    ref = ipm.solve(p)
+    with Context(p, solver=L.SDP_SOLVER_MINRES, inner_tol=1e-13) as ctx:
+        res = ctx.solve()
+        X, y, S = ctx.get_point()
+    print(f"minres solve: its {res['iterations']} krylov {res['pcg_iterations']}")
+    check_solution(p, res, X, y, S, ref["history"][-1]["pobj"])
