@@ -230,6 +230,156 @@ def bench_adjoint(args):
     print(json.dumps(line))
 
 
+MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
+
+
+def bench_completion(args):
+    """Config 2: the n=4000 matrix-completion operator, where E Y E on the matrix cores dominates.
+
+    At a closed-form centred point with a rank-4 split (the shape of the late
+    iterates) every form of the operator is applied in a tight loop: FP64,
+    and the FP32 and BF16 forms that the refinement sweeps use.  The two
+    n x n x n GEMMs of E Y E are timed by the library with HIP events on its
+    stream (kernel class SDP_K_SANDWICH): 2 n^3 flops per launch.  With
+    --solve, the full FP64 and FP32-mixed solves to the 1e-8 tolerances are
+    timed as well (minutes).
+    """
+    import torch
+
+    import workloads
+    from paper_2407_14013_amd import Context
+    from paper_2407_14013_amd import _lib as L
+
+    torch.cuda.set_device(0)
+    p = workloads.config(2)
+    n, m, r0, mu = p["n"], p["m"], 4, 1e-2
+    X, S, V, x, s = workloads.centred_pair(n, r0, mu, seed=21)
+    Xd, Sd = torch.from_numpy(X).cuda(), torch.from_numpy(S).cuda()
+    yd = torch.zeros(m, dtype=torch.float64, device="cuda")
+    del X, S
+    flops = 2.0 * n ** 3
+    forms = {}
+    for name, prec in (("f64", L.SDP_PREC_F64), ("f32", L.SDP_PREC_F32), ("bf16", L.SDP_PREC_BF16)):
+        with Context(p, inner_prec=prec) as ctx:
+            ctx.set_point(Xd, yd, Sd)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sc = ctx.get_scaling()
+            torch.cuda.synchronize()
+            t_scaling = time.perf_counter() - t0
+            N = ctx.aug_dim()
+            xin = torch.randn(N, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
+            xout = torch.empty_like(xin)
+            pr = None if prec == L.SDP_PREC_F64 else prec
+            for _ in range(3):
+                ctx.newton_apply(xin, xout, prec=pr)
+            torch.cuda.synchronize()
+            ctx.profile_enable([L.SDP_K_SANDWICH])
+            calls = args.apply_loop
+            t0 = time.perf_counter()
+            for _ in range(calls):
+                ctx.newton_apply(xin, xout, prec=pr)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            sw = ctx.profile_get(L.SDP_K_SANDWICH)
+            ctx.profile_enable([])
+            t0 = time.perf_counter()
+            for _ in range(20):
+                ctx.precond_apply(xin, xout)
+            torch.cuda.synchronize()
+            t_prec = (time.perf_counter() - t0) / 20
+            tf = flops * sw["launches"] / (sw["ms"] * 1e-3) / 1e12
+            forms[name] = {
+                "matvec_per_s": calls / el,
+                "ms_per_matvec": 1e3 * el / calls,
+                "sandwich_gemm": {"launches": sw["launches"], "avg_launch_ms": sw["ms"] / sw["launches"],
+                                  "achieved_tflops": tf, "peak_tflops": MFMA_PEAK_TFLOPS[name],
+                                  "frac": tf / MFMA_PEAK_TFLOPS[name]},
+                "precond_apply_ms": 1e3 * t_prec,
+                "scaling_setup_s": t_scaling,
+                "r": sc["r"],
+                "d": N - m,
+            }
+        print(f"{name}: {forms[name]['ms_per_matvec']:.3f} ms per operator product, sandwich GEMM "
+              f"{tf:.1f} TFLOP/s, scaling setup {t_scaling:.2f} s", file=sys.stderr, flush=True)
+    f64 = forms["f64"]
+    line = {
+        "metric": METRIC,
+        "value": f64["matvec_per_s"],
+        "unit": "matvec/s",
+        "n_gpus": 1,
+        "steps": args.apply_loop,
+        "warmup": 3,
+        "ms_per_step": f64["ms_per_matvec"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "matrix completion SDP n=4000 r=4 m=160000 (entry sampling) at a centred point, "
+                               "mu=1e-2, rank-4 split"},
+        "forms": forms,
+        "roofline": {
+            "kernel": "dgemm_kernel<false, false>: the two n x n x n products of E Y E",
+            "bound": "mfma",
+            "achieved": f64["sandwich_gemm"]["achieved_tflops"],
+            "peak": MFMA_PEAK_TFLOPS["f64"],
+            "unit": "TFLOP/s",
+            "frac": f64["sandwich_gemm"]["frac"],
+            "traffic": None,
+            "flops_per_launch": flops,
+            "avg_launch_ms": f64["sandwich_gemm"]["avg_launch_ms"],
+        },
+    }
+    if args.solve:
+        solves = {}
+        for name, prec in (("f64", L.SDP_PREC_F64), ("f32", L.SDP_PREC_F32)):
+            with Context(p, inner_prec=prec) as ctx:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = ctx.solve(raise_on_stall=False)
+                torch.cuda.synchronize()
+                solves[name] = {"time_to_gap_s": time.perf_counter() - t0, "status": res["status"],
+                                "iterations": res["iterations"], "pcg_iterations": res["pcg_iterations"],
+                                "fp64_matvecs": res["newton_matvecs"], "lowp_matvecs": res["lp_matvecs"],
+                                "relgap": res["relgap"], "pinf": res["pinf"], "dinf": res["dinf"],
+                                "pobj": res["pobj"]}
+            print(f"solve {name}: {solves[name]}", file=sys.stderr, flush=True)
+        line["ipm"] = solves
+    if not args.no_cpu_baseline:
+        from oracle import reform as rf
+
+        try:
+            from threadpoolctl import threadpool_info
+
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        except Exception:
+            threads = os.cpu_count()
+        w = np.sqrt(x / s)
+        order = np.argsort(-w, kind="stable")
+        lam, Vo = w[order], V[:, order]
+        sp = {"n": n, "r": r0, "tau": 0.5 * lam[r0], "lam": lam, "V": Vo, "Q": Vo[:, :r0], "Qp": Vo[:, r0:],
+              "lam_top": lam[:r0], "lam_perp": lam[r0:]}
+        E = rf.e_matrix(sp)
+        sig = rf.sigma_diag(sp)
+        xh = np.random.default_rng(0).standard_normal(m + rf.dim_d(n, r0))
+        calls = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 15.0:
+            rf.aug_apply(p, sp, E, sig, xh[:m], xh[m:])
+            calls += 1
+        el = time.perf_counter() - t0
+        line["cpu_baseline"] = {
+            "value": calls / el,
+            "unit": "matvec/s",
+            "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{calls} applications of the oracle's augmented operator (Section 5 products) on the same "
+                      f"workload and point, split supplied in closed form, {el:.1f} s",
+        }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,9 +389,10 @@ def main():
     ap.add_argument("--apply-loop", type=int, default=200)
     ap.add_argument("--pmc-pass", action="store_true", help="only the short run profiled for HBM counters")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solves")
-    ap.add_argument("--workload", choices=["sensing", "batched", "adjoint"], default="sensing",
+    ap.add_argument("--workload", choices=["sensing", "batched", "adjoint", "completion"], default="sensing",
                     help="sensing: the headline line (n=200 dense); batched: 1024 small SDPs in one launch; "
-                         "adjoint: n=1000 completion forward + backward")
+                         "adjoint: n=1000 completion forward + backward; completion: n=4000 completion operator")
+    ap.add_argument("--solve", action="store_true", help="completion: also time the full FP64 and mixed solves")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every instance of this workload fits one MI355X, "
@@ -255,6 +406,9 @@ def main():
         return
     if args.workload == "adjoint":
         bench_adjoint(args)
+        return
+    if args.workload == "completion":
+        bench_completion(args)
         return
 
     import torch

@@ -198,6 +198,17 @@ sdp_status sdp_newton_apply(sdp_ctx* ctx, const double* uv_in, double* uv_out);
 sdp_status sdp_newton_apply_prec(sdp_ctx* ctx, int32_t prec, const double* uv_in, double* uv_out);
 
 /*
+ * The preconditioner of Section 6 applied to a vector of the augmented space:
+ * uv_out = P^{-1} uv_in with P = [beta I, AQ; (AQ)^T, -tau^2 Sigma], by block
+ * elimination through the Schur complement C = tau^2 Sigma + (AQ)^T (AQ) / beta
+ * followed by one step of iterative refinement -- the operation every PCG
+ * iteration of sdp_inner_solve performs.  FP64.  Same layout and pointer
+ * rules as sdp_newton_apply (device pointers of length m + d, not aliased);
+ * the scaling point is prepared first if needed.
+ */
+sdp_status sdp_precond_apply(sdp_ctx* ctx, const double* uv_in, double* uv_out);
+
+/*
  * Solve eq. Newt-eps at the current scaling point: given b_tilde (m) and the
  * symmetric C_tilde (n x n), return dX (n x n) and dy (m) with
  *   dX = W (A^T(dy) - C_tilde) W,   A(dX) = b_tilde
@@ -318,7 +329,9 @@ enum {
     SDP_K_AT_APPLY = 1,  /* A^T(u): slab partial column sums of the packed rows */
     SDP_K_GEMM = 2,      /* every FP64 GEMM launch */
     SDP_K_NEWTON = 3,    /* a whole sdp_newton_apply */
-    SDP_K_COUNT = 4
+    SDP_K_SANDWICH = 4,  /* each n x n x n GEMM of E Y E inside the operator, FP64 or low precision
+                            (2 n^3 flops per launch; bytes = its operands and result) */
+    SDP_K_COUNT = 5
 };
 
 /*

@@ -15,7 +15,7 @@ SDP_OK, SDP_EINVAL, SDP_ENOMEM, SDP_EDEVICE, SDP_ENOTCONV, SDP_ENUMERIC, SDP_EST
 SDP_A_DENSE, SDP_A_ENTRY = 0, 1
 SDP_SOLVER_PCG, SDP_SOLVER_MINRES = 0, 1
 SDP_PREC_F64, SDP_PREC_F32, SDP_PREC_BF16 = 0, 1, 2
-SDP_K_A_APPLY, SDP_K_AT_APPLY, SDP_K_GEMM, SDP_K_NEWTON = 0, 1, 2, 3
+SDP_K_A_APPLY, SDP_K_AT_APPLY, SDP_K_GEMM, SDP_K_NEWTON, SDP_K_SANDWICH = 0, 1, 2, 3, 4
 
 STATUS_NAMES = {
     0: "SDP_OK",
@@ -142,6 +142,7 @@ _SIGNATURES = [
     ("sdp_aug_dim", C.c_int64, [C.c_void_p]),
     ("sdp_newton_apply", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("sdp_newton_apply_prec", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    ("sdp_precond_apply", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("sdp_inner_solve", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SdpInnerStats)]),
     ("sdp_ipm_step", C.c_int32, [C.c_void_p, C.POINTER(SdpStepStats)]),
     ("sdp_solve_batched", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(SdpOptions), C.c_void_p, C.c_void_p,

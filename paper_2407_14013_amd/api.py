@@ -142,6 +142,15 @@ class Context:
         self._check(st)
         return uv_out
 
+    def precond_apply(self, uv_in: torch.Tensor, uv_out: torch.Tensor | None = None):
+        """P^{-1} [f; h] with the Section 6 preconditioner (block elimination + one refinement step)."""
+        N = self.aug_dim()
+        if uv_out is None:
+            uv_out = torch.empty(N, dtype=torch.float64, device=uv_in.device)
+        st = self._lib.sdp_precond_apply(self._ctx, _dptr(uv_in, "uv_in", N), _dptr(uv_out, "uv_out", N))
+        self._check(st)
+        return uv_out
+
     def inner_solve(self, b_tilde: torch.Tensor, C_tilde: torch.Tensor, raise_on_notconv: bool = True):
         n, m = self.n, self.m
         dX = torch.empty((n, n), dtype=torch.float64, device=b_tilde.device)
@@ -203,7 +212,7 @@ class Context:
     def profile_enable(self, classes=None):
         """Time the given kernel classes (iterable of SDP_K_*; None = all; [] = off)."""
         if classes is None:
-            mask = (1 << 4) - 1
+            mask = (1 << 5) - 1
         else:
             mask = 0
             for k in classes:

@@ -135,6 +135,15 @@ sdp_status sdp_newton_apply(sdp_ctx* ctx, const double* uv_in, double* uv_out) {
     });
 }
 
+sdp_status sdp_precond_apply(sdp_ctx* ctx, const double* uv_in, double* uv_out) {
+    if (!ctx) return SDP_EINVAL;
+    return guarded(ctx, [&]() {
+        wc::require(uv_in && uv_out && uv_in != uv_out, "uv_in / uv_out must be distinct device pointers");
+        wc::precond(ctx, uv_in, uv_out);
+        return SDP_OK;
+    });
+}
+
 sdp_status sdp_newton_apply_prec(sdp_ctx* ctx, int32_t prec, const double* uv_in, double* uv_out) {
     if (!ctx) return SDP_EINVAL;
     return guarded(ctx, [&]() {

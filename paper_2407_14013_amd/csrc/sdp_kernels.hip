@@ -328,32 +328,120 @@ void f_to_aq(hipStream_t st, int m, int n, int r, const double* F, long si, long
     WC_LAUNCH_CHECK();
 }
 
-// Entry-sampling rows of script-A script-Q: G^T A_i Q = (G_j^T Q_k + G_k^T Q_j) / 2.
-__global__ void aq_entry_kernel(int m, int n, int r, const int* __restrict__ jk, const double* __restrict__ G,
-                                double* __restrict__ AQ, long ldaq) {
-    const int nb = r * (r + 1) / 2;
-    const int d = nb + (n - r) * r;
-    long t = blockIdx.x * 256L + threadIdx.x;
-    if (t >= (long)m * ldaq) return;
-    int c = static_cast<int>(t % ldaq);
-    int i = static_cast<int>(t / ldaq);
-    int j = jk[2 * i], k = jk[2 * i + 1];
-    double val = 0.0;
-    if (c < nb) {
-        int a, b;
-        svec_pair(c, r, a, b);
-        double f = 0.5 * (G[j + (long)a * n] * G[k + (long)b * n] + G[k + (long)a * n] * G[j + (long)b * n]);
-        val = (a == b) ? f : kSqrt2 * f;
-    } else if (c < d) {
-        int s = c - nb;
-        int kk = s % (n - r), b = s / (n - r);
-        int a = r + kk;
-        val = kSqrt2 * 0.5 * (G[j + (long)a * n] * G[k + (long)b * n] + G[k + (long)a * n] * G[j + (long)b * n]);
-    }
-    AQ[(long)i * ldaq + c] = val;
+// ---- entry-sampling script-A script-Q without forming it (Section 6) -----------------
+// For A_i = sym(e_j e_k^T) the i-th row of script-A script-Q, read in the
+// n x r coordinates H = [B; sqrt2 N] of v, is F_i = (g_j q_k^T + g_k q_j^T) / 2
+// with g_j the j-th row of G_w and q_j its first r entries.  Hence
+//   (AQ v)_i   = (U_j . q_k + U_k . q_j) / 2 with U = G_w H, and
+//   AQ^T u     = [svec; sqrt2 vec] of G_w^T (Y Q) with Y = A^T(u) sparse,
+// and (AQ)^T (AQ) has the blocks G_w^T B_{b b'} G_w (b, b' < r) of a sparse
+// Gram matrix in U-coordinates.  The symmetric pattern is kept in CSR form:
+// row j lists every pair (j, p) or (p, j) together with its constraint.
+
+// out_i = alpha (U_j . Q_k + U_k . Q_j) / 2 + beta out_i, U and Q n x r (ld n and ldq).
+__global__ void aq_entry_apply_kernel(int m, int n, int r, const int* __restrict__ jk, const double* __restrict__ U,
+                                      const double* __restrict__ Q, long ldq, double* __restrict__ out, double alpha,
+                                      double beta) {
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int j = jk[2 * i], k = jk[2 * i + 1];
+    double s = 0.0;
+    for (int b = 0; b < r; ++b)
+        s += U[j + (long)b * n] * Q[k + (long)b * ldq] + U[k + (long)b * n] * Q[j + (long)b * ldq];
+    const double v = 0.5 * alpha * s;
+    out[i] = (beta == 0.0) ? v : v + beta * out[i];
 }
-void aq_entry(hipStream_t st, int m, int n, int r, const int* jk, const double* G, double* AQ, long ldaq) {
-    hipLaunchKernelGGL(aq_entry_kernel, g1((long)m * ldaq), dim3(256), 0, st, m, n, r, jk, G, AQ, ldaq);
+void aq_entry_apply(hipStream_t st, int m, int n, int r, const int* jk, const double* U, const double* Q, long ldq,
+                    double* out, double alpha, double beta) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(aq_entry_apply_kernel, g1(m), dim3(256), 0, st, m, n, r, jk, U, Q, ldq, out, alpha, beta);
+    WC_LAUNCH_CHECK();
+}
+
+// YQ (n x r, ld n) = A^T(u) Q: row j sums u_i Q[p, :] over its pattern
+// entries, weighted 1/2 off the diagonal and 1 on it.  One thread per (j, b).
+__global__ void entry_yq_kernel(int n, int r, const int* __restrict__ rptr, const int* __restrict__ rcol,
+                                const int* __restrict__ ridx, const double* __restrict__ u,
+                                const double* __restrict__ Q, long ldq, double* __restrict__ YQ) {
+    long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)n * r) return;
+    const int j = static_cast<int>(t % n), b = static_cast<int>(t / n);
+    double s = 0.0;
+    for (int e = rptr[j]; e < rptr[j + 1]; ++e) {
+        const int p = rcol[e];
+        const double w = (p == j) ? 1.0 : 0.5;
+        s += w * u[ridx[e]] * Q[p + (long)b * ldq];
+    }
+    YQ[j + (long)b * n] = s;
+}
+void entry_yq(hipStream_t st, int n, int r, const int* rptr, const int* rcol, const int* ridx, const double* u,
+              const double* Q, long ldq, double* YQ) {
+    hipLaunchKernelGGL(entry_yq_kernel, g1((long)n * r), dim3(256), 0, st, n, r, rptr, rcol, ridx, u, Q, ldq, YQ);
+    WC_LAUNCH_CHECK();
+}
+
+// B_{b b'} (n x n, ld ldb, zeroed beforehand) = sum_i of the U-coordinate Gram
+// terms of constraint i:  off the diagonal B[j, p] = Q[p, b] Q[j, b'] / 4 for
+// every pattern entry (j, p), p != j; on it B[j, j] = sum over the row's
+// entries of Q[p, b] Q[p, b'] / 4, or Q[j, b] Q[j, b'] for an observed
+// diagonal.  One thread per row, so every entry has one writer.
+__global__ void entry_gram_block_kernel(int n, int b, int b2, const int* __restrict__ rptr,
+                                        const int* __restrict__ rcol, const double* __restrict__ Q, long ldq,
+                                        double* __restrict__ B, long ldb) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const double qj2 = Q[j + (long)b2 * ldq];
+    double diag = 0.0;
+    for (int e = rptr[j]; e < rptr[j + 1]; ++e) {
+        const int p = rcol[e];
+        const double qpb = Q[p + (long)b * ldq];
+        if (p == j) {
+            diag += qpb * qj2;
+        } else {
+            diag += 0.25 * qpb * Q[p + (long)b2 * ldq];
+            B[j + (long)p * ldb] = 0.25 * qpb * qj2;
+        }
+    }
+    B[j + (long)j * ldb] = diag;
+}
+void entry_gram_block(hipStream_t st, int n, int b, int b2, const int* rptr, const int* rcol, const double* Q, long ldq,
+                      double* B, long ldb) {
+    hipLaunchKernelGGL(entry_gram_block_kernel, g1(n), dim3(256), 0, st, n, b, b2, rptr, rcol, Q, ldq, B, ldb);
+    WC_LAUNCH_CHECK();
+}
+
+// Coordinate of entry (a, b) of H (a >= b when a < r) in v = [svec(B); vec(N)],
+// and its weight: 1 on the diagonal of B, sqrt2 elsewhere.
+__device__ inline int h_coord(int n, int r, int a, int b, double& w) {
+    if (a < r) {
+        w = (a == b) ? 1.0 : kSqrt2;
+        return b * r - b * (b - 1) / 2 + (a - b);
+    }
+    w = kSqrt2;
+    return r * (r + 1) / 2 + (a - r) + (n - r) * b;
+}
+
+// C[c, c'] = w_c w_c' Z[a, a'] / beta (+ t2 sig_c on the diagonal) for every
+// coordinate c = (a, b), a in [b, n), and c' = (a', b2), a' in [b2, n), with
+// Z = G_w^T B_{b b2} G_w; the mirror entry is written too when b != b2.
+__global__ void c_assemble_kernel(int n, int r, int b, int b2, const double* __restrict__ Z, long ldz,
+                                  const double* __restrict__ sig, double t2, double ib, double* __restrict__ C,
+                                  long ldc) {
+    const int a = b + blockIdx.x * 64 + (threadIdx.x & 63);
+    const int a2 = b2 + blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (a >= n || a2 >= n) return;
+    double w, w2;
+    const int c = h_coord(n, r, a, b, w);
+    const int c2 = h_coord(n, r, a2, b2, w2);
+    double v = w * w2 * ib * Z[a + (long)a2 * ldz];
+    if (c == c2) v += t2 * sig[c];
+    C[c + (long)c2 * ldc] = v;
+    if (b != b2) C[c2 + (long)c * ldc] = v;
+}
+void c_assemble(hipStream_t st, int n, int r, int b, int b2, const double* Z, long ldz, const double* sig, double t2,
+                double ib, double* C, long ldc) {
+    dim3 grid(static_cast<unsigned>(cdiv(n - b, 64)), static_cast<unsigned>(cdiv(n - b2, 4)));
+    hipLaunchKernelGGL(c_assemble_kernel, grid, dim3(256), 0, st, n, r, b, b2, Z, ldz, sig, t2, ib, C, ldc);
     WC_LAUNCH_CHECK();
 }
 

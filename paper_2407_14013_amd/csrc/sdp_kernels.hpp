@@ -28,7 +28,15 @@ void f_to_v(hipStream_t st, int n, int r, const double* F, long ldf, const doubl
 void symlr(hipStream_t st, int n, int r, const double* U, const double* Q, long ldq, double* M, long ldm, double beta);
 // AQ rows from F_i = G_w^T A_i Q stored at F[i * si + (a + n b) * sab].
 void f_to_aq(hipStream_t st, int m, int n, int r, const double* F, long si, long sab, double* AQ, long ldaq);
-void aq_entry(hipStream_t st, int m, int n, int r, const int* jk, const double* G, double* AQ, long ldaq);
+// Entry-sampling script-A script-Q products and Schur-complement blocks (implicit, see sdp_kernels.hip).
+void aq_entry_apply(hipStream_t st, int m, int n, int r, const int* jk, const double* U, const double* Q, long ldq,
+                    double* out, double alpha, double beta);
+void entry_yq(hipStream_t st, int n, int r, const int* rptr, const int* rcol, const int* ridx, const double* u,
+              const double* Q, long ldq, double* YQ);
+void entry_gram_block(hipStream_t st, int n, int b, int b2, const int* rptr, const int* rcol, const double* Q, long ldq,
+                      double* B, long ldb);
+void c_assemble(hipStream_t st, int n, int r, int b, int b2, const double* Z, long ldz, const double* sig, double t2,
+                double ib, double* C, long ldc);
 void add_diag_vec(hipStream_t st, int d, double* A, long lda, const double* sig, double t2);
 void neg_div(hipStream_t st, int d, const double* qc, const double* sig, double* out);
 void corrector_h(hipStream_t st, int n, const double* Pm, const double* dv, double smu, double* H);

@@ -126,10 +126,12 @@ static void alloc_work(sdp_ctx* c) {
     c->U.alloc((long)n * c->rmax);
     c->YQ.alloc((long)n * c->rmax);
     c->F.alloc((long)n * c->rmax);
-    c->AQ.alloc((long)m * c->dmaxp);
-    c->ldAQt = round_up(m, 32);
-    c->AQt.alloc(c->ldAQt * c->dmaxp);
-    fill(c->st, c->ldAQt * c->dmaxp, c->AQt, 0.0);
+    if (c->kind == SDP_A_DENSE) {
+        c->AQ.alloc((long)m * c->dmaxp);
+        c->ldAQt = round_up(m, 32);
+        c->AQt.alloc(c->ldAQt * c->dmaxp);
+        fill(c->st, c->ldAQt * c->dmaxp, c->AQt, 0.0);
+    }
     c->Cm.alloc(c->dmaxp * c->dmaxp);
     c->Cinv.alloc(c->dmaxp * c->dmaxp);
     c->Zw.alloc(c->dmaxp * c->dmaxp);
@@ -137,6 +139,7 @@ static void alloc_work(sdp_ctx* c) {
     c->td.alloc(c->dmaxp);
     c->td2.alloc(c->dmaxp);
     c->td3.alloc(c->dmaxp);
+    c->td4.alloc(c->dmaxp);
     c->rho.alloc(m + c->dmaxp + 32);
     c->dz.alloc(m + 32);
     fill(c->st, m + c->dmaxp + 32, c->rho, 0.0);
@@ -149,9 +152,12 @@ static void alloc_work(sdp_ctx* c) {
         c->Afull.alloc((long)m * n * n);
         unpack_rows(c->st, m, c->N2, c->ldP, c->P, c->pj, c->pk, n, c->Afull);
     }
-    long gp = (long)gemv_cols_parts(m) * std::max<long>(round_up(c->N2, 2), c->dmaxp);
-    gp = std::max(gp, (long)packed_cols_parts_f32(m) * round_up(c->N2, 4));
-    c->gpart.alloc(gp);
+    if (c->kind == SDP_A_DENSE) {
+        // partial sums of the packed A^T pass (FP64 and FP32 forms)
+        long gp = (long)packed_cols_parts(m) * round_up(c->N2, 2);
+        gp = std::max(gp, (long)packed_cols_parts_f32(m) * round_up(c->N2, 4));
+        c->gpart.alloc(gp);
+    }
     if (c->lowp) {
         c->Elp.alloc(nn);
         c->Ylp.alloc(nn);
@@ -171,6 +177,7 @@ static void alloc_work(sdp_ctx* c) {
     fill(c->st, c->dmaxp, c->td, 0.0);
     fill(c->st, c->dmaxp, c->td2, 0.0);
     fill(c->st, c->dmaxp, c->td3, 0.0);
+    fill(c->st, c->dmaxp, c->td4, 0.0);
     c->dya.alloc(m + 32);
     c->dy.alloc(m + 32);
     c->rp.alloc(m + 32);
@@ -287,6 +294,32 @@ void setup(sdp_ctx* c, const sdp_problem* p, const sdp_options* o, hipStream_t s
             require(hjk[2 * i] >= 0 && hjk[2 * i + 1] < n && hjk[2 * i] <= hjk[2 * i + 1], "bad entry pair");
             norms2[i] = (hjk[2 * i] == hjk[2 * i + 1]) ? 1.0 : 0.5;
         }
+        // symmetric pattern in CSR form: pair (j, k) is listed in row j with
+        // partner k and, off the diagonal, in row k with partner j
+        std::vector<int> cnt(n + 1, 0);
+        for (int i = 0; i < m; ++i) {
+            ++cnt[hjk[2 * i] + 1];
+            if (hjk[2 * i] != hjk[2 * i + 1]) ++cnt[hjk[2 * i + 1] + 1];
+        }
+        for (int j = 0; j < n; ++j) cnt[j + 1] += cnt[j];
+        const int nnz = cnt[n];
+        std::vector<int> col(nnz), idx(nnz), pos(cnt.begin(), cnt.end() - 1);
+        for (int i = 0; i < m; ++i) {
+            const int j = hjk[2 * i], k = hjk[2 * i + 1];
+            col[pos[j]] = k;
+            idx[pos[j]++] = i;
+            if (j != k) {
+                col[pos[k]] = j;
+                idx[pos[k]++] = i;
+            }
+        }
+        c->rptr.alloc(n + 1);
+        c->rcol.alloc(nnz);
+        c->ridx.alloc(nnz);
+        WC_HIP(hipMemcpyAsync(c->rptr.get(), cnt.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, st));
+        WC_HIP(hipMemcpyAsync(c->rcol.get(), col.data(), sizeof(int) * nnz, hipMemcpyHostToDevice, st));
+        WC_HIP(hipMemcpyAsync(c->ridx.get(), idx.data(), sizeof(int) * nnz, hipMemcpyHostToDevice, st));
+        WC_HIP(hipStreamSynchronize(st));
     }
     std::vector<double> hb(m), hC(nn);
     WC_HIP(hipMemcpyAsync(hb.data(), c->b.get(), sizeof(double) * m, hipMemcpyDeviceToHost, st));
@@ -409,14 +442,25 @@ void ensure_scaling(sdp_ctx* c) {
               (long)n * r);
         gemm(c, true, false, n, m * r, n, 1.0, c->Gw, n, c->Tcat, n, 0.0, c->Fcat, n);
         f_to_aq(st, m, n, r, c->Fcat, (long)n * r, 1, c->AQ, c->dmaxp);
+        // row-major copy of (AQ)^T: the products (AQ)^T f become row passes
+        transpose(st, d, m, c->AQ, c->dmaxp, c->AQt, c->ldAQt);
+        // Schur complement of the preconditioner: C = tau^2 Sigma + (AQ)^T (AQ) / beta
+        gemm(c, false, true, d, d, m, 1.0 / c->beta, c->AQ, c->dmaxp, c->AQ, c->dmaxp, 0.0, c->Cm, c->dmaxp);
+        add_diag_vec(st, d, c->Cm, c->dmaxp, c->sig, c->tau * c->tau);
     } else {
-        aq_entry(st, m, n, r, c->jk, c->Gw, c->AQ, c->dmaxp);
+        // the same C from the sparse Gram blocks in U-coordinates:
+        // (AQ)^T (AQ) restricted to columns b, b2 of H is G_w^T B_{b b2} G_w
+        for (int b = 0; b < r; ++b) {
+            for (int b2 = b; b2 < r; ++b2) {
+                fill(st, nn, c->T1, 0.0);
+                entry_gram_block(st, n, b, b2, c->rptr, c->rcol, c->Gw, n, c->T1, n);
+                gemm(c, false, false, n, n, n, 1.0, c->T1, n, c->Gw, n, 0.0, c->T2, n);
+                gemm(c, true, false, n, n, n, 1.0, c->Gw, n, c->T2, n, 0.0, c->Mm, n);
+                c_assemble(st, n, r, b, b2, c->Mm, n, c->sig, c->tau * c->tau, 1.0 / c->beta, c->Cm, c->dmaxp);
+            }
+        }
     }
-    // row-major copy of (AQ)^T: the products (AQ)^T f become row passes
-    transpose(st, d, m, c->AQ, c->dmaxp, c->AQt, c->ldAQt);
-    // Schur complement of the preconditioner: C = tau^2 Sigma + (AQ)^T (AQ) / beta, then C^{-1}
-    gemm(c, false, true, d, d, m, 1.0 / c->beta, c->AQ, c->dmaxp, c->AQ, c->dmaxp, 0.0, c->Cm, c->dmaxp);
-    add_diag_vec(st, d, c->Cm, c->dmaxp, c->sig, c->tau * c->tau);
+    // C = L_C L_C^T, then C^{-1} = L_C^{-T} L_C^{-1}
     potrf(st, d, c->Cm, c->dmaxp, c->info.get());
     WC_HIP(hipMemcpyAsync(hinfo, c->info.get(), sizeof(int), hipMemcpyDeviceToHost, st));
     WC_HIP(hipStreamSynchronize(st));
@@ -433,6 +477,7 @@ void ensure_scaling(sdp_ctx* c) {
 void newton_apply(sdp_ctx* c, const double* in, double* out) {
     ensure_scaling(c);
     const int n = c->n, m = c->m, r = c->r;
+    const long nn = (long)n * n;
     hipStream_t st = c->st;
     hipEvent_t e;
     prof_begin(c, SDP_K_NEWTON, &e);
@@ -444,8 +489,14 @@ void newton_apply(sdp_ctx* c, const double* in, double* out) {
     v_to_h(st, n, r, v, c->Hm);
     gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
     symlr(st, n, r, c->U, c->Gw, n, c->Mm, n, 0.0);
+    const double sw_bytes = 8.0 * 4.0 * nn;  // two operands, C read and written
+    hipEvent_t es;
+    prof_begin(c, SDP_K_SANDWICH, &es);
     gemm(c, false, false, n, n, n, 1.0, c->Y, n, c->E, n, 0.0, c->T1, n);
+    prof_end(c, SDP_K_SANDWICH, es, sw_bytes);
+    prof_begin(c, SDP_K_SANDWICH, &es);
     gemm(c, false, false, n, n, n, 1.0, c->E, n, c->T1, n, 1.0, c->Mm, n);
+    prof_end(c, SDP_K_SANDWICH, es, sw_bytes);
     // top = A(Mm)
     a_apply(c, c->Mm, out, 1.0, 0.0);
     // bottom = Q^T svec(Y) - tau^2 Sigma v, with Q^T svec(Y) read from F = G_w^T Y Q
@@ -454,6 +505,20 @@ void newton_apply(sdp_ctx* c, const double* in, double* out) {
     f_to_v(st, n, r, c->F, n, v, c->sig, c->tau * c->tau, out + m);
     prof_end(c, SDP_K_NEWTON, e, 0.0);
     c->matvecs += 1;
+}
+
+// E Y E on the matrix cores in low precision: T = Y E (stored in `tout`),
+// then M (<-|+=) E T in FP64 as `mout` says.
+static void sandwich_lp(sdp_ctx* c, LpOut tout, LpOut mout) {
+    const int n = c->n;
+    const double bytes = (c->lp == Lp::F32 ? 4.0 : 2.0) * 3.0 * n * n + 8.0 * n * n;
+    hipEvent_t es;
+    prof_begin(c, SDP_K_SANDWICH, &es);
+    lp_gemm_nn(c->st, c->lp, tout, n, n, n, c->Ylp, n, c->Elp, n, c->Tlp, n);
+    prof_end(c, SDP_K_SANDWICH, es, bytes);
+    prof_begin(c, SDP_K_SANDWICH, &es);
+    lp_gemm_nn(c->st, c->lp, mout, n, n, n, c->Elp, n, c->Tlp, n, c->Mm, n);
+    prof_end(c, SDP_K_SANDWICH, es, bytes);
 }
 
 // The augmented operator with its A E A^T block in low precision (the
@@ -477,8 +542,7 @@ void newton_apply_lowp(sdp_ctx* c, const double* in, double* out) {
         packed_cols_partial_f32(st, m, static_cast<int>(c->N2), c->P32, c->ldP, u, c->gpart);
         at_reduce_unpack_lp(st, c->lp, c->N2, packed_cols_parts_f32(m), c->gpart, round_up(c->N2, 4), c->pj, c->pk,
                             nullptr, n, c->Ylp);
-        lp_gemm_nn(st, c->lp, tout, n, n, n, c->Ylp, n, c->Elp, n, c->Tlp, n);
-        lp_gemm_nn(st, c->lp, LpOut::F64, n, n, n, c->Elp, n, c->Tlp, n, c->Mm, n);
+        sandwich_lp(c, tout, LpOut::F64);
         pack_weighted_f32(st, c->N2, c->ldP, c->Mm, n, c->pj, c->pk, c->mw32);
         packed_rows_f32(st, m, static_cast<int>(c->N2), c->P32, c->ldP, c->mw32, out, 1.0, 0.0);
         // top += AQ v (v staged in an aligned, zero-padded buffer); bottom = AQ^T u - tau^2 Sigma v
@@ -493,14 +557,41 @@ void newton_apply_lowp(sdp_ctx* c, const double* in, double* out) {
         v_to_h(st, n, r, v, c->Hm);
         gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
         symlr(st, n, r, c->U, c->Gw, n, c->Mm, n, 0.0);
-        lp_gemm_nn(st, c->lp, tout, n, n, n, c->Ylp, n, c->Elp, n, c->Tlp, n);
-        lp_gemm_nn(st, c->lp, LpOut::ADD_F64, n, n, n, c->Elp, n, c->Tlp, n, c->Mm, n);
+        sandwich_lp(c, tout, LpOut::ADD_F64);
         entry_gather(st, m, c->jk, c->Mm, n, out, 1.0, 0.0);
         gemm(c, false, false, n, r, n, 1.0, c->Y, n, c->Gw, n, 0.0, c->YQ, n);
         gemm(c, true, false, n, r, n, 1.0, c->Gw, n, c->YQ, n, 0.0, c->F, n);
         f_to_v(st, n, r, c->F, n, v, c->sig, c->tau * c->tau, out + m);
     }
     c->lp_matvecs += 1;
+}
+
+// out = alpha (script-A script-Q) v + beta out (m).  Dense A: the explicit
+// matrix (v in an aligned, zero-padded buffer).  Entry sampling: U = G_w H(v),
+// then one gather per constraint.  Uses Hm and U.
+static void aq_mul(sdp_ctx* c, const double* v, double* out, double alpha, double beta) {
+    if (c->kind == SDP_A_DENSE) {
+        gemv_rows(c->st, c->m, c->d, c->AQ, c->dmaxp, v, out, alpha, beta);
+        return;
+    }
+    const int n = c->n, r = c->r;
+    v_to_h(c->st, n, r, v, c->Hm);
+    gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
+    aq_entry_apply(c->st, c->m, n, r, c->jk, c->U, c->Gw, n, out, alpha, beta);
+}
+
+// out = alpha (script-A script-Q)^T u + beta out (d).  Entry sampling:
+// F = G_w^T (A^T(u) Q) with the sparse product row by row.  Uses YQ, F, td4.
+static void aqt_mul(sdp_ctx* c, const double* u, double* out, double alpha, double beta) {
+    if (c->kind == SDP_A_DENSE) {
+        gemv_rows(c->st, c->d, c->m, c->AQt, c->ldAQt, u, out, alpha, beta);
+        return;
+    }
+    const int n = c->n, r = c->r;
+    entry_yq(c->st, n, r, c->rptr, c->rcol, c->ridx, u, c->Gw, n, c->YQ);
+    gemm(c, true, false, n, r, n, 1.0, c->Gw, n, c->YQ, n, 0.0, c->F, n);
+    f_to_v(c->st, n, r, c->F, n, nullptr, c->sig, 0.0, c->td4);
+    axpby(c->st, c->d, alpha, c->td4, beta, out);
 }
 
 // Block elimination with P = [beta I, AQ; AQ^T, -tau^2 Sigma] (Section 6, with
@@ -512,10 +603,10 @@ static void precond_block(sdp_ctx* c, const double* f, const double* h, double* 
     const int m = c->m, d = c->d;
     hipStream_t st = c->st;
     const double ib = 1.0 / c->beta;
-    gemv_rows(st, d, m, c->AQt, c->ldAQt, f, c->td, -ib, 0.0);           // td = -AQ^T f / beta
+    aqt_mul(c, f, c->td, -ib, 0.0);                                      // td = -AQ^T f / beta
     axpby(st, d, 1.0, h, 1.0, c->td);                                    // td += h
     gemv_rows(st, d, d, c->Cinv, c->dmaxp, c->td, zv, -1.0, 0.0);        // zv = -C^{-1} td
-    gemv_rows(st, m, d, c->AQ, c->dmaxp, zv, c->tm, 1.0, 0.0);           // tm = AQ zv
+    aq_mul(c, zv, c->tm, 1.0, 0.0);                                      // tm = AQ zv
     axpbypcz(st, m, ib, f, -ib, c->tm, 0.0, z1);                          // z1 = (f - tm) / beta
 }
 
@@ -535,11 +626,21 @@ static void precond_apply(sdp_ctx* c, const double* rv, double* z) {
     // rho = rv - P z:  rho_u = f - tm - beta z1,  rho_v = h - AQ^T z1 + tau^2 Sigma zv
     axpbypcz(st, m, 1.0, f, -1.0, c->tm, 0.0, c->rho);
     axpby(st, m, -c->beta, z1, 1.0, c->rho);
-    gemv_rows(st, d, m, c->AQt, c->ldAQt, z1, c->td3, 1.0, 0.0);           // td3 = AQ^T z1
+    aqt_mul(c, z1, c->td3, 1.0, 0.0);                                      // td3 = AQ^T z1
     rho_bottom(st, d, h, c->td3, c->sig, c->tau * c->tau, c->td2, c->rho + m);
     precond_block(c, c->rho, c->rho + m, c->dz, c->td3);
     axpby(st, m, 1.0, c->dz, 1.0, z1);
     axpbypcz(st, d, 1.0, c->td2, 1.0, c->td3, 0.0, z + m);
+}
+
+// P^{-1} on caller buffers: staged through the aligned, zero-padded Krylov
+// buffers that the row passes expect.
+void precond(sdp_ctx* c, const double* in, double* out) {
+    ensure_scaling(c);
+    const long N = (long)c->m + c->d;
+    copy(c->st, N, in, c->vres);
+    precond_apply(c, c->vres, c->vdx);
+    copy(c->st, N, c->vdx, out);
 }
 
 // [u; v] -> (dX, dy) by eq. recover: dy = u / tau^2, dX = E (A^T u - tau^2 C~) E + Q v.

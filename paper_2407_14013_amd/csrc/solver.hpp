@@ -21,6 +21,7 @@ struct sdp_ctx {
     wc::DevBuf<double> Afull;   // dense: the m symmetric A_i, n x n column-major each
     wc::DevBuf<int> pj, pk;     // packed index -> (j, k)
     wc::DevBuf<int> jk;         // entry: 2 m pairs
+    wc::DevBuf<int> rptr, rcol, ridx;  // entry: symmetric pattern in CSR form (row j: partner, constraint)
     wc::DevBuf<double> b, C;    // m, n x n
     double bnorm = 0, Cnorm = 0, mean_a2 = 0, xi = 1, eta = 1;
 
@@ -38,12 +39,13 @@ struct sdp_ctx {
     wc::DevBuf<double> L, Rs, Linv, Rinv, Mt, Vs, dnt, G, Ginv, Gt, Gw, lam, evE, E, sig;
     std::vector<double> lam_h;
     wc::DevBuf<double> Tcat, Fcat, AQ, AQt, Cm, Cinv, Zw;
-    long ldAQt = 0;             // AQt: (script-A script-Q)^T, d x m row-major, zero padded
+    long ldAQt = 0;             // dense: AQt = (script-A script-Q)^T, d x m row-major, zero padded
+                                // (entry-sampling problems apply script-A script-Q without forming it)
     wc::JacobiWork jw;
     wc::LanczosWork lw;
 
     // ---- temporaries -------------------------------------------------------------
-    wc::DevBuf<double> Y, T1, T2, Mm, Hm, U, YQ, F, mw, yp, part, gpart, tm, td, td2, td3, rho, dz;
+    wc::DevBuf<double> Y, T1, T2, Mm, Hm, U, YQ, F, mw, yp, part, gpart, tm, td, td2, td3, td4, rho, dz;
     wc::DevBuf<double> vx, vr, vz, vp, vKp, vg, vtmp;   // Krylov vectors (m + dmax, padded)
     wc::DevBuf<double> vres, vdx;                       // refinement residual and correction
 
@@ -79,6 +81,7 @@ void setup(sdp_ctx* c, const sdp_problem* p, const sdp_options* o, hipStream_t s
 void ensure_scaling(sdp_ctx* c);
 void newton_apply(sdp_ctx* c, const double* in, double* out);
 void newton_apply_lowp(sdp_ctx* c, const double* in, double* out);
+void precond(sdp_ctx* c, const double* in, double* out);
 int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, double* dy, sdp_inner_stats* stats);
 int ipm_step(sdp_ctx* c, sdp_step_stats* stats);
 int solve(sdp_ctx* c, sdp_result* res);

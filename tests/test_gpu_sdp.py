@@ -122,6 +122,43 @@ def test_newton_apply_config1_matches_oracle():
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("which", ["cfg0", "entry", "entry150"])
+def test_precond_apply_matches_oracle(which):
+    # Section 6: z = P^{-1} x with P = [beta I, AQ; AQ^T, -tau^2 Sigma], the
+    # oracle's P assembled from the explicit script-A script-Q and solved
+    # densely.  Entry-sampling problems never form AQ on the GPU (sparse Gram
+    # blocks in U-coordinates for C, gathers for the products), so this pins
+    # that construction; "entry150" spans several tiles of every kernel.
+    if which == "cfg0":
+        p = workloads.config(0)
+    elif which == "entry":
+        p = small_entry()
+    else:
+        p = workloads.matrix_completion(150, 3, 1800, seed=6)
+    m = p["m"]
+    rng = np.random.default_rng(11)
+    for name, X, y, S in points(p):
+        sp = oracle_split(X, S)
+        sig = rf.sigma_diag(sp)
+        AQ = rf.aq_matrix(p, sp)
+        P = rf.precond_matrix(AQ, sp, sig, rf.beta_rule(sp, p))
+        with Context(p) as ctx:
+            ctx.set_point(dev(X), dev(y), dev(S))
+            N = ctx.aug_dim()
+            assert N == P.shape[0]
+            for trial in range(2):
+                x = rng.standard_normal(N)
+                if trial == 1:
+                    x[m:] = 0.0  # f only: the bottom block comes from the elimination alone
+                z = host(ctx.precond_apply(dev(x)))
+                ref = np.linalg.solve(P, x)
+                err = np.abs(z - ref).max() / np.abs(ref).max()
+                # normwise backward error of the GPU's z as a solution of P z = x
+                bwd = np.linalg.norm(P @ z - x) / (np.linalg.norm(P, 2) * np.linalg.norm(z) + np.linalg.norm(x))
+                print(f"{which} {name} trial {trial}: element error {err:.1e} backward error {bwd:.1e}")
+                assert bwd <= 1e-13 and err <= 1e-8, (name, trial)
+
+
 @pytest.mark.parametrize("which", ["cfg0", "entry"])
 @pytest.mark.parametrize("iters", [2, 6])
 def test_inner_solve_matches_direct(which, iters):

@@ -26,6 +26,7 @@ __all__ = [
     "matrix_completion",
     "batched_sensing",
     "random_pd_pair",
+    "centred_pair",
     "config",
     "CONFIGS",
 ]
@@ -222,6 +223,29 @@ def random_pd_pair(n: int, seed: int, spread: float = 1.0):
     X = one()
     S = one()
     return X, S
+
+
+def centred_pair(n: int, r: int, mu: float, seed: int):
+    """A perfectly centred primal-dual point with a rank-r split, in closed form.
+
+    X = V diag(x) V^T and S = V diag(s) V^T share the orthogonal eigenvectors
+    V, with x_i s_i = mu for every i: the r leading x_i are large
+    (log-uniform in [n/2, 2n], the scale of a planted U U^T with unit
+    Gaussian U) and the other s_i are uniform in [1/2, 2] (the dual slack of
+    the complement).  Such a point is where the late iterates of an
+    interior-point method sit.  Returns (X, S, V, x, s).
+    """
+    rng = np.random.default_rng(seed)
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    x = np.empty(n)
+    s = np.empty(n)
+    x[:r] = np.sort(10.0 ** rng.uniform(np.log10(n / 2), np.log10(2 * n), size=r))[::-1]
+    s[:r] = mu / x[:r]
+    s[r:] = rng.uniform(0.5, 2.0, size=n - r)
+    x[r:] = mu / s[r:]
+    X = (V * x) @ V.T
+    S = (V * s) @ V.T
+    return 0.5 * (X + X.T), 0.5 * (S + S.T), V, x, s
 
 
 # The five workloads the hot path is measured on.  Each entry is
