@@ -33,17 +33,84 @@ __device__ inline void tournament_pair(int round, int w, int N, int& a, int& b) 
     }
 }
 
+// Rotation (c, s) that annihilates H[p][q] of the symmetric 2 x 2 block
+// [app apq; apq aqq] (J[p][p] = J[q][q] = c, J[p][q] = s, J[q][p] = -s);
+// the identity when the entry is already negligible.
+__device__ inline bool jacobi_angle(double app, double aqq, double apq, double& c, double& s) {
+    c = 1.0;
+    s = 0.0;
+    if (!(fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app * aqq))) || apq == 0.0) return false;
+    const double th = (aqq - app) / (2.0 * apq);
+    double t;
+    if (fabs(th) > 1e150) t = 0.5 / th;
+    else t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+    c = 1.0 / sqrt(1.0 + t * t);
+    s = t * c;
+    return true;
+}
+
+// Cyclic two-sided Jacobi on the 32 x 32 symmetric H (LDS), accumulating the
+// rotations into R (LDS, identity on entry).  A rotation step applies the 16
+// disjoint rotations of one tournament round, H' = J^T H J and R' = R J.
+// Thread t owns the 2 x 2 block of H at the pairs (t mod 16, t / 16): it
+// computes the two rotations it needs itself (every thread that needs a
+// pair's rotation computes it from the same entries, so all agree bit for
+// bit), reads its block from H and writes the rotated block to Hs, and
+// rotates rows t mod 16 and t mod 16 + 16 of R's column pair t / 16 in place
+// -- one barrier per step.  Runs at most `sweeps` sweeps (31 steps each),
+// fewer when a sweep applies no rotation.  256 threads; H is overwritten.
+__device__ void inner_jacobi(double (*H)[JW + 1], double (*Hs)[JW + 1], double (*R)[JW + 1], int sweeps,
+                             int* rot_any) {
+    const int tid = threadIdx.x;
+    const int a = tid & 15, b = tid >> 4;
+    for (int t = tid; t < JW * JW; t += 256) R[t % JW][t / JW] = (t % JW == t / JW) ? 1.0 : 0.0;
+    double (*Hc)[JW + 1] = H;
+    double (*Hn)[JW + 1] = Hs;
+    for (int sweep = 0; sweep < sweeps; ++sweep) {
+        if (tid == 0) *rot_any = 0;
+        __syncthreads();
+        for (int rr = 0; rr < JW - 1; ++rr) {
+            int pa, qa, pb, qb;
+            tournament_pair(rr, a, JW, pa, qa);
+            tournament_pair(rr, b, JW, pb, qb);
+            double ca, sa, cb, sb;
+            const bool rot = jacobi_angle(Hc[pa][pa], Hc[qa][qa], Hc[pa][qa], ca, sa);
+            jacobi_angle(Hc[pb][pb], Hc[qb][qb], Hc[pb][qb], cb, sb);
+            if (rot && b == 0) *rot_any = 1;
+            // block (a, b): T = H J_b on the columns, then J_a^T T on the rows
+            const double h11 = Hc[pa][pb], h12 = Hc[pa][qb], h21 = Hc[qa][pb], h22 = Hc[qa][qb];
+            const double t11 = cb * h11 - sb * h12, t12 = sb * h11 + cb * h12;
+            const double t21 = cb * h21 - sb * h22, t22 = sb * h21 + cb * h22;
+            Hn[pa][pb] = ca * t11 - sa * t21;
+            Hn[pa][qb] = ca * t12 - sa * t22;
+            Hn[qa][pb] = sa * t11 + ca * t21;
+            Hn[qa][qb] = sa * t12 + ca * t22;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int i = a + 16 * h;
+                const double rp = R[i][pb], rq = R[i][qb];
+                R[i][pb] = cb * rp - sb * rq;
+                R[i][qb] = sb * rp + cb * rq;
+            }
+            __syncthreads();
+            double (*tmp)[JW + 1] = Hc;
+            Hc = Hn;
+            Hn = tmp;
+        }
+        if (!*rot_any) break;
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(256) void jacobi_round_kernel(int n, int nblk, int round, double* __restrict__ A,
                                                            long lda, double* __restrict__ V, long ldv, double tol,
                                                            unsigned long long* offmax, const int* __restrict__ done,
                                                            int inner_sweeps) {
     if (*done) return;  // an earlier sweep already converged
     __shared__ double P[JR][JW + 1];
-    __shared__ double H[JW][JW + 1];
+    __shared__ double H[JW][JW + 1], Hs[JW][JW + 1];
     __shared__ double R[JW][JW + 1];
     __shared__ int cols[JW];
-    __shared__ double cs[JB], sn[JB];
-    __shared__ int pp[JB], qq[JB];
     __shared__ double red[4];
     __shared__ int rot_any;
 
@@ -101,64 +168,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(int n, int nblk, int 
     // ---- 2. two-sided Jacobi sweeps on H (at most inner_sweeps) ---------------
     // The pair need not be diagonalised exactly: the outer sweeps revisit it,
     // and convergence is judged only by the outer tolerance test above.
-    for (int t = tid; t < JW * JW; t += 256) {
-        int i = t % JW, j = t / JW;
-        R[i][j] = (i == j) ? 1.0 : 0.0;
-    }
-    const double eps_in = 2.220446049250313e-16;
-    for (int sweep = 0; sweep < inner_sweeps; ++sweep) {
-        if (tid == 0) rot_any = 0;
-        __syncthreads();
-        for (int rr = 0; rr < JW - 1; ++rr) {
-            if (tid < JB) {
-                int p, q;
-                tournament_pair(rr, tid, JW, p, q);
-                double app = H[p][p], aqq = H[q][q], apq = H[p][q];
-                double c = 1.0, s = 0.0;
-                if (fabs(apq) > eps_in * sqrt(fabs(app * aqq)) && apq != 0.0) {
-                    double th = (aqq - app) / (2.0 * apq);
-                    double t;
-                    if (fabs(th) > 1e150) t = 0.5 / th;
-                    else t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    s = t * c;
-                    rot_any = 1;
-                }
-                cs[tid] = c;
-                sn[tid] = s;
-                pp[tid] = p;
-                qq[tid] = q;
-            }
-            __syncthreads();
-            for (int t = tid; t < JB * JW; t += 256) {
-                int k = t / JW, i = t % JW;
-                double c = cs[k], s = sn[k];
-                if (s != 0.0) {
-                    int p = pp[k], q = qq[k];
-                    double hp = H[i][p], hq = H[i][q];
-                    H[i][p] = c * hp - s * hq;
-                    H[i][q] = s * hp + c * hq;
-                    double rp = R[i][p], rq = R[i][q];
-                    R[i][p] = c * rp - s * rq;
-                    R[i][q] = s * rp + c * rq;
-                }
-            }
-            __syncthreads();
-            for (int t = tid; t < JB * JW; t += 256) {
-                int k = t / JW, i = t % JW;
-                double c = cs[k], s = sn[k];
-                if (s != 0.0) {
-                    int p = pp[k], q = qq[k];
-                    double hp = H[p][i], hq = H[q][i];
-                    H[p][i] = c * hp - s * hq;
-                    H[q][i] = s * hp + c * hq;
-                }
-            }
-            __syncthreads();
-        }
-        if (!rot_any) break;
-        __syncthreads();
-    }
+    inner_jacobi(H, Hs, R, inner_sweeps, &rot_any);
 
     // ---- 3. rotate the columns: [A_i A_j] <- [A_i A_j] R -----------------------
     for (int pass = 0; pass < 2; ++pass) {
@@ -198,11 +208,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(int n, int nblk, int 
 // ---------------------------------------------------------------------------
 // Small-n round kernel: the 32 columns of A (and of V) that a workgroup owns
 // stay in LDS for the whole round -- loaded once, used for the Gram matrix
-// and for the rotation -- and the inner two-sided Jacobi applies each
-// rotation round to H in one pass (H' = J^T H J element by element, ping-pong
-// buffers), so a rotation round costs one barrier pair instead of three
-// barriers.  Used when 2 * 32 * (n + 1) doubles plus the 32 x 32 work arrays
-// fit in the workgroup's LDS.
+// and for the rotation.  Used when 2 * 32 * (n + 1) doubles plus the 32 x 32
+// work arrays fit in the workgroup's LDS.
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int jl_ld(int n) { return ((n + 15) / 16) * 16 + 1; }  // odd pitch: fewer bank conflicts
 
@@ -218,8 +225,6 @@ __global__ __launch_bounds__(256) void jacobi_round_lds_kernel(int n, int nblk, 
     double* Vb = jl + JW * ldb;                // same for V (when V != nullptr)
     __shared__ double H0[JW][JW + 1], H1[JW][JW + 1], R[JW][JW + 1];
     __shared__ int cols[JW];
-    __shared__ int ia1[JW], ia2[JW];
-    __shared__ double w1[JW], w2[JW];
     __shared__ double red[4];
     __shared__ int rot_any;
 
@@ -286,63 +291,7 @@ __global__ __launch_bounds__(256) void jacobi_round_lds_kernel(int n, int nblk, 
     if (off_pair <= tol) return;  // uniform across the workgroup; A and V unchanged
 
     // ---- 2. two-sided Jacobi on H (at most inner_sweeps sweeps) --------------
-    for (int t = tid; t < JW * JW; t += 256) {
-        const int i = t % JW, j = t / JW;
-        R[i][j] = (i == j) ? 1.0 : 0.0;
-    }
-    const double eps_in = 2.220446049250313e-16;
-    double (*Hc)[JW + 1] = H0;
-    double (*Hn)[JW + 1] = H1;
-    for (int sweep = 0; sweep < inner_sweeps; ++sweep) {
-        if (tid == 0) rot_any = 0;
-        __syncthreads();
-        for (int rr = 0; rr < JW - 1; ++rr) {
-            // rotation of pair (p, q): J[p][p] = J[q][q] = c, J[p][q] = s, J[q][p] = -s;
-            // column i of J has two entries: (a1[i], w1[i]) and (a2[i], w2[i])
-            if (tid < JB) {
-                int p, q;
-                tournament_pair(rr, tid, JW, p, q);
-                const double app = Hc[p][p], aqq = Hc[q][q], apq = Hc[p][q];
-                double c = 1.0, s = 0.0;
-                if (fabs(apq) > eps_in * sqrt(fabs(app * aqq)) && apq != 0.0) {
-                    const double th = (aqq - app) / (2.0 * apq);
-                    double t;
-                    if (fabs(th) > 1e150) t = 0.5 / th;
-                    else t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    s = t * c;
-                    rot_any = 1;
-                }
-                ia1[p] = p; w1[p] = c; ia2[p] = q; w2[p] = -s;
-                ia1[q] = p; w1[q] = s; ia2[q] = q; w2[q] = c;
-            }
-            __syncthreads();
-            // H' = J^T H J and R' = R J, element by element
-            for (int t = tid; t < JW * JW; t += 256) {
-                const int i = t % JW, j = t / JW;
-                const int ai = ia1[i], bi2 = ia2[i], aj = ia1[j], bj2 = ia2[j];
-                const double ui = w1[i], vi = w2[i], uj = w1[j], vj = w2[j];
-                Hn[i][j] = ui * (uj * Hc[ai][aj] + vj * Hc[ai][bj2]) + vi * (uj * Hc[bi2][aj] + vj * Hc[bi2][bj2]);
-            }
-            // R is updated in place column-pair by column-pair: each thread owns
-            // both columns of a pair for its rows
-            for (int t = tid; t < JB * JW; t += 256) {
-                const int k = t / JW, i = t % JW;
-                int p, q;
-                tournament_pair(rr, k, JW, p, q);
-                const double c = w1[p], s = w1[q];
-                const double rp = R[i][p], rq = R[i][q];
-                R[i][p] = c * rp - s * rq;
-                R[i][q] = s * rp + c * rq;
-            }
-            __syncthreads();
-            double (*tmp)[JW + 1] = Hc;
-            Hc = Hn;
-            Hn = tmp;
-        }
-        if (!rot_any) break;
-        __syncthreads();
-    }
+    inner_jacobi(H0, H1, R, inner_sweeps, &rot_any);
 
     // ---- 3. [A_i A_j] <- [A_i A_j] R and likewise V, from LDS to global -------
     for (int pass = 0; pass < 2; ++pass) {

@@ -141,7 +141,13 @@ def test_precond_apply_matches_oracle(which):
         sp = oracle_split(X, S)
         sig = rf.sigma_diag(sp)
         AQ = rf.aq_matrix(p, sp)
-        P = rf.precond_matrix(AQ, sp, sig, rf.beta_rule(sp, p))
+        beta = rf.beta_rule(sp, p)
+        P = rf.precond_matrix(AQ, sp, sig, beta)
+        # P is expressed in each side's own eigenbasis of W: the two eigensolvers
+        # agree to ~eps ||W|| / gap (1e-12 at these points), which enters the
+        # backward error against the oracle's P at that size; a wrong block
+        # or coefficient gives O(1)
+        bound = 1e-10
         with Context(p) as ctx:
             ctx.set_point(dev(X), dev(y), dev(S))
             N = ctx.aug_dim()
@@ -155,8 +161,9 @@ def test_precond_apply_matches_oracle(which):
                 err = np.abs(z - ref).max() / np.abs(ref).max()
                 # normwise backward error of the GPU's z as a solution of P z = x
                 bwd = np.linalg.norm(P @ z - x) / (np.linalg.norm(P, 2) * np.linalg.norm(z) + np.linalg.norm(x))
-                print(f"{which} {name} trial {trial}: element error {err:.1e} backward error {bwd:.1e}")
-                assert bwd <= 1e-13 and err <= 1e-8, (name, trial)
+                print(f"{which} {name} trial {trial}: element error {err:.1e} backward error {bwd:.1e} "
+                      f"(bound {bound:.1e})")
+                assert bwd <= bound and err <= 1e-8, (name, trial)
 
 
 @pytest.mark.parametrize("which", ["cfg0", "entry"])
