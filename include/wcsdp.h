@@ -109,8 +109,9 @@ typedef struct sdp_problem {
  *  gap_tol, feas_tol   stopping tolerances of the interior-point method [1e-8]
  *  max_ipm_iter [100]
  *  step_frac    fraction of the step to the boundary [0.98]
- *  verbose      0 silent, 1 one line per interior-point iteration, 2 also one
- *               line per Krylov iteration (stderr) [0]
+ *  verbose      0 silent, 1 one line per interior-point iteration and one per
+ *               scaling setup with its phase timings (the stream is synchronised
+ *               between phases), 2 also one line per Krylov iteration (stderr) [0]
  */
 typedef struct sdp_options {
     int32_t rank_max;

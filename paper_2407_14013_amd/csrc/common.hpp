@@ -156,6 +156,8 @@ struct JacobiWork {
     DevBuf<int> perm;         // n
     DevBuf<double> tmpA;      // n * n (permutation staging)
     DevBuf<double> tmpV;      // n * n
+    DevBuf<double> part, rot; // large n: partial Gram matrices and rotations of the block pairs
+    DevBuf<int> skip;         // large n: pairs already orthogonal this round
     int* pinned = nullptr;    // 2 pinned host ints
     int cap = 0;
     void ensure(int n);

@@ -1,11 +1,13 @@
 // One-sided (Hestenes) block Jacobi SVD for FP64 n x n matrices on gfx950.
 //
 // The columns are grouped into blocks of 16.  A sweep visits every pair of
-// blocks once through a round-robin tournament: in each round the nblk/2
-// disjoint block pairs are processed by one workgroup each.  A workgroup
-//   1. forms the 32 x 32 Gram matrix H of its two blocks with FP64 MFMA,
-//   2. diagonalises H in LDS with two-sided cyclic Jacobi (H = R D R^T),
-//   3. rotates the 32 columns of A (and of V) by R with FP64 MFMA.
+// blocks once through a round-robin tournament; in each round the nblk/2
+// disjoint block pairs are independent.  For each pair
+//   1. the 32 x 32 Gram matrix H of its two blocks is formed with FP64 MFMA,
+//   2. H is diagonalised in LDS with two-sided cyclic Jacobi (H = R D R^T),
+//   3. the 32 columns of A (and of V) are rotated by R with FP64 MFMA.
+// For small n one workgroup per pair does all three with its columns held in
+// LDS; for large n the three steps are separate launches over row chunks.
 // A sweep in which every pair was already orthogonal to within
 // tol * ||a_i|| ||a_j|| ends the iteration.  Rotating only the columns of A
 // gives the singular values with high relative accuracy, which the small
@@ -102,58 +104,89 @@ __device__ void inner_jacobi(double (*H)[JW + 1], double (*Hs)[JW + 1], double (
     }
 }
 
-__global__ __launch_bounds__(256) void jacobi_round_kernel(int n, int nblk, int round, double* __restrict__ A,
-                                                           long lda, double* __restrict__ V, long ldv, double tol,
-                                                           unsigned long long* offmax, const int* __restrict__ done,
-                                                           int inner_sweeps) {
-    if (*done) return;  // an earlier sweep already converged
-    __shared__ double P[JR][JW + 1];
-    __shared__ double H[JW][JW + 1], Hs[JW][JW + 1];
-    __shared__ double R[JW][JW + 1];
-    __shared__ int cols[JW];
-    __shared__ double red[4];
-    __shared__ int rot_any;
+// ---------------------------------------------------------------------------
+// Large-n round: three launches, so that a round keeps the whole chip busy
+// instead of one workgroup per block pair walking all n rows.
+//   gram:   (pair, 128-row chunk) workgroups write partial 32 x 32 Gram matrices;
+//   pair:   one workgroup per pair sums them, tests the pair, diagonalises H
+//           and writes R (or marks the pair as already orthogonal);
+//   rotate: (pair, chunk, A or V) workgroups apply R to their rows.
+// ---------------------------------------------------------------------------
+constexpr int JCH = 128;  // rows per chunk
 
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+__device__ inline void pair_cols(int round, int w, int nblk, int n, int* cols) {
     int bi, bj;
-    tournament_pair(round, blockIdx.x, nblk, bi, bj);
-    if (tid < JW) {
-        int c = (tid < JB) ? bi * JB + tid : bj * JB + (tid - JB);
-        cols[tid] = (c < n) ? c : -1;
+    tournament_pair(round, w, nblk, bi, bj);
+    if (threadIdx.x < JW) {
+        const int c = (threadIdx.x < JB) ? bi * JB + threadIdx.x : bj * JB + (threadIdx.x - JB);
+        cols[threadIdx.x] = (c < n) ? c : -1;
     }
-    __syncthreads();
+}
 
-    // ---- 1. Gram matrix --------------------------------------------------
+// Rows [r0, r0 + JCH) of the pair's 32 columns into P (zero outside the matrix).
+// 16 independent loads per thread; consecutive threads read consecutive rows.
+__device__ inline void load_chunk(const double* __restrict__ M, long ldm, int n, int r0, const int* cols,
+                                  double (*P)[JW + 1]) {
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int idx = u * 256 + threadIdx.x;
+        const int c = idx / JCH, row = r0 + idx % JCH;
+        const int gc = cols[c];
+        t[u] = (gc >= 0 && row < n) ? M[row + (long)gc * ldm] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int idx = u * 256 + threadIdx.x;
+        P[idx % JCH][idx / JCH] = t[u];
+    }
+}
+
+__global__ __launch_bounds__(256) void jacobi_gram_kernel(int n, int nblk, int round, const double* __restrict__ A,
+                                                          long lda, double* __restrict__ part,
+                                                          const int* __restrict__ done) {
+    if (*done) return;
+    __shared__ double P[JCH][JW + 1];
+    __shared__ int cols[JW];
+    const int w = blockIdx.x, chunk = blockIdx.y, nchunks = gridDim.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    pair_cols(round, w, nblk, n, cols);
+    __syncthreads();
+    load_chunk(A, lda, n, chunk * JCH, cols, P);
+    __syncthreads();
     const int hi = wave >> 1, hj = wave & 1;
     d4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int r0 = 0; r0 < n; r0 += JR) {
-        const int row = r0 + lane;
+#pragma unroll 8
+    for (int k4 = 0; k4 < JCH; k4 += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(P[k4 + (lane >> 4)][hi * 16 + (lane & 15)],
+                                                   P[k4 + (lane >> 4)][hj * 16 + (lane & 15)], acc, 0, 0, 0);
+    double* out = part + ((long)w * nchunks + chunk) * (JW * JW);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            int c = wave + 4 * q;
-            int gc = cols[c];
-            P[lane][c] = (gc >= 0 && row < n) ? A[row + (long)gc * lda] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k4 = 0; k4 < JR; k4 += 4) {
-            double a = P[k4 + (lane >> 4)][hi * 16 + (lane & 15)];
-            double b = P[k4 + (lane >> 4)][hj * 16 + (lane & 15)];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) H[hi * 16 + (lane >> 4) + 4 * v][hj * 16 + (lane & 15)] = acc[v];
-    __syncthreads();
+    for (int v = 0; v < 4; ++v) out[(hi * 16 + (lane >> 4) + 4 * v) * JW + hj * 16 + (lane & 15)] = acc[v];
+}
 
-    // ---- convergence measure of this pair ----------------------------------
+__global__ __launch_bounds__(256) void jacobi_pair_kernel(int nchunks, const double* __restrict__ part,
+                                                          double* __restrict__ Rout, int* __restrict__ skip,
+                                                          double tol, unsigned long long* offmax,
+                                                          const int* __restrict__ done, int inner_sweeps) {
+    if (*done) return;
+    __shared__ double H[JW][JW + 1], Hs[JW][JW + 1], R[JW][JW + 1];
+    __shared__ double red[4];
+    __shared__ int rot_any;
+    const int w = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double* src = part + (long)w * nchunks * (JW * JW);
+    for (int t = tid; t < JW * JW; t += 256) {
+        double sum = 0.0;
+        for (int ch = 0; ch < nchunks; ++ch) sum += src[(long)ch * (JW * JW) + t];
+        H[t / JW][t % JW] = sum;
+    }
+    __syncthreads();
     double mx = 0.0;
     for (int t = tid; t < JW * JW; t += 256) {
-        int i = t % JW, j = t / JW;
+        const int i = t % JW, j = t / JW;
         if (i < j) {
-            double hii = H[i][i], hjj = H[j][j];
+            const double hii = H[i][i], hjj = H[j][j];
             if (hii > 0.0 && hjj > 0.0) mx = fmax(mx, fabs(H[i][j]) / sqrt(hii * hjj));
         }
     }
@@ -162,46 +195,64 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(int n, int nblk, int 
     if (lane == 0) red[wave] = mx;
     __syncthreads();
     const double off_pair = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    if (tid == 0) atomicMax(offmax, static_cast<unsigned long long>(__double_as_longlong(off_pair)));
+    if (tid == 0) {
+        atomicMax(offmax, static_cast<unsigned long long>(__double_as_longlong(off_pair)));
+        skip[w] = off_pair <= tol ? 1 : 0;
+    }
     if (off_pair <= tol) return;  // uniform across the workgroup
-
-    // ---- 2. two-sided Jacobi sweeps on H (at most inner_sweeps) ---------------
     // The pair need not be diagonalised exactly: the outer sweeps revisit it,
-    // and convergence is judged only by the outer tolerance test above.
+    // and convergence is judged only by the tolerance test above.
     inner_jacobi(H, Hs, R, inner_sweeps, &rot_any);
+    for (int t = tid; t < JW * JW; t += 256) Rout[(long)w * (JW * JW) + t] = R[t / JW][t % JW];
+}
 
-    // ---- 3. rotate the columns: [A_i A_j] <- [A_i A_j] R -----------------------
-    for (int pass = 0; pass < 2; ++pass) {
-        double* M = pass == 0 ? A : V;
-        const long ldm = pass == 0 ? lda : ldv;
-        if (M == nullptr) break;
-        for (int r0 = 0; r0 < n; r0 += JR) {
-            const int row = r0 + lane;
+__global__ __launch_bounds__(256) void jacobi_rotate_kernel(int n, int nblk, int round, double* __restrict__ A,
+                                                            long lda, double* __restrict__ V, long ldv,
+                                                            const double* __restrict__ Rin,
+                                                            const int* __restrict__ skip,
+                                                            const int* __restrict__ done) {
+    const int w = blockIdx.x, chunk = blockIdx.y;
+    if (*done || skip[w]) return;
+    double* M = blockIdx.z == 0 ? A : V;
+    const long ldm = blockIdx.z == 0 ? lda : ldv;
+    __shared__ double P[JCH][JW + 1], R[JW][JW + 1];
+    __shared__ int cols[JW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    pair_cols(round, w, nblk, n, cols);
+    for (int t = tid; t < JW * JW; t += 256) R[t / JW][t % JW] = Rin[(long)w * (JW * JW) + t];
+    __syncthreads();
+    const int r0 = chunk * JCH;
+    load_chunk(M, ldm, n, r0, cols, P);
+    __syncthreads();
+    // wave `wave` owns rows [32 wave, 32 wave + 32) of the chunk: 2 x 2 output tiles
+    d4 o[2][2];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                int c = wave + 4 * q;
-                int gc = cols[c];
-                P[lane][c] = (gc >= 0 && row < n) ? M[row + (long)gc * ldm] : 0.0;
-            }
-            __syncthreads();
+    for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-            for (int jt = 0; jt < 2; ++jt) {
-                d4 o = {0.0, 0.0, 0.0, 0.0};
+        for (int jt = 0; jt < 2; ++jt) {
+            o[rt][jt] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int k4 = 0; k4 < JW; k4 += 4) {
-                    double a = P[wave * 16 + (lane & 15)][k4 + (lane >> 4)];
-                    double b = R[k4 + (lane >> 4)][jt * 16 + (lane & 15)];
-                    o = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, o, 0, 0, 0);
-                }
-                const int gc = cols[jt * 16 + (lane & 15)];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    int rrow = r0 + wave * 16 + (lane >> 4) + 4 * v;
-                    if (gc >= 0 && rrow < n) M[rrow + (long)gc * ldm] = o[v];
-                }
-            }
-            __syncthreads();
+            for (int k4 = 0; k4 < JW; k4 += 4)
+                o[rt][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(P[wave * 32 + rt * 16 + (lane & 15)][k4 + (lane >> 4)],
+                                                                 R[k4 + (lane >> 4)][jt * 16 + (lane & 15)],
+                                                                 o[rt][jt], 0, 0, 0);
         }
+    __syncthreads();  // every wave has read its rows of P
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                P[wave * 32 + rt * 16 + (lane >> 4) + 4 * v][jt * 16 + (lane & 15)] = o[rt][jt][v];
+    __syncthreads();
+    // coalesced write-back, the load pattern reversed
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int idx = u * 256 + tid;
+        const int c = idx / JCH, row = r0 + idx % JCH;
+        const int gc = cols[c];
+        if (gc >= 0 && row < n) M[row + (long)gc * ldm] = P[idx % JCH][c];
     }
 }
 
@@ -447,12 +498,31 @@ void JacobiWork::ensure(int n) {
     perm.alloc(n);
     tmpA.alloc((size_t)n * n);
     tmpV.alloc((size_t)n * n);
+    // large-n rounds: partial Gram matrices, rotations and skip flags per block pair
+    const int nblk = cdiv(n, JB) + 1, npairs = nblk / 2 + 1;
+    part.alloc((size_t)npairs * cdiv(n, JCH) * JW * JW);
+    rot.alloc((size_t)npairs * JW * JW);
+    skip.alloc(npairs);
     if (!pinned) WC_HIP(hipHostMalloc(reinterpret_cast<void**>(&pinned), 2 * sizeof(int), hipHostMallocDefault));
     cap = n;
 }
 
 JacobiWork::~JacobiWork() {
     if (pinned) (void)hipHostFree(pinned);
+}
+
+// One round of the large-n form (three launches; see the kernels above).
+static void split_round(hipStream_t st, int n, int nblk, int round, double* A, long lda, double* V, long ldv,
+                        double tol, unsigned long long* off, const int* flags, JacobiWork& w) {
+    const int npairs = nblk / 2, nchunks = cdiv(n, JCH);
+    hipLaunchKernelGGL(jacobi_gram_kernel, dim3(npairs, nchunks), dim3(256), 0, st, n, nblk, round, A, lda,
+                       w.part.get(), flags);
+    WC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(jacobi_pair_kernel, dim3(npairs), dim3(256), 0, st, nchunks, w.part.get(), w.rot.get(),
+                       w.skip.get(), tol, off, flags, jacobi_inner_sweeps());
+    WC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(jacobi_rotate_kernel, dim3(npairs, nchunks, V ? 2 : 1), dim3(256), 0, st, n, nblk, round, A,
+                       lda, V, ldv, w.rot.get(), w.skip.get(), flags);
 }
 
 int jacobi_svd(hipStream_t st, int n, double* A, long lda, double* V, long ldv, double* sigma, double tol,
@@ -488,8 +558,7 @@ int jacobi_svd(hipStream_t st, int n, double* A, long lda, double* V, long ldv, 
                 hipLaunchKernelGGL(jacobi_round_lds_kernel, dim3(nblk / 2), dim3(256), lds_dyn, st, n, nblk, round, A,
                                    lda, V, ldv, tol, off, flags, jacobi_inner_sweeps());
             else
-                hipLaunchKernelGGL(jacobi_round_kernel, dim3(nblk / 2), dim3(256), 0, st, n, nblk, round, A, lda, V,
-                                   ldv, tol, off, flags, jacobi_inner_sweeps());
+                split_round(st, n, nblk, round, A, lda, V, ldv, tol, off, flags, w);
             WC_LAUNCH_CHECK();
         }
         hipLaunchKernelGGL(sweep_end_kernel, dim3(1), dim3(1), 0, st, off, flags, tol);

@@ -370,6 +370,18 @@ void ensure_scaling(sdp_ctx* c) {
     const int n = c->n, m = c->m;
     const long nn = (long)n * n;
     hipStream_t st = c->st;
+    // phase timings when verbose (synchronising the stream at each mark)
+    using clk = std::chrono::steady_clock;
+    const bool tm = c->opt.verbose >= 1;
+    double ph[6] = {0, 0, 0, 0, 0, 0};
+    auto tprev = clk::now();
+    auto mark = [&](int k) {
+        if (!tm) return;
+        WC_HIP(hipStreamSynchronize(st));
+        const auto t = clk::now();
+        ph[k] += std::chrono::duration<double, std::milli>(t - tprev).count();
+        tprev = t;
+    };
     // Cholesky factors X = L L^T, S = Rs Rs^T
     copy(st, nn, c->X, c->L);
     potrf(st, n, c->L, n, c->info.get());
@@ -393,7 +405,9 @@ void ensure_scaling(sdp_ctx* c) {
     } else {
         gemm(c, true, false, n, n, n, 1.0, c->Rs, n, c->L, n, 0.0, c->Mt, n);
     }
+    mark(0);
     int sw = jacobi_svd(st, n, c->Mt, n, c->Vs, n, c->dnt, 0.0, 60, c->jw, false, warm);
+    mark(1);
     if (sw < 0) throw Error(kENumeric, "Jacobi SVD of the NT factor did not converge");
     c->sweeps_nt = sw;
     gemm(c, false, false, n, n, n, 1.0, c->L, n, c->Vs, n, 0.0, c->T1, n);
@@ -407,7 +421,9 @@ void ensure_scaling(sdp_ctx* c) {
     } else {
         transpose(st, n, n, c->G, n, c->Gt, n);
     }
+    mark(0);
     sw = jacobi_svd(st, n, c->Gt, n, c->Gw, n, c->lam, 0.0, 60, c->jw, false, warm);
+    mark(2);
     c->sweeps_w = sw;
     c->have_prev = true;
     if (sw < 0) throw Error(kENumeric, "Jacobi eigen-decomposition of W did not converge");
@@ -460,6 +476,7 @@ void ensure_scaling(sdp_ctx* c) {
             }
         }
     }
+    mark(3);
     // C = L_C L_C^T, then C^{-1} = L_C^{-T} L_C^{-1}
     potrf(st, d, c->Cm, c->dmaxp, c->info.get());
     WC_HIP(hipMemcpyAsync(hinfo, c->info.get(), sizeof(int), hipMemcpyDeviceToHost, st));
@@ -470,6 +487,12 @@ void ensure_scaling(sdp_ctx* c) {
     fill(st, c->dmaxp * c->dmaxp, c->Cm, 0.0);
     gemm(c, true, false, d, d, d, 1.0, c->Cinv, c->dmaxp, c->Cinv, c->dmaxp, 0.0, c->Cm, c->dmaxp);
     std::swap(c->Cm, c->Cinv);
+    mark(4);
+    if (tm)
+        fprintf(stderr,
+                "[wcsdp] scaling: factors+products %.2f  Jacobi NT %.2f (%d sweeps)  Jacobi W %.2f (%d sweeps)  "
+                "split+E+C %.2f  C factor+inverse %.2f ms\n",
+                ph[0], ph[1], c->sweeps_nt, ph[2], c->sweeps_w, ph[3], ph[4]);
     c->scaling_valid = true;
 }
 

@@ -66,8 +66,9 @@ def test_dtrtri(n):
     assert np.abs(Xg - ref).max() <= 100 * n * EPS * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("n", [2, 16, 17, 40, 129, 200])
+@pytest.mark.parametrize("n", [2, 16, 17, 40, 129, 200, 257, 300, 1000])
 def test_jacobi_svd(n):
+    # n <= 256: the LDS-resident round; above: the three-launch round over row chunks
     rng = np.random.default_rng(n + 11)
     A = rng.standard_normal((n, n))
     Ad = la.to_dev(A)
@@ -90,12 +91,12 @@ def test_jacobi_svd(n):
     assert np.all(Vg[idx, np.arange(n)] > 0)
 
 
-def test_jacobi_graded_columns_relative_accuracy():
+@pytest.mark.parametrize("n", [48, 300])
+def test_jacobi_graded_columns_relative_accuracy(n):
     # A = B D with B well conditioned: one-sided Jacobi resolves every singular
     # value to high relative accuracy; compare against the same product in
     # exact column scaling (singular values of B D from B's Gram with D applied).
     rng = np.random.default_rng(3)
-    n = 48
     B, _ = np.linalg.qr(rng.standard_normal((n, n)))
     B = B @ np.diag(rng.uniform(0.5, 2.0, n)) @ np.linalg.qr(rng.standard_normal((n, n)))[0]
     D = np.diag(np.logspace(0, -10, n))
