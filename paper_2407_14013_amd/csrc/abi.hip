@@ -299,8 +299,13 @@ int32_t wc_dgemm(void* stream, char transa, char transb, int32_t m, int32_t n, i
         wc::require(lda >= std::max(1, ta ? k : m), "lda too small");
         wc::require(ldb >= std::max(1, tb ? n : k), "ldb too small");
         hipStream_t st = static_cast<hipStream_t>(stream);
-        if (tb || !wc::dgemm_thin(st, ta, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc))
+        // a split-K workspace for thin products with a long K, held until the work is done
+        wc::DevBuf<double> ws;
+        if (!tb && !ta && n >= 1 && n <= 16 && m >= 1 && k >= 256) ws.alloc(wc::thin_splitk_ws(m, n));
+        if (tb || !wc::dgemm_thin(st, ta, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws.get(),
+                                  static_cast<long>(ws.n)))
             wc::dgemm(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+        if (ws.get()) WC_HIP(hipStreamSynchronize(st));
         return (int32_t)0;
     });
 }

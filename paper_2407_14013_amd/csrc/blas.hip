@@ -168,6 +168,7 @@ void dgemm(hipStream_t st, bool ta, bool tb, int m, int n, int k, double alpha, 
 // ---------------------------------------------------------------------------
 constexpr int THIN_N = 16;
 constexpr int THIN_LDS = 4096;  // doubles of B staged in LDS
+constexpr int THIN_SPLITS = 32;  // most K-splits of the split-K form
 
 // 64 rows per workgroup; the four waves split K and their partial sums are
 // added in LDS in wave order.
@@ -238,13 +239,81 @@ __global__ __launch_bounds__(256) void dgemm_thin_t_kernel(int M, int N, int K, 
     }
 }
 
+// Split-K form of the thin product for large K: workgroup (rows, split)
+// computes the partial product of its K-chunk (the chunk of B staged in LDS)
+// into part[split][j][i]; thin_reduce_kernel sums the splits in a fixed order.
+__global__ __launch_bounds__(256) void dgemm_thin_splitk_kernel(int M, int N, int K, int kc,
+                                                                const double* __restrict__ A, long lda,
+                                                                const double* __restrict__ B, long ldb,
+                                                                double* __restrict__ part) {
+    __shared__ double Bs[THIN_LDS];
+    __shared__ double red[4][THIN_N][64];
+    const int ks0 = blockIdx.y * kc, ks1 = min(K, ks0 + kc);
+    const int len = ks1 - ks0;
+    for (int t = threadIdx.x; t < len * N; t += 256) Bs[t] = B[ks0 + (t % len) + (long)(t / len) * ldb];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
+    const int q = (len + 3) / 4;
+    const int k0 = wv * q, k1 = min(len, k0 + q);
+    double acc[THIN_N];
+#pragma unroll
+    for (int j = 0; j < THIN_N; ++j) acc[j] = 0.0;
+    if (i < M) {
+#pragma unroll 8
+        for (int k = k0; k < k1; ++k) {
+            const double a = A[i + (long)(ks0 + k) * lda];
+#pragma unroll
+            for (int j = 0; j < THIN_N; ++j)
+                if (j < N) acc[j] += a * Bs[k + j * len];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < THIN_N; ++j)
+        if (j < N) red[wv][j][lane] = acc[j];
+    __syncthreads();
+    if (wv == 0 && i < M) {
+        for (int j = 0; j < N; ++j)
+            part[((long)blockIdx.y * N + j) * M + i] = ((red[0][j][lane] + red[1][j][lane]) + red[2][j][lane]) +
+                                                       red[3][j][lane];
+    }
+}
+
+__global__ void thin_reduce_kernel(int M, int N, int splits, const double* __restrict__ part, double alpha,
+                                   double beta, double* __restrict__ C, long ldc) {
+    const long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)M * N) return;
+    const int i = static_cast<int>(t % M), j = static_cast<int>(t / M);
+    double v = 0.0;
+    for (int sp = 0; sp < splits; ++sp) v += part[((long)sp * N + j) * M + i];
+    double* c = C + i + (long)j * ldc;
+    *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
+}
+
+long thin_splitk_ws(int m, int n) { return (long)THIN_SPLITS * m * n; }
+
 bool dgemm_thin(hipStream_t st, bool ta, int m, int n, int k, double alpha, const double* A, long lda,
-                const double* B, long ldb, double beta, double* C, long ldc) {
+                const double* B, long ldb, double beta, double* C, long ldc, double* ws, long ws_len) {
     if (n < 1 || n > THIN_N || m < 1 || k < 1) return false;
     if (!ta) {
-        if ((long)k * n > THIN_LDS) return false;
-        hipLaunchKernelGGL(dgemm_thin_n_kernel, dim3(cdiv(m, 64)), dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb,
-                           beta, C, ldc);
+        // one workgroup per 64 rows covers the chip only for m >= 64 * #CUs;
+        // otherwise split K as well (when a workspace is given)
+        int splits = std::max(1, cdiv((long)k * n, THIN_LDS));
+        if (ws != nullptr) splits = std::max(splits, std::min(cdiv(k, 256), cdiv(512, cdiv(m, 64))));
+        splits = std::min(splits, THIN_SPLITS);
+        const int kc = cdiv(k, splits);
+        splits = cdiv(k, kc);
+        if (splits == 1) {
+            hipLaunchKernelGGL(dgemm_thin_n_kernel, dim3(cdiv(m, 64)), dim3(256), 0, st, m, n, k, alpha, A, lda, B,
+                               ldb, beta, C, ldc);
+        } else {
+            if (ws == nullptr || (long)splits * m * n > ws_len || (long)kc * n > THIN_LDS) return false;
+            hipLaunchKernelGGL(dgemm_thin_splitk_kernel, dim3(cdiv(m, 64), splits), dim3(256), 0, st, m, n, k, kc, A,
+                               lda, B, ldb, ws);
+            WC_LAUNCH_CHECK();
+            hipLaunchKernelGGL(thin_reduce_kernel, dim3(cdiv((long)m * n, 256)), dim3(256), 0, st, m, n, splits, ws,
+                               alpha, beta, C, ldc);
+        }
     } else {
         hipLaunchKernelGGL(dgemm_thin_t_kernel, dim3(cdiv(m, 4)), dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb,
                            beta, C, ldc);

@@ -85,9 +85,11 @@ void dgemm(hipStream_t st, bool ta, bool tb, int m, int n, int k, double alpha, 
            long sA = 0, long sB = 0, long sC = 0);
 
 // C = alpha op(A) B + beta C for a thin B (n <= 16 columns); returns false
-// (nothing launched) when the shape is not handled.
+// (nothing launched) when the shape is not handled.  With a workspace of
+// thin_splitk_ws(m, n) doubles, op(A) = A with a long K is split over K as well.
 bool dgemm_thin(hipStream_t st, bool ta, int m, int n, int k, double alpha, const double* A, long lda,
-                const double* B, long ldb, double beta, double* C, long ldc);
+                const double* B, long ldb, double beta, double* C, long ldc, double* ws = nullptr, long ws_len = 0);
+long thin_splitk_ws(int m, int n);
 
 // y = alpha A x + beta y for row-major A (m rows, k used columns, row pitch
 // lda, lda even, 16-byte aligned rows); x must be readable up to

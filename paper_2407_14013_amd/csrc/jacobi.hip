@@ -38,15 +38,17 @@ __device__ inline void tournament_pair(int round, int w, int N, int& a, int& b) 
 // Rotation (c, s) that annihilates H[p][q] of the symmetric 2 x 2 block
 // [app apq; apq aqq] (J[p][p] = J[q][q] = c, J[p][q] = s, J[q][p] = -s);
 // the identity when the entry is already negligible.
+// With x = aqq - app and y = 2 apq, the smaller root of t^2 + 2 (x / y) t - 1
+// is t = sgn(x) y / (|x| + sqrt(x^2 + y^2)), so |t| <= 1 (one square root,
+// one division and one reciprocal square root on the dependent chain).
 __device__ inline bool jacobi_angle(double app, double aqq, double apq, double& c, double& s) {
     c = 1.0;
     s = 0.0;
     if (!(fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app * aqq))) || apq == 0.0) return false;
-    const double th = (aqq - app) / (2.0 * apq);
-    double t;
-    if (fabs(th) > 1e150) t = 0.5 / th;
-    else t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-    c = 1.0 / sqrt(1.0 + t * t);
+    const double x = aqq - app, y = 2.0 * apq;
+    const double h = sqrt(fma(x, x, y * y));
+    const double t = (x >= 0.0 ? y : -y) / (fabs(x) + h);
+    c = rsqrt(fma(t, t, 1.0));
     s = t * c;
     return true;
 }
@@ -155,14 +157,18 @@ __global__ __launch_bounds__(256) void jacobi_gram_kernel(int n, int nblk, int r
     load_chunk(A, lda, n, chunk * JCH, cols, P);
     __syncthreads();
     const int hi = wave >> 1, hj = wave & 1;
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 8
-    for (int k4 = 0; k4 < JCH; k4 += 4)
+    d4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k4 = 0; k4 < JCH; k4 += 8) {
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(P[k4 + (lane >> 4)][hi * 16 + (lane & 15)],
                                                    P[k4 + (lane >> 4)][hj * 16 + (lane & 15)], acc, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(P[k4 + 4 + (lane >> 4)][hi * 16 + (lane & 15)],
+                                                    P[k4 + 4 + (lane >> 4)][hj * 16 + (lane & 15)], acc2, 0, 0, 0);
+    }
     double* out = part + ((long)w * nchunks + chunk) * (JW * JW);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) out[(hi * 16 + (lane >> 4) + 4 * v) * JW + hj * 16 + (lane & 15)] = acc[v];
+    for (int v = 0; v < 4; ++v)
+        out[(hi * 16 + (lane >> 4) + 4 * v) * JW + hj * 16 + (lane & 15)] = acc[v] + acc2[v];
 }
 
 __global__ __launch_bounds__(256) void jacobi_pair_kernel(int nchunks, const double* __restrict__ part,
@@ -315,12 +321,17 @@ __global__ __launch_bounds__(256) void jacobi_round_lds_kernel(int n, int nblk, 
     // ---- 1. Gram matrix from LDS ----------------------------------------------
     {
         const int hi = wave >> 1, hj = wave & 1;
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        // two accumulators halve the dependent MFMA chain (nr is a multiple of 16)
+        d4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
         const double* ca = Ab + (hi * 16 + (lane & 15)) * ldb + (lane >> 4);
         const double* cb = Ab + (hj * 16 + (lane & 15)) * ldb + (lane >> 4);
-        for (int k4 = 0; k4 < nr; k4 += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[k4], cb[k4], acc, 0, 0, 0);
+#pragma unroll 2
+        for (int k4 = 0; k4 < nr; k4 += 8) {
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[k4], cb[k4], acc, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[k4 + 4], cb[k4 + 4], acc2, 0, 0, 0);
+        }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) H0[hi * 16 + (lane >> 4) + 4 * v][hj * 16 + (lane & 15)] = acc[v];
+        for (int v = 0; v < 4; ++v) H0[hi * 16 + (lane >> 4) + 4 * v][hj * 16 + (lane & 15)] = acc[v] + acc2[v];
     }
     __syncthreads();
 

@@ -103,7 +103,7 @@ static void gemm(sdp_ctx* c, bool ta, bool tb, int m, int n, int k, double alpha
                  const double* B, long ldb, double beta, double* C, long ldc) {
     hipEvent_t e;
     prof_begin(c, SDP_K_GEMM, &e);
-    if (tb || !dgemm_thin(c->st, ta, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc))
+    if (tb || !dgemm_thin(c->st, ta, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, c->thin_ws, static_cast<long>(c->thin_ws.n)))
         dgemm(c->st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
     prof_end(c, SDP_K_GEMM, e, 8.0 * ((double)m * k + (double)k * n + 2.0 * (double)m * n));
 }
@@ -170,6 +170,7 @@ static void alloc_work(sdp_ctx* c) {
     }
 
     c->part.alloc(1024);
+    c->thin_ws.alloc(thin_splitk_ws(n, c->rmax));
     for (auto* b : {&c->vx, &c->vr, &c->vz, &c->vp, &c->vKp, &c->vg, &c->vtmp, &c->vres, &c->vdx}) {
         b->alloc(Nmax);
         fill(c->st, Nmax, b->get(), 0.0);

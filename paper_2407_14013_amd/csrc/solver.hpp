@@ -49,6 +49,7 @@ struct sdp_ctx {
     wc::DevBuf<double> vx, vr, vz, vp, vKp, vg, vtmp;   // Krylov vectors (m + dmax, padded)
     wc::DevBuf<double> vres, vdx;                       // refinement residual and correction
 
+    wc::DevBuf<double> thin_ws; // split-K partial sums of the thin GEMMs
     wc::DevBuf<double> sc;      // device scalars
     double* pin = nullptr;      // pinned host scalars
     wc::DevBuf<int> info;

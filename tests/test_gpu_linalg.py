@@ -16,7 +16,8 @@ EPS = np.finfo(np.float64).eps
 @pytest.mark.parametrize("ta", ["N", "T"])
 @pytest.mark.parametrize("tb", ["N", "T"])
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1), (17, 33, 9), (64, 64, 64), (130, 67, 95), (200, 200, 200), (65, 1, 129),
-                                   (200, 3, 200), (301, 16, 77), (5000, 2, 300)])
+                                   (200, 3, 200), (301, 16, 77), (5000, 2, 300), (4000, 4, 4000), (300, 10, 1000),
+                                   (77, 3, 20000)])
 def test_dgemm(ta, tb, m, n, k):
     rng = np.random.default_rng(m * 1000 + n * 10 + k)
     A = rng.standard_normal((k, m) if ta == "T" else (m, k))
