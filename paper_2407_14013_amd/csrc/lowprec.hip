@@ -179,6 +179,115 @@ __global__ __launch_bounds__(256) void bgemm_nn_kernel(int M, int N, int K, cons
             lp_store<OUT>(C, ldc, M, N, row0 + wm * 32 + x * 16, col0 + wn * 32 + y * 16, acc[x][y]);
 }
 
+// ---- BF16 product with a symmetric left operand ------------------------------------
+// C = A B with A symmetric (M x M) and B (M x N), both column-major BF16.
+// Because A is symmetric, A(i, k) = A[k + i lda]: row i of A is contiguous in k
+// like column j of B, so both MFMA operands arrive as 16-byte (8 x BF16)
+// k-contiguous loads and are stored to LDS as they are, without the
+// transposition a general A needs.  128 x 128 output tile per workgroup, four
+// waves in a 2 x 2 grid with 4 x 4 MFMA tiles (16 x 16 x 32) each; K advances
+// 32 at a time through double-buffered LDS with one barrier per step, the next
+// step's loads held in registers while the current one multiplies.  Requires
+// lda and ldb multiples of 8 and 16-byte aligned A and B.
+constexpr int ST = 128;  // output tile
+constexpr int SK = 32;   // k per step (one MFMA k-extent)
+constexpr int SP = SK + 8;  // LDS row pitch in halves (80 bytes: 16-byte aligned, spreads banks)
+
+__device__ __forceinline__ v8us load8_guarded(const unsigned short* __restrict__ p, int k, int K) {
+    if (k + 8 <= K) return *reinterpret_cast<const v8us*>(p);
+    v8us v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (k + e < K) ? p[e] : static_cast<unsigned short>(0);
+    return v;
+}
+
+template <LpOut OUT>
+__global__ __launch_bounds__(256) void bgemm_sym_kernel(int M, int N, const unsigned short* __restrict__ A, long lda,
+                                                        const unsigned short* __restrict__ B, long ldb,
+                                                        void* __restrict__ C, long ldc) {
+    __shared__ __attribute__((aligned(16))) unsigned short As[2][ST][SP];  // [buffer][row][k]
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][ST][SP];  // [buffer][col][k]
+    const int K = M;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv & 1, wn = wv >> 1;
+    const int row0 = blockIdx.x * ST, col0 = blockIdx.y * ST;
+    // loader: vector q = tid + 256 h covers row (or column) q / 4 and k offset 8 (q % 4)
+    v8us ra[2], rb[2];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = tid + 256 * h, r = q >> 2, k = k0 + 8 * (q & 3);
+            const int gi = row0 + r, gj = col0 + r;
+            ra[h] = gi < M ? load8_guarded(A + k + (long)gi * lda, k, K) : v8us{0, 0, 0, 0, 0, 0, 0, 0};
+            rb[h] = gj < N ? load8_guarded(B + k + (long)gj * ldb, k, K) : v8us{0, 0, 0, 0, 0, 0, 0, 0};
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = tid + 256 * h, r = q >> 2, k = 8 * (q & 3);
+            *reinterpret_cast<v8us*>(&As[buf][r][k]) = ra[h];
+            *reinterpret_cast<v8us*>(&Bs[buf][r][k]) = rb[h];
+        }
+    };
+    v4f acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    const int kg = 8 * (lane >> 4);
+    int buf = 0;
+    for (int k0 = 0; k0 < K; k0 += SK) {
+        const bool more = k0 + SK < K;
+        if (more) fetch(k0 + SK);
+        v8us a[4], b[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) a[x] = *reinterpret_cast<const v8us*>(&As[buf][wm * 64 + x * 16 + (lane & 15)][kg]);
+#pragma unroll
+        for (int y = 0; y < 4; ++y) b[y] = *reinterpret_cast<const v8us*>(&Bs[buf][wn * 64 + y * 16 + (lane & 15)][kg]);
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y)
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a[x]),
+                                                                    __builtin_bit_cast(v8bf, b[y]), acc[x][y], 0, 0,
+                                                                    0);
+        if (more) stash(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+            lp_store<OUT>(C, ldc, M, N, row0 + wm * 64 + x * 16, col0 + wn * 64 + y * 16, acc[x][y]);
+}
+
+bool lp_gemm_sym(hipStream_t st, Lp in, LpOut out, int M, int N, const void* A, long lda, const void* B, long ldb,
+                 void* C, long ldc) {
+    require(M >= 0 && N >= 0, "lp_gemm_sym: negative size");
+    require(lda >= std::max(1, M) && ldb >= std::max(1, M) && ldc >= std::max(1, M),
+            "lp_gemm_sym: bad leading dimension");
+    if (M == 0 || N == 0) return true;
+    const bool aligned = (lda % 8 == 0) && (ldb % 8 == 0) && (reinterpret_cast<uintptr_t>(A) % 16 == 0) &&
+                         (reinterpret_cast<uintptr_t>(B) % 16 == 0);
+    if (in != Lp::BF16 || !aligned || cdiv(N, ST) > 65535) return false;
+    dim3 grid(cdiv(M, ST), cdiv(N, ST));
+    const auto* a = static_cast<const unsigned short*>(A);
+    const auto* b = static_cast<const unsigned short*>(B);
+    switch (out) {
+        case LpOut::F32: hipLaunchKernelGGL(bgemm_sym_kernel<LpOut::F32>, grid, dim3(256), 0, st, M, N, a, lda, b, ldb, C, ldc); break;
+        case LpOut::BF16: hipLaunchKernelGGL(bgemm_sym_kernel<LpOut::BF16>, grid, dim3(256), 0, st, M, N, a, lda, b, ldb, C, ldc); break;
+        case LpOut::F64: hipLaunchKernelGGL(bgemm_sym_kernel<LpOut::F64>, grid, dim3(256), 0, st, M, N, a, lda, b, ldb, C, ldc); break;
+        case LpOut::ADD_F64: hipLaunchKernelGGL(bgemm_sym_kernel<LpOut::ADD_F64>, grid, dim3(256), 0, st, M, N, a, lda, b, ldb, C, ldc); break;
+    }
+    WC_LAUNCH_CHECK();
+    return true;
+}
+
 template <LpOut OUT>
 static void lp_gemm_launch(hipStream_t st, Lp in, int M, int N, int K, const void* A, long lda, const void* B,
                            long ldb, void* C, long ldc) {

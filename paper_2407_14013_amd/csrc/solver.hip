@@ -537,11 +537,15 @@ static void sandwich_lp(sdp_ctx* c, LpOut tout, LpOut mout) {
     const int n = c->n;
     const double bytes = (c->lp == Lp::F32 ? 4.0 : 2.0) * 3.0 * n * n + 8.0 * n * n;
     hipEvent_t es;
+    // Y and E are symmetric, so both products take the symmetric-left-operand
+    // kernel where it applies (BF16, aligned rows)
     prof_begin(c, SDP_K_SANDWICH, &es);
-    lp_gemm_nn(c->st, c->lp, tout, n, n, n, c->Ylp, n, c->Elp, n, c->Tlp, n);
+    if (!lp_gemm_sym(c->st, c->lp, tout, n, n, c->Ylp, n, c->Elp, n, c->Tlp, n))
+        lp_gemm_nn(c->st, c->lp, tout, n, n, n, c->Ylp, n, c->Elp, n, c->Tlp, n);
     prof_end(c, SDP_K_SANDWICH, es, bytes);
     prof_begin(c, SDP_K_SANDWICH, &es);
-    lp_gemm_nn(c->st, c->lp, mout, n, n, n, c->Elp, n, c->Tlp, n, c->Mm, n);
+    if (!lp_gemm_sym(c->st, c->lp, mout, n, n, c->Elp, n, c->Tlp, n, c->Mm, n))
+        lp_gemm_nn(c->st, c->lp, mout, n, n, n, c->Elp, n, c->Tlp, n, c->Mm, n);
     prof_end(c, SDP_K_SANDWICH, es, bytes);
 }
 
