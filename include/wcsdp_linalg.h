@@ -34,6 +34,16 @@ int32_t wc_dgemm(void* stream, char transa, char transb, int32_t m, int32_t n, i
                  const double* A, int32_t lda, const double* B, int32_t ldb, double beta, double* C, int32_t ldc);
 
 /*
+ * y = alpha A x + beta y for a symmetric d x d matrix A held in full
+ * (column-major, lda even, A 16-byte aligned): only one triangle is read,
+ * half the bytes of a general product -- the preconditioner applies C^{-1}
+ * (Section 6) this way.  x and y have d entries; when beta == 0, y is not
+ * read.  A temporary workspace; the stream is synchronised before returning.
+ */
+int32_t wc_dsymv(void* stream, int32_t d, double alpha, const double* A, int32_t lda, const double* x, double beta,
+                 double* y);
+
+/*
  * In-place Cholesky factorisation A = L L^T of the n x n symmetric positive
  * definite A (lower triangle read and overwritten with L; the strict upper
  * triangle is set to zero).  Returns 0, or -5 when a pivot is not positive;

@@ -164,6 +164,8 @@ _SIGNATURES = [
     ("wc_dtrtri", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
     ("wc_djacobi_svd", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                    C.c_double, C.c_int32, C.POINTER(C.c_int32)]),
+    ("wc_dsymv", C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_int32, C.c_void_p, C.c_double,
+                             C.c_void_p]),
     ("wc_gemm_lp", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
     ("wc_gemm_lp_sym", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,

@@ -310,6 +310,18 @@ int32_t wc_dgemm(void* stream, char transa, char transb, int32_t m, int32_t n, i
     });
 }
 
+int32_t wc_dsymv(void* stream, int32_t d, double alpha, const double* A, int32_t lda, const double* x, double beta,
+                 double* y) {
+    return guarded_la([&]() {
+        wc::require(d >= 0 && lda >= std::max(1, d), "bad size or leading dimension");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        wc::DevBuf<double> ws(static_cast<size_t>(std::max<long>(1, wc::symv_ws(d))));
+        wc::symv(st, d, A, lda, x, y, alpha, beta, ws.get());
+        WC_HIP(hipStreamSynchronize(st));
+        return (int32_t)0;
+    });
+}
+
 int32_t wc_gemm_lp(void* stream, int32_t prec_in, int32_t out_kind, int32_t m, int32_t n, int32_t k, const void* A,
                    int32_t lda, const void* B, int32_t ldb, void* C, int32_t ldc) {
     return guarded_la([&]() {

@@ -2,6 +2,8 @@
 // row-major matrices, deterministic reductions and element-wise helpers.
 #include <hip/hip_ext.h>
 
+#include <cstdint>
+
 #include "common.hpp"
 
 namespace wc {
@@ -172,32 +174,33 @@ constexpr int THIN_SPLITS = 32;  // most K-splits of the split-K form
 
 // 64 rows per workgroup; the four waves split K and their partial sums are
 // added in LDS in wave order.
+template <int NM>  // NM >= N: accumulators per row; B (K x N) in dynamic LDS
 __global__ __launch_bounds__(256) void dgemm_thin_n_kernel(int M, int N, int K, double alpha,
                                                            const double* __restrict__ A, long lda,
                                                            const double* __restrict__ B, long ldb, double beta,
                                                            double* __restrict__ C, long ldc) {
-    __shared__ double Bs[THIN_LDS];
-    __shared__ double part[4][THIN_N][64];
+    extern __shared__ double Bs[];
+    __shared__ double part[4][NM][64];
     for (int t = threadIdx.x; t < K * N; t += 256) Bs[t] = B[(t % K) + (long)(t / K) * ldb];
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = blockIdx.x * 64 + lane;
     const int kc = (K + 3) / 4;
     const int k0 = wv * kc, k1 = min(K, k0 + kc);
-    double acc[THIN_N];
+    double acc[NM];
 #pragma unroll
-    for (int j = 0; j < THIN_N; ++j) acc[j] = 0.0;
+    for (int j = 0; j < NM; ++j) acc[j] = 0.0;
     if (i < M) {
 #pragma unroll 8
         for (int k = k0; k < k1; ++k) {
             const double a = A[i + (long)k * lda];
 #pragma unroll
-            for (int j = 0; j < THIN_N; ++j)
+            for (int j = 0; j < NM; ++j)
                 if (j < N) acc[j] += a * Bs[k + j * K];
         }
     }
 #pragma unroll
-    for (int j = 0; j < THIN_N; ++j)
+    for (int j = 0; j < NM; ++j)
         if (j < N) part[wv][j][lane] = acc[j];
     __syncthreads();
     if (wv == 0 && i < M) {
@@ -209,30 +212,56 @@ __global__ __launch_bounds__(256) void dgemm_thin_n_kernel(int M, int N, int K, 
     }
 }
 
+// C = alpha A^T B + beta C, A K x M column-major, B K x N (N <= 16): a
+// workgroup owns four output rows; wave w sums the K-quarter w of all four
+// (so each load of B serves four rows), and the quarters are added in LDS.
+template <int NM>  // NM >= N: the accumulators kept per row
 __global__ __launch_bounds__(256) void dgemm_thin_t_kernel(int M, int N, int K, double alpha,
                                                            const double* __restrict__ A, long lda,
                                                            const double* __restrict__ B, long ldb, double beta,
                                                            double* __restrict__ C, long ldc) {
-    const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= M) return;  // whole waves leave together
-    const double* a = A + (long)i * lda;
-    double acc[THIN_N];
+    __shared__ double red[4][4][NM];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i0 = blockIdx.x * 4;
+    const int kq = (K + 3) / 4, k0 = wv * kq, k1 = min(K, k0 + kq);
+    const double* a[4];
 #pragma unroll
-    for (int j = 0; j < THIN_N; ++j) acc[j] = 0.0;
-    for (int k = lane; k < K; k += 64) {
-        const double av = a[k];
+    for (int t = 0; t < 4; ++t) a[t] = A + (long)min(i0 + t, M - 1) * lda;
+    double acc[4][NM];
 #pragma unroll
-        for (int j = 0; j < THIN_N; ++j)
-            if (j < N) acc[j] += av * B[k + (long)j * ldb];
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int j = 0; j < NM; ++j) acc[t][j] = 0.0;
+#pragma unroll 2
+    for (int k = k0 + lane; k < k1; k += 64) {
+        const double av0 = a[0][k], av1 = a[1][k], av2 = a[2][k], av3 = a[3][k];
+#pragma unroll
+        for (int j = 0; j < NM; ++j) {
+            if (j < N) {
+                const double bv = B[k + (long)j * ldb];
+                acc[0][j] += av0 * bv;
+                acc[1][j] += av1 * bv;
+                acc[2][j] += av2 * bv;
+                acc[3][j] += av3 * bv;
+            }
+        }
     }
 #pragma unroll
-    for (int j = 0; j < THIN_N; ++j) {
-        if (j >= N) break;
-        double v = acc[j];
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) {
+        for (int j = 0; j < NM; ++j) {
+            if (j < N) {
+                double v = acc[t][j];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                if (lane == 0) red[wv][t][j] = v;
+            }
+        }
+    __syncthreads();
+    if (threadIdx.x < 4 * N) {
+        const int t = threadIdx.x / N, j = threadIdx.x % N, i = i0 + t;
+        if (i < M) {
+            const double v = (red[0][t][j] + red[1][t][j]) + (red[2][t][j] + red[3][t][j]);
             double* c = C + i + (long)j * ldc;
             *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
         }
@@ -242,12 +271,13 @@ __global__ __launch_bounds__(256) void dgemm_thin_t_kernel(int M, int N, int K, 
 // Split-K form of the thin product for large K: workgroup (rows, split)
 // computes the partial product of its K-chunk (the chunk of B staged in LDS)
 // into part[split][j][i]; thin_reduce_kernel sums the splits in a fixed order.
+template <int NM>  // NM >= N; the K-chunk of B (kc x N) in dynamic LDS
 __global__ __launch_bounds__(256) void dgemm_thin_splitk_kernel(int M, int N, int K, int kc,
                                                                 const double* __restrict__ A, long lda,
                                                                 const double* __restrict__ B, long ldb,
                                                                 double* __restrict__ part) {
-    __shared__ double Bs[THIN_LDS];
-    __shared__ double red[4][THIN_N][64];
+    extern __shared__ double Bs[];
+    __shared__ double red[4][NM][64];
     const int ks0 = blockIdx.y * kc, ks1 = min(K, ks0 + kc);
     const int len = ks1 - ks0;
     for (int t = threadIdx.x; t < len * N; t += 256) Bs[t] = B[ks0 + (t % len) + (long)(t / len) * ldb];
@@ -256,20 +286,20 @@ __global__ __launch_bounds__(256) void dgemm_thin_splitk_kernel(int M, int N, in
     const int i = blockIdx.x * 64 + lane;
     const int q = (len + 3) / 4;
     const int k0 = wv * q, k1 = min(len, k0 + q);
-    double acc[THIN_N];
+    double acc[NM];
 #pragma unroll
-    for (int j = 0; j < THIN_N; ++j) acc[j] = 0.0;
+    for (int j = 0; j < NM; ++j) acc[j] = 0.0;
     if (i < M) {
 #pragma unroll 8
         for (int k = k0; k < k1; ++k) {
             const double a = A[i + (long)(ks0 + k) * lda];
 #pragma unroll
-            for (int j = 0; j < THIN_N; ++j)
+            for (int j = 0; j < NM; ++j)
                 if (j < N) acc[j] += a * Bs[k + j * len];
         }
     }
 #pragma unroll
-    for (int j = 0; j < THIN_N; ++j)
+    for (int j = 0; j < NM; ++j)
         if (j < N) red[wv][j][lane] = acc[j];
     __syncthreads();
     if (wv == 0 && i < M) {
@@ -299,24 +329,39 @@ bool dgemm_thin(hipStream_t st, bool ta, int m, int n, int k, double alpha, cons
         // one workgroup per 64 rows covers the chip only for m >= 64 * #CUs;
         // otherwise split K as well (when a workspace is given)
         int splits = std::max(1, cdiv((long)k * n, THIN_LDS));
-        if (ws != nullptr) splits = std::max(splits, std::min(cdiv(k, 256), cdiv(512, cdiv(m, 64))));
+        // about 2048 workgroups (8 waves per SIMD) keep enough loads in flight
+        if (ws != nullptr) splits = std::max(splits, std::min(cdiv(k, 128), cdiv(2048, cdiv(m, 64))));
         splits = std::min(splits, THIN_SPLITS);
         const int kc = cdiv(k, splits);
         splits = cdiv(k, kc);
         if (splits == 1) {
-            hipLaunchKernelGGL(dgemm_thin_n_kernel, dim3(cdiv(m, 64)), dim3(256), 0, st, m, n, k, alpha, A, lda, B,
-                               ldb, beta, C, ldc);
+            const size_t lds = sizeof(double) * (size_t)k * n;
+            if (n <= 4)
+                hipLaunchKernelGGL(dgemm_thin_n_kernel<4>, dim3(cdiv(m, 64)), dim3(256), lds, st, m, n, k, alpha, A,
+                                   lda, B, ldb, beta, C, ldc);
+            else
+                hipLaunchKernelGGL(dgemm_thin_n_kernel<THIN_N>, dim3(cdiv(m, 64)), dim3(256), lds, st, m, n, k, alpha,
+                                   A, lda, B, ldb, beta, C, ldc);
         } else {
             if (ws == nullptr || (long)splits * m * n > ws_len || (long)kc * n > THIN_LDS) return false;
-            hipLaunchKernelGGL(dgemm_thin_splitk_kernel, dim3(cdiv(m, 64), splits), dim3(256), 0, st, m, n, k, kc, A,
-                               lda, B, ldb, ws);
+            const size_t lds = sizeof(double) * (size_t)kc * n;
+            if (n <= 4)
+                hipLaunchKernelGGL(dgemm_thin_splitk_kernel<4>, dim3(cdiv(m, 64), splits), dim3(256), lds, st, m, n, k,
+                                   kc, A, lda, B, ldb, ws);
+            else
+                hipLaunchKernelGGL(dgemm_thin_splitk_kernel<THIN_N>, dim3(cdiv(m, 64), splits), dim3(256), lds, st, m,
+                                   n, k, kc, A, lda, B, ldb, ws);
             WC_LAUNCH_CHECK();
             hipLaunchKernelGGL(thin_reduce_kernel, dim3(cdiv((long)m * n, 256)), dim3(256), 0, st, m, n, splits, ws,
                                alpha, beta, C, ldc);
         }
     } else {
-        hipLaunchKernelGGL(dgemm_thin_t_kernel, dim3(cdiv(m, 4)), dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb,
-                           beta, C, ldc);
+        if (n <= 4)
+            hipLaunchKernelGGL(dgemm_thin_t_kernel<4>, dim3(cdiv(m, 4)), dim3(256), 0, st, m, n, k, alpha, A, lda, B,
+                               ldb, beta, C, ldc);
+        else
+            hipLaunchKernelGGL(dgemm_thin_t_kernel<THIN_N>, dim3(cdiv(m, 4)), dim3(256), 0, st, m, n, k, alpha, A, lda,
+                               B, ldb, beta, C, ldc);
     }
     WC_LAUNCH_CHECK();
     return true;
@@ -390,6 +435,133 @@ void gemv_rows(hipStream_t st, int m, int k, const double* A, long lda, const do
     if (m <= 0) return;
     int k2 = static_cast<int>(round_up(k, 2) / 2);
     hipLaunchKernelGGL(gemv_rows_kernel, dim3(cdiv(m, GV_ROWS)), dim3(256), 0, st, m, k2, A, lda, x, y, alpha, beta);
+    WC_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// symv: y = alpha A x + beta y for a symmetric d x d matrix A (full storage,
+// pitch lda), reading only the triangle c <= r of the row-major view -- half
+// the bytes of gemv_rows.  Pass 1: one workgroup per 64 x 64 tile (R, C),
+// C <= R, of that triangle writes the tile's row sums A_RC x_C and, for its
+// entries strictly below the diagonal, its column sums A_RC^T x_R; pass 2
+// adds, for each i, the row sums of the tiles in its block row and the column
+// sums of the tiles in its block column, in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int SY_T = 64;
+
+long symv_ws(int d) {
+    const long nb = cdiv(d, SY_T);
+    return 2 * (nb * (nb + 1) / 2) * SY_T;
+}
+
+__device__ inline void tri_tile(long t, int& R, int& C) {
+    // t = R (R + 1) / 2 + C, 0 <= C <= R
+    int r = static_cast<int>((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((long)(r + 1) * (r + 2) / 2 <= t) ++r;
+    while ((long)r * (r + 1) / 2 > t) --r;
+    R = r;
+    C = static_cast<int>(t - (long)r * (r + 1) / 2);
+}
+
+__global__ __launch_bounds__(256) void symv_tiles_kernel(int d, const double* __restrict__ A, long lda,
+                                                         const double* __restrict__ x, double* __restrict__ prow,
+                                                         double* __restrict__ pcol) {
+    __shared__ double colsum[4][SY_T];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int R, C;
+    tri_tile(blockIdx.x, R, C);
+    // thread: rows 4 rg .. 4 rg + 3 and columns 4 cg .. 4 cg + 3 of the tile
+    const int rg = tid >> 4, cg = tid & 15;
+    const int r0 = R * SY_T + 4 * rg, cc0 = C * SY_T + 4 * cg;
+    const bool diag = R == C;
+    double a[4][4], xc[4], xr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        xc[q] = cc0 + q < d ? x[cc0 + q] : 0.0;
+        xr[q] = r0 + q < d ? x[r0 + q] : 0.0;
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int gr = r0 + p;
+        const double* ar = A + (long)gr * lda + cc0;
+        if (gr < d && cc0 + 4 <= d && (!diag || 4 * cg + 3 <= 4 * rg + p)) {
+            const d2 v0 = *reinterpret_cast<const d2*>(ar), v1 = *reinterpret_cast<const d2*>(ar + 2);
+            a[p][0] = v0.x;
+            a[p][1] = v0.y;
+            a[p][2] = v1.x;
+            a[p][3] = v1.y;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                a[p][q] = (gr < d && cc0 + q < d && (!diag || 4 * cg + q <= 4 * rg + p)) ? ar[q] : 0.0;
+        }
+    }
+    // row sums (entries with c <= r): over the thread's columns, then over the 16 column groups
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        double v = ((a[p][0] * xc[0] + a[p][1] * xc[1]) + a[p][2] * xc[2]) + a[p][3] * xc[3];
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 8, 64);
+        if (cg == 0) prow[(long)blockIdx.x * SY_T + 4 * rg + p] = v;
+    }
+    // column sums (entries with c < r): over the thread's rows, the wave's four
+    // row groups, then the four waves
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double v = 0.0;
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+            if (!diag || 4 * cg + q < 4 * rg + p) v += a[p][q] * xr[p];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (lane < 16) colsum[wave][4 * cg + q] = v;
+    }
+    __syncthreads();
+    if (tid < SY_T)
+        pcol[(long)blockIdx.x * SY_T + tid] = (colsum[0][tid] + colsum[1][tid]) + (colsum[2][tid] + colsum[3][tid]);
+}
+
+// One workgroup per 64-row block I; wave w takes every fourth tile of the
+// block row and of the block column, and the four waves' sums are added in a
+// fixed order.
+__global__ __launch_bounds__(256) void symv_reduce_kernel(int d, const double* __restrict__ prow,
+                                                          const double* __restrict__ pcol, double* __restrict__ y,
+                                                          double alpha, double beta) {
+    __shared__ double part[4][SY_T];
+    const int I = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nb = (d + SY_T - 1) / SY_T;
+    double s0 = 0.0, s1 = 0.0;
+    for (int Cb = wave; Cb <= I; Cb += 8) {
+        s0 += prow[((long)I * (I + 1) / 2 + Cb) * SY_T + lane];
+        if (Cb + 4 <= I) s1 += prow[((long)I * (I + 1) / 2 + Cb + 4) * SY_T + lane];
+    }
+    for (int Rb = I + wave; Rb < nb; Rb += 8) {
+        s0 += pcol[((long)Rb * (Rb + 1) / 2 + I) * SY_T + lane];
+        if (Rb + 4 < nb) s1 += pcol[((long)(Rb + 4) * (Rb + 5) / 2 + I) * SY_T + lane];
+    }
+    part[wave][lane] = s0 + s1;
+    __syncthreads();
+    const int i = I * SY_T + threadIdx.x;
+    if (threadIdx.x < SY_T && i < d) {
+        const double v = (part[0][threadIdx.x] + part[1][threadIdx.x]) + (part[2][threadIdx.x] + part[3][threadIdx.x]);
+        y[i] = (beta == 0.0) ? alpha * v : alpha * v + beta * y[i];
+    }
+}
+
+void symv(hipStream_t st, int d, const double* A, long lda, const double* x, double* y, double alpha, double beta,
+          double* ws) {
+    if (d <= 0) return;
+    require(lda % 2 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0, "symv: rows must be 16-byte aligned");
+    const long nb = cdiv(d, SY_T), tiles = nb * (nb + 1) / 2;
+    double* prow = ws;
+    double* pcol = ws + tiles * SY_T;
+    hipLaunchKernelGGL(symv_tiles_kernel, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, st, d, A, lda, x, prow,
+                       pcol);
+    WC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(symv_reduce_kernel, dim3(static_cast<unsigned>(nb)), dim3(256), 0, st, d, prow, pcol, y, alpha,
+                       beta);
     WC_LAUNCH_CHECK();
 }
 

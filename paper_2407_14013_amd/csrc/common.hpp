@@ -97,6 +97,12 @@ long thin_splitk_ws(int m, int n);
 void gemv_rows(hipStream_t st, int m, int k, const double* A, long lda, const double* x, double* y, double alpha,
                double beta);
 
+// y = alpha A x + beta y for a symmetric d x d A stored in full (pitch lda
+// even, rows 16-byte aligned), reading half of it; ws holds symv_ws(d) doubles.
+long symv_ws(int d);
+void symv(hipStream_t st, int d, const double* A, long lda, const double* x, double* y, double alpha, double beta,
+          double* ws);
+
 // y = alpha A^T x + beta y for the same row-major A.  `part` must hold
 // gemv_cols_parts(m) * round_up(k, 2) doubles.
 int gemv_cols_parts(int m);

@@ -359,25 +359,44 @@ void aq_entry_apply(hipStream_t st, int m, int n, int r, const int* jk, const do
 }
 
 // YQ (n x r, ld n) = A^T(u) Q: row j sums u_i Q[p, :] over its pattern
-// entries, weighted 1/2 off the diagonal and 1 on it.  One thread per (j, b).
-__global__ void entry_yq_kernel(int n, int r, const int* __restrict__ rptr, const int* __restrict__ rcol,
-                                const int* __restrict__ ridx, const double* __restrict__ u,
-                                const double* __restrict__ Q, long ldq, double* __restrict__ YQ) {
-    long t = blockIdx.x * 256L + threadIdx.x;
-    if (t >= (long)n * r) return;
-    const int j = static_cast<int>(t % n), b = static_cast<int>(t / n);
-    double s = 0.0;
-    for (int e = rptr[j]; e < rptr[j + 1]; ++e) {
+// entries, weighted 1/2 off the diagonal and 1 on it.  One wave per row: the
+// lanes share the row's entries (coalesced index reads) and the r sums are
+// reduced across the wave at the end.
+constexpr int YQ_R = 16;  // most columns of Q handled (r <= the largest rank)
+__global__ __launch_bounds__(256) void entry_yq_kernel(int n, int r, const int* __restrict__ rptr,
+                                                       const int* __restrict__ rcol, const int* __restrict__ ridx,
+                                                       const double* __restrict__ u, const double* __restrict__ Q,
+                                                       long ldq, double* __restrict__ YQ) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= n) return;  // whole waves leave together
+    double acc[YQ_R];
+#pragma unroll
+    for (int b = 0; b < YQ_R; ++b) acc[b] = 0.0;
+    for (int e = rptr[j] + lane; e < rptr[j + 1]; e += 64) {
         const int p = rcol[e];
-        const double w = (p == j) ? 1.0 : 0.5;
-        s += w * u[ridx[e]] * Q[p + (long)b * ldq];
+        const double w = (p == j ? 1.0 : 0.5) * u[ridx[e]];
+#pragma unroll
+        for (int b = 0; b < YQ_R; ++b)
+            if (b < r) acc[b] += w * Q[p + (long)b * ldq];
     }
-    YQ[j + (long)b * n] = s;
+#pragma unroll
+    for (int b = 0; b < YQ_R; ++b) {
+        if (b >= r) break;
+        double v = acc[b];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) YQ[j + (long)b * n] = v;
+    }
 }
 void entry_yq(hipStream_t st, int n, int r, const int* rptr, const int* rcol, const int* ridx, const double* u,
               const double* Q, long ldq, double* YQ) {
-    hipLaunchKernelGGL(entry_yq_kernel, g1((long)n * r), dim3(256), 0, st, n, r, rptr, rcol, ridx, u, Q, ldq, YQ);
-    WC_LAUNCH_CHECK();
+    for (int b0 = 0; b0 < r; b0 += YQ_R) {  // YQ_R columns of Q per launch
+        const int rr = std::min(YQ_R, r - b0);
+        hipLaunchKernelGGL(entry_yq_kernel, dim3(cdiv(n, 4)), dim3(256), 0, st, n, rr, rptr, rcol, ridx, u,
+                           Q + (long)b0 * ldq, ldq, YQ + (long)b0 * n);
+        WC_LAUNCH_CHECK();
+    }
 }
 
 // B_{b b'} (n x n, ld ldb, zeroed beforehand) = sum_i of the U-coordinate Gram

@@ -171,6 +171,7 @@ static void alloc_work(sdp_ctx* c) {
 
     c->part.alloc(1024);
     c->thin_ws.alloc(thin_splitk_ws(n, c->rmax));
+    c->sy_ws.alloc(symv_ws(static_cast<int>(c->dmaxp)));
     for (auto* b : {&c->vx, &c->vr, &c->vz, &c->vp, &c->vKp, &c->vg, &c->vtmp, &c->vres, &c->vdx}) {
         b->alloc(Nmax);
         fill(c->st, Nmax, b->get(), 0.0);
@@ -633,7 +634,7 @@ static void precond_block(sdp_ctx* c, const double* f, const double* h, double* 
     const double ib = 1.0 / c->beta;
     aqt_mul(c, f, c->td, -ib, 0.0);                                      // td = -AQ^T f / beta
     axpby(st, d, 1.0, h, 1.0, c->td);                                    // td += h
-    gemv_rows(st, d, d, c->Cinv, c->dmaxp, c->td, zv, -1.0, 0.0);        // zv = -C^{-1} td
+    symv(st, d, c->Cinv, c->dmaxp, c->td, zv, -1.0, 0.0, c->sy_ws);      // zv = -C^{-1} td
     aq_mul(c, zv, c->tm, 1.0, 0.0);                                      // tm = AQ zv
     axpbypcz(st, m, ib, f, -ib, c->tm, 0.0, z1);                          // z1 = (f - tm) / beta
 }

@@ -36,6 +36,20 @@ def _chk(st):
         raise SdpError(st, L.lib().sdp_last_error(None).decode())
 
 
+def dsymv(alpha, A: torch.Tensor, x: torch.Tensor, beta=0.0, y: torch.Tensor | None = None):
+    """y = alpha A x + beta y for a symmetric column-major A (d x d, as from to_dev), reading one triangle."""
+    d = A.shape[0]
+    lda = d + (d & 1)  # the kernel wants an even pitch
+    Ap = A
+    if lda != d:
+        Ap = torch.zeros((d, lda), dtype=torch.float64, device=A.device)
+        Ap[:, :d] = A
+    if y is None:
+        y = torch.zeros(d, dtype=torch.float64, device=A.device)
+    _chk(L.lib().wc_dsymv(_stream_ptr(), d, alpha, _p(Ap), lda, _p(x), beta, _p(y)))
+    return y
+
+
 def dgemm(transa: str, transb: str, alpha, A: torch.Tensor, B: torch.Tensor, beta=0.0, Cm: torch.Tensor | None = None):
     """C = alpha op(A) op(B) + beta C on column-major device buffers (shapes as in to_dev)."""
     ka, ma = A.shape  # A is ma x ka column-major

@@ -32,6 +32,20 @@ def test_dgemm(ta, tb, m, n, k):
     assert err <= bound
 
 
+@pytest.mark.parametrize("d", [1, 5, 64, 65, 130, 597, 2049])
+def test_dsymv(d):
+    # one triangle read (64 x 64 tiles, partial sums per tile), against the full product
+    rng = np.random.default_rng(d + 3)
+    M = rng.standard_normal((d, d))
+    A = M + M.T
+    x = rng.standard_normal(d)
+    y0 = rng.standard_normal(d)
+    y = la.dsymv(1.5, la.to_dev(A), torch.from_numpy(x).cuda(), -0.5, torch.from_numpy(y0).cuda())
+    ref = 1.5 * A @ x - 0.5 * y0
+    bound = 4 * d * EPS * (1.5 * np.abs(A).max() * np.abs(x).max() + 0.5 * np.abs(y0).max())
+    assert np.abs(y.cpu().numpy() - ref).max() <= bound
+
+
 @pytest.mark.parametrize("n", [1, 5, 31, 32, 33, 64, 100, 200, 597])
 def test_dpotrf(n):
     rng = np.random.default_rng(n)
