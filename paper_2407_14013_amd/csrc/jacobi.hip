@@ -44,7 +44,8 @@ __device__ inline void tournament_pair(int round, int w, int N, int& a, int& b) 
 __device__ inline bool jacobi_angle(double app, double aqq, double apq, double& c, double& s) {
     c = 1.0;
     s = 0.0;
-    if (!(fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app * aqq))) || apq == 0.0) return false;
+    // negligible when |apq| <= eps sqrt(|app aqq|), tested on the squares
+    if (!(apq * apq > 4.930380657631324e-32 * fabs(app * aqq)) || apq == 0.0) return false;
     const double x = aqq - app, y = 2.0 * apq;
     const double h = sqrt(fma(x, x, y * y));
     const double t = (x >= 0.0 ? y : -y) / (fabs(x) + h);
@@ -57,11 +58,12 @@ __device__ inline bool jacobi_angle(double app, double aqq, double apq, double& 
 // rotations into R (LDS, identity on entry).  A rotation step applies the 16
 // disjoint rotations of one tournament round, H' = J^T H J and R' = R J.
 // Thread t owns the 2 x 2 block of H at the pairs (t mod 16, t / 16): it
-// computes the two rotations it needs itself (every thread that needs a
-// pair's rotation computes it from the same entries, so all agree bit for
-// bit), reads its block from H and writes the rotated block to Hs, and
-// rotates rows t mod 16 and t mod 16 + 16 of R's column pair t / 16 in place
-// -- one barrier per step.  Runs at most `sweeps` sweeps (31 steps each),
+// computes the rotation of pair t mod 16 itself (the four threads of a wave
+// that share it compute it from the same entries, so all agree bit for bit)
+// and takes that of pair t / 16 by a shuffle from lane t / 16 of its wave,
+// reads its block from H and writes the rotated block to Hs, and rotates rows
+// t mod 16 and t mod 16 + 16 of R's column pair t / 16 in place -- one barrier
+// per step.  Runs at most `sweeps` sweeps (31 steps each),
 // fewer when a sweep applies no rotation.  256 threads; H is overwritten.
 __device__ void inner_jacobi(double (*H)[JW + 1], double (*Hs)[JW + 1], double (*R)[JW + 1], int sweeps,
                              int* rot_any) {
@@ -77,10 +79,11 @@ __device__ void inner_jacobi(double (*H)[JW + 1], double (*Hs)[JW + 1], double (
             int pa, qa, pb, qb;
             tournament_pair(rr, a, JW, pa, qa);
             tournament_pair(rr, b, JW, pb, qb);
-            double ca, sa, cb, sb;
+            double ca, sa;
             const bool rot = jacobi_angle(Hc[pa][pa], Hc[qa][qa], Hc[pa][qa], ca, sa);
-            jacobi_angle(Hc[pb][pb], Hc[qb][qb], Hc[pb][qb], cb, sb);
-            if (rot && b == 0) *rot_any = 1;
+            // lane b (b < 16) of every wave computed the rotation of pair b
+            const double cb = __shfl(ca, b, 64), sb = __shfl(sa, b, 64);
+            if (rot) *rot_any = 1;
             // block (a, b): T = H J_b on the columns, then J_a^T T on the rows
             const double h11 = Hc[pa][pb], h12 = Hc[pa][qb], h21 = Hc[qa][pb], h22 = Hc[qa][qb];
             const double t11 = cb * h11 - sb * h12, t12 = sb * h11 + cb * h12;
@@ -193,14 +196,14 @@ __global__ __launch_bounds__(256) void jacobi_pair_kernel(int nchunks, const dou
         const int i = t % JW, j = t / JW;
         if (i < j) {
             const double hii = H[i][i], hjj = H[j][j];
-            if (hii > 0.0 && hjj > 0.0) mx = fmax(mx, fabs(H[i][j]) / sqrt(hii * hjj));
+            if (hii > 0.0 && hjj > 0.0) mx = fmax(mx, H[i][j] * H[i][j] / (hii * hjj));  // squared
         }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
     if (lane == 0) red[wave] = mx;
     __syncthreads();
-    const double off_pair = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const double off_pair = sqrt(fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
     if (tid == 0) {
         atomicMax(offmax, static_cast<unsigned long long>(__double_as_longlong(off_pair)));
         skip[w] = off_pair <= tol ? 1 : 0;
@@ -341,14 +344,14 @@ __global__ __launch_bounds__(256) void jacobi_round_lds_kernel(int n, int nblk, 
         const int i = t % JW, j = t / JW;
         if (i < j) {
             const double hii = H0[i][i], hjj = H0[j][j];
-            if (hii > 0.0 && hjj > 0.0) mx = fmax(mx, fabs(H0[i][j]) / sqrt(hii * hjj));
+            if (hii > 0.0 && hjj > 0.0) mx = fmax(mx, H0[i][j] * H0[i][j] / (hii * hjj));  // squared
         }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
     if (lane == 0) red[wave] = mx;
     __syncthreads();
-    const double off_pair = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const double off_pair = sqrt(fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
     if (tid == 0) atomicMax(offmax, static_cast<unsigned long long>(__double_as_longlong(off_pair)));
     if (off_pair <= tol) return;  // uniform across the workgroup; A and V unchanged
 
