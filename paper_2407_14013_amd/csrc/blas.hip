@@ -10,7 +10,6 @@ namespace wc {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
-typedef float f4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // GEMM: 64 x 64 output tile per 256-thread workgroup, K step 16.  The four
@@ -464,8 +463,7 @@ __device__ inline void tri_tile(long t, int& R, int& C) {
     C = static_cast<int>(t - (long)r * (r + 1) / 2);
 }
 
-template <typename T>  // storage of A: double, or float (accumulated in double)
-__global__ __launch_bounds__(256) void symv_tiles_kernel(int d, const T* __restrict__ A, long lda,
+__global__ __launch_bounds__(256) void symv_tiles_kernel(int d, const double* __restrict__ A, long lda,
                                                          const double* __restrict__ x, double* __restrict__ prow,
                                                          double* __restrict__ pcol) {
     __shared__ double colsum[4][SY_T];
@@ -485,21 +483,13 @@ __global__ __launch_bounds__(256) void symv_tiles_kernel(int d, const T* __restr
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const int gr = r0 + p;
-        const T* ar = A + (long)gr * lda + cc0;
+        const double* ar = A + (long)gr * lda + cc0;
         if (gr < d && cc0 + 4 <= d && (!diag || 4 * cg + 3 <= 4 * rg + p)) {
-            if constexpr (sizeof(T) == 8) {
-                const d2 v0 = *reinterpret_cast<const d2*>(ar), v1 = *reinterpret_cast<const d2*>(ar + 2);
-                a[p][0] = v0.x;
-                a[p][1] = v0.y;
-                a[p][2] = v1.x;
-                a[p][3] = v1.y;
-            } else {
-                const f4 v = *reinterpret_cast<const f4*>(ar);
-                a[p][0] = v.x;
-                a[p][1] = v.y;
-                a[p][2] = v.z;
-                a[p][3] = v.w;
-            }
+            const d2 v0 = *reinterpret_cast<const d2*>(ar), v1 = *reinterpret_cast<const d2*>(ar + 2);
+            a[p][0] = v0.x;
+            a[p][1] = v0.y;
+            a[p][2] = v1.x;
+            a[p][3] = v1.y;
         } else {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
@@ -560,31 +550,19 @@ __global__ __launch_bounds__(256) void symv_reduce_kernel(int d, const double* _
     }
 }
 
-template <typename T>
-static void symv_t(hipStream_t st, int d, const T* A, long lda, const double* x, double* y, double alpha, double beta,
-                   double* ws) {
+void symv(hipStream_t st, int d, const double* A, long lda, const double* x, double* y, double alpha, double beta,
+          double* ws) {
     if (d <= 0) return;
-    require(lda % (16 / sizeof(T)) == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0,
-            "symv: rows must be 16-byte aligned");
+    require(lda % 2 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0, "symv: rows must be 16-byte aligned");
     const long nb = cdiv(d, SY_T), tiles = nb * (nb + 1) / 2;
     double* prow = ws;
     double* pcol = ws + tiles * SY_T;
-    hipLaunchKernelGGL(symv_tiles_kernel<T>, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, st, d, A, lda, x, prow,
+    hipLaunchKernelGGL(symv_tiles_kernel, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, st, d, A, lda, x, prow,
                        pcol);
     WC_LAUNCH_CHECK();
     hipLaunchKernelGGL(symv_reduce_kernel, dim3(static_cast<unsigned>(nb)), dim3(256), 0, st, d, prow, pcol, y, alpha,
                        beta);
     WC_LAUNCH_CHECK();
-}
-
-void symv(hipStream_t st, int d, const double* A, long lda, const double* x, double* y, double alpha, double beta,
-          double* ws) {
-    symv_t(st, d, A, lda, x, y, alpha, beta, ws);
-}
-
-void symv_f32(hipStream_t st, int d, const float* A, long lda, const double* x, double* y, double alpha, double beta,
-              double* ws) {
-    symv_t(st, d, A, lda, x, y, alpha, beta, ws);
 }
 
 // ---------------------------------------------------------------------------

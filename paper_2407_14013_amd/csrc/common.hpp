@@ -102,9 +102,6 @@ void gemv_rows(hipStream_t st, int m, int k, const double* A, long lda, const do
 long symv_ws(int d);
 void symv(hipStream_t st, int d, const double* A, long lda, const double* x, double* y, double alpha, double beta,
           double* ws);
-// The same with A stored in FP32 (lda a multiple of 4), accumulated in FP64.
-void symv_f32(hipStream_t st, int d, const float* A, long lda, const double* x, double* y, double alpha, double beta,
-              double* ws);
 
 // y = alpha A^T x + beta y for the same row-major A.  `part` must hold
 // gemv_cols_parts(m) * round_up(k, 2) doubles.
