@@ -39,9 +39,16 @@ __device__ inline double lz_block_sum(double v, double* red) {
 // The product w = T q splits each row into `nch` column chunks so that all
 // threads take part: thread t < n * nch forms the partial sum of row t % n
 // over chunk t / n, and the partials are added in chunk order.
-__global__ __launch_bounds__(LZ_THREADS) void lanczos_kernel(int n, const double* __restrict__ T, long ldt, int kmax,
+// Workgroup b of the launch works on T_b (T0 or T1) with its own basis
+// buffer, coefficients and step count.
+__global__ __launch_bounds__(LZ_THREADS) void lanczos_kernel(int n, const double* __restrict__ T0,
+                                                             const double* __restrict__ T1, long ldt, int kmax,
                                                              double* __restrict__ Qg, int qlds,
                                                              double* __restrict__ ab, int* __restrict__ kout) {
+    const double* __restrict__ T = blockIdx.x == 0 ? T0 : T1;
+    Qg += (long)blockIdx.x * n * (LZ_MAX_K + 1);
+    ab += blockIdx.x * 2 * LZ_MAX_K;
+    kout += blockIdx.x;
     extern __shared__ double sm[];
     double* q = sm;                 // current Lanczos vector
     double* w = sm + n;             // work vector
@@ -189,10 +196,10 @@ __global__ __launch_bounds__(LZ_THREADS) void lanczos_kernel(int n, const double
 
 void LanczosWork::ensure(int n) {
     if (n <= cap) return;
-    Q.alloc((size_t)n * (LZ_MAX_K + 1));
-    ab.alloc(2 * LZ_MAX_K);
-    kout.alloc(1);
-    if (!pinned) WC_HIP(hipHostMalloc(reinterpret_cast<void**>(&pinned), (2 * LZ_MAX_K + 2) * sizeof(double),
+    Q.alloc(2 * (size_t)n * (LZ_MAX_K + 1));  // two runs side by side
+    ab.alloc(4 * LZ_MAX_K);
+    kout.alloc(2);
+    if (!pinned) WC_HIP(hipHostMalloc(reinterpret_cast<void**>(&pinned), (4 * LZ_MAX_K + 2) * sizeof(double),
                                       hipHostMallocDefault));
     cap = n;
 }
@@ -229,7 +236,10 @@ double tridiag_min_eig(const double* a, const double* b, int k) {
     return 0.5 * (lo + hi);
 }
 
-double lanczos_min_eig(hipStream_t st, int n, const double* T, long ldt, int kmax, LanczosWork& w) {
+// Smallest Ritz values of T0 and (when T1 is not null) T1, one workgroup each
+// in one launch.
+void lanczos_min_eig2(hipStream_t st, int n, const double* T0, const double* T1, long ldt, int kmax, LanczosWork& w,
+                      double* out) {
     require(n >= 1 && n <= LZ_MAX_N, "lanczos: n out of range");
     w.ensure(n);
     kmax = std::max(1, std::min({kmax, n, LZ_MAX_K}));
@@ -248,14 +258,24 @@ double lanczos_min_eig(hipStream_t st, int n, const double* T, long ldt, int kma
     const int qlds = shm + qbytes + static_lds <= lds_max ? 1 : 0;
     if (qlds) shm += qbytes;
     require(shm + static_lds <= lds_max, "lanczos: n too large for the workgroup's LDS");
-    hipLaunchKernelGGL(lanczos_kernel, dim3(1), dim3(LZ_THREADS), shm, st, n, T, ldt, kmax, w.Q.get(), qlds,
-                       w.ab.get(), w.kout.get());
+    const int runs = T1 ? 2 : 1;
+    hipLaunchKernelGGL(lanczos_kernel, dim3(runs), dim3(LZ_THREADS), shm, st, n, T0, T1 ? T1 : T0, ldt, kmax,
+                       w.Q.get(), qlds, w.ab.get(), w.kout.get());
     WC_LAUNCH_CHECK();
-    WC_HIP(hipMemcpyAsync(w.pinned, w.ab.get(), 2 * kmax * sizeof(double), hipMemcpyDeviceToHost, st));
-    int k = 0;
-    WC_HIP(hipMemcpyAsync(&k, w.kout.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+    WC_HIP(hipMemcpyAsync(w.pinned, w.ab.get(), 2 * LZ_MAX_K * runs * sizeof(double), hipMemcpyDeviceToHost, st));
+    int k[2] = {0, 0};
+    WC_HIP(hipMemcpyAsync(k, w.kout.get(), runs * sizeof(int), hipMemcpyDeviceToHost, st));
     WC_HIP(hipStreamSynchronize(st));
-    return tridiag_min_eig(w.pinned, w.pinned + kmax, k);
+    for (int b = 0; b < runs; ++b) {
+        const double* abb = w.pinned + 2 * LZ_MAX_K * b;
+        out[b] = tridiag_min_eig(abb, abb + kmax, k[b]);
+    }
+}
+
+double lanczos_min_eig(hipStream_t st, int n, const double* T, long ldt, int kmax, LanczosWork& w) {
+    double out[2];
+    lanczos_min_eig2(st, n, T, nullptr, ldt, kmax, w, out);
+    return out[0];
 }
 
 }  // namespace wc

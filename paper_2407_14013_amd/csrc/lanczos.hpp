@@ -25,5 +25,9 @@ double tridiag_min_eig(const double* a, const double* b, int k);
 // Smallest Ritz value of the symmetric T after min(kmax, n, LZ_MAX_K) Lanczos
 // steps (an upper bound on lambda_min(T), equal to it once converged).
 double lanczos_min_eig(hipStream_t st, int n, const double* T, long ldt, int kmax, LanczosWork& w);
+// The same for two matrices at once (one workgroup each; T1 may be null):
+// out[0] for T0, out[1] for T1.
+void lanczos_min_eig2(hipStream_t st, int n, const double* T0, const double* T1, long ldt, int kmax, LanczosWork& w,
+                      double* out);
 
 }  // namespace wc

@@ -116,7 +116,7 @@ static void alloc_work(sdp_ctx* c) {
     c->dmaxp = round_up(dmax + 1, 32);
     const long Nmax = m + c->dmaxp + 32;
     for (auto* b : {&c->L, &c->Rs, &c->Linv, &c->Rinv, &c->Mt, &c->Vs, &c->G, &c->Ginv, &c->Gt, &c->Gw, &c->E, &c->Y,
-                    &c->T1, &c->T2, &c->Mm, &c->dXa, &c->dSa, &c->dX, &c->dS, &c->Ct, &c->Rd, &c->Hc, &c->Dx, &c->Ds})
+                    &c->T1, &c->T2, &c->T3, &c->Mm, &c->dXa, &c->dSa, &c->dX, &c->dS, &c->Ct, &c->Rd, &c->Hc, &c->Dx, &c->Ds})
         b->alloc(nn);
     c->dnt.alloc(n);
     c->lam.alloc(2 * (size_t)n);
@@ -940,6 +940,28 @@ static double max_step(sdp_ctx* c, const double* Linv, const double* D) {
     return lmin >= 0.0 ? std::numeric_limits<double>::infinity() : -1.0 / lmin;
 }
 
+// max_step for the primal (L^{-1}, DX) and dual (R^{-1}, DS) directions
+// together: both Lanczos runs share one launch.
+static void max_step2(sdp_ctx* c, const double* DX, const double* DS, double* ap, double* ad) {
+    const int n = c->n;
+    if (n > LZ_MAX_N) {
+        *ap = max_step(c, c->Linv, DX);
+        *ad = max_step(c, c->Rinv, DS);
+        return;
+    }
+    hipStream_t st = c->st;
+    gemm(c, false, false, n, n, n, 1.0, c->Linv, n, DX, n, 0.0, c->T1, n);
+    gemm(c, false, true, n, n, n, 1.0, c->T1, n, c->Linv, n, 0.0, c->T2, n);
+    symmetrize(st, n, c->T2, n);
+    gemm(c, false, false, n, n, n, 1.0, c->Rinv, n, DS, n, 0.0, c->T1, n);
+    gemm(c, false, true, n, n, n, 1.0, c->T1, n, c->Rinv, n, 0.0, c->T3, n);
+    symmetrize(st, n, c->T3, n);
+    double lmin[2];
+    lanczos_min_eig2(st, n, c->T2, c->T3, n, LZ_MAX_K, c->lw, lmin);
+    *ap = lmin[0] >= 0.0 ? std::numeric_limits<double>::infinity() : -1.0 / lmin[0];
+    *ad = lmin[1] >= 0.0 ? std::numeric_limits<double>::infinity() : -1.0 / lmin[1];
+}
+
 // Shrink alpha until M + alpha D passes a Cholesky test (the Lanczos step
 // length is an upper estimate until converged).
 static double guard_step(sdp_ctx* c, const double* M, const double* D, double alpha) {
@@ -1020,8 +1042,10 @@ int ipm_step(sdp_ctx* c, sdp_step_stats* stats) {
     s.pcg_pred = is.iterations;
     at_apply(c, c->dya, c->Y);
     axpbypcz(st, nn, 1.0, c->Rd, -1.0, c->Y, 0.0, c->dSa);
-    double ap = std::min(1.0, max_step(c, c->Linv, c->dXa));
-    double ad = std::min(1.0, max_step(c, c->Rinv, c->dSa));
+    double ap, ad;
+    max_step2(c, c->dXa, c->dSa, &ap, &ad);
+    ap = std::min(1.0, ap);
+    ad = std::min(1.0, ad);
     double* sc = c->sc;
     dot(st, nn, c->X, c->dSa, sc + 16, c->part);
     dot(st, nn, c->dXa, c->S, sc + 17, c->part);
@@ -1048,8 +1072,9 @@ int ipm_step(sdp_ctx* c, sdp_step_stats* stats) {
     at_apply(c, c->dy, c->Y);
     axpbypcz(st, nn, 1.0, c->Rd, -1.0, c->Y, 0.0, c->dS);
     const double frac = c->opt.step_frac;
-    ap = guard_step(c, c->X, c->dX, std::min(1.0, frac * max_step(c, c->Linv, c->dX)));
-    ad = guard_step(c, c->S, c->dS, std::min(1.0, frac * max_step(c, c->Rinv, c->dS)));
+    max_step2(c, c->dX, c->dS, &ap, &ad);
+    ap = guard_step(c, c->X, c->dX, std::min(1.0, frac * ap));
+    ad = guard_step(c, c->S, c->dS, std::min(1.0, frac * ad));
     axpby(st, nn, ap, c->dX, 1.0, c->X);
     axpby(st, m, ad, c->dy, 1.0, c->y);
     axpby(st, nn, ad, c->dS, 1.0, c->S);
@@ -1127,7 +1152,9 @@ int adjoint(sdp_ctx* c, const double* GX, double* gb, double* gC, sdp_adjoint_st
         if (rc != 0) break;  // keep the closest point so far
         at_apply(c, c->dy, c->Y);
         axpbypcz(st, nn, 1.0, c->Rd, -1.0, c->Y, 0.0, c->dS);
-        double a = std::min({1.0, 0.95 * max_step(c, c->Linv, c->dX), 0.95 * max_step(c, c->Rinv, c->dS)});
+        double sp, sd;
+        max_step2(c, c->dX, c->dS, &sp, &sd);
+        double a = std::min({1.0, 0.95 * sp, 0.95 * sd});
         a = guard_step(c, c->X, c->dX, a);
         a = guard_step(c, c->S, c->dS, a);
         axpby(st, nn, a, c->dX, 1.0, c->X);

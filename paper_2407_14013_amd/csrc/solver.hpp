@@ -45,7 +45,7 @@ struct sdp_ctx {
     wc::LanczosWork lw;
 
     // ---- temporaries -------------------------------------------------------------
-    wc::DevBuf<double> Y, T1, T2, Mm, Hm, U, YQ, F, mw, yp, part, gpart, tm, td, td2, td3, td4, rho, dz;
+    wc::DevBuf<double> Y, T1, T2, T3, Mm, Hm, U, YQ, F, mw, yp, part, gpart, tm, td, td2, td3, td4, rho, dz;
     wc::DevBuf<double> vx, vr, vz, vp, vKp, vg, vtmp;   // Krylov vectors (m + dmax, padded)
     wc::DevBuf<double> vres, vdx;                       // refinement residual and correction
 
