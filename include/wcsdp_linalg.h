@@ -26,9 +26,11 @@ extern "C" {
 /*
  * C = alpha op(A) op(B) + beta C with op(X) = X (trans 'N') or X^T ('T');
  * op(A) is m x k, op(B) is k x n, C is m x n.  FP64 MFMA (16x16x4) tiles;
- * with op(B) = B and n <= 16 a row-parallel thin kernel instead, split over
- * K as well for long K (a temporary workspace, and the stream is synchronised
- * before returning).  When beta == 0, C is not read.
+ * with op(B) = B and n <= 16 a row-parallel thin kernel instead.  Products
+ * with few output tiles and a long K (and thin ones with a long K) are split
+ * over K into partial products summed in a fixed order (a temporary
+ * workspace; the stream is then synchronised before returning).  When
+ * beta == 0, C is not read.
  */
 int32_t wc_dgemm(void* stream, char transa, char transb, int32_t m, int32_t n, int32_t k, double alpha,
                  const double* A, int32_t lda, const double* B, int32_t ldb, double beta, double* C, int32_t ldc);

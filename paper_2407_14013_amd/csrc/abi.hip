@@ -303,8 +303,14 @@ int32_t wc_dgemm(void* stream, char transa, char transb, int32_t m, int32_t n, i
         wc::DevBuf<double> ws;
         if (!tb && !ta && n >= 1 && n <= 16 && m >= 1 && k >= 256) ws.alloc(wc::thin_splitk_ws(m, n));
         if (tb || !wc::dgemm_thin(st, ta, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws.get(),
-                                  static_cast<long>(ws.n)))
-            wc::dgemm(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+                                  static_cast<long>(ws.n))) {
+            // small products with a long K are split over K, as inside the solver
+            wc::DevBuf<double> gws;
+            if ((long)wc::cdiv(m, 64) * wc::cdiv(n, 64) < 64 && k >= 64) gws.alloc(wc::dgemm_splitk_ws());
+            wc::dgemm(st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, false, 1, 0, 0, 0, gws.get(),
+                      static_cast<long>(gws.n));
+            if (gws.get()) WC_HIP(hipStreamSynchronize(st));
+        }
         if (ws.get()) WC_HIP(hipStreamSynchronize(st));
         return (int32_t)0;
     });

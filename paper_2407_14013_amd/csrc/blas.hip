@@ -19,12 +19,16 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 // lane l is D[l / 16 + 4 v][l % 16].
 // ---------------------------------------------------------------------------
 constexpr int GBM = 64, GBN = 64, GBK = 16;
+constexpr int GEMM_SPLITS = 8;        // most K-splits of a small product
+constexpr int GEMM_SPLIT_TILES = 64;  // split K only below this many output tiles
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void dgemm_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
                                                     long lda, const double* __restrict__ B, long ldb, double beta,
                                                     double* __restrict__ C, long ldc, int lower_only, long sA,
-                                                    long sB, long sC) {
+                                                    long sB, long sC, int klast) {
+    // split-K launches give the last z-slice the remainder of K
+    if (klast > 0 && blockIdx.z == gridDim.z - 1) K = klast;
     const int tile_m = blockIdx.x * GBM;
     const int tile_n = blockIdx.y * GBN;
     if (lower_only && tile_n > tile_m + GBM - 1) return;
@@ -122,9 +126,31 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int M, int N, int K, double 
             }
 }
 
+// C = alpha sum_s P_s + beta C over the split-K partial products P_s (m x n, ld m).
+__global__ void dgemm_reduce_kernel(int M, int N, int splits, const double* __restrict__ P, double alpha, double beta,
+                                    double* __restrict__ C, long ldc) {
+    const long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)M * N) return;
+    const int i = static_cast<int>(t % M), j = static_cast<int>(t / M);
+    double v = 0.0;
+    for (int sp = 0; sp < splits; ++sp) v += P[(long)sp * M * N + t];
+    double* c = C + i + (long)j * ldc;
+    *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
+}
+
+long dgemm_splitk_ws() { return (long)GEMM_SPLITS * GEMM_SPLIT_TILES * GBM * GBN; }
+
+template <bool TA, bool TB>
+static void dgemm_launch(hipStream_t st, dim3 grid, int m, int n, int k, double alpha, const double* A, long lda,
+                         const double* B, long ldb, double beta, double* C, long ldc, int lo, long sA, long sB, long sC,
+                         int klast) {
+    hipLaunchKernelGGL((dgemm_kernel<TA, TB>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, lo,
+                       sA, sB, sC, klast);
+}
+
 void dgemm(hipStream_t st, bool ta, bool tb, int m, int n, int k, double alpha, const double* A, long lda,
            const double* B, long ldb, double beta, double* C, long ldc, bool lower_only, int batch, long sA, long sB,
-           long sC) {
+           long sC, double* ws, long ws_len) {
     if (m <= 0 || n <= 0 || batch <= 0) return;
     if (k <= 0) {
         // C = beta C
@@ -144,21 +170,37 @@ void dgemm(hipStream_t st, bool ta, bool tb, int m, int n, int k, double alpha, 
                   std::min(65535, batch - b0), sA, sB, sC);
         return;
     }
-    dim3 grid(cdiv(m, GBM), cdiv(n, GBN), batch);
     int lo = lower_only ? 1 : 0;
-    if (!ta && !tb)
-        hipLaunchKernelGGL((dgemm_kernel<false, false>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta,
-                           C, ldc, lo, sA, sB, sC);
-    else if (!ta && tb)
-        hipLaunchKernelGGL((dgemm_kernel<false, true>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta,
-                           C, ldc, lo, sA, sB, sC);
-    else if (ta && !tb)
-        hipLaunchKernelGGL((dgemm_kernel<true, false>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta,
-                           C, ldc, lo, sA, sB, sC);
-    else
-        hipLaunchKernelGGL((dgemm_kernel<true, true>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta, C,
-                           ldc, lo, sA, sB, sC);
-    WC_LAUNCH_CHECK();
+    const long tiles = (long)cdiv(m, GBM) * cdiv(n, GBN);
+    // kk: the K of every z-slice but a split launch's last (klast)
+    auto launch = [&](dim3 grid, int kk, double al, double be, double* Cx, long ldx, long sa, long sb, long sc,
+                      int klast) {
+        if (!ta && !tb) dgemm_launch<false, false>(st, grid, m, n, kk, al, A, lda, B, ldb, be, Cx, ldx, lo, sa, sb, sc, klast);
+        else if (!ta && tb) dgemm_launch<false, true>(st, grid, m, n, kk, al, A, lda, B, ldb, be, Cx, ldx, lo, sa, sb, sc, klast);
+        else if (ta && !tb) dgemm_launch<true, false>(st, grid, m, n, kk, al, A, lda, B, ldb, be, Cx, ldx, lo, sa, sb, sc, klast);
+        else dgemm_launch<true, true>(st, grid, m, n, kk, al, A, lda, B, ldb, be, Cx, ldx, lo, sa, sb, sc, klast);
+        WC_LAUNCH_CHECK();
+    };
+    // Few output tiles and a long K (the n = 200 products): split K over the
+    // z dimension into partial products, then add them in a fixed order.
+    if (batch == 1 && !lower_only && ws != nullptr && tiles < GEMM_SPLIT_TILES && k >= 64) {
+        int splits = static_cast<int>(std::min<long>(GEMM_SPLITS, std::min<long>(cdiv(k, 32), cdiv(128, tiles))));
+        if (splits >= 2) {
+            const int kc = static_cast<int>(round_up(cdiv(k, splits), GBK));
+            splits = cdiv(k, kc);
+            if (splits >= 2 && (long)splits * m * n <= ws_len) {
+                const int klast = k - (splits - 1) * kc;
+                const long sa = ta ? kc : (long)kc * lda, sb = tb ? (long)kc * ldb : kc;
+                // each slice computes K = kc (the last one klast) from its offset operands
+                launch(dim3(cdiv(m, GBM), cdiv(n, GBN), splits), kc, 1.0, 0.0, ws, m, sa, sb, (long)m * n, klast);
+                hipLaunchKernelGGL(dgemm_reduce_kernel, dim3(cdiv((long)m * n, 256)), dim3(256), 0, st, m, n, splits,
+                                   ws, alpha, beta, C, ldc);
+                WC_LAUNCH_CHECK();
+                return;
+            }
+        }
+    }
+    launch(dim3(cdiv(m, GBM), cdiv(n, GBN), batch), k, alpha, beta, C, ldc, sA, sB, sC, 0);
 }
 
 // ---------------------------------------------------------------------------

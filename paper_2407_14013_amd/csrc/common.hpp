@@ -80,9 +80,13 @@ inline long round_up(long a, long b) { return ((a + b - 1) / b) * b; }
 // C = alpha op(A) op(B) + beta C, column-major.  lower_only writes only the
 // entries with row >= col (used for symmetric rank-k updates).  Batched over
 // `batch` with element strides sA, sB, sC.
+// With a workspace of dgemm_splitk_ws() doubles, a single product with few
+// output tiles and a long K is split over K (partial products, then a sum in a
+// fixed order).
 void dgemm(hipStream_t st, bool ta, bool tb, int m, int n, int k, double alpha, const double* A, long lda,
            const double* B, long ldb, double beta, double* C, long ldc, bool lower_only = false, int batch = 1,
-           long sA = 0, long sB = 0, long sC = 0);
+           long sA = 0, long sB = 0, long sC = 0, double* ws = nullptr, long ws_len = 0);
+long dgemm_splitk_ws();
 
 // C = alpha op(A) B + beta C for a thin B (n <= 16 columns); returns false
 // (nothing launched) when the shape is not handled.  With a workspace of

@@ -104,7 +104,8 @@ static void gemm(sdp_ctx* c, bool ta, bool tb, int m, int n, int k, double alpha
     hipEvent_t e;
     prof_begin(c, SDP_K_GEMM, &e);
     if (tb || !dgemm_thin(c->st, ta, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, c->thin_ws, static_cast<long>(c->thin_ws.n)))
-        dgemm(c->st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+        dgemm(c->st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, false, 1, 0, 0, 0, c->gemm_ws,
+              static_cast<long>(c->gemm_ws.n));
     prof_end(c, SDP_K_GEMM, e, 8.0 * ((double)m * k + (double)k * n + 2.0 * (double)m * n));
 }
 
@@ -171,6 +172,7 @@ static void alloc_work(sdp_ctx* c) {
 
     c->part.alloc(1024);
     c->thin_ws.alloc(thin_splitk_ws(n, c->rmax));
+    c->gemm_ws.alloc(dgemm_splitk_ws());
     c->sy_ws.alloc(symv_ws(static_cast<int>(c->dmaxp)));
     for (auto* b : {&c->vx, &c->vr, &c->vz, &c->vp, &c->vKp, &c->vg, &c->vtmp, &c->vres, &c->vdx}) {
         b->alloc(Nmax);

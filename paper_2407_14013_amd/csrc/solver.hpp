@@ -50,6 +50,7 @@ struct sdp_ctx {
     wc::DevBuf<double> vres, vdx;                       // refinement residual and correction
 
     wc::DevBuf<double> thin_ws; // split-K partial sums of the thin GEMMs
+    wc::DevBuf<double> gemm_ws; // split-K partial products of the small square GEMMs
     wc::DevBuf<double> sy_ws;   // tile partial sums of the symmetric C^{-1} products
     wc::DevBuf<double> sc;      // device scalars
     double* pin = nullptr;      // pinned host scalars
