@@ -19,109 +19,134 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 // lane l is D[l / 16 + 4 v][l % 16].
 // ---------------------------------------------------------------------------
 constexpr int GBM = 64, GBN = 64, GBK = 16;
+constexpr int GBIG = 128;  // tile edge for large products
+constexpr size_t dgemm_lds(int bm, int bn) { return sizeof(double) * 2 * GBK * (bm + 1 + bn + 1); }
 constexpr int GEMM_SPLITS = 8;        // most K-splits of a small product
 constexpr int GEMM_SPLIT_TILES = 64;  // split K only below this many output tiles
 
-template <bool TA, bool TB>
+// Block tile BM x BN (64 x 64 or 128 x 128), four waves in a 2 x 2 grid, each
+// wave (BM/2) x (BN/2) of 16 x 16 FP64 MFMA tiles.  K advances GBK at a time
+// through double-buffered LDS (dynamic, 2 GBK (BM + BN + 2) doubles) with
+// one barrier per step; the next step's global loads sit in registers while
+// the current step multiplies.
+// EPI: 0 stores the product as it is (alpha = 1, beta = 0), 1 scales it by
+// alpha, 2 also adds beta C.  Scaling or reading C in the epilogue moves every
+// accumulator through vector registers at once (the compiler schedules the
+// reads together), which halves the occupancy of the 128 x 128 form, so that
+// form is only instantiated with EPI = 0.
+template <bool TA, bool TB, int BM, int BN, int EPI>
 __global__ __launch_bounds__(256) void dgemm_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
                                                     long lda, const double* __restrict__ B, long ldb, double beta,
                                                     double* __restrict__ C, long ldc, int lower_only, long sA,
                                                     long sB, long sC, int klast) {
     // split-K launches give the last z-slice the remainder of K
     if (klast > 0 && blockIdx.z == gridDim.z - 1) K = klast;
-    const int tile_m = blockIdx.x * GBM;
-    const int tile_n = blockIdx.y * GBN;
-    if (lower_only && tile_n > tile_m + GBM - 1) return;
+    const int tile_m = blockIdx.x * BM;
+    const int tile_n = blockIdx.y * BN;
+    if (lower_only && tile_n > tile_m + BM - 1) return;
     A += blockIdx.z * sA;
     B += blockIdx.z * sB;
     C += blockIdx.z * sC;
 
-    __shared__ double As[GBK][GBM + 1];
-    __shared__ double Bs[GBK][GBN + 1];
+    extern __shared__ double gsm[];
+    double (*As)[GBK][BM + 1] = reinterpret_cast<double (*)[GBK][BM + 1]>(gsm);
+    double (*Bs)[GBK][BN + 1] = reinterpret_cast<double (*)[GBK][BN + 1]>(gsm + 2 * GBK * (BM + 1));
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
+    constexpr int TM = BM / 32, TN = BN / 32;       // MFMA tiles per wave
+    constexpr int QA = BM * GBK / 256, QB = BN * GBK / 256;
 
-    double ra[4], rb[4];
+    // element q of a thread: consecutive threads walk the operand's contiguous index
+    auto a_ik = [&](int q, int& i, int& k) {
+        const int idx = tid + 256 * q;
+        if (!TA) { i = idx % BM; k = idx / BM; }
+        else { k = idx % GBK; i = idx / GBK; }
+    };
+    auto b_kj = [&](int q, int& k, int& j) {
+        const int idx = tid + 256 * q;
+        if (!TB) { k = idx % GBK; j = idx / GBK; }
+        else { j = idx % BN; k = idx / BN; }
+    };
+    double ra[QA], rb[QB];
     auto load = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < QA; ++q) {
             int i, k;
-            if (!TA) { i = tid & 63; k = (tid >> 6) + 4 * q; }
-            else { k = tid & 15; i = (tid >> 4) + 16 * q; }
-            int gi = tile_m + i, gk = k0 + k;
-            double v = 0.0;
-            if (gi < M && gk < K) v = TA ? A[gk + (long)gi * lda] : A[gi + (long)gk * lda];
-            ra[q] = v;
+            a_ik(q, i, k);
+            const int gi = tile_m + i, gk = k0 + k;
+            ra[q] = (gi < M && gk < K) ? (TA ? A[gk + (long)gi * lda] : A[gi + (long)gk * lda]) : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int j, k;
-            if (!TB) { k = tid & 15; j = (tid >> 4) + 16 * q; }
-            else { j = tid & 63; k = (tid >> 6) + 4 * q; }
-            int gj = tile_n + j, gk = k0 + k;
-            double v = 0.0;
-            if (gj < N && gk < K) v = TB ? B[gj + (long)gk * ldb] : B[gk + (long)gj * ldb];
-            rb[q] = v;
+        for (int q = 0; q < QB; ++q) {
+            int k, j;
+            b_kj(q, k, j);
+            const int gj = tile_n + j, gk = k0 + k;
+            rb[q] = (gj < N && gk < K) ? (TB ? B[gj + (long)gk * ldb] : B[gk + (long)gj * ldb]) : 0.0;
         }
     };
-    auto store = [&]() {
+    auto store = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < QA; ++q) {
             int i, k;
-            if (!TA) { i = tid & 63; k = (tid >> 6) + 4 * q; }
-            else { k = tid & 15; i = (tid >> 4) + 16 * q; }
-            As[k][i] = ra[q];
+            a_ik(q, i, k);
+            As[buf][k][i] = ra[q];
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int j, k;
-            if (!TB) { k = tid & 15; j = (tid >> 4) + 16 * q; }
-            else { j = tid & 63; k = (tid >> 6) + 4 * q; }
-            Bs[k][j] = rb[q];
+        for (int q = 0; q < QB; ++q) {
+            int k, j;
+            b_kj(q, k, j);
+            Bs[buf][k][j] = rb[q];
         }
     };
 
-    d4 acc[2][2];
+    d4 acc[TM][TN];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < TM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < TN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
     load(0);
+    store(0);
+    __syncthreads();
+    int buf = 0;
     for (int k0 = 0; k0 < K; k0 += GBK) {
-        __syncthreads();
-        store();
-        __syncthreads();
-        if (k0 + GBK < K) load(k0 + GBK);
+        const bool more = k0 + GBK < K;
+        if (more) load(k0 + GBK);
 #pragma unroll
         for (int kk = 0; kk < GBK; kk += 4) {
             const int kr = kk + (lane >> 4);
-            double a0 = As[kr][wm * 32 + (lane & 15)];
-            double a1 = As[kr][wm * 32 + 16 + (lane & 15)];
-            double b0 = Bs[kr][wn * 32 + (lane & 15)];
-            double b1 = Bs[kr][wn * 32 + 16 + (lane & 15)];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+            double av[TM], bv[TN];
+#pragma unroll
+            for (int a = 0; a < TM; ++a) av[a] = As[buf][kr][wm * (BM / 2) + a * 16 + (lane & 15)];
+#pragma unroll
+            for (int b = 0; b < TN; ++b) bv[b] = Bs[buf][kr][wn * (BN / 2) + b * 16 + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
     }
 
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < TM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < TN; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int gi = tile_m + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
-                int gj = tile_n + wn * 32 + b * 16 + (lane & 15);
+                const int gi = tile_m + wm * (BM / 2) + a * 16 + (lane >> 4) + 4 * v;
+                const int gj = tile_n + wn * (BN / 2) + b * 16 + (lane & 15);
                 if (gi < M && gj < N && (!lower_only || gi >= gj)) {
                     double* c = C + gi + (long)gj * ldc;
-                    double val = alpha * acc[a][b][v];
-                    *c = (beta == 0.0) ? val : val + beta * (*c);
+                    if constexpr (EPI == 0) *c = acc[a][b][v];
+                    else if constexpr (EPI == 1) *c = alpha * acc[a][b][v];
+                    else *c = (beta == 0.0) ? alpha * acc[a][b][v] : alpha * acc[a][b][v] + beta * (*c);
                 }
             }
 }
@@ -141,11 +166,18 @@ __global__ void dgemm_reduce_kernel(int M, int N, int splits, const double* __re
 long dgemm_splitk_ws() { return (long)GEMM_SPLITS * GEMM_SPLIT_TILES * GBM * GBN; }
 
 template <bool TA, bool TB>
-static void dgemm_launch(hipStream_t st, dim3 grid, int m, int n, int k, double alpha, const double* A, long lda,
-                         const double* B, long ldb, double beta, double* C, long ldc, int lo, long sA, long sB, long sC,
-                         int klast) {
-    hipLaunchKernelGGL((dgemm_kernel<TA, TB>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, lo,
-                       sA, sB, sC, klast);
+static void dgemm_launch(hipStream_t st, dim3 grid, bool big, int m, int n, int k, double alpha, const double* A,
+                         long lda, const double* B, long ldb, double beta, double* C, long ldc, int lo, long sA,
+                         long sB, long sC, int klast) {
+    if (big)  // only with alpha == 1 and beta == 0
+        hipLaunchKernelGGL((dgemm_kernel<TA, TB, GBIG, GBIG, 0>), grid, dim3(256), dgemm_lds(GBIG, GBIG), st, m, n, k,
+                           1.0, A, lda, B, ldb, 0.0, C, ldc, lo, sA, sB, sC, klast);
+    else if (beta == 0.0)
+        hipLaunchKernelGGL((dgemm_kernel<TA, TB, GBM, GBN, 1>), grid, dim3(256), dgemm_lds(GBM, GBN), st, m, n, k,
+                           alpha, A, lda, B, ldb, beta, C, ldc, lo, sA, sB, sC, klast);
+    else
+        hipLaunchKernelGGL((dgemm_kernel<TA, TB, GBM, GBN, 2>), grid, dim3(256), dgemm_lds(GBM, GBN), st, m, n, k,
+                           alpha, A, lda, B, ldb, beta, C, ldc, lo, sA, sB, sC, klast);
 }
 
 void dgemm(hipStream_t st, bool ta, bool tb, int m, int n, int k, double alpha, const double* A, long lda,
@@ -172,13 +204,13 @@ void dgemm(hipStream_t st, bool ta, bool tb, int m, int n, int k, double alpha, 
     }
     int lo = lower_only ? 1 : 0;
     const long tiles = (long)cdiv(m, GBM) * cdiv(n, GBN);
-    // kk: the K of every z-slice but a split launch's last (klast)
-    auto launch = [&](dim3 grid, int kk, double al, double be, double* Cx, long ldx, long sa, long sb, long sc,
-                      int klast) {
-        if (!ta && !tb) dgemm_launch<false, false>(st, grid, m, n, kk, al, A, lda, B, ldb, be, Cx, ldx, lo, sa, sb, sc, klast);
-        else if (!ta && tb) dgemm_launch<false, true>(st, grid, m, n, kk, al, A, lda, B, ldb, be, Cx, ldx, lo, sa, sb, sc, klast);
-        else if (ta && !tb) dgemm_launch<true, false>(st, grid, m, n, kk, al, A, lda, B, ldb, be, Cx, ldx, lo, sa, sb, sc, klast);
-        else dgemm_launch<true, true>(st, grid, m, n, kk, al, A, lda, B, ldb, be, Cx, ldx, lo, sa, sb, sc, klast);
+    // kk: the K of every z-slice but a split launch's last (klast); big: 128 x 128 tiles
+    auto launch = [&](dim3 grid, bool big, int kk, double al, double be, double* Cx, long ldx, long sa, long sb,
+                      long sc, int klast) {
+        if (!ta && !tb) dgemm_launch<false, false>(st, grid, big, m, n, kk, al, A, lda, B, ldb, be, Cx, ldx, lo, sa, sb, sc, klast);
+        else if (!ta && tb) dgemm_launch<false, true>(st, grid, big, m, n, kk, al, A, lda, B, ldb, be, Cx, ldx, lo, sa, sb, sc, klast);
+        else if (ta && !tb) dgemm_launch<true, false>(st, grid, big, m, n, kk, al, A, lda, B, ldb, be, Cx, ldx, lo, sa, sb, sc, klast);
+        else dgemm_launch<true, true>(st, grid, big, m, n, kk, al, A, lda, B, ldb, be, Cx, ldx, lo, sa, sb, sc, klast);
         WC_LAUNCH_CHECK();
     };
     // Few output tiles and a long K (the n = 200 products): split K over the
@@ -192,7 +224,8 @@ void dgemm(hipStream_t st, bool ta, bool tb, int m, int n, int k, double alpha, 
                 const int klast = k - (splits - 1) * kc;
                 const long sa = ta ? kc : (long)kc * lda, sb = tb ? (long)kc * ldb : kc;
                 // each slice computes K = kc (the last one klast) from its offset operands
-                launch(dim3(cdiv(m, GBM), cdiv(n, GBN), splits), kc, 1.0, 0.0, ws, m, sa, sb, (long)m * n, klast);
+                launch(dim3(cdiv(m, GBM), cdiv(n, GBN), splits), false, kc, 1.0, 0.0, ws, m, sa, sb, (long)m * n,
+                       klast);
                 hipLaunchKernelGGL(dgemm_reduce_kernel, dim3(cdiv((long)m * n, 256)), dim3(256), 0, st, m, n, splits,
                                    ws, alpha, beta, C, ldc);
                 WC_LAUNCH_CHECK();
@@ -200,7 +233,10 @@ void dgemm(hipStream_t st, bool ta, bool tb, int m, int n, int k, double alpha, 
             }
         }
     }
-    launch(dim3(cdiv(m, GBM), cdiv(n, GBN), batch), k, alpha, beta, C, ldc, sA, sB, sC, 0);
+    // 128 x 128 tiles once they still give every CU several workgroups (plain C = A B only)
+    const bool big = alpha == 1.0 && beta == 0.0 && (long)cdiv(m, GBIG) * cdiv(n, GBIG) * batch >= 4L * 256;
+    if (big) launch(dim3(cdiv(m, GBIG), cdiv(n, GBIG), batch), true, k, alpha, beta, C, ldc, sA, sB, sC, 0);
+    else launch(dim3(cdiv(m, GBM), cdiv(n, GBN), batch), false, k, alpha, beta, C, ldc, sA, sB, sC, 0);
 }
 
 // ---------------------------------------------------------------------------

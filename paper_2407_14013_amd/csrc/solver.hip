@@ -513,17 +513,18 @@ void newton_apply(sdp_ctx* c, const double* in, double* out) {
     // Y = A^T(u)
     at_apply(c, u, c->Y);
     // U = [Q Qp][B; sqrt2 N];  Mm = sym(U Q^T) + E Y E
-    v_to_h(st, n, r, v, c->Hm);
-    gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
-    symlr(st, n, r, c->U, c->Gw, n, c->Mm, n, 0.0);
-    const double sw_bytes = 8.0 * 4.0 * nn;  // two operands, C read and written
+    const double sw_bytes = 8.0 * 3.0 * nn;  // two operands, C written
     hipEvent_t es;
     prof_begin(c, SDP_K_SANDWICH, &es);
     gemm(c, false, false, n, n, n, 1.0, c->Y, n, c->E, n, 0.0, c->T1, n);
     prof_end(c, SDP_K_SANDWICH, es, sw_bytes);
     prof_begin(c, SDP_K_SANDWICH, &es);
-    gemm(c, false, false, n, n, n, 1.0, c->E, n, c->T1, n, 1.0, c->Mm, n);
+    gemm(c, false, false, n, n, n, 1.0, c->E, n, c->T1, n, 0.0, c->Mm, n);
     prof_end(c, SDP_K_SANDWICH, es, sw_bytes);
+    // Mm += sym(U Q^T) (after the products, which then need not read Mm)
+    v_to_h(st, n, r, v, c->Hm);
+    gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
+    symlr(st, n, r, c->U, c->Gw, n, c->Mm, n, 1.0);
     // top = A(Mm)
     a_apply(c, c->Mm, out, 1.0, 0.0);
     // bottom = Q^T svec(Y) - tau^2 Sigma v, with Q^T svec(Y) read from F = G_w^T Y Q
@@ -684,10 +685,10 @@ static void recover(sdp_ctx* c, const double* x, const double* Ct, double* dX, d
     at_apply(c, x, c->Y);
     axpby(st, nn, -t2, Ct, 1.0, c->Y);
     gemm(c, false, false, n, n, n, 1.0, c->Y, n, c->E, n, 0.0, c->T1, n);
+    gemm(c, false, false, n, n, n, 1.0, c->E, n, c->T1, n, 0.0, dX, n);
     v_to_h(st, n, r, x + m, c->Hm);
     gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
-    symlr(st, n, r, c->U, c->Gw, n, dX, n, 0.0);
-    gemm(c, false, false, n, n, n, 1.0, c->E, n, c->T1, n, 1.0, dX, n);
+    symlr(st, n, r, c->U, c->Gw, n, dX, n, 1.0);
     symmetrize(st, n, dX, n);
 }
 
