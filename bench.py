@@ -442,6 +442,18 @@ def main():
     for r in results:
         assert r["status"] == 0 and r["relgap"] <= 1e-8, r
 
+    # one more FP64 solve step by step (untimed): mu, rank and PCG iterations of
+    # the predictor and corrector systems along the trajectory (Corollary pcg:
+    # the counts stay bounded as mu -> 0)
+    ctx.set_point(X0, y0, S0)
+    trajectory = []
+    for _ in range(100):
+        st = ctx.ipm_step()
+        if st["converged"]:
+            break
+        trajectory.append({"mu": st["mu"], "relgap": st["relgap"], "r": st["r"], "pcg_pred": st["pcg_pred"],
+                           "pcg_corr": st["pcg_corr"]})
+
     # the same solves with the mixed-precision inner operator
     mixed = {}
     if not args.no_mixed:
@@ -519,6 +531,7 @@ def main():
             "relgap": results[-1]["relgap"],
             "pobj": results[-1]["pobj"],
         },
+        "trajectory": trajectory,
         "newton_apply_loop": {"matvec_per_s": loop_rate, "calls": args.apply_loop},
         "mixed": mixed,
         "roofline": {
