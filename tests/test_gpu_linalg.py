@@ -32,6 +32,22 @@ def test_dgemm(ta, tb, m, n, k):
     assert err <= bound
 
 
+@pytest.mark.parametrize("ta", ["N", "T"])
+@pytest.mark.parametrize("tb", ["N", "T"])
+@pytest.mark.parametrize("m,n,k", [(4096, 4096, 64), (4100, 4097, 129)])
+def test_dgemm_large_tiles(ta, tb, m, n, k):
+    # C = A B with alpha = 1, beta = 0 and at least 1024 tiles of 128 x 128:
+    # the large-tile kernel, including ragged row, column and K edges
+    rng = np.random.default_rng(m + n + k)
+    A = rng.standard_normal((k, m) if ta == "T" else (m, k))
+    B = rng.standard_normal((n, k) if tb == "T" else (k, n))
+    ref = (A.T if ta == "T" else A) @ (B.T if tb == "T" else B)
+    Cd = la.to_dev(np.full((m, n), np.nan))
+    la.dgemm(ta, tb, 1.0, la.to_dev(A), la.to_dev(B), 0.0, Cd)
+    err = np.abs(la.from_dev(Cd) - ref).max()
+    assert err <= 4 * k * EPS * np.abs(A).max() * np.abs(B).max()
+
+
 @pytest.mark.parametrize("d", [1, 5, 64, 65, 130, 597, 2049])
 def test_dsymv(d):
     # one triangle read (64 x 64 tiles, partial sums per tile), against the full product
