@@ -86,15 +86,16 @@ int32_t wc_gemm_lp(void* stream, int32_t prec_in, int32_t out_kind, int32_t m, i
                    int32_t lda, const void* B, int32_t ldb, void* C, int32_t ldc);
 
 /*
- * C = A B for a symmetric m x m BF16 matrix A and an m x n BF16 matrix B
- * (column-major bit patterns, FP32 accumulation), written as out_kind says
- * (as in wc_gemm_lp).  A is read by rows, which is what makes both operands
- * k-contiguous; only the triangle-symmetric A may be passed.  With lda and ldb
- * multiples of 8 and 16-byte aligned A and B a 128 x 128-tile kernel runs;
- * otherwise the general kernel of wc_gemm_lp.
+ * C = A B for a symmetric m x m matrix A and an m x n matrix B, both stored in
+ * precision prec_in (1 FP32, 2 BF16 bit patterns; column-major) and
+ * accumulated in FP32, written as out_kind says (as in wc_gemm_lp).  A is
+ * read by rows, which is what makes both operands k-contiguous; only a
+ * symmetric A may be passed.  With lda and ldb multiples of 4 (FP32) or 8
+ * (BF16), 16-byte aligned A and B and at least 64 output tiles of 128 x 128,
+ * a 128 x 128-tile kernel runs; otherwise the general kernel of wc_gemm_lp.
  */
-int32_t wc_gemm_lp_sym(void* stream, int32_t out_kind, int32_t m, int32_t n, const void* A, int32_t lda, const void* B,
-                       int32_t ldb, void* C, int32_t ldc);
+int32_t wc_gemm_lp_sym(void* stream, int32_t prec_in, int32_t out_kind, int32_t m, int32_t n, const void* A,
+                       int32_t lda, const void* B, int32_t ldb, void* C, int32_t ldc);
 
 /*
  * B = A rounded to FP32 (prec = 1, round to nearest) or to BF16 (prec = 2,

@@ -168,8 +168,8 @@ _SIGNATURES = [
                              C.c_void_p]),
     ("wc_gemm_lp", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
-    ("wc_gemm_lp_sym", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
-                                   C.c_int32, C.c_void_p, C.c_int32]),
+    ("wc_gemm_lp_sym", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+                                   C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
     ("wc_to_lowp", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                C.c_int32]),
 ]

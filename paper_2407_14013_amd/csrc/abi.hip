@@ -343,17 +343,19 @@ int32_t wc_gemm_lp(void* stream, int32_t prec_in, int32_t out_kind, int32_t m, i
     });
 }
 
-int32_t wc_gemm_lp_sym(void* stream, int32_t out_kind, int32_t m, int32_t n, const void* A, int32_t lda, const void* B,
-                       int32_t ldb, void* C, int32_t ldc) {
+int32_t wc_gemm_lp_sym(void* stream, int32_t prec_in, int32_t out_kind, int32_t m, int32_t n, const void* A,
+                       int32_t lda, const void* B, int32_t ldb, void* C, int32_t ldc) {
     return guarded_la([&]() {
+        wc::require(prec_in == 1 || prec_in == 2, "prec_in must be 1 (FP32) or 2 (BF16)");
         wc::require(out_kind >= 0 && out_kind <= 3, "out_kind must be 0, 1, 2 or 3");
+        const wc::Lp in = prec_in == 1 ? wc::Lp::F32 : wc::Lp::BF16;
         const wc::LpOut out = out_kind == 0   ? wc::LpOut::F32
                               : out_kind == 1 ? wc::LpOut::BF16
                               : out_kind == 2 ? wc::LpOut::ADD_F64
                                               : wc::LpOut::F64;
         hipStream_t st = static_cast<hipStream_t>(stream);
-        if (!wc::lp_gemm_sym(st, wc::Lp::BF16, out, m, n, A, lda, B, ldb, C, ldc))
-            wc::lp_gemm_nn(st, wc::Lp::BF16, out, m, n, m, A, lda, B, ldb, C, ldc);
+        if (!wc::lp_gemm_sym(st, in, out, m, n, A, lda, B, ldb, C, ldc))
+            wc::lp_gemm_nn(st, in, out, m, n, m, A, lda, B, ldb, C, ldc);
         return (int32_t)0;
     });
 }

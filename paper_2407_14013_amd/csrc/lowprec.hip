@@ -266,16 +266,126 @@ __global__ __launch_bounds__(256) void bgemm_sym_kernel(int M, int N, const unsi
             lp_store<OUT>(C, ldc, M, N, row0 + wm * 64 + x * 16, col0 + wn * 64 + y * 16, acc[x][y]);
 }
 
+// FP32 form of the same product: 128 x 128 tiles, four waves of 4 x 4 MFMA
+// tiles (16 x 16 x 4, FP32).  Within a 32-deep K step, lane group g (= lane /
+// 16) owns the k-run 8g .. 8g + 7 and feeds k = 8g + j to MFMA step j, so the
+// four k-slots of step j are 8g + j (g = 0..3) and the eight steps cover the
+// 32 values of k once each -- every lane reads its A row and B column as two
+// 16-byte LDS loads.  K advances through double-buffered dynamic LDS
+// (2 x 2 x 128 x 36 floats) with one barrier per step.  Requires lda and ldb
+// multiples of 4 and 16-byte aligned A and B.
+constexpr int FP = SK + 4;  // LDS row pitch in floats (144 bytes)
+typedef float lf4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ lf4v load4_guarded(const float* __restrict__ p, int k, int K) {
+    if (k + 4 <= K) return *reinterpret_cast<const lf4v*>(p);
+    lf4v v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = (k + e < K) ? p[e] : 0.f;
+    return v;
+}
+
+template <LpOut OUT>
+__global__ __launch_bounds__(256) void sgemm_sym_kernel(int M, int N, const float* __restrict__ A, long lda,
+                                                        const float* __restrict__ B, long ldb, void* __restrict__ C,
+                                                        long ldc) {
+    extern __shared__ float fsm[];
+    float (*As)[ST][FP] = reinterpret_cast<float (*)[ST][FP]>(fsm);             // [buffer][row][k]
+    float (*Bs)[ST][FP] = reinterpret_cast<float (*)[ST][FP]>(fsm + 2 * ST * FP);  // [buffer][col][k]
+    const int K = M;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv & 1, wn = wv >> 1;
+    const int row0 = blockIdx.x * ST, col0 = blockIdx.y * ST;
+    // loader: vector q = tid + 256 h covers row (column) q / 8 and k offset 4 (q % 8)
+    lf4v ra[4], rb[4];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int q = tid + 256 * h, r = q >> 3, k = k0 + 4 * (q & 7);
+            const int gi = row0 + r, gj = col0 + r;
+            ra[h] = gi < M ? load4_guarded(A + k + (long)gi * lda, k, K) : lf4v{0.f, 0.f, 0.f, 0.f};
+            rb[h] = gj < N ? load4_guarded(B + k + (long)gj * ldb, k, K) : lf4v{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int q = tid + 256 * h, r = q >> 3, k = 4 * (q & 7);
+            *reinterpret_cast<lf4v*>(&As[buf][r][k]) = ra[h];
+            *reinterpret_cast<lf4v*>(&Bs[buf][r][k]) = rb[h];
+        }
+    };
+    v4f acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    const int kg = 8 * (lane >> 4);
+    int buf = 0;
+    for (int k0 = 0; k0 < K; k0 += SK) {
+        const bool more = k0 + SK < K;
+        if (more) fetch(k0 + SK);
+        lf4v a[4][2], b[4][2];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            const float* pa = &As[buf][wm * 64 + x * 16 + (lane & 15)][kg];
+            a[x][0] = *reinterpret_cast<const lf4v*>(pa);
+            a[x][1] = *reinterpret_cast<const lf4v*>(pa + 4);
+        }
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const float* pb = &Bs[buf][wn * 64 + y * 16 + (lane & 15)][kg];
+            b[y][0] = *reinterpret_cast<const lf4v*>(pb);
+            b[y][1] = *reinterpret_cast<const lf4v*>(pb + 4);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x][j >> 2][j & 3], b[y][j >> 2][j & 3],
+                                                                     acc[x][y], 0, 0, 0);
+        if (more) stash(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+            lp_store<OUT>(C, ldc, M, N, row0 + wm * 64 + x * 16, col0 + wn * 64 + y * 16, acc[x][y]);
+}
+
 bool lp_gemm_sym(hipStream_t st, Lp in, LpOut out, int M, int N, const void* A, long lda, const void* B, long ldb,
                  void* C, long ldc) {
     require(M >= 0 && N >= 0, "lp_gemm_sym: negative size");
     require(lda >= std::max(1, M) && ldb >= std::max(1, M) && ldc >= std::max(1, M),
             "lp_gemm_sym: bad leading dimension");
     if (M == 0 || N == 0) return true;
-    const bool aligned = (lda % 8 == 0) && (ldb % 8 == 0) && (reinterpret_cast<uintptr_t>(A) % 16 == 0) &&
+    const int vec = in == Lp::BF16 ? 8 : 4;  // elements per 16-byte load
+    const bool aligned = (lda % vec == 0) && (ldb % vec == 0) && (reinterpret_cast<uintptr_t>(A) % 16 == 0) &&
                          (reinterpret_cast<uintptr_t>(B) % 16 == 0);
-    if (in != Lp::BF16 || !aligned || cdiv(N, ST) > 65535) return false;
+    // the 128 x 128 tiles only pay once there are enough of them (n >~ 1000);
+    // smaller products keep the 64 x 64 kernel's parallelism
+    if (!aligned || cdiv(N, ST) > 65535 || (long)cdiv(M, ST) * cdiv(N, ST) < 64) return false;
     dim3 grid(cdiv(M, ST), cdiv(N, ST));
+    if (in == Lp::F32) {
+        const auto* a = static_cast<const float*>(A);
+        const auto* b = static_cast<const float*>(B);
+        const size_t lds = sizeof(float) * 2 * 2 * ST * FP;
+        switch (out) {
+            case LpOut::F32: hipLaunchKernelGGL(sgemm_sym_kernel<LpOut::F32>, grid, dim3(256), lds, st, M, N, a, lda, b, ldb, C, ldc); break;
+            case LpOut::BF16: hipLaunchKernelGGL(sgemm_sym_kernel<LpOut::BF16>, grid, dim3(256), lds, st, M, N, a, lda, b, ldb, C, ldc); break;
+            case LpOut::F64: hipLaunchKernelGGL(sgemm_sym_kernel<LpOut::F64>, grid, dim3(256), lds, st, M, N, a, lda, b, ldb, C, ldc); break;
+            case LpOut::ADD_F64: hipLaunchKernelGGL(sgemm_sym_kernel<LpOut::ADD_F64>, grid, dim3(256), lds, st, M, N, a, lda, b, ldb, C, ldc); break;
+        }
+        WC_LAUNCH_CHECK();
+        return true;
+    }
     const auto* a = static_cast<const unsigned short*>(A);
     const auto* b = static_cast<const unsigned short*>(B);
     switch (out) {

@@ -24,10 +24,11 @@ enum class LpOut { F32, BF16, F64, ADD_F64 };
 void lp_gemm_nn(hipStream_t st, Lp in, LpOut out, int M, int N, int K, const void* A, long lda, const void* B,
                 long ldb, void* C, long ldc);
 
-// C = A B with A symmetric (M x M), B (M x N), in BF16 on the matrix cores:
-// A is read by rows, so both operands load k-contiguous.  Returns false (nothing
-// launched) unless in is BF16, lda and ldb are multiples of 8 and A, B are
-// 16-byte aligned; the caller then uses lp_gemm_nn.
+// C = A B with A symmetric (M x M), B (M x N), in FP32 or BF16 on the matrix
+// cores: A is read by rows, so both operands load k-contiguous.  Returns false
+// (nothing launched) unless lda and ldb are multiples of the elements in 16
+// bytes, A, B are 16-byte aligned and the product has at least 64 tiles of
+// 128 x 128; the caller then uses lp_gemm_nn.
 bool lp_gemm_sym(hipStream_t st, Lp in, LpOut out, int M, int N, const void* A, long lda, const void* B, long ldb,
                  void* C, long ldc);
 

@@ -542,7 +542,7 @@ static void sandwich_lp(sdp_ctx* c, LpOut tout, LpOut mout) {
     const double bytes = (c->lp == Lp::F32 ? 4.0 : 2.0) * 3.0 * n * n + 8.0 * n * n;
     hipEvent_t es;
     // Y and E are symmetric, so both products take the symmetric-left-operand
-    // kernel where it applies (BF16, aligned rows)
+    // kernels where they apply (rows 16-byte aligned)
     prof_begin(c, SDP_K_SANDWICH, &es);
     if (!lp_gemm_sym(c->st, c->lp, tout, n, n, c->Ylp, n, c->Elp, n, c->Tlp, n))
         lp_gemm_nn(c->st, c->lp, tout, n, n, n, c->Ylp, n, c->Elp, n, c->Tlp, n);

@@ -105,15 +105,15 @@ def to_lowp(A: torch.Tensor, prec: int) -> torch.Tensor:
     return out
 
 
-def gemm_lp_sym(out_kind: int, A: torch.Tensor, B: torch.Tensor, Cm: torch.Tensor | None = None):
-    """C = A B for a symmetric BF16 A (m x m) and BF16 B (m x n), column-major as from to_lowp; out_kind as gemm_lp."""
+def gemm_lp_sym(prec: int, out_kind: int, A: torch.Tensor, B: torch.Tensor, Cm: torch.Tensor | None = None):
+    """C = A B for a symmetric A (m x m) and B (m x n) in precision prec, column-major as from to_lowp."""
     m, m2 = A.shape
     n, kb = B.shape
     assert m == m2 == kb, "A must be square and match B"
     if Cm is None:
         dt = {0: torch.float32, 1: torch.int16, 2: torch.float64, 3: torch.float64}[out_kind]
         Cm = torch.zeros((n, m), dtype=dt, device=A.device)
-    _chk(L.lib().wc_gemm_lp_sym(_stream_ptr(), out_kind, m, n, _praw(A), m, _praw(B), m, _praw(Cm), m))
+    _chk(L.lib().wc_gemm_lp_sym(_stream_ptr(), prec, out_kind, m, n, _praw(A), m, _praw(B), m, _praw(Cm), m))
     return Cm
 
 

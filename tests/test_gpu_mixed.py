@@ -96,29 +96,30 @@ def test_gemm_lp(prec, m, n, k):
     assert e.max() <= 0
 
 
-@pytest.mark.parametrize("m,n", [(8, 8), (17, 5), (136, 136), (200, 200), (264, 100), (400, 3)])
-def test_gemm_lp_sym(m, n):
-    # the BF16 product with a symmetric left operand (the E Y E products of the
-    # operator), same bounds as test_gemm_lp with K = m; m = 17 takes the
-    # general kernel (rows not 16-byte aligned), the others the 128 x 128 tiles
-    # with ragged row, column and K edges
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("m,n", [(17, 5), (200, 200), (1032, 1032), (1100, 1030), (2056, 520)])
+def test_gemm_lp_sym(prec, m, n):
+    # the product with a symmetric left operand (the E Y E products of the
+    # operator), same bounds as test_gemm_lp with K = m; m = 17 (rows not
+    # 16-byte aligned) and m = 200 (fewer than 64 tiles) take the general
+    # kernel, the others the 128 x 128 tiles with ragged row, column and K edges
     rng = np.random.default_rng(m * 5 + n)
     M0 = rng.standard_normal((m, m))
     A = 0.5 * (M0 + M0.T)
     B = rng.standard_normal((m, n))
-    Al, Av = rounded(A, L.SDP_PREC_BF16)
-    Bl, Bv = rounded(B, L.SDP_PREC_BF16)
+    Al, Av = rounded(A, prec)
+    Bl, Bv = rounded(B, prec)
     exact = Av @ Bv
     mag = np.abs(Av) @ np.abs(Bv)
-    got = host(la.gemm_lp_sym(0, Al, Bl)).T.astype(np.float64)
+    got = host(la.gemm_lp_sym(prec, 0, Al, Bl)).T.astype(np.float64)
     assert (np.abs(got - exact) - (2 * m * U32 * mag + U32 * np.abs(exact))).max() <= 0
-    got = bf16_value(host(la.gemm_lp_sym(1, Al, Bl)).view(np.uint16).T)
+    got = bf16_value(host(la.gemm_lp_sym(prec, 1, Al, Bl)).view(np.uint16).T)
     assert (np.abs(got - exact) - (2 * m * U32 * mag * (1 + UBF) + UBF * np.abs(exact))).max() <= 0
-    got = la.from_dev(la.gemm_lp_sym(3, Al, Bl, la.to_dev(np.full((m, n), np.nan))))
+    got = la.from_dev(la.gemm_lp_sym(prec, 3, Al, Bl, la.to_dev(np.full((m, n), np.nan))))
     assert (np.abs(got - exact) - (2 * m * U32 * mag + U32 * np.abs(exact))).max() <= 0
     C0 = rng.standard_normal((m, n))
     Cd = la.to_dev(C0)
-    la.gemm_lp_sym(2, Al, Bl, Cd)
+    la.gemm_lp_sym(prec, 2, Al, Bl, Cd)
     got = la.from_dev(Cd)
     assert (np.abs(got - (C0 + exact)) - (2 * m * U32 * mag + U32 * np.abs(exact))).max() <= 0
 
