@@ -234,15 +234,17 @@ MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 
 
 def bench_completion(args):
-    """Config 2: the n=4000 matrix-completion operator, where E Y E on the matrix cores dominates.
+    """The n=4000 matrix-completion operator, where E Y E on the matrix cores dominates.
 
     At a closed-form centred point with a rank-4 split (the shape of the late
     iterates) every form of the operator is applied in a tight loop: FP64,
     and the FP32 and BF16 forms that the refinement sweeps use.  The two
     n x n x n GEMMs of E Y E are timed by the library with HIP events on its
     stream (kernel class SDP_K_SANDWICH): 2 n^3 flops per launch.  With
-    --solve, the full FP64 and FP32-mixed solves to the 1e-8 tolerances are
-    timed as well (minutes).
+    --solve, the full solves to the 1e-8 tolerances are timed as well
+    (minutes): FP64 with the sampled A(E Y E) form, FP64 with the dense
+    products, and FP32-mixed.  The sampled form (sparse_sandwich) is timed
+    per kernel class too: Z = Y E and the per-constraint dot products.
     """
     import torch
 
@@ -259,8 +261,12 @@ def bench_completion(args):
     del X, S
     flops = 2.0 * n ** 3
     forms = {}
-    for name, prec in (("f64", L.SDP_PREC_F64), ("f32", L.SDP_PREC_F32), ("bf16", L.SDP_PREC_BF16)):
-        with Context(p, inner_prec=prec) as ctx:
+    wanted_forms = args.forms.split(",")
+    for name, prec, sparse in (("f64", L.SDP_PREC_F64, 0), ("f32", L.SDP_PREC_F32, 0), ("bf16", L.SDP_PREC_BF16, 0),
+                               ("f64_sampled", L.SDP_PREC_F64, 1)):
+        if name not in wanted_forms:
+            continue
+        with Context(p, inner_prec=prec, sparse_sandwich=sparse) as ctx:
             ctx.set_point(Xd, yd, Sd)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -274,35 +280,78 @@ def bench_completion(args):
             for _ in range(3):
                 ctx.newton_apply(xin, xout, prec=pr)
             torch.cuda.synchronize()
-            ctx.profile_enable([L.SDP_K_SANDWICH])
+            classes = [L.SDP_K_SAMPLED_YE, L.SDP_K_SAMPLED_DOTS] if sparse else [L.SDP_K_SANDWICH]
+            ctx.profile_enable(classes)
             calls = args.apply_loop
             t0 = time.perf_counter()
             for _ in range(calls):
                 ctx.newton_apply(xin, xout, prec=pr)
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
-            sw = ctx.profile_get(L.SDP_K_SANDWICH)
+            prof = {k: ctx.profile_get(k) for k in classes}
             ctx.profile_enable([])
             t0 = time.perf_counter()
             for _ in range(20):
                 ctx.precond_apply(xin, xout)
             torch.cuda.synchronize()
             t_prec = (time.perf_counter() - t0) / 20
-            tf = flops * sw["launches"] / (sw["ms"] * 1e-3) / 1e12
             forms[name] = {
                 "matvec_per_s": calls / el,
                 "ms_per_matvec": 1e3 * el / calls,
-                "sandwich_gemm": {"launches": sw["launches"], "avg_launch_ms": sw["ms"] / sw["launches"],
-                                  "achieved_tflops": tf, "peak_tflops": MFMA_PEAK_TFLOPS[name],
-                                  "frac": tf / MFMA_PEAK_TFLOPS[name]},
                 "precond_apply_ms": 1e3 * t_prec,
                 "scaling_setup_s": t_scaling,
                 "r": sc["r"],
                 "d": N - m,
             }
-        print(f"{name}: {forms[name]['ms_per_matvec']:.3f} ms per operator product, sandwich GEMM "
-              f"{tf:.1f} TFLOP/s, scaling setup {t_scaling:.2f} s", file=sys.stderr, flush=True)
-    f64 = forms["f64"]
+            if sparse:
+                # the two sampled kernels, HBM-bound: algorithmic bytes per launch
+                # as the library counts them (one column of Z per constraint)
+                for key, k in (("sampled_ye", L.SDP_K_SAMPLED_YE), ("sampled_dots", L.SDP_K_SAMPLED_DOTS)):
+                    pk = prof[k]
+                    gbs = pk["bytes"] / (pk["ms"] * 1e-3) / 1e9
+                    forms[name][key] = {"launches": pk["launches"], "avg_launch_ms": pk["ms"] / pk["launches"],
+                                        "bytes_per_launch": pk["bytes"] / pk["launches"], "achieved_gbs": gbs,
+                                        "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}
+                note = (f"Y E {forms[name]['sampled_ye']['avg_launch_ms']:.3f} ms, dots "
+                        f"{forms[name]['sampled_dots']['avg_launch_ms']:.3f} ms")
+            else:
+                sw = prof[L.SDP_K_SANDWICH]
+                tf = flops * sw["launches"] / (sw["ms"] * 1e-3) / 1e12
+                forms[name]["sandwich_gemm"] = {"launches": sw["launches"], "avg_launch_ms": sw["ms"] / sw["launches"],
+                                                "achieved_tflops": tf, "peak_tflops": MFMA_PEAK_TFLOPS[name],
+                                                "frac": tf / MFMA_PEAK_TFLOPS[name]}
+                note = f"sandwich GEMM {tf:.1f} TFLOP/s"
+        print(f"{name}: {forms[name]['ms_per_matvec']:.3f} ms per operator product, {note}, "
+              f"scaling setup {t_scaling:.2f} s", file=sys.stderr, flush=True)
+    # the line's value and roofline: the FP64 dense-product form when it was
+    # run, else the FP64 sampled form with its per-constraint dot kernel
+    head = "f64" if "f64" in forms else "f64_sampled"
+    f64 = forms[head]
+    if head == "f64":
+        roof = {
+            "kernel": "dgemm_kernel<false, false>: the two n x n x n products of E Y E",
+            "bound": "mfma",
+            "achieved": f64["sandwich_gemm"]["achieved_tflops"],
+            "peak": MFMA_PEAK_TFLOPS["f64"],
+            "unit": "TFLOP/s",
+            "frac": f64["sandwich_gemm"]["frac"],
+            "traffic": None,
+            "flops_per_launch": flops,
+            "avg_launch_ms": f64["sandwich_gemm"]["avg_launch_ms"],
+        }
+    else:
+        dots = f64["sampled_dots"]
+        roof = {
+            "kernel": "sampled_dots_kernel: E[:, j] . Z[:, k] per constraint",
+            "bound": "hbm",
+            "achieved": dots["achieved_gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": dots["frac"],
+            "traffic": None,
+            "bytes_per_launch": dots["bytes_per_launch"],
+            "avg_launch_ms": dots["avg_launch_ms"],
+        }
     line = {
         "metric": METRIC,
         "value": f64["matvec_per_s"],
@@ -317,24 +366,18 @@ def bench_completion(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "matrix completion SDP n=4000 r=4 m=160000 (entry sampling) at a centred point, "
-                               "mu=1e-2, rank-4 split"},
+                               "mu=1e-2, rank-4 split", "form": head},
         "forms": forms,
-        "roofline": {
-            "kernel": "dgemm_kernel<false, false>: the two n x n x n products of E Y E",
-            "bound": "mfma",
-            "achieved": f64["sandwich_gemm"]["achieved_tflops"],
-            "peak": MFMA_PEAK_TFLOPS["f64"],
-            "unit": "TFLOP/s",
-            "frac": f64["sandwich_gemm"]["frac"],
-            "traffic": None,
-            "flops_per_launch": flops,
-            "avg_launch_ms": f64["sandwich_gemm"]["avg_launch_ms"],
-        },
+        "roofline": roof,
     }
     if args.solve:
         solves = {}
-        for name, prec in (("f64", L.SDP_PREC_F64), ("f32", L.SDP_PREC_F32)):
-            with Context(p, inner_prec=prec) as ctx:
+        wanted = args.solve.split(",")
+        for name, prec, sparse in (("f64_sampled", L.SDP_PREC_F64, 1), ("f64", L.SDP_PREC_F64, 0),
+                                   ("f32", L.SDP_PREC_F32, 0)):
+            if name not in wanted:
+                continue
+            with Context(p, inner_prec=prec, sparse_sandwich=sparse) as ctx:
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 res = ctx.solve(raise_on_stall=False)
@@ -392,7 +435,10 @@ def main():
     ap.add_argument("--workload", choices=["sensing", "batched", "adjoint", "completion"], default="sensing",
                     help="sensing: the headline line (n=200 dense); batched: 1024 small SDPs in one launch; "
                          "adjoint: n=1000 completion forward + backward; completion: n=4000 completion operator")
-    ap.add_argument("--solve", action="store_true", help="completion: also time the full FP64 and mixed solves")
+    ap.add_argument("--forms", default="f64,f32,bf16,f64_sampled",
+                    help="completion: operator forms to time (comma list of f64, f32, bf16, f64_sampled)")
+    ap.add_argument("--solve", nargs="?", const="f64_sampled,f64,f32", default="",
+                    help="completion: also time full solves, a comma list of f64_sampled, f64, f32 (default all)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every instance of this workload fits one MI355X, "

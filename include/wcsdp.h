@@ -112,6 +112,13 @@ typedef struct sdp_problem {
  *  verbose      0 silent, 1 one line per interior-point iteration and one per
  *               scaling setup with its phase timings (the stream is synchronised
  *               between phases), 2 also one line per Krylov iteration (stderr) [0]
+ *  sparse_sandwich  entry-sampling constraints only, FP64 inner precision,
+ *               n <= 16384: nonzero forms the A E A^T block of the operator
+ *               (Section 5) at the sampled pairs only, as Z = A^T(u) E (a
+ *               sparse-dense product) followed by one length-n dot product
+ *               per constraint, instead of the two dense n x n x n products
+ *               of E Y E.  Same operator up to rounding; it pays when m is far
+ *               below n^2 [0]
  */
 typedef struct sdp_options {
     int32_t rank_max;
@@ -128,6 +135,7 @@ typedef struct sdp_options {
     double step_frac;
     int32_t verbose;
     double refine_tol;
+    int32_t sparse_sandwich;
 } sdp_options;
 
 typedef struct sdp_inner_stats {
@@ -332,7 +340,11 @@ enum {
     SDP_K_NEWTON = 3,    /* a whole sdp_newton_apply */
     SDP_K_SANDWICH = 4,  /* each n x n x n GEMM of E Y E inside the operator, FP64 or low precision
                             (2 n^3 flops per launch; bytes = its operands and result) */
-    SDP_K_COUNT = 5
+    SDP_K_SAMPLED_YE = 5,   /* sparse_sandwich: Z = A^T(u) E from the sliced pattern (bytes = E read
+                               and Z written once, 10 per pattern slot) */
+    SDP_K_SAMPLED_DOTS = 6, /* sparse_sandwich: E[:, j] . Z[:, k] per constraint (bytes = one column
+                               of Z per constraint, E once, 16 per constraint) */
+    SDP_K_COUNT = 7
 };
 
 /*

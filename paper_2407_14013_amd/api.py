@@ -212,7 +212,7 @@ class Context:
     def profile_enable(self, classes=None):
         """Time the given kernel classes (iterable of SDP_K_*; None = all; [] = off)."""
         if classes is None:
-            mask = (1 << 5) - 1
+            mask = (1 << L.SDP_K_COUNT) - 1
         else:
             mask = 0
             for k in classes:

@@ -429,6 +429,166 @@ void entry_gram_block(hipStream_t st, int n, int b, int b2, const int* rptr, con
     WC_LAUNCH_CHECK();
 }
 
+// ---- sampled form of A(E Y E) for entry sampling ----------------------------------
+// With m far below n^2, (E Y E)[j, k] is formed only at the sampled pairs:
+// Z = Y E as a sparse-dense product, then out_i = E[:, j] . Z[:, k] (E and Y
+// symmetric, so this equals the symmetrised gather of E Y E).  The pattern
+// rows are ordered by length (longest first) and cut into slices of 64 rows
+// (lane = row within the slice, srow = its row of Y, -1 past the last row);
+// each slice is padded to its longest row, so a slot index is
+// base + 64 t + lane and the loads of a wave are coalesced.  A slot holds its
+// column (16 bits: n <= 16384) and in eidx its constraint i off the diagonal,
+// -2 - i on it, and -1 in a pad (column 0).
+
+// val[e] = the entry of Y = A^T(u) at slot e: u_i on the diagonal, u_i / 2
+// off it, 0 in pads.
+__global__ __launch_bounds__(256) void sliced_values_kernel(long slots, const int* __restrict__ eidx,
+                                                            const double* __restrict__ u, double* __restrict__ val) {
+    const long e = blockIdx.x * 256L + threadIdx.x;
+    if (e >= slots) return;
+    const int i = eidx[e];
+    val[e] = (i >= 0) ? 0.5 * u[i] : (i == -1 ? 0.0 : u[-2 - i]);
+}
+void sliced_values(hipStream_t st, long slots, const int* eidx, const double* u, double* val) {
+    if (slots <= 0) return;
+    hipLaunchKernelGGL(sliced_values_kernel, g1(slots), dim3(256), 0, st, slots, eidx, u, val);
+    WC_LAUNCH_CHECK();
+}
+
+// Z[:, k0 + c] = Y E[:, k0 + c] for c < kc: the workgroup stages its KC
+// columns of E in LDS (Es[c n + q]: a slot's KC reads fall on banks spread
+// by its row q), then each wave walks slices and gathers E[q, k0 .. k0 + KC)
+// for every slot (p, q).  The slot stream (16-bit column, FP64 value) is
+// re-read once per workgroup from L2, which bounds the kernel; 16 waves per
+// workgroup keep enough of those loads in flight.  Sums run in slot order.
+constexpr int YE_THREADS = 1024;
+template <int KC>
+__global__ __launch_bounds__(YE_THREADS) void sampled_ye_kernel(int n, int nsl, const int* __restrict__ sptr,
+                                                                const int* __restrict__ srow,
+                                                                const uint16_t* __restrict__ ecol,
+                                                                const double* __restrict__ val,
+                                                                const double* __restrict__ E, long lde,
+                                                                double* __restrict__ Z, long ldz) {
+    extern __shared__ double Es[];  // KC x n
+    const int k0 = blockIdx.x * KC;
+    const int kc = min(KC, n - k0);
+#pragma unroll
+    for (int c = 0; c < KC; ++c)
+        for (int q = threadIdx.x; q < n; q += YE_THREADS)
+            Es[c * n + q] = (c < kc) ? E[q + (long)(k0 + c) * lde] : 0.0;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int s = wave; s < nsl; s += YE_THREADS / 64) {
+        const int e0 = sptr[s] + lane;
+        const int len = (sptr[s + 1] - sptr[s]) >> 6;
+        double acc[KC];
+#pragma unroll
+        for (int c = 0; c < KC; ++c) acc[c] = 0.0;
+        int t = 0;
+        for (; t + 4 <= len; t += 4) {
+            int q[4];
+            double w[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                q[h] = ecol[e0 + 64 * (t + h)];
+                w[h] = val[e0 + 64 * (t + h)];
+            }
+#pragma unroll
+            for (int h = 0; h < 4; ++h)
+#pragma unroll
+                for (int c = 0; c < KC; ++c) acc[c] += w[h] * Es[c * n + q[h]];
+        }
+        for (; t < len; ++t) {
+            const int q = ecol[e0 + 64 * t];
+            const double w = val[e0 + 64 * t];
+#pragma unroll
+            for (int c = 0; c < KC; ++c) acc[c] += w * Es[c * n + q];
+        }
+        const int p = srow[s * 64 + lane];
+        if (p >= 0) {
+#pragma unroll
+            for (int c = 0; c < KC; ++c)
+                if (c < kc) Z[p + (long)(k0 + c) * ldz] = acc[c];
+        }
+    }
+}
+constexpr long YE_LDS = 128 * 1024;  // bytes of LDS the staged columns may take
+int sampled_ye_columns(int n) {
+    for (int kc = 8; kc >= 1; kc >>= 1)
+        if ((long)kc * n * 8 <= YE_LDS) return kc;
+    return 0;
+}
+void sampled_ye(hipStream_t st, int n, int nsl, const int* sptr, const int* srow, const uint16_t* ecol,
+                const double* val, const double* E, long lde, double* Z, long ldz) {
+    const int kc = sampled_ye_columns(n);
+    require(kc > 0, "the sampled E Y E form needs n <= 16384");
+    const dim3 grid(cdiv(n, kc)), block(YE_THREADS);
+    const size_t lds = sizeof(double) * kc * n;
+    switch (kc) {
+        case 8:
+            hipLaunchKernelGGL(sampled_ye_kernel<8>, grid, block, lds, st, n, nsl, sptr, srow, ecol, val, E, lde, Z, ldz);
+            break;
+        case 4:
+            hipLaunchKernelGGL(sampled_ye_kernel<4>, grid, block, lds, st, n, nsl, sptr, srow, ecol, val, E, lde, Z, ldz);
+            break;
+        case 2:
+            hipLaunchKernelGGL(sampled_ye_kernel<2>, grid, block, lds, st, n, nsl, sptr, srow, ecol, val, E, lde, Z, ldz);
+            break;
+        default:
+            hipLaunchKernelGGL(sampled_ye_kernel<1>, grid, block, lds, st, n, nsl, sptr, srow, ecol, val, E, lde, Z, ldz);
+            break;
+    }
+    WC_LAUNCH_CHECK();
+}
+
+// out_i = E[:, j] . Z[:, k] for every constraint i = (j, k), j <= k, grouped
+// by j (dptr, dpart = k, didx = i): the workgroup of row j stages E[:, j] in
+// LDS and each wave takes one constraint at a time, reading Z[:, k]
+// coalesced with eight loads in flight per lane, then reducing across the
+// wave (fixed order).
+constexpr int DOT_U = 8;
+__global__ __launch_bounds__(256) void sampled_dots_kernel(int n, const int* __restrict__ dptr,
+                                                           const int* __restrict__ dpart,
+                                                           const int* __restrict__ didx,
+                                                           const double* __restrict__ E, long lde,
+                                                           const double* __restrict__ Z, long ldz,
+                                                           double* __restrict__ out) {
+    extern __shared__ double ej[];  // n
+    const int j = blockIdx.x;
+    const int g0 = dptr[j], g1 = dptr[j + 1];
+    if (g0 == g1) return;  // the whole workgroup leaves together
+    for (int q = threadIdx.x; q < n; q += 256) ej[q] = E[q + (long)j * lde];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int g = g0 + wave; g < g1; g += 4) {
+        const double* zk = Z + (long)dpart[g] * ldz;
+        double s[DOT_U];
+#pragma unroll
+        for (int h = 0; h < DOT_U; ++h) s[h] = 0.0;
+        int q = lane;
+        for (; q + 64 * (DOT_U - 1) < n; q += 64 * DOT_U) {
+            double z[DOT_U];
+#pragma unroll
+            for (int h = 0; h < DOT_U; ++h) z[h] = zk[q + 64 * h];
+#pragma unroll
+            for (int h = 0; h < DOT_U; ++h) s[h] += ej[q + 64 * h] * z[h];
+        }
+        double v = 0.0;
+        for (; q < n; q += 64) v += ej[q] * zk[q];  // at most DOT_U - 1 more
+#pragma unroll
+        for (int h = 0; h < DOT_U; ++h) v += s[h];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) out[didx[g]] = v;
+    }
+}
+void sampled_dots(hipStream_t st, int n, const int* dptr, const int* dpart, const int* didx, const double* E, long lde,
+                  const double* Z, long ldz, double* out) {
+    hipLaunchKernelGGL(sampled_dots_kernel, dim3(n), dim3(256), sizeof(double) * n, st, n, dptr, dpart, didx, E, lde,
+                       Z, ldz, out);
+    WC_LAUNCH_CHECK();
+}
+
 // Coordinate of entry (a, b) of H (a >= b when a < r) in v = [svec(B); vec(N)],
 // and its weight: 1 on the diagonal of B, sqrt2 elsewhere.
 __device__ inline int h_coord(int n, int r, int a, int b, double& w) {

@@ -35,6 +35,15 @@ void entry_yq(hipStream_t st, int n, int r, const int* rptr, const int* rcol, co
               const double* Q, long ldq, double* YQ);
 void entry_gram_block(hipStream_t st, int n, int b, int b2, const int* rptr, const int* rcol, const double* Q, long ldq,
                       double* B, long ldb);
+// Sampled A(E Y E) for entry sampling: slot values of the sliced pattern,
+// Z = Y E (KC columns of E staged in LDS per workgroup), and one dot product
+// per constraint.
+void sliced_values(hipStream_t st, long slots, const int* eidx, const double* u, double* val);
+int sampled_ye_columns(int n);
+void sampled_ye(hipStream_t st, int n, int nsl, const int* sptr, const int* srow, const uint16_t* ecol,
+                const double* val, const double* E, long lde, double* Z, long ldz);
+void sampled_dots(hipStream_t st, int n, const int* dptr, const int* dpart, const int* didx, const double* E, long lde,
+                  const double* Z, long ldz, double* out);
 void c_assemble(hipStream_t st, int n, int r, int b, int b2, const double* Z, long ldz, const double* sig, double t2,
                 double ib, double* C, long ldc);
 void add_diag_vec(hipStream_t st, int d, double* A, long lda, const double* sig, double t2);

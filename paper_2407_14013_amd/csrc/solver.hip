@@ -249,6 +249,7 @@ void setup(sdp_ctx* c, const sdp_problem* p, const sdp_options* o, hipStream_t s
     if (o) c->opt = *o;
     else sdp_default_options(&c->opt);
     c->lowp = c->opt.inner_prec != SDP_PREC_F64;
+    c->sampled = c->opt.sparse_sandwich != 0 && p->a_kind == SDP_A_ENTRY;
     c->lp = c->opt.inner_prec == SDP_PREC_BF16 ? Lp::BF16 : Lp::F32;
     c->rmax = std::max(1, std::min(c->opt.rank_max, n - 1));
     if (c->opt.rank_fixed > 0) c->rmax = std::max(c->rmax, std::min(c->opt.rank_fixed, n - 1));
@@ -324,6 +325,70 @@ void setup(sdp_ctx* c, const sdp_problem* p, const sdp_options* o, hipStream_t s
         WC_HIP(hipMemcpyAsync(c->rcol.get(), col.data(), sizeof(int) * nnz, hipMemcpyHostToDevice, st));
         WC_HIP(hipMemcpyAsync(c->ridx.get(), idx.data(), sizeof(int) * nnz, hipMemcpyHostToDevice, st));
         WC_HIP(hipStreamSynchronize(st));
+        if (c->sampled) {
+            // the same pattern with its rows ordered by length (longest first)
+            // in slices of 64 rows, each slice padded to its longest row
+            // (slot = base + 64 t + lane); eidx holds i off the diagonal,
+            // -2 - i on it and -1 in pads
+            require(n <= 16384, "sparse_sandwich needs n <= 16384");  // 16-bit columns, LDS staging
+            c->nsl = cdiv(n, 64);
+            std::vector<int> order(n);
+            for (int p = 0; p < n; ++p) order[p] = p;
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int a, int b) { return cnt[a + 1] - cnt[a] > cnt[b + 1] - cnt[b]; });
+            std::vector<int> srow(64L * c->nsl, -1);
+            std::vector<long> sp(c->nsl + 1, 0);
+            for (int s = 0; s < c->nsl; ++s) {
+                int len = 0;
+                for (int l = 0; l < 64 && 64 * s + l < n; ++l) {
+                    const int p = order[64 * s + l];
+                    srow[64 * s + l] = p;
+                    len = std::max(len, cnt[p + 1] - cnt[p]);
+                }
+                sp[s + 1] = sp[s] + 64L * len;
+            }
+            require(sp[c->nsl] < (1L << 31), "the sliced pattern of the sampled E Y E form is too large");
+            const long slots = std::max(1L, sp[c->nsl]);
+            std::vector<int> sptr(sp.begin(), sp.end()), eidx(slots, -1);
+            std::vector<uint16_t> ecol(slots, 0);
+            for (int s = 0; s < c->nsl; ++s) {
+                const long len = (sp[s + 1] - sp[s]) / 64;
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int p = srow[64 * s + lane];
+                    for (long t = 0; p >= 0 && t < std::min<long>(len, cnt[p + 1] - cnt[p]); ++t) {
+                        const long e = sp[s] + 64 * t + lane;
+                        ecol[e] = static_cast<uint16_t>(col[cnt[p] + t]);
+                        eidx[e] = col[cnt[p] + t] == p ? -2 - idx[cnt[p] + t] : idx[cnt[p] + t];
+                    }
+                }
+            }
+            // constraints grouped by their smaller index j (partner k >= j)
+            std::vector<int> dp(n + 1, 0), dk(std::max(1, m)), di(std::max(1, m));
+            for (int i = 0; i < m; ++i) ++dp[hjk[2 * i] + 1];
+            for (int j = 0; j < n; ++j) dp[j + 1] += dp[j];
+            std::vector<int> at(dp.begin(), dp.end() - 1);
+            for (int i = 0; i < m; ++i) {
+                const int g = at[hjk[2 * i]]++;
+                dk[g] = hjk[2 * i + 1];
+                di[g] = i;
+            }
+            c->sptr.alloc(c->nsl + 1);
+            c->srow.alloc(srow.size());
+            c->ecol.alloc(slots);
+            c->eidx.alloc(slots);
+            c->sval.alloc(slots);
+            c->dptr.alloc(n + 1);
+            c->dpart.alloc(dk.size());
+            c->didx.alloc(di.size());
+            WC_HIP(hipMemcpyAsync(c->sptr.get(), sptr.data(), sizeof(int) * (c->nsl + 1), hipMemcpyHostToDevice, st));
+            WC_HIP(hipMemcpyAsync(c->srow.get(), srow.data(), sizeof(int) * srow.size(), hipMemcpyHostToDevice, st));
+            WC_HIP(hipMemcpyAsync(c->ecol.get(), ecol.data(), sizeof(uint16_t) * slots, hipMemcpyHostToDevice, st));
+            WC_HIP(hipMemcpyAsync(c->eidx.get(), eidx.data(), sizeof(int) * slots, hipMemcpyHostToDevice, st));
+            WC_HIP(hipMemcpyAsync(c->dptr.get(), dp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, st));
+            WC_HIP(hipMemcpyAsync(c->dpart.get(), dk.data(), sizeof(int) * dk.size(), hipMemcpyHostToDevice, st));
+            WC_HIP(hipMemcpyAsync(c->didx.get(), di.data(), sizeof(int) * di.size(), hipMemcpyHostToDevice, st));
+            WC_HIP(hipStreamSynchronize(st));
+        }
     }
     std::vector<double> hb(m), hC(nn);
     WC_HIP(hipMemcpyAsync(hb.data(), c->b.get(), sizeof(double) * m, hipMemcpyDeviceToHost, st));
@@ -510,6 +575,29 @@ void newton_apply(sdp_ctx* c, const double* in, double* out) {
     prof_begin(c, SDP_K_NEWTON, &e);
     const double* u = in;
     const double* v = in + m;
+    if (c->sampled) {
+        // top = A(E Y E) at the sampled pairs: Z = Y E from the sliced
+        // pattern, then one dot product per constraint
+        hipEvent_t es;
+        const double slots = static_cast<double>(c->sval.n);
+        sliced_values(st, static_cast<long>(c->sval.n), c->eidx, u, c->sval);
+        prof_begin(c, SDP_K_SAMPLED_YE, &es);
+        sampled_ye(st, n, c->nsl, c->sptr, c->srow, c->ecol, c->sval, c->E, n, c->T1, n);
+        prof_end(c, SDP_K_SAMPLED_YE, es, 16.0 * nn + 10.0 * slots);
+        prof_begin(c, SDP_K_SAMPLED_DOTS, &es);
+        sampled_dots(st, n, c->dptr, c->dpart, c->didx, c->E, n, c->T1, n, out);
+        prof_end(c, SDP_K_SAMPLED_DOTS, es, 8.0 * m * (double)n + 8.0 * nn + 16.0 * m);
+        // top += script-A script-Q v;  bottom = (script-A script-Q)^T u - tau^2 Sigma v
+        v_to_h(st, n, r, v, c->Hm);
+        gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
+        aq_entry_apply(st, m, n, r, c->jk, c->U, c->Gw, n, out, 1.0, 1.0);
+        entry_yq(st, n, r, c->rptr, c->rcol, c->ridx, u, c->Gw, n, c->YQ);
+        gemm(c, true, false, n, r, n, 1.0, c->Gw, n, c->YQ, n, 0.0, c->F, n);
+        f_to_v(st, n, r, c->F, n, v, c->sig, c->tau * c->tau, out + m);
+        prof_end(c, SDP_K_NEWTON, e, 0.0);
+        c->matvecs += 1;
+        return;
+    }
     // Y = A^T(u)
     at_apply(c, u, c->Y);
     // U = [Q Qp][B; sqrt2 N];  Mm = sym(U Q^T) + E Y E

@@ -22,6 +22,13 @@ struct sdp_ctx {
     wc::DevBuf<int> pj, pk;     // packed index -> (j, k)
     wc::DevBuf<int> jk;         // entry: 2 m pairs
     wc::DevBuf<int> rptr, rcol, ridx;  // entry: symmetric pattern in CSR form (row j: partner, constraint)
+    bool sampled = false;       // entry: A(E Y E) formed at the sampled pairs only (sparse_sandwich)
+    int nsl = 0;                // slices of 64 rows of the sliced pattern
+    wc::DevBuf<int> sptr, srow, eidx;  // sliced pattern: slice start slot, row of each lane, constraint
+                                       // (i off the diagonal, -2 - i on it, -1 in pads)
+    wc::DevBuf<uint16_t> ecol;         // sliced pattern: column of each slot
+    wc::DevBuf<int> dptr, dpart, didx; // constraints grouped by their smaller index j: partner k, constraint
+    wc::DevBuf<double> sval;    // slot values of Y = A^T(u) in the sliced pattern
     wc::DevBuf<double> b, C;    // m, n x n
     double bnorm = 0, Cnorm = 0, mean_a2 = 0, xi = 1, eta = 1;
 

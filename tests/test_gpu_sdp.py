@@ -122,6 +122,72 @@ def test_newton_apply_config1_matches_oracle():
     assert err <= 1e-10
 
 
+def skewed_entry():
+    """Matrix completion with row 0 fully observed: one row far longer than the
+    rest, so the first 64-row slice of the sliced pattern is mostly padding."""
+    p = workloads.matrix_completion(130, 2, 1500, seed=8)
+    n, U = p["n"], p["U"]
+    pairs = {(int(j), int(k)) for j, k in p["jk"]} | {(0, k) for k in range(n)}
+    jk = np.array(sorted(pairs), dtype=np.int32)
+    p = dict(p, jk=jk, m=len(jk), b=np.einsum("ir,ir->i", U[jk[:, 0]], U[jk[:, 1]]))
+    return p
+
+
+@pytest.mark.parametrize("which", ["entry", "entry150", "skewed"])
+def test_newton_apply_sparse_sandwich_matches_oracle(which):
+    # sparse_sandwich forms A(E Y E) at the sampled pairs (Z = Y E from the
+    # sliced pattern, one dot product per constraint): the same operator as
+    # the dense products up to rounding, so the same 1e-10 bound against the
+    # oracle, and 1e-12 against the dense form in the same eigenbasis.
+    # "entry150" spans three slices (the last ragged) and 19 workgroups of Z
+    # columns (the last with 6 of 8); "skewed" pads one slice heavily.
+    if which == "entry":
+        p = small_entry()
+    elif which == "entry150":
+        p = workloads.matrix_completion(150, 3, 1800, seed=6)
+    else:
+        p = skewed_entry()
+    m = p["m"]
+    rng = np.random.default_rng(17)
+    for name, X, y, S in points(p):
+        sp = oracle_split(X, S)
+        E = rf.e_matrix(sp)
+        sig = rf.sigma_diag(sp)
+        xs = [rng.standard_normal(m + rf.dim_d(p["n"], sp["r"])) for _ in range(3)]
+        xs[1][m:] = 0.0
+        xs[2][:m] = 0.0
+        outs = {}
+        for sparse in (0, 1):
+            with Context(p, sparse_sandwich=sparse) as ctx:
+                ctx.set_point(dev(X), dev(y), dev(S))
+                assert ctx.aug_dim() == len(xs[0])
+                outs[sparse] = [host(ctx.newton_apply(dev(x))) for x in xs]
+        for trial, x in enumerate(xs):
+            t, b = rf.aug_apply(p, sp, E, sig, x[:m], x[m:])
+            ref = np.concatenate([t, b])
+            scale = np.abs(ref).max()
+            err = np.abs(outs[1][trial] - ref).max() / scale
+            diff = np.abs(outs[1][trial] - outs[0][trial]).max() / scale
+            print(f"{which} {name} trial {trial}: vs oracle {err:.1e}, vs dense form {diff:.1e}")
+            assert err <= 1e-10 and diff <= 1e-12, (name, trial)
+
+
+def test_solve_sparse_sandwich_matches_oracle():
+    p = small_entry()
+    ref = ipm.solve(p)
+    with Context(p, sparse_sandwich=1) as ctx:
+        res = ctx.solve()
+        X, y, S = ctx.get_point()
+    check_solution(p, res, X, y, S, ref["history"][-1]["pobj"])
+
+
+def test_sparse_sandwich_rejects_unsupported_options():
+    with pytest.raises(SdpError):
+        Context(workloads.config(0), sparse_sandwich=1)
+    with pytest.raises(SdpError):
+        Context(small_entry(), sparse_sandwich=1, inner_prec=L.SDP_PREC_F32)
+
+
 @pytest.mark.parametrize("which", ["cfg0", "entry", "entry150"])
 def test_precond_apply_matches_oracle(which):
     # Section 6: z = P^{-1} x with P = [beta I, AQ; AQ^T, -tau^2 Sigma], the
