@@ -442,7 +442,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every instance of this workload fits one MI355X, "
-              "and multi-GPU runs are not part of this build", file=sys.stderr)
+              "and the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.pmc_pass:
         pmc_pass()
