@@ -13,6 +13,9 @@ eigensolver at this size:
 * the preconditioner of Section 6 (never formed as AQ on the GPU for this
   constraint kind) by the residual of P z = x, with P z computed as
   K z - [A(E A^T(z_u) E) - beta z_u; 0] from the GPU's K and the closed-form E.
+
+Each check runs for both forms of A(E Y E) in the operator: the dense
+products and the sampled form (option sparse_sandwich).
 """
 import numpy as np
 import pytest
@@ -38,8 +41,10 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.fixture(scope="module")
-def full():
+@pytest.fixture(scope="module", params=[0, 1], ids=["dense_products", "sampled"])
+def full(request):
+    # both forms of A(E Y E): the two n x n x n products, and the sampled
+    # form (sparse_sandwich: Z = Y E from the pattern, one dot per constraint)
     p = workloads.config(2)
     n = p["n"]
     X, S, V, x, s = workloads.centred_pair(n, R, MU, seed=21)
@@ -51,7 +56,7 @@ def full():
           "lam_top": lam[:R], "lam_perp": lam[R:]}
     e = rf.e_eigenvalues(sp)
     jk = p["jk"]
-    ctx = Context(p)
+    ctx = Context(p, sparse_sandwich=request.param)
     ctx.set_point(dev(X), dev(np.zeros(p["m"])), dev(S))
     yield p, sp, e, jk, ctx
     ctx.close()

@@ -232,7 +232,7 @@ def test_precond_apply_matches_oracle(which):
                 assert bwd <= bound and err <= 1e-8, (name, trial)
 
 
-@pytest.mark.parametrize("which", ["cfg0", "entry"])
+@pytest.mark.parametrize("which", ["cfg0", "entry", "entry_sampled"])
 @pytest.mark.parametrize("iters", [2, 6])
 def test_inner_solve_matches_direct(which, iters):
     # eq. Newt-eps at an oracle iterate.  Its two equations are checked by
@@ -241,6 +241,7 @@ def test_inner_solve_matches_direct(which, iters):
     # residual), and dX = W (A^T(dy) - C~) W to rounding.  Element-wise
     # agreement with the direct Schur solve is required where the KKT matrix
     # is still well conditioned (the first iterations).
+    # "entry_sampled": the entry instance with A(E Y E) in the sampled form
     p = workloads.config(0) if which == "cfg0" else small_entry()
     res = ipm.solve(p, maxit=iters)
     X, y, S = res["X"], res["y"], res["S"]
@@ -250,7 +251,7 @@ def test_inner_solve_matches_direct(which, iters):
     G, d, Lf = nt.nt_factor(X, S)
     W = G @ G.T
     dX0, dy0, _ = ipm.newton_direct(p, G, ipm.schur_factor(p, G, W), bt, Ct, r["Rd"])
-    with Context(p) as ctx:
+    with Context(p, sparse_sandwich=int(which == "entry_sampled")) as ctx:
         ctx.set_point(dev(X), dev(y), dev(S))
         dX, dy, st = ctx.inner_solve(dev(bt), dev(Ct))
     dX, dy = host(dX), host(dy)
@@ -364,7 +365,7 @@ def test_ipm_step_matches_oracle_step(which):
             assert e <= 1e-6, (k, key, st[key], hist[k][key])
 
 
-@pytest.mark.parametrize("which", ["cfg0", "entry"])
+@pytest.mark.parametrize("which", ["cfg0", "entry", "entry_sampled"])
 @pytest.mark.parametrize("iters", [2, 6])
 def test_inner_solve_minres(which, iters):
     # Corollary minres: MINRES (identity preconditioner, zero start) on eq.
@@ -380,7 +381,8 @@ def test_inner_solve_minres(which, iters):
     bt = r["rp"]
     G, d, Lf = nt.nt_factor(X, S)
     W = G @ G.T
-    with Context(p, solver=L.SDP_SOLVER_MINRES, inner_tol=1e-13) as ctx:
+    with Context(p, solver=L.SDP_SOLVER_MINRES, inner_tol=1e-13,
+                 sparse_sandwich=int(which == "entry_sampled")) as ctx:
         ctx.set_point(dev(X), dev(y), dev(S))
         dX, dy, st = ctx.inner_solve(dev(bt), dev(Ct))
     dX, dy = host(dX), host(dy)
