@@ -157,8 +157,17 @@ __global__ void dgemm_reduce_kernel(int M, int N, int splits, const double* __re
     const long t = blockIdx.x * 256L + threadIdx.x;
     if (t >= (long)M * N) return;
     const int i = static_cast<int>(t % M), j = static_cast<int>(t / M);
+    // fixed split order; the loads of a batch are issued before their sums
     double v = 0.0;
-    for (int sp = 0; sp < splits; ++sp) v += P[(long)sp * M * N + t];
+    int sp = 0;
+    for (; sp + 4 <= splits; sp += 4) {
+        double x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = P[(long)(sp + u) * M * N + t];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v += x[u];
+    }
+    for (; sp < splits; ++sp) v += P[(long)sp * M * N + t];
     double* c = C + i + (long)j * ldc;
     *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
 }
@@ -392,8 +401,17 @@ __global__ void thin_reduce_kernel(int M, int N, int splits, const double* __res
     const long t = blockIdx.x * 256L + threadIdx.x;
     if (t >= (long)M * N) return;
     const int i = static_cast<int>(t % M), j = static_cast<int>(t / M);
+    // fixed split order; the loads of a batch are issued before their sums
     double v = 0.0;
-    for (int sp = 0; sp < splits; ++sp) v += part[((long)sp * N + j) * M + i];
+    int sp = 0;
+    for (; sp + 8 <= splits; sp += 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = part[((long)(sp + u) * N + j) * M + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += x[u];
+    }
+    for (; sp < splits; ++sp) v += part[((long)sp * N + j) * M + i];
     double* c = C + i + (long)j * ldc;
     *c = (beta == 0.0) ? alpha * v : alpha * v + beta * (*c);
 }
@@ -610,12 +628,45 @@ __global__ __launch_bounds__(256) void symv_reduce_kernel(int d, const double* _
     __shared__ double part[4][SY_T];
     const int I = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nb = (d + SY_T - 1) / SY_T;
+    // s0 takes the blocks wave, wave + 8, ... and s1 those 4 further on, in
+    // that order; four steps' loads are issued before their sums
     double s0 = 0.0, s1 = 0.0;
-    for (int Cb = wave; Cb <= I; Cb += 8) {
-        s0 += prow[((long)I * (I + 1) / 2 + Cb) * SY_T + lane];
-        if (Cb + 4 <= I) s1 += prow[((long)I * (I + 1) / 2 + Cb + 4) * SY_T + lane];
+    const long rb = (long)I * (I + 1) / 2;
+    int Cb = wave;
+    for (; Cb + 24 <= I; Cb += 32) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = Cb + 8 * u;
+            a[u] = prow[(rb + c) * SY_T + lane];
+            b[u] = (c + 4 <= I) ? prow[(rb + c + 4) * SY_T + lane] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            s0 += a[u];
+            if (Cb + 8 * u + 4 <= I) s1 += b[u];
+        }
     }
-    for (int Rb = I + wave; Rb < nb; Rb += 8) {
+    for (; Cb <= I; Cb += 8) {
+        s0 += prow[(rb + Cb) * SY_T + lane];
+        if (Cb + 4 <= I) s1 += prow[(rb + Cb + 4) * SY_T + lane];
+    }
+    int Rb = I + wave;
+    for (; Rb + 24 < nb; Rb += 32) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long r = Rb + 8 * u;
+            a[u] = pcol[(r * (r + 1) / 2 + I) * SY_T + lane];
+            b[u] = (r + 4 < nb) ? pcol[((r + 4) * (r + 5) / 2 + I) * SY_T + lane] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            s0 += a[u];
+            if (Rb + 8 * u + 4 < nb) s1 += b[u];
+        }
+    }
+    for (; Rb < nb; Rb += 8) {
         s0 += pcol[((long)Rb * (Rb + 1) / 2 + I) * SY_T + lane];
         if (Rb + 4 < nb) s1 += pcol[((long)(Rb + 4) * (Rb + 5) / 2 + I) * SY_T + lane];
     }
@@ -683,8 +734,17 @@ __global__ __launch_bounds__(256) void gemv_cols_reduce(int k, int nparts, const
                                                         double beta) {
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c >= k) return;
+    // fixed part order; the loads of a batch are issued before their sums
     double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += part[p * pstride + c];
+    int p = 0;
+    for (; p + 8 <= nparts; p += 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = part[(p + u) * pstride + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += x[u];
+    }
+    for (; p < nparts; ++p) s += part[p * pstride + c];
     double v = alpha * s;
     y[c] = (beta == 0.0) ? v : v + beta * y[c];
 }

@@ -185,10 +185,31 @@ __global__ __launch_bounds__(256) void jacobi_pair_kernel(int nchunks, const dou
     const int w = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double* src = part + (long)w * nchunks * (JW * JW);
-    for (int t = tid; t < JW * JW; t += 256) {
-        double sum = 0.0;
-        for (int ch = 0; ch < nchunks; ++ch) sum += src[(long)ch * (JW * JW) + t];
-        H[t / JW][t % JW] = sum;
+    // the partial Gram matrices summed in chunk order; each thread owns four
+    // entries and keeps PB chunks of loads in flight (a plain loop waits for
+    // every load before the next)
+    {
+        constexpr int PB = 8, NQ = JW * JW / 256;
+        double sum[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sum[q] = 0.0;
+        int ch = 0;
+        for (; ch + PB <= nchunks; ch += PB) {
+            double v[PB][NQ];
+#pragma unroll
+            for (int u = 0; u < PB; ++u)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) v[u][q] = src[(long)(ch + u) * (JW * JW) + tid + 256 * q];
+#pragma unroll
+            for (int u = 0; u < PB; ++u)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) sum[q] += v[u][q];
+        }
+        for (; ch < nchunks; ++ch)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) sum[q] += src[(long)ch * (JW * JW) + tid + 256 * q];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) H[(tid + 256 * q) / JW][(tid + 256 * q) % JW] = sum[q];
     }
     __syncthreads();
     double mx = 0.0;

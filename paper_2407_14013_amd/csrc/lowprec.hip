@@ -580,8 +580,17 @@ __global__ void at_reduce_unpack_lp_kernel(long N2, int nparts, const double* __
                                            double* __restrict__ Y, long ldy, void* __restrict__ Ylp) {
     const long p = blockIdx.x * 256L + threadIdx.x;
     if (p >= N2) return;
+    // fixed part order; the loads of a batch are issued before their sums
     double s = 0.0;
-    for (int q = 0; q < nparts; ++q) s += part[q * pstride + p];
+    int q = 0;
+    for (; q + 8 <= nparts; q += 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = part[(q + u) * pstride + p];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += x[u];
+    }
+    for (; q < nparts; ++q) s += part[q * pstride + p];
     const int j = pj[p], k = pk[p];
     const long o1 = j + (long)k * ldy, o2 = k + (long)j * ldy;
     if (Y) {

@@ -152,8 +152,17 @@ __global__ void at_reduce_unpack_kernel(long N2, int nparts, const double* __res
                                         double* __restrict__ Y, long ldy) {
     long p = blockIdx.x * 256L + threadIdx.x;
     if (p >= N2) return;
+    // fixed part order; the loads of a batch are issued before their sums
     double s = 0.0;
-    for (int q = 0; q < nparts; ++q) s += part[q * pstride + p];
+    int q = 0;
+    for (; q + 8 <= nparts; q += 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = part[(q + u) * pstride + p];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += x[u];
+    }
+    for (; q < nparts; ++q) s += part[q * pstride + p];
     int j = pj[p], k = pk[p];
     Y[j + (long)k * ldy] = s;
     Y[k + (long)j * ldy] = s;
