@@ -268,7 +268,18 @@ __global__ __launch_bounds__(256) void dgemm_thin_n_kernel(int M, int N, int K, 
                                                            double* __restrict__ C, long ldc) {
     extern __shared__ double Bs[];
     __shared__ double part[4][NM][64];
-    for (int t = threadIdx.x; t < K * N; t += 256) Bs[t] = B[(t % K) + (long)(t / K) * ldb];
+    {  // four loads per thread in flight before their LDS stores
+        const int tot = K * N;
+        int t = threadIdx.x;
+        for (; t + 768 < tot; t += 1024) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = B[((t + 256 * u) % K) + (long)((t + 256 * u) / K) * ldb];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) Bs[t + 256 * u] = v[u];
+        }
+        for (; t < tot; t += 256) Bs[t] = B[(t % K) + (long)(t / K) * ldb];
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = blockIdx.x * 64 + lane;
@@ -367,7 +378,18 @@ __global__ __launch_bounds__(256) void dgemm_thin_splitk_kernel(int M, int N, in
     __shared__ double red[4][NM][64];
     const int ks0 = blockIdx.y * kc, ks1 = min(K, ks0 + kc);
     const int len = ks1 - ks0;
-    for (int t = threadIdx.x; t < len * N; t += 256) Bs[t] = B[ks0 + (t % len) + (long)(t / len) * ldb];
+    {  // four loads per thread in flight before their LDS stores
+        const int tot = len * N;
+        int t = threadIdx.x;
+        for (; t + 768 < tot; t += 1024) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = B[ks0 + ((t + 256 * u) % len) + (long)((t + 256 * u) / len) * ldb];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) Bs[t + 256 * u] = v[u];
+        }
+        for (; t < tot; t += 256) Bs[t] = B[ks0 + (t % len) + (long)(t / len) * ldb];
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = blockIdx.x * 64 + lane;
@@ -488,41 +510,49 @@ __device__ inline double block_sum(double v, double* sh) {
 }
 
 // ---------------------------------------------------------------------------
-// gemv_rows: y = alpha A x + beta y, A row-major.  ROWS rows per 256-thread
-// workgroup share every load of x; each thread streams 16-byte pairs.
+// gemv_rows: y = alpha A x + beta y, A row-major (rows 16-byte aligned).
+// One wave per row, GV_ROWS rows per 256-thread workgroup; each lane streams
+// 16-byte pairs of its row.
 // ---------------------------------------------------------------------------
 constexpr int GV_ROWS = 4;
 
 __global__ __launch_bounds__(256) void gemv_rows_kernel(int m, int k2, const double* __restrict__ A, long lda,
                                                         const double* __restrict__ x, double* __restrict__ y,
                                                         double alpha, double beta) {
-    __shared__ double sh[8];
-    const int row0 = blockIdx.x * GV_ROWS;
-    double acc[GV_ROWS];
-#pragma unroll
-    for (int r = 0; r < GV_ROWS; ++r) acc[r] = 0.0;
+    // one wave per row: the lanes stride over its 16-byte column pairs with
+    // four loads in flight, then a shuffle reduction (no barrier)
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * GV_ROWS + (threadIdx.x >> 6);
+    if (row >= m) return;  // whole waves leave
     const d2* x2 = reinterpret_cast<const d2*>(x);
-    const d2* arow[GV_ROWS];
+    const d2* a2 = reinterpret_cast<const d2*>(A + (long)row * lda);
+    double s0 = 0.0, s1 = 0.0;
+    int c = lane;
+    for (; c + 192 < k2; c += 256) {
+        d2 av[4], xv[4];
 #pragma unroll
-    for (int r = 0; r < GV_ROWS; ++r) {
-        int row = row0 + r < m ? row0 + r : m - 1;
-        arow[r] = reinterpret_cast<const d2*>(A + (long)row * lda);
-    }
-    for (int c = threadIdx.x; c < k2; c += 256) {
-        d2 xv = x2[c];
+        for (int u = 0; u < 4; ++u) {
+            av[u] = __builtin_nontemporal_load(&a2[c + 64 * u]);
+            xv[u] = x2[c + 64 * u];
+        }
 #pragma unroll
-        for (int r = 0; r < GV_ROWS; ++r) {
-            d2 av = __builtin_nontemporal_load(&arow[r][c]);
-            acc[r] += av.x * xv.x + av.y * xv.y;
+        for (int u = 0; u < 4; ++u) {
+            const double t = av[u].x * xv[u].x + av[u].y * xv[u].y;
+            if (u & 1) s1 += t;
+            else s0 += t;
         }
     }
+    for (; c < k2; c += 64) {
+        const d2 av = __builtin_nontemporal_load(&a2[c]);
+        const d2 xv = x2[c];
+        s0 += av.x * xv.x + av.y * xv.y;
+    }
+    double s = s0 + s1;
 #pragma unroll
-    for (int r = 0; r < GV_ROWS; ++r) {
-        double s = block_sum<256>(acc[r], sh);
-        if (threadIdx.x == 0 && row0 + r < m) {
-            double v = alpha * s;
-            y[row0 + r] = (beta == 0.0) ? v : v + beta * y[row0 + r];
-        }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+        const double v = alpha * s;
+        y[row] = (beta == 0.0) ? v : v + beta * y[row];
     }
 }
 

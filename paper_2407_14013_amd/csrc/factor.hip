@@ -18,23 +18,31 @@ __global__ __launch_bounds__(256) void potf2_kernel(int nb, double* A, long lda,
     __shared__ int bad;
     const int tid = threadIdx.x;
     if (tid == 0) bad = 0;
-    for (int t = tid; t < PNB * PNB; t += 256) {
-        int i = t % PNB, j = t / PNB;
-        T[i][j] = (i < nb && j < nb && i >= j) ? A[i + (long)j * lda] : 0.0;
+    {  // all of a thread's loads in flight before the LDS stores
+        constexpr int NL = PNB * PNB / 256;
+        double v[NL];
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int t = tid + 256 * u, i = t % PNB, j = t / PNB;
+            v[u] = (i < nb && j < nb && i >= j) ? A[i + (long)j * lda] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NL; ++u) T[(tid + 256 * u) % PNB][(tid + 256 * u) / PNB] = v[u];
     }
     __syncthreads();
     for (int j = 0; j < nb; ++j) {
-        if (tid == 0) {
-            double d = T[j][j];
-            if (!(d > 0.0)) {
-                if (!bad) bad = offset + j + 1;
-                d = 1.0;
-            }
-            T[j][j] = sqrt(d);
+        // every thread takes the pivot's square root itself (one barrier
+        // fewer per column); the diagonal entry is written in the update
+        // phase, which does not read it
+        double d = T[j][j];
+        if (!(d > 0.0)) {
+            if (tid == 0 && !bad) bad = offset + j + 1;
+            d = 1.0;
         }
+        d = sqrt(d);
+        if (tid > j && tid < nb) T[tid][j] /= d;
         __syncthreads();
-        if (tid > j && tid < nb) T[tid][j] /= T[j][j];
-        __syncthreads();
+        if (tid == 0) T[j][j] = d;
         // trailing update of the remaining lower triangle
         for (int t = tid; t < PNB * PNB; t += 256) {
             int i = t % PNB, k = t / PNB;
@@ -53,9 +61,19 @@ __global__ __launch_bounds__(256) void potf2_kernel(int nb, double* A, long lda,
 // replaced by P L11^{-T}.
 __global__ __launch_bounds__(256) void trsm_rows_kernel(int rows, int nb, const double* L11, long lda, double* P) {
     __shared__ double Ls[PNB][PNB + 1];
-    for (int t = threadIdx.x; t < PNB * PNB; t += 256) {
-        int i = t % PNB, j = t / PNB;
-        Ls[i][j] = (i < nb && j < nb) ? L11[i + (long)j * lda] : 0.0;
+    {  // all of a thread's loads in flight before the LDS stores
+        constexpr int NL = PNB * PNB / 256;
+        double v[NL];
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int t = threadIdx.x + 256 * u, i = t % PNB, j = t / PNB;
+            v[u] = (i < nb && j < nb) ? L11[i + (long)j * lda] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int t = threadIdx.x + 256 * u;
+            Ls[t % PNB][t / PNB] = v[u];
+        }
     }
     __syncthreads();
     int r = blockIdx.x * 256 + threadIdx.x;
@@ -103,9 +121,19 @@ void potrf(hipStream_t st, int n, double* A, long lda, int* info) {
 // computes column j of L^{-1} by forward substitution.
 __global__ __launch_bounds__(64) void trtri_leaf_kernel(int nb, const double* L, long ldl, double* X, long ldx) {
     __shared__ double Ls[PNB][PNB + 1];
-    for (int t = threadIdx.x; t < PNB * PNB; t += 64) {
-        int i = t % PNB, j = t / PNB;
-        Ls[i][j] = (i < nb && j < nb && i >= j) ? L[i + (long)j * ldl] : 0.0;
+    {  // all of a thread's loads in flight before the LDS stores
+        constexpr int NL = PNB * PNB / 64;
+        double v[NL];
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int t = threadIdx.x + 64 * u, i = t % PNB, j = t / PNB;
+            v[u] = (i < nb && j < nb && i >= j) ? L[i + (long)j * ldl] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int t = threadIdx.x + 64 * u;
+            Ls[t % PNB][t / PNB] = v[u];
+        }
     }
     __syncthreads();
     int j = threadIdx.x;

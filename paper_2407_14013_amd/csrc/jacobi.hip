@@ -249,7 +249,13 @@ __global__ __launch_bounds__(256) void jacobi_rotate_kernel(int n, int nblk, int
     __shared__ int cols[JW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     pair_cols(round, w, nblk, n, cols);
-    for (int t = tid; t < JW * JW; t += 256) R[t / JW][t % JW] = Rin[(long)w * (JW * JW) + t];
+    {  // the four loads of a thread in flight before the LDS stores
+        double v[JW * JW / 256];
+#pragma unroll
+        for (int u = 0; u < JW * JW / 256; ++u) v[u] = Rin[(long)w * (JW * JW) + tid + 256 * u];
+#pragma unroll
+        for (int u = 0; u < JW * JW / 256; ++u) R[(tid + 256 * u) / JW][(tid + 256 * u) % JW] = v[u];
+    }
     __syncthreads();
     const int r0 = chunk * JCH;
     load_chunk(M, ldm, n, r0, cols, P);
