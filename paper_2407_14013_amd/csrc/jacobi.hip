@@ -324,26 +324,29 @@ __global__ __launch_bounds__(256) void jacobi_round_lds_kernel(int n, int nblk, 
         cols[tid] = (c < n) ? c : -1;
     }
     __syncthreads();
-    // ---- load both column blocks: thread `row` holds 16 loads in flight ------
-    // (nr <= 256 whenever this kernel is selected, so one row per thread)
+    // ---- load both column blocks of A and of V: thread `row` holds all its
+    // loads in flight at once (nr <= 256 whenever this kernel is selected,
+    // so one row per thread)
     if (tid < nr) {
         const int row = tid;
-        for (int pass = 0; pass < 2; ++pass) {
-            const double* M = pass == 0 ? A : V;
-            double* Mb = pass == 0 ? Ab : Vb;
-            const long ldm = pass == 0 ? lda : ldv;
-            if (M == nullptr) break;
+        double ta[JW], tv[JW];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                double t[16];
+        for (int u = 0; u < JW; ++u) {
+            const int gc = cols[u];
+            ta[u] = (gc >= 0 && row < n) ? A[row + (long)gc * lda] : 0.0;
+        }
+        if (V) {
 #pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    const int gc = cols[h * 16 + u];
-                    t[u] = (gc >= 0 && row < n) ? M[row + (long)gc * ldm] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 16; ++u) Mb[(h * 16 + u) * ldb + row] = t[u];
+            for (int u = 0; u < JW; ++u) {
+                const int gc = cols[u];
+                tv[u] = (gc >= 0 && row < n) ? V[row + (long)gc * ldv] : 0.0;
             }
+        }
+#pragma unroll
+        for (int u = 0; u < JW; ++u) Ab[u * ldb + row] = ta[u];
+        if (V) {
+#pragma unroll
+            for (int u = 0; u < JW; ++u) Vb[u * ldb + row] = tv[u];
         }
     }
     __syncthreads();
