@@ -243,7 +243,7 @@ def bench_completion(args):
     stream (kernel class SDP_K_SANDWICH): 2 n^3 flops per launch.  With
     --solve, the full solves to the 1e-8 tolerances are timed as well
     (minutes): FP64 with the sampled A(E Y E) form, FP64 with the dense
-    products, and FP32-mixed.  The sampled form (sparse_sandwich) is timed
+    products, FP32-mixed and BF16-mixed.  The sampled form (sparse_sandwich) is timed
     per kernel class too: Z = Y E and the per-constraint dot products.
     """
     import torch
@@ -374,7 +374,7 @@ def bench_completion(args):
         solves = {}
         wanted = args.solve.split(",")
         for name, prec, sparse in (("f64_sampled", L.SDP_PREC_F64, 1), ("f64", L.SDP_PREC_F64, 0),
-                                   ("f32", L.SDP_PREC_F32, 0)):
+                                   ("f32", L.SDP_PREC_F32, 0), ("bf16", L.SDP_PREC_BF16, 0)):
             if name not in wanted:
                 continue
             with Context(p, inner_prec=prec, sparse_sandwich=sparse) as ctx:
@@ -437,8 +437,9 @@ def main():
                          "adjoint: n=1000 completion forward + backward; completion: n=4000 completion operator")
     ap.add_argument("--forms", default="f64,f32,bf16,f64_sampled",
                     help="completion: operator forms to time (comma list of f64, f32, bf16, f64_sampled)")
-    ap.add_argument("--solve", nargs="?", const="f64_sampled,f64,f32", default="",
-                    help="completion: also time full solves, a comma list of f64_sampled, f64, f32 (default all)")
+    ap.add_argument("--solve", nargs="?", const="f64_sampled,f64,f32,bf16", default="",
+                    help="completion: also time full solves, a comma list of f64_sampled, f64, f32, bf16 "
+                         "(default all)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every instance of this workload fits one MI355X, "
