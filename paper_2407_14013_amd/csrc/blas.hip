@@ -902,8 +902,21 @@ constexpr int DOT_MAX_BLOCKS = 512;
 __global__ __launch_bounds__(256) void dot_partial(long n, const double* __restrict__ x, const double* __restrict__ y,
                                                    double* __restrict__ part) {
     __shared__ double sh[8];
+    // four strides' loads issued before their products are summed (same order)
     double acc = 0.0;
-    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) acc += x[i] * y[i];
+    const long stride = (long)gridDim.x * 256;
+    long i = blockIdx.x * 256L + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = x[i + stride * u];
+            b[u] = y[i + stride * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += a[u] * b[u];
+    }
+    for (; i < n; i += stride) acc += x[i] * y[i];
     double s = block_sum<256>(acc, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
@@ -946,8 +959,20 @@ constexpr long DOT_SINGLE_MAX = 1L << 15;
 __global__ __launch_bounds__(1024) void dot_single(long n, const double* __restrict__ x, const double* __restrict__ y,
                                                    double* __restrict__ out) {
     __shared__ double sh[16];
+    // four steps' loads issued before their products are summed (same order)
     double acc = 0.0;
-    for (long i = threadIdx.x; i < n; i += 1024) acc += x[i] * y[i];
+    long i = threadIdx.x;
+    for (; i + 3 * 1024 < n; i += 4 * 1024) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = x[i + 1024 * u];
+            b[u] = y[i + 1024 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += a[u] * b[u];
+    }
+    for (; i < n; i += 1024) acc += x[i] * y[i];
     double s = block_sum<1024>(acc, sh);
     if (threadIdx.x == 0) out[0] = s;
 }
