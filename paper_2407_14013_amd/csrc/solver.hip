@@ -13,6 +13,7 @@
 
 sdp_ctx::~sdp_ctx() {
     if (pin) (void)hipHostFree(pin);
+    if (ev_rr) (void)hipEventDestroy(ev_rr);
     for (auto& p : prof)
         for (auto e : p.ev) (void)hipEventDestroy(e);
 }
@@ -189,6 +190,7 @@ static void alloc_work(sdp_ctx* c) {
     fill(c->st, 64, c->sc, 0.0);
     c->info.alloc(4);
     WC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->pin), 64 * sizeof(double), hipHostMallocDefault));
+    WC_HIP(hipEventCreateWithFlags(&c->ev_rr, hipEventDisableTiming));
 }
 
 static void validate_host(const sdp_problem* p) {
@@ -811,13 +813,15 @@ static PcgOut pcg_loop(sdp_ctx* c, bool lowp, const double* g, double* x, double
     o.ref = std::sqrt(c->pin[0]);
     o.rr = o.ref;
     const double tol = tol_rel * (o.ref > 0 ? o.ref : 1.0);
+    bool have_kp = false;  // vKp already holds K p for the current p
     while (true) {
         if (!(o.rr > tol)) {
             o.conv = std::isfinite(o.rr);
             break;
         }
         if (o.it >= maxit) break;
-        K(c->vp, c->vKp);
+        if (!have_kp) K(c->vp, c->vKp);
+        have_kp = false;
         dot(st, N, c->vp, c->vKp, sc + 1, c->part);
         pcg_alpha(st, sc);
         pcg_xr(st, N, m, x, c->vr, c->vp, c->vKp, sc);
@@ -834,8 +838,22 @@ static PcgOut pcg_loop(sdp_ctx* c, bool lowp, const double* g, double* x, double
                     lowp ? "(lp)" : "", o.it, std::sqrt(c->pin[4]), std::sqrt(c->pin[6]), c->pin[0], c->pin[1],
                     c->pin[2], c->pin[3]);
         }
-        fetch(c, sc + 4, 1);
+        // |r_u|^2 to the host; while it travels and the host waits, the GPU
+        // already runs the next iteration's operator product on the new p (it
+        // writes only vKp and scratch, so it is harmless when the loop stops)
+        WC_HIP(hipMemcpyAsync(c->pin, sc + 4, sizeof(double), hipMemcpyDeviceToHost, st));
+        WC_HIP(hipEventRecord(c->ev_rr, st));
+        if (o.it < maxit) {
+            K(c->vp, c->vKp);
+            have_kp = true;
+        }
+        WC_HIP(hipEventSynchronize(c->ev_rr));
         o.rr = std::sqrt(c->pin[0]);
+    }
+    // a product started for an iteration that did not run is not counted
+    if (have_kp) {
+        if (lowp) c->lp_matvecs -= 1;
+        else c->matvecs -= 1;
     }
     return o;
 }

@@ -60,6 +60,7 @@ struct sdp_ctx {
     wc::DevBuf<double> gemm_ws; // split-K partial products of the small square GEMMs
     wc::DevBuf<double> sy_ws;   // tile partial sums of the symmetric C^{-1} products
     wc::DevBuf<double> sc;      // device scalars
+    hipEvent_t ev_rr = nullptr; // the residual norm's copy to pin has landed
     double* pin = nullptr;      // pinned host scalars
     wc::DevBuf<int> info;
 
