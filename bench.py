@@ -119,7 +119,7 @@ def pmc_pass():
 
 
 def bench_batched(args):
-    """Config 3: 1024 Gaussian sensing SDPs (n in [16,128], r in {1,2,3}, m = 3nr) in one persistent launch."""
+    """The batched workload: 1024 Gaussian sensing SDPs (n in [16,128], r in {1,2,3}, m = 3nr) in one persistent launch."""
     import torch
 
     import workloads
@@ -189,7 +189,7 @@ def bench_batched(args):
 
 
 def bench_adjoint(args):
-    """Config 4: FP64 solve of the n=1000 completion SDP, then the KKT adjoint with the FP32 inner operator."""
+    """The adjoint workload: FP64 solve of the n=1000 completion SDP, then the KKT adjoint with the FP32 inner operator."""
     import torch
 
     import workloads

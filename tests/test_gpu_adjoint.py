@@ -3,7 +3,7 @@
 sdp_adjoint returns the derivative of the central-path point at the current
 mu (after re-centring), i.e. the self-adjoint Newton KKT system of eq.
 Newt-eps solved with C~ = dL/dX, b~ = 0.  Checked on the Gaussian sensing
-workload (config 0), whose problems are strictly feasible on both sides:
+workload (n = 20, m = 120), whose problems are strictly feasible on both sides:
 
 * against the oracle's gradient from the same interior point (both re-centre
   to a distance <= 1e-8 and solve the same KKT system).  The gradient solve

@@ -239,7 +239,7 @@ def test_solve_mixed_config1_matches_oracle(prec):
     e_obj = abs(c["pobj"] - gold["certificate"]["pobj"]) / abs(gold["certificate"]["pobj"])
     Xs = p["U"] @ p["U"].T
     e_rec = np.linalg.norm(X - Xs) / np.linalg.norm(Xs)
-    print(f"config 1 prec {prec}: objective error {e_obj:.1e}, planted recovery {e_rec:.1e}, "
+    print(f"n=200 sensing, prec {prec}: objective error {e_obj:.1e}, planted recovery {e_rec:.1e}, "
           f"fp64 matvecs {res['newton_matvecs']}, low-precision matvecs {res['lp_matvecs']}")
     assert e_obj <= 1e-8
     assert e_rec <= 1e-6

@@ -12,7 +12,7 @@
   random joint (db, dC) directions.
 * Central finite differences (step 1e-7) of central-path points at a fixed
   mu, which exist whenever both problems are strictly feasible -- also for
-  the planted, primal-degenerate sensing workload (config 0).
+  the planted, primal-degenerate sensing workload (n = 20, m = 120).
 
 The last two need a differentiable solution map, i.e. a nondegenerate,
 strictly complementary problem: generic data (workloads.generic_*).  The
