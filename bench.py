@@ -377,7 +377,7 @@ def bench_completion(args):
                                    ("f32", L.SDP_PREC_F32, 0), ("bf16", L.SDP_PREC_BF16, 0)):
             if name not in wanted:
                 continue
-            with Context(p, inner_prec=prec, sparse_sandwich=sparse) as ctx:
+            with Context(p, inner_prec=prec, sparse_sandwich=sparse, verbose=1 if args.verbose else 0) as ctx:
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 res = ctx.solve(raise_on_stall=False)
@@ -435,6 +435,8 @@ def main():
     ap.add_argument("--workload", choices=["sensing", "batched", "adjoint", "completion"], default="sensing",
                     help="sensing: the headline line (n=200 dense); batched: 1024 small SDPs in one launch; "
                          "adjoint: n=1000 completion forward + backward; completion: n=4000 completion operator")
+    ap.add_argument("--verbose", action="store_true",
+                    help="completion --solve: one line per interior-point iteration on stderr")
     ap.add_argument("--forms", default="f64,f32,bf16,f64_sampled",
                     help="completion: operator forms to time (comma list of f64, f32, bf16, f64_sampled)")
     ap.add_argument("--solve", nargs="?", const="f64_sampled,f64,f32,bf16", default="",
