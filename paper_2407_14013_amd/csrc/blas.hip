@@ -289,8 +289,20 @@ __global__ __launch_bounds__(256) void dgemm_thin_n_kernel(int M, int N, int K, 
 #pragma unroll
     for (int j = 0; j < NM; ++j) acc[j] = 0.0;
     if (i < M) {
-#pragma unroll 8
-        for (int k = k0; k < k1; ++k) {
+        // eight K-steps' loads of A are issued before their products (the
+        // guarded column loop would otherwise make every step wait for its load)
+        int k = k0;
+        for (; k + 8 <= k1; k += 8) {
+            double a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = A[i + (long)(k + u) * lda];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int j = 0; j < NM; ++j)
+                    if (j < N) acc[j] += a[u] * Bs[k + u + j * K];
+        }
+        for (; k < k1; ++k) {
             const double a = A[i + (long)k * lda];
 #pragma unroll
             for (int j = 0; j < NM; ++j)
@@ -330,8 +342,33 @@ __global__ __launch_bounds__(256) void dgemm_thin_t_kernel(int M, int N, int K, 
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int j = 0; j < NM; ++j) acc[t][j] = 0.0;
+    int k = k0 + lane;
+    if constexpr (NM <= 4) {
+        // two steps' loads of A and B issued before their products (B's column
+        // index clamped to a valid one, the value used only for j < N); the
+        // guarded loop below waits for every load
+        for (; k + 64 < k1; k += 128) {
+            double av[2][4], bv[2][NM];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) av[h][t] = a[t][k + 64 * h];
+#pragma unroll
+                for (int j = 0; j < NM; ++j) bv[h][j] = B[k + 64 * h + (long)min(j, N - 1) * ldb];
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int j = 0; j < NM; ++j) {
+                    if (j < N) {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) acc[t][j] += av[h][t] * bv[h][j];
+                    }
+                }
+        }
+    }
 #pragma unroll 2
-    for (int k = k0 + lane; k < k1; k += 64) {
+    for (; k < k1; k += 64) {
         const double av0 = a[0][k], av1 = a[1][k], av2 = a[2][k], av3 = a[3][k];
 #pragma unroll
         for (int j = 0; j < NM; ++j) {
@@ -399,8 +436,20 @@ __global__ __launch_bounds__(256) void dgemm_thin_splitk_kernel(int M, int N, in
 #pragma unroll
     for (int j = 0; j < NM; ++j) acc[j] = 0.0;
     if (i < M) {
-#pragma unroll 8
-        for (int k = k0; k < k1; ++k) {
+        // eight K-steps' loads of A are issued before their products (the
+        // guarded column loop would otherwise make every step wait for its load)
+        int k = k0;
+        for (; k + 8 <= k1; k += 8) {
+            double a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = A[i + (long)(ks0 + k + u) * lda];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int j = 0; j < NM; ++j)
+                    if (j < N) acc[j] += a[u] * Bs[k + u + j * len];
+        }
+        for (; k < k1; ++k) {
             const double a = A[i + (long)(ks0 + k) * lda];
 #pragma unroll
             for (int j = 0; j < NM; ++j)
