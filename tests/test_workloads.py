@@ -30,7 +30,9 @@ def test_centred_pair_closed_form(n, r, mu):
     G, _, _ = nt.nt_factor(X, S)
     bound = 100 * (x.max() / x.min()) * np.finfo(float).eps
     assert np.abs(G @ G.T - W).max() <= bound * np.abs(W).max()
-    assert np.abs(W @ S @ W - X).max() <= 1e-9 * np.abs(X).max()
+    # W S W = X, up to the rounding of the product (|W|^2 |S| eps per entry)
+    wsw = 10 * n * np.finfo(float).eps * np.abs(W).max() ** 2 * np.abs(S).max()
+    assert np.abs(W @ S @ W - X).max() <= wsw
     # the rank rule finds the r planted directions, and tau = lambda_{r+1} / 2
     sp = rf.eig_split(W, rank_max=10)
     lam = np.sort(np.sqrt(x / s))[::-1]
