@@ -210,7 +210,7 @@ def bench_adjoint(args):
     with Context(p, inner_prec=L.SDP_PREC_F32) as bwd:
         bwd.set_point(X, y, S)
         t0 = time.perf_counter()
-        gb, gC, st = bwd.adjoint(2.0 * (X - target))
+        gb, gC, st = bwd.adjoint(2.0 * (X - target), raise_off_centre=False)
         torch.cuda.synchronize()
         t_bwd = time.perf_counter() - t0
     line = {
@@ -224,7 +224,7 @@ def bench_adjoint(args):
         "config": {"workload": "matrix completion SDP n=1000 r=3 m=30000, loss ||X - X_target||_F^2"},
         "forward": {"time_s": t_fwd, "iterations": res["iterations"], "pcg_iterations": res["pcg_iterations"],
                     "relgap": res["relgap"]},
-        "backward": {"time_s": t_bwd, **st},
+        "backward": {"time_s": t_bwd, "status": L.STATUS_NAMES.get(st.pop("status")), **st},
         "grad_norms": {"dL_db": float(gb.norm()), "dL_dC": float(gC.norm())},
     }
     print(json.dumps(line))

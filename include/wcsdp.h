@@ -50,8 +50,12 @@ enum {
     SDP_EDEVICE = -3,   /* a HIP call failed */
     SDP_ENOTCONV = -4,  /* inner Krylov solve reached inner_maxit */
     SDP_ENUMERIC = -5,  /* a factorisation met a non-positive pivot */
-    SDP_ESTALL = -6     /* the interior-point method hit max_ipm_iter or stalled */
+    SDP_ESTALL = -6,    /* the interior-point method hit max_ipm_iter or stalled */
+    SDP_ECENTER = -7    /* sdp_adjoint could not bring the iterate onto the central path */
 };
+
+/* Largest distance to the central path at which sdp_adjoint reports SDP_OK. */
+#define SDP_ADJOINT_CENTER_TOL 1e-6
 
 enum { SDP_A_DENSE = 0, SDP_A_ENTRY = 1 };
 enum { SDP_SOLVER_PCG = 0, SDP_SOLVER_MINRES = 1 };
@@ -262,12 +266,15 @@ typedef struct sdp_adjoint_stats {
  * point is kept and becomes the context's iterate), and the gradient is that
  * of the central-path point, which tends to the solution map's derivative as
  * mu -> 0 when that derivative exists (nondegenerate, strictly complementary
- * problems).  Without a strictly feasible point there is no central path and
- * stats->centrality stays large: the result is then the Newton-system
- * gradient at the iterate, not a derivative of the solution.  dL_dX (n x n symmetric, read), dL_db (m, written), dL_dC
- * (n x n symmetric, written): device pointers.  stats may be NULL.  The inner
- * solves use the context's inner precision.  Returns SDP_ENOTCONV if the
- * gradient solve reached inner_maxit.
+ * problems).  Without a strictly feasible point there is no central path:
+ * centring stalls, and when the closest point reached is farther than
+ * SDP_ADJOINT_CENTER_TOL from it the call returns SDP_ECENTER (the outputs
+ * then hold the Newton-system solution at that point, which is not a
+ * derivative of the solution; stats->centrality gives the distance).
+ * dL_dX (n x n symmetric, read), dL_db (m, written), dL_dC (n x n symmetric,
+ * written): device pointers.  stats may be NULL.  The inner solves use the
+ * context's inner precision.  Returns SDP_ENOTCONV if the gradient solve
+ * reached inner_maxit (checked before SDP_ECENTER).
  */
 sdp_status sdp_adjoint(sdp_ctx* ctx, const double* dL_dX, double* dL_db, double* dL_dC, sdp_adjoint_stats* stats);
 
@@ -342,8 +349,10 @@ enum {
                             (2 n^3 flops per launch; bytes = its operands and result) */
     SDP_K_SAMPLED_YE = 5,   /* sparse_sandwich: Z = A^T(u) E from the sliced pattern (bytes = E read
                                and Z written once, 10 per pattern slot) */
-    SDP_K_SAMPLED_DOTS = 6, /* sparse_sandwich: E[:, j] . Z[:, k] per constraint (bytes = one column
-                               of Z per constraint, E once, 16 per constraint) */
+    SDP_K_SAMPLED_DOTS = 6, /* sparse_sandwich: E[:, j] . Z[:, k] per constraint (algorithmic HBM
+                               bytes = E and Z read once each, 16 per constraint for the pair
+                               index and the result; the per-constraint re-reads of Z's
+                               columns are cache traffic and not counted) */
     SDP_K_COUNT = 7
 };
 

@@ -12,6 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwcsdp.so")
 
 SDP_OK, SDP_EINVAL, SDP_ENOMEM, SDP_EDEVICE, SDP_ENOTCONV, SDP_ENUMERIC, SDP_ESTALL = 0, -1, -2, -3, -4, -5, -6
+SDP_ECENTER = -7
+SDP_ADJOINT_CENTER_TOL = 1e-6
 SDP_A_DENSE, SDP_A_ENTRY = 0, 1
 SDP_SOLVER_PCG, SDP_SOLVER_MINRES = 0, 1
 SDP_PREC_F64, SDP_PREC_F32, SDP_PREC_BF16 = 0, 1, 2
@@ -27,6 +29,7 @@ STATUS_NAMES = {
     -4: "SDP_ENOTCONV",
     -5: "SDP_ENUMERIC",
     -6: "SDP_ESTALL",
+    -7: "SDP_ECENTER",
 }
 
 

@@ -162,16 +162,25 @@ class Context:
             self._check(st)
         return dX, dy, L.struct_dict(s)
 
-    def adjoint(self, dL_dX: torch.Tensor):
-        """(dL/db, dL/dC, stats) for a loss gradient dL/dX at the current (re-centred) iterate."""
+    def adjoint(self, dL_dX: torch.Tensor, raise_off_centre: bool = True):
+        """(dL/db, dL/dC, stats) for a loss gradient dL/dX at the current (re-centred) iterate.
+
+        Raises SdpError(SDP_ECENTER) when the iterate could not be brought onto
+        the central path, unless raise_off_centre is False (then stats["status"]
+        says so and the outputs are the Newton-system solution at the iterate).
+        """
         n, m = self.n, self.m
         G = dL_dX.detach().to(dtype=torch.float64).contiguous()
         gb = torch.empty(m, dtype=torch.float64, device=G.device)
         gC = torch.empty((n, n), dtype=torch.float64, device=G.device)
         s = L.SdpAdjointStats()
-        self._check(self._lib.sdp_adjoint(self._ctx, _dptr(G, "dL_dX", n * n), _dptr(gb, "dL_db"), _dptr(gC, "dL_dC"),
-                                          C.byref(s)))
-        return gb, gC, L.struct_dict(s)
+        st = self._lib.sdp_adjoint(self._ctx, _dptr(G, "dL_dX", n * n), _dptr(gb, "dL_db"), _dptr(gC, "dL_dC"),
+                                   C.byref(s))
+        if st != L.SDP_OK and (raise_off_centre or st != L.SDP_ECENTER):
+            self._check(st)
+        out = L.struct_dict(s)
+        out["status"] = int(st)
+        return gb, gC, out
 
     def ipm_step(self) -> dict:
         s = L.SdpStepStats()

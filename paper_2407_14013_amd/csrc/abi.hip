@@ -182,7 +182,7 @@ sdp_status sdp_adjoint(sdp_ctx* ctx, const double* dL_dX, double* dL_db, double*
         wc::require(dL_dX && dL_db && dL_dC, "adjoint: NULL argument");
         wc::require(dL_dX != dL_dC, "adjoint: dL_dX and dL_dC must not alias");
         int rc = wc::adjoint(ctx, dL_dX, dL_db, dL_dC, stats);
-        if (rc != 0) ctx->last_error = "adjoint solve reached inner_maxit";
+        if (rc == SDP_ENOTCONV) ctx->last_error = "adjoint solve reached inner_maxit";
         return (sdp_status)rc;
     });
 }

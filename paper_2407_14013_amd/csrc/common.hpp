@@ -22,6 +22,7 @@ constexpr int32_t kEDevice = -3;
 constexpr int32_t kENotConv = -4;
 constexpr int32_t kENumeric = -5;
 constexpr int32_t kEStall = -6;
+constexpr int32_t kECenter = -7;
 
 #define WC_HIP(expr)                                                                              \
     do {                                                                                          \

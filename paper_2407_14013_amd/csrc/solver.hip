@@ -470,6 +470,9 @@ void ensure_scaling(sdp_ctx* c) {
     // (Jacobi on A V0 with the rotations accumulated onto V0): consecutive
     // scaling points are close, so few sweeps remain.
     const bool warm = c->have_prev;
+    // the vectors are overwritten below; they seed the next setup only once
+    // both decompositions have converged
+    c->have_prev = false;
     if (warm) {
         gemm(c, true, false, n, n, n, 1.0, c->Rs, n, c->L, n, 0.0, c->T1, n);
         gemm(c, false, false, n, n, n, 1.0, c->T1, n, c->Vs, n, 0.0, c->Mt, n);
@@ -496,8 +499,8 @@ void ensure_scaling(sdp_ctx* c) {
     sw = jacobi_svd(st, n, c->Gt, n, c->Gw, n, c->lam, 0.0, 60, c->jw, false, warm);
     mark(2);
     c->sweeps_w = sw;
-    c->have_prev = true;
     if (sw < 0) throw Error(kENumeric, "Jacobi eigen-decomposition of W did not converge");
+    c->have_prev = true;
     c->lam_h.resize(n);
     WC_HIP(hipMemcpyAsync(c->lam_h.data(), c->lam.get(), sizeof(double) * n, hipMemcpyDeviceToHost, st));
     WC_HIP(hipStreamSynchronize(st));
@@ -588,7 +591,7 @@ void newton_apply(sdp_ctx* c, const double* in, double* out) {
         prof_end(c, SDP_K_SAMPLED_YE, es, 16.0 * nn + 10.0 * slots);
         prof_begin(c, SDP_K_SAMPLED_DOTS, &es);
         sampled_dots(st, n, c->dptr, c->dpart, c->didx, c->E, n, c->T1, n, out);
-        prof_end(c, SDP_K_SAMPLED_DOTS, es, 8.0 * m * (double)n + 8.0 * nn + 16.0 * m);
+        prof_end(c, SDP_K_SAMPLED_DOTS, es, 16.0 * nn + 16.0 * m);
         // top += script-A script-Q v;  bottom = (script-A script-Q)^T u - tau^2 Sigma v
         v_to_h(st, n, r, v, c->Hm);
         gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
@@ -1296,6 +1299,17 @@ int adjoint(sdp_ctx* c, const double* GX, double* gb, double* gC, sdp_adjoint_st
         stats->inner_iterations = inner_its;
         stats->converged = rc == 0 ? 1 : 0;
     }
+    if (rc == 0 && !(dev <= SDP_ADJOINT_CENTER_TOL)) {
+        // off the central path the Newton direction is not the derivative of
+        // anything: report it rather than hand back a plausible-looking number
+        char msg[160];
+        snprintf(msg, sizeof msg,
+                 "adjoint: centring stalled at distance %.3e from the central path (limit %.0e); "
+                 "no strictly feasible point near the iterate?",
+                 dev, SDP_ADJOINT_CENTER_TOL);
+        c->last_error = msg;
+        return kECenter;
+    }
     return rc;
 }
 
@@ -1351,6 +1365,9 @@ void set_point(sdp_ctx* c, const double* X, const double* y, const double* S) {
     symmetrize(c->st, n, c->X, n);
     symmetrize(c->st, n, c->S, n);
     c->scaling_valid = false;
+    // a new point starts from cold eigen-solvers, so that results do not
+    // depend on what the context computed before
+    c->have_prev = false;
     c->iter = 0;
     WC_HIP(hipStreamSynchronize(c->st));
 }

@@ -32,7 +32,7 @@ torch = pytest.importorskip("torch")
 
 import workloads  # noqa: E402
 from oracle import adjoint as oadj, ipm, nt, operators as ops  # noqa: E402
-from paper_2407_14013_amd import Context  # noqa: E402
+from paper_2407_14013_amd import Context, SdpError  # noqa: E402
 from paper_2407_14013_amd import _lib as L  # noqa: E402
 from paper_2407_14013_amd.layer import SDPLayer  # noqa: E402
 
@@ -78,6 +78,48 @@ def test_adjoint_matches_oracle_gradient(tol, prec):
     assert e_primal <= 1e-9 and e_second <= 1e-8
     if tol >= 1e-2:
         assert e_b <= 1e-5 and e_C <= 1e-5
+
+
+@pytest.mark.parametrize("n,r,seed", [(16, 2, 1), (40, 3, 2)])
+@pytest.mark.parametrize("tol", [1e-2, 1e-4])
+def test_adjoint_entry_sampling_matches_oracle(n, r, seed, tol):
+    # entry-sampling constraints (A_i = sym(e_j e_k^T)) on a planted,
+    # strictly complementary instance with m = n r - r (r - 1) / 2: both
+    # problems are strictly feasible, so the central path exists and the
+    # re-centring must reach it
+    m = n * r - r * (r - 1) // 2
+    p = workloads.planted_pair(n, r, m, seed=seed, kind="entry")
+    res = ipm.solve(p, tol=tol)
+    X, y, S = res["X"], res["y"], res["S"]
+    GX = 2.0 * (X - target_of(n))
+    gC0, gb0 = oadj.solution_gradient(p, X, y, S, GX)
+    with Context(p, inner_tol=1e-13) as ctx:
+        ctx.set_point(dev(X), dev(y), dev(S))
+        gb, gC, st = ctx.adjoint(dev(GX))
+    gb, gC = host(gb), host(gC)
+    e_b = np.abs(gb - gb0).max() / np.abs(gb0).max()
+    e_C = np.abs(gC - gC0).max() / np.abs(gC0).max()
+    print(f"entry n {n} r {r} tol {tol}: centring steps {st['centring_steps']} distance {st['centrality']:.1e} "
+          f"inner its {st['inner_iterations']} e_b {e_b:.1e} e_C {e_C:.1e}")
+    assert st["status"] == L.SDP_OK and st["converged"] == 1 and st["centrality"] <= 1e-8
+    assert e_b <= 1e-5 and e_C <= 1e-5
+
+
+def test_adjoint_reports_missing_central_path():
+    # observing 120 of the 210 entries of a rank-2 20 x 20 matrix leaves no
+    # strictly feasible primal point (the oracle's centring stalls at a
+    # distance ~1.6): the adjoint must say so instead of returning SDP_OK
+    p = workloads.matrix_completion(20, 2, 120, seed=5)
+    with Context(p) as ctx:
+        ctx.solve()
+        X = ctx.get_point()[0]
+        G = 2.0 * (X - dev(target_of(p["n"])))
+        with pytest.raises(SdpError) as ei:
+            ctx.adjoint(G)
+        assert ei.value.status == L.SDP_ECENTER
+        _, _, st = ctx.adjoint(G, raise_off_centre=False)
+    print(f"no central path: status {st['status']} distance {st['centrality']:.2e}")
+    assert st["status"] == L.SDP_ECENTER and st["centrality"] > L.SDP_ADJOINT_CENTER_TOL
 
 
 def test_adjoint_matches_gpu_central_path_differences():

@@ -405,3 +405,25 @@ def test_solve_minres_config0_matches_oracle():
         X, y, S = ctx.get_point()
     print(f"minres solve: its {res['iterations']} krylov {res['pcg_iterations']}")
     check_solution(p, res, X, y, S, ref["history"][-1]["pobj"])
+
+
+@pytest.mark.parametrize("which", ["cfg1", "entry_sampled"])
+def test_repeated_solves_are_reproducible(which):
+    # a solve depends only on its starting point: the same context re-started
+    # with sdp_set_point and a fresh context both repeat it bit for bit
+    p = workloads.config(1) if which == "cfg1" else small_entry()
+    opts = {"sparse_sandwich": 1} if which == "entry_sampled" else {}
+    with Context(p, **opts) as a:
+        X0, y0, S0 = (t.clone() for t in a.get_point())
+        r1 = a.solve()
+        X1 = a.get_point()[0].clone()
+        a.set_point(X0, y0, S0)
+        r2 = a.solve()
+        X2 = a.get_point()[0].clone()
+    with Context(p, **opts) as b:
+        r3 = b.solve()
+        X3 = b.get_point()[0].clone()
+    counts = [(r["iterations"], r["pcg_iterations"], r["newton_matvecs"]) for r in (r1, r2, r3)]
+    print(f"{which}: (iterations, PCG, products) {counts}")
+    assert counts[0] == counts[1] == counts[2]
+    assert torch.equal(X1, X2) and torch.equal(X1, X3)

@@ -148,6 +148,29 @@ def test_direct_newton_solves_unsubstituted_system():
     assert np.allclose(R.T @ R, M, rtol=1e-10, atol=1e-12 * np.abs(M).max())
 
 
+@pytest.mark.parametrize("kind", ["dense", "entry"])
+def test_schur_matrix_matches_definition(kind):
+    # M_ij = <A_i, W A_j W> written out with the explicit matrices A_i, against
+    # the oracle's two ways of forming it: the closed form for entry sampling
+    # (M_(jk),(pq) = (W_jp W_kq + W_jq W_kp) / 2) or A~ A~^T for dense rows,
+    # and R^T R from the thin QR of the scaled rows.  The entry instance has
+    # diagonal and off-diagonal pairs, so both halves of the closed form count.
+    p = small_problem(kind, seed=3)
+    X, y, S = ipm_point(p, 2)
+    G, d, L = nt.nt_factor(X, S)
+    W = sym(G @ G.T)
+    if kind == "entry":
+        jk = p["jk"]
+        assert np.any(jk[:, 0] == jk[:, 1]) and np.any(jk[:, 0] != jk[:, 1])
+    m = p["m"]
+    A = [ops.a_matrix(p, i) for i in range(m)]
+    M = np.array([[np.sum(A[i] * (W @ A[j] @ W)) for j in range(m)] for i in range(m)])
+    got = ipm.schur_matrix(p, G, W)
+    assert np.allclose(got, M, rtol=1e-12, atol=1e-13 * np.abs(M).max())
+    _, _, R = ipm.schur_factor(p, G, W)
+    assert np.allclose(R.T @ R, M, rtol=1e-10, atol=1e-12 * np.abs(M).max())
+
+
 def test_lemma_smallres():
     # Lemma smallres: with residual [p; d] of eq. augsys, the recovered (x, y)
     # has eq. Newt-eps residual [tau^-2 E^-1 Q C^-1 d; p], C = tau^2 Sigma + Q^T E^-1 Q.
