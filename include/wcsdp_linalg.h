@@ -46,6 +46,22 @@ int32_t wc_dsymv(void* stream, int32_t d, double alpha, const double* A, int32_t
                  double* y);
 
 /*
+ * wc_dsymv for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same product and kernels, with the tile partial sums kept in a file-scope
+ * device array of the library (one per GPU, about 32 MiB, held until the
+ * process ends) instead of a workspace allocated per call.  Allocates and
+ * frees nothing and does not synchronise the stream.  d must not exceed
+ * WC_DSYMV_NOALLOC_MAX_D (-1 otherwise, nothing enqueued); the other
+ * arguments and the result are as for wc_dsymv.  All calls on one GPU share
+ * that array: calls that overlap on one GPU (different streams or host
+ * threads without ordering between them) race and give wrong results.
+ */
+#define WC_DSYMV_NOALLOC_MAX_D 16384
+int32_t wc_dsymv_noalloc(void* stream, int32_t d, double alpha, const double* A, int32_t lda, const double* x,
+                         double beta, double* y);
+
+/*
  * In-place Cholesky factorisation A = L L^T of the n x n symmetric positive
  * definite A (lower triangle read and overwritten with L; the strict upper
  * triangle is set to zero).  Returns 0, or -5 when a pivot is not positive;

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libwcsdp.so")
 
 SDP_OK, SDP_EINVAL, SDP_ENOMEM, SDP_EDEVICE, SDP_ENOTCONV, SDP_ENUMERIC, SDP_ESTALL = 0, -1, -2, -3, -4, -5, -6
 SDP_ECENTER = -7
+WC_DSYMV_NOALLOC_MAX_D = 16384
 SDP_ADJOINT_CENTER_TOL = 1e-6
 SDP_A_DENSE, SDP_A_ENTRY = 0, 1
 SDP_SOLVER_PCG, SDP_SOLVER_MINRES = 0, 1
@@ -172,6 +173,8 @@ _SIGNATURES = [
                                    C.c_double, C.c_int32, C.POINTER(C.c_int32)]),
     ("wc_dsymv", C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_int32, C.c_void_p, C.c_double,
                              C.c_void_p]),
+    ("wc_dsymv_noalloc", C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_int32, C.c_void_p,
+                                     C.c_double, C.c_void_p]),
     ("wc_gemm_lp", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
     ("wc_gemm_lp_sym", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,

@@ -334,6 +334,20 @@ int32_t wc_dsymv(void* stream, int32_t d, double alpha, const double* A, int32_t
     });
 }
 
+int32_t wc_dsymv_noalloc(void* stream, int32_t d, double alpha, const double* A, int32_t lda, const double* x,
+                         double beta, double* y) {
+    return guarded_la([&]() {
+        wc::require(d >= 0 && lda >= std::max(1, d), "bad size or leading dimension");
+        wc::require(d <= WC_DSYMV_NOALLOC_MAX_D, "d exceeds WC_DSYMV_NOALLOC_MAX_D");
+        if (d == 0) return (int32_t)0;
+        // no allocation and no synchronisation: the partial sums go to the
+        // device's scratch array, stream-ordered like the kernels that use them
+        double* ws = wc::symv_noalloc_scratch(d);
+        wc::symv(static_cast<hipStream_t>(stream), d, A, lda, x, y, alpha, beta, ws);
+        return (int32_t)0;
+    });
+}
+
 int32_t wc_gemm_lp(void* stream, int32_t prec_in, int32_t out_kind, int32_t m, int32_t n, int32_t k, const void* A,
                    int32_t lda, const void* B, int32_t ldb, void* C, int32_t ldc) {
     return guarded_la([&]() {

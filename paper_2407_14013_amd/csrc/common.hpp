@@ -105,6 +105,9 @@ void gemv_rows(hipStream_t st, int m, int k, const double* A, long lda, const do
 // y = alpha A x + beta y for a symmetric d x d A stored in full (pitch lda
 // even, rows 16-byte aligned), reading half of it; ws holds symv_ws(d) doubles.
 long symv_ws(int d);
+// Device address, on the current device, of the file-scope scratch array that
+// wc_dsymv_noalloc uses as symv's workspace (d <= WC_DSYMV_NOALLOC_MAX_D).
+double* symv_noalloc_scratch(int d);
 void symv(hipStream_t st, int d, const double* A, long lda, const double* x, double* y, double alpha, double beta,
           double* ws);
 
