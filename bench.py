@@ -1,18 +1,31 @@
 """Benchmark: Newton-operator mat-vecs per second and IPM time to a 1e-8 gap.
 
-One step = one full FP64 interior-point solve (sdp_solve) of the dense
-Gaussian matrix-sensing workload n=200, r=3, m=2400 from the standard
-starting point to relative gap, primal and dual infeasibility <= 1e-8.  The
-constraint data is resident in HBM before timing starts (the setup upload
-and packing are outside the timed region).  value = augmented-operator
-applications performed by the timed solves / timed seconds.
+Default workload: the matrix-completion SDP n=4000, r=4, m=160000 (entry
+sampling), the largest configuration that one GPU holds.  One step = one
+FP64 application of the augmented operator of eq. augsys (sdp_newton_apply)
+with the two n x n x n products of E Y E on the FP64 matrix cores, at a
+closed-form centred point (mu = 1e-2, rank-4 split: the shape of the late
+iterates; workloads.centred_pair).  value = steps / timed seconds; the
+scaling point and its split are prepared before the timed region and every
+input is resident in HBM.
 
 The JSON line also carries:
-  roofline      the dominant kernel (the packed A / A^T passes, HBM bound)
-                timed live with HIP events on the library's stream;
-  cpu_baseline  the CPU oracle's augmented operator on the same workload
-                (bounded sample, all host cores);
-  newton_apply  a tight loop of sdp_newton_apply at the final scaling point.
+  roofline      the dominant kernel, dgemm_kernel (E Y E, 2 n^3 flops per
+                launch), timed live with HIP events on the library's stream;
+  forms         the other forms of the same operator (FP64 with the sampled
+                A(E Y E), and the FP32 and BF16 forms of the refinement
+                sweeps), the preconditioner apply, and the PCG-iteration rate;
+  ipm           time to the 1e-8 tolerances from the standard start for the
+                fastest FP64 form (sampled) and the BF16-mixed form
+                (--solve chooses, FP32-mixed and dense FP64 on request);
+  config1       the Gaussian sensing workload n=200, m=2400 (dense A): FP64
+                and mixed solves to 1e-8 and its packed-pass HBM roofline;
+  cpu_baseline  the CPU oracle's operator at n=4000 on the host cores, and
+                the oracle's time to the 1e-8 gap on a reduced completion
+                instance of the same generator next to the GPU's.
+
+--workload sensing prints the n=200 line on its own; batched and adjoint
+print their own lines.
 """
 import argparse
 import json
@@ -30,6 +43,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "packed_passes_gaussian_n200_m2400
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2407_14013_amd", "csrc", "blas.hip")
 METRIC = "Newton-op matvecs/s and IPM time-to-1e-8 gap, FP64 vs mixed prec, 1 GPU"
 WORKLOAD = "gaussian sensing SDP n=200 r=3 m=2400 (dense A, FP64)"
+COMPLETION = "matrix completion SDP n=4000 r=4 m=160000 (entry sampling) at a centred point, mu=1e-2, rank-4 split"
+MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
+REDUCED = (100, 4, 2000)  # reduced completion instance for the oracle's time to gap
+
+
+def host_threads():
+    try:
+        from threadpoolctl import threadpool_info
+
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [1]))
+    except Exception:
+        return os.cpu_count()
 
 
 def cpu_baseline(p, budget_s=15.0):
@@ -230,236 +255,8 @@ def bench_adjoint(args):
     print(json.dumps(line))
 
 
-MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
-
-
-def bench_completion(args):
-    """The n=4000 matrix-completion operator, where E Y E on the matrix cores dominates.
-
-    At a closed-form centred point with a rank-4 split (the shape of the late
-    iterates) every form of the operator is applied in a tight loop: FP64,
-    and the FP32 and BF16 forms that the refinement sweeps use.  The two
-    n x n x n GEMMs of E Y E are timed by the library with HIP events on its
-    stream (kernel class SDP_K_SANDWICH): 2 n^3 flops per launch.  With
-    --solve, the full solves to the 1e-8 tolerances are timed as well
-    (minutes): FP64 with the sampled A(E Y E) form, FP64 with the dense
-    products, FP32-mixed and BF16-mixed.  The sampled form (sparse_sandwich) is timed
-    per kernel class too: Z = Y E and the per-constraint dot products.
-    """
-    import torch
-
-    import workloads
-    from paper_2407_14013_amd import Context
-    from paper_2407_14013_amd import _lib as L
-
-    torch.cuda.set_device(0)
-    p = workloads.config(2)
-    n, m, r0, mu = p["n"], p["m"], 4, 1e-2
-    X, S, V, x, s = workloads.centred_pair(n, r0, mu, seed=21)
-    Xd, Sd = torch.from_numpy(X).cuda(), torch.from_numpy(S).cuda()
-    yd = torch.zeros(m, dtype=torch.float64, device="cuda")
-    del X, S
-    flops = 2.0 * n ** 3
-    forms = {}
-    wanted_forms = args.forms.split(",")
-    for name, prec, sparse in (("f64", L.SDP_PREC_F64, 0), ("f32", L.SDP_PREC_F32, 0), ("bf16", L.SDP_PREC_BF16, 0),
-                               ("f64_sampled", L.SDP_PREC_F64, 1)):
-        if name not in wanted_forms:
-            continue
-        with Context(p, inner_prec=prec, sparse_sandwich=sparse) as ctx:
-            ctx.set_point(Xd, yd, Sd)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            sc = ctx.get_scaling()
-            torch.cuda.synchronize()
-            t_scaling = time.perf_counter() - t0
-            N = ctx.aug_dim()
-            xin = torch.randn(N, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
-            xout = torch.empty_like(xin)
-            pr = None if prec == L.SDP_PREC_F64 else prec
-            for _ in range(3):
-                ctx.newton_apply(xin, xout, prec=pr)
-            torch.cuda.synchronize()
-            classes = [L.SDP_K_SAMPLED_YE, L.SDP_K_SAMPLED_DOTS] if sparse else [L.SDP_K_SANDWICH]
-            ctx.profile_enable(classes)
-            calls = args.apply_loop
-            t0 = time.perf_counter()
-            for _ in range(calls):
-                ctx.newton_apply(xin, xout, prec=pr)
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
-            prof = {k: ctx.profile_get(k) for k in classes}
-            ctx.profile_enable([])
-            t0 = time.perf_counter()
-            for _ in range(20):
-                ctx.precond_apply(xin, xout)
-            torch.cuda.synchronize()
-            t_prec = (time.perf_counter() - t0) / 20
-            forms[name] = {
-                "matvec_per_s": calls / el,
-                "ms_per_matvec": 1e3 * el / calls,
-                "precond_apply_ms": 1e3 * t_prec,
-                "scaling_setup_s": t_scaling,
-                "r": sc["r"],
-                "d": N - m,
-            }
-            if sparse:
-                # the two sampled kernels, HBM-bound: algorithmic bytes per launch
-                # as the library counts them (one column of Z per constraint)
-                for key, k in (("sampled_ye", L.SDP_K_SAMPLED_YE), ("sampled_dots", L.SDP_K_SAMPLED_DOTS)):
-                    pk = prof[k]
-                    gbs = pk["bytes"] / (pk["ms"] * 1e-3) / 1e9
-                    forms[name][key] = {"launches": pk["launches"], "avg_launch_ms": pk["ms"] / pk["launches"],
-                                        "bytes_per_launch": pk["bytes"] / pk["launches"], "achieved_gbs": gbs,
-                                        "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}
-                note = (f"Y E {forms[name]['sampled_ye']['avg_launch_ms']:.3f} ms, dots "
-                        f"{forms[name]['sampled_dots']['avg_launch_ms']:.3f} ms")
-            else:
-                sw = prof[L.SDP_K_SANDWICH]
-                tf = flops * sw["launches"] / (sw["ms"] * 1e-3) / 1e12
-                forms[name]["sandwich_gemm"] = {"launches": sw["launches"], "avg_launch_ms": sw["ms"] / sw["launches"],
-                                                "achieved_tflops": tf, "peak_tflops": MFMA_PEAK_TFLOPS[name],
-                                                "frac": tf / MFMA_PEAK_TFLOPS[name]}
-                note = f"sandwich GEMM {tf:.1f} TFLOP/s"
-        print(f"{name}: {forms[name]['ms_per_matvec']:.3f} ms per operator product, {note}, "
-              f"scaling setup {t_scaling:.2f} s", file=sys.stderr, flush=True)
-    # the line's value and roofline: the FP64 dense-product form when it was
-    # run, else the FP64 sampled form with its per-constraint dot kernel
-    head = "f64" if "f64" in forms else "f64_sampled"
-    f64 = forms[head]
-    if head == "f64":
-        roof = {
-            "kernel": "dgemm_kernel<false, false>: the two n x n x n products of E Y E",
-            "bound": "mfma",
-            "achieved": f64["sandwich_gemm"]["achieved_tflops"],
-            "peak": MFMA_PEAK_TFLOPS["f64"],
-            "unit": "TFLOP/s",
-            "frac": f64["sandwich_gemm"]["frac"],
-            "traffic": None,
-            "flops_per_launch": flops,
-            "avg_launch_ms": f64["sandwich_gemm"]["avg_launch_ms"],
-        }
-    else:
-        dots = f64["sampled_dots"]
-        roof = {
-            "kernel": "sampled_dots_kernel: E[:, j] . Z[:, k] per constraint",
-            "bound": "hbm",
-            "achieved": dots["achieved_gbs"],
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": dots["frac"],
-            "traffic": None,
-            "bytes_per_launch": dots["bytes_per_launch"],
-            "avg_launch_ms": dots["avg_launch_ms"],
-        }
-    line = {
-        "metric": METRIC,
-        "value": f64["matvec_per_s"],
-        "unit": "matvec/s",
-        "n_gpus": 1,
-        "steps": args.apply_loop,
-        "warmup": 3,
-        "ms_per_step": f64["ms_per_matvec"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "matrix completion SDP n=4000 r=4 m=160000 (entry sampling) at a centred point, "
-                               "mu=1e-2, rank-4 split", "form": head},
-        "forms": forms,
-        "roofline": roof,
-    }
-    if args.solve:
-        solves = {}
-        wanted = args.solve.split(",")
-        for name, prec, sparse in (("f64_sampled", L.SDP_PREC_F64, 1), ("f64", L.SDP_PREC_F64, 0),
-                                   ("f32", L.SDP_PREC_F32, 0), ("bf16", L.SDP_PREC_BF16, 0)):
-            if name not in wanted:
-                continue
-            with Context(p, inner_prec=prec, sparse_sandwich=sparse, verbose=1 if args.verbose else 0) as ctx:
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                res = ctx.solve(raise_on_stall=False)
-                torch.cuda.synchronize()
-                solves[name] = {"time_to_gap_s": time.perf_counter() - t0, "status": res["status"],
-                                "iterations": res["iterations"], "pcg_iterations": res["pcg_iterations"],
-                                "fp64_matvecs": res["newton_matvecs"], "lowp_matvecs": res["lp_matvecs"],
-                                "relgap": res["relgap"], "pinf": res["pinf"], "dinf": res["dinf"],
-                                "pobj": res["pobj"]}
-            print(f"solve {name}: {solves[name]}", file=sys.stderr, flush=True)
-        line["ipm"] = solves
-    if not args.no_cpu_baseline:
-        from oracle import reform as rf
-
-        try:
-            from threadpoolctl import threadpool_info
-
-            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-        except Exception:
-            threads = os.cpu_count()
-        w = np.sqrt(x / s)
-        order = np.argsort(-w, kind="stable")
-        lam, Vo = w[order], V[:, order]
-        sp = {"n": n, "r": r0, "tau": 0.5 * lam[r0], "lam": lam, "V": Vo, "Q": Vo[:, :r0], "Qp": Vo[:, r0:],
-              "lam_top": lam[:r0], "lam_perp": lam[r0:]}
-        E = rf.e_matrix(sp)
-        sig = rf.sigma_diag(sp)
-        xh = np.random.default_rng(0).standard_normal(m + rf.dim_d(n, r0))
-        calls = 0
-        t0 = time.perf_counter()
-        while time.perf_counter() - t0 < 15.0:
-            rf.aug_apply(p, sp, E, sig, xh[:m], xh[m:])
-            calls += 1
-        el = time.perf_counter() - t0
-        line["cpu_baseline"] = {
-            "value": calls / el,
-            "unit": "matvec/s",
-            "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"{calls} applications of the oracle's augmented operator (Section 5 products) on the same "
-                      f"workload and point, split supplied in closed form, {el:.1f} s",
-        }
-    print(json.dumps(line))
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--apply-loop", type=int, default=200)
-    ap.add_argument("--pmc-pass", action="store_true", help="only the short run profiled for HBM counters")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solves")
-    ap.add_argument("--workload", choices=["sensing", "batched", "adjoint", "completion"], default="sensing",
-                    help="sensing: the headline line (n=200 dense); batched: 1024 small SDPs in one launch; "
-                         "adjoint: n=1000 completion forward + backward; completion: n=4000 completion operator")
-    ap.add_argument("--verbose", action="store_true",
-                    help="completion --solve: one line per interior-point iteration on stderr")
-    ap.add_argument("--forms", default="f64,f32,bf16,f64_sampled",
-                    help="completion: operator forms to time (comma list of f64, f32, bf16, f64_sampled)")
-    ap.add_argument("--solve", nargs="?", const="f64_sampled,f64,f32,bf16", default="",
-                    help="completion: also time full solves, a comma list of f64_sampled, f64, f32, bf16 "
-                         "(default all)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: every instance of this workload fits one MI355X, "
-              "and the library has no multi-GPU path", file=sys.stderr)
-        sys.exit(2)
-    if args.pmc_pass:
-        pmc_pass()
-        return
-    if args.workload == "batched":
-        bench_batched(args)
-        return
-    if args.workload == "adjoint":
-        bench_adjoint(args)
-        return
-    if args.workload == "completion":
-        bench_completion(args)
-        return
-
+def sensing_line(args, steps, warmup, with_cpu=True, with_mixed=True):
+    """The n=200 dense Gaussian sensing workload: FP64 solves to 1e-8, mixed solves, packed-pass roofline."""
     import torch
 
     import workloads
@@ -475,13 +272,13 @@ def main():
         ctx.set_point(X0, y0, S0)
         return ctx.solve()
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         one_solve()
     torch.cuda.synchronize()
     ctx.profile_enable([L.SDP_K_A_APPLY, L.SDP_K_AT_APPLY])
     results = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         results.append(one_solve())
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -505,21 +302,20 @@ def main():
 
     # the same solves with the mixed-precision inner operator
     mixed = {}
-    if not args.no_mixed:
+    if with_mixed:
         for name, prec in (("f32", L.SDP_PREC_F32), ("bf16", L.SDP_PREC_BF16)):
             mctx = Context(p, inner_prec=prec)
-            mctx.set_point(X0, y0, S0)
 
             def msolve():
                 mctx.set_point(X0, y0, S0)
                 return mctx.solve()
 
-            for _ in range(args.warmup):
+            for _ in range(warmup):
                 msolve()
             torch.cuda.synchronize()
             mres = []
             tm0 = time.perf_counter()
-            for _ in range(args.steps):
+            for _ in range(steps):
                 mres.append(msolve())
             torch.cuda.synchronize()
             mel = time.perf_counter() - tm0
@@ -527,8 +323,8 @@ def main():
             for r in mres:
                 assert r["status"] == 0 and r["relgap"] <= 1e-8, r
             mixed[name] = {
-                "time_to_gap_s": mel / args.steps,
-                "speedup_vs_fp64": (el / args.steps) / (mel / args.steps),
+                "time_to_gap_s": mel / steps,
+                "speedup_vs_fp64": el / mel,
                 "iterations": mres[-1]["iterations"],
                 "fp64_matvecs": mres[-1]["newton_matvecs"],
                 "lowp_matvecs": mres[-1]["lp_matvecs"],
@@ -543,7 +339,6 @@ def main():
     bytes_per = kp["bytes"] / max(kp["launches"], 1)
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9
     kname = "packed_rows_kernel" if kcls == L.SDP_K_A_APPLY else "packed_cols_partial_kernel"
-    traffic = measured_traffic(kname)
 
     # tight loop of the operator at the final point
     N = ctx.aug_dim()
@@ -559,21 +354,15 @@ def main():
     loop_rate = args.apply_loop / (time.perf_counter() - t1)
 
     line = {
-        "metric": METRIC,
         "value": matvecs / el,
         "unit": "matvec/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": el * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": el * 1e3 / steps,
         "dtype": "f64",
-        "data": "synthetic",
         "config": {"workload": WORKLOAD, "precision": "fp64", "ipm_tol": 1e-8, "inner_tol": 1e-10},
         "ipm": {
-            "time_to_gap_s": el / args.steps,
+            "time_to_gap_s": el / steps,
             "iterations": [r["iterations"] for r in results],
             "pcg_iterations": [r["pcg_iterations"] for r in results],
             "newton_matvecs": [r["newton_matvecs"] for r in results],
@@ -592,7 +381,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
+            "traffic": measured_traffic(kname),
             "avg_launch_ms": avg_ms,
             "launches": kp["launches"],
             "bytes_per_launch": bytes_per,
@@ -600,9 +389,288 @@ def main():
         "kernel_time_ms": {"A_apply": prof[L.SDP_K_A_APPLY]["ms"], "AT_apply": prof[L.SDP_K_AT_APPLY]["ms"],
                            "gemm": prof[L.SDP_K_GEMM]["ms"], "newton_apply": prof[L.SDP_K_NEWTON]["ms"]},
     }
-    if not args.no_cpu_baseline:
+    if with_cpu:
         line["cpu_baseline"] = cpu_baseline(p)
     ctx.close()
+    return line
+
+
+SOLVE_FORMS = {  # name: (inner precision, sparse_sandwich)
+    "f64_sampled": (0, 1),
+    "f64": (0, 0),
+    "f32": (1, 0),
+    "bf16": (2, 0),
+}
+
+
+def completion_line(args):
+    """The n=4000 matrix-completion workload: operator rate, its roofline, and the solves to 1e-8."""
+    import torch
+
+    import workloads
+    from paper_2407_14013_amd import Context
+    from paper_2407_14013_amd import _lib as L
+
+    torch.cuda.set_device(0)
+    p = workloads.config(2)
+    n, m, r0, mu = p["n"], p["m"], 4, 1e-2
+    X, S, V, x, s = workloads.centred_pair(n, r0, mu, seed=21)
+    Xd, Sd = torch.from_numpy(X).cuda(), torch.from_numpy(S).cuda()
+    yd = torch.zeros(m, dtype=torch.float64, device="cuda")
+    del X, S
+    flops = 2.0 * n ** 3  # one n x n x n product of E Y E
+    print("completion workload generated", file=sys.stderr, flush=True)
+
+    def xin_for(N):
+        return torch.randn(N, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(0))
+
+    def time_precond(ctx, xin, xout, reps=20):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.precond_apply(xin, xout)
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / reps
+
+    # ---- the headline: FP64 operator with the dense E Y E products ----------------------
+    with Context(p) as ctx:
+        ctx.set_point(Xd, yd, Sd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sc = ctx.get_scaling()  # prepares the scaling point and its split (not timed below)
+        torch.cuda.synchronize()
+        t_scaling = time.perf_counter() - t0
+        N = ctx.aug_dim()
+        xin = xin_for(N)
+        xout = torch.empty_like(xin)
+        for _ in range(args.warmup):
+            ctx.newton_apply(xin, xout)
+        torch.cuda.synchronize()
+        ctx.profile_enable([L.SDP_K_SANDWICH])
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.newton_apply(xin, xout)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sw = ctx.profile_get(L.SDP_K_SANDWICH)
+        ctx.profile_enable([])
+        prec_ms = time_precond(ctx, xin, xout)
+    avg_ms = sw["ms"] / max(sw["launches"], 1)
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    op_ms = 1e3 * el / args.steps
+    forms = {"f64": {"ms_per_matvec": op_ms, "matvec_per_s": args.steps / el, "precond_apply_ms": prec_ms,
+                     "pcg_iterations_per_s": 1e3 / (op_ms + prec_ms), "scaling_setup_s": t_scaling,
+                     "r": sc["r"], "d": N - m,
+                     "sandwich_gemm": {"launches": sw["launches"], "avg_launch_ms": avg_ms,
+                                       "achieved_tflops": achieved, "peak_tflops": MFMA_PEAK_TFLOPS["f64"],
+                                       "frac": achieved / MFMA_PEAK_TFLOPS["f64"]}}}
+    print(f"f64: {op_ms:.3f} ms per operator product, E Y E GEMM {achieved:.1f} TFLOP/s, "
+          f"preconditioner {prec_ms:.3f} ms", file=sys.stderr, flush=True)
+
+    # ---- the other forms of the same operator ---------------------------------------------
+    for name in [f for f in args.forms.split(",") if f and f != "f64"]:
+        prec, sparse = SOLVE_FORMS[name]
+        with Context(p, inner_prec=prec, sparse_sandwich=sparse) as ctx:
+            ctx.set_point(Xd, yd, Sd)
+            ctx.get_scaling()
+            N = ctx.aug_dim()
+            xin = xin_for(N)
+            xout = torch.empty_like(xin)
+            pr = None if prec == 0 else prec
+            for _ in range(3):
+                ctx.newton_apply(xin, xout, prec=pr)
+            torch.cuda.synchronize()
+            classes = [L.SDP_K_SAMPLED_YE, L.SDP_K_SAMPLED_DOTS] if sparse else [L.SDP_K_SANDWICH]
+            ctx.profile_enable(classes)
+            calls = args.form_loop
+            t0 = time.perf_counter()
+            for _ in range(calls):
+                ctx.newton_apply(xin, xout, prec=pr)
+            torch.cuda.synchronize()
+            fel = time.perf_counter() - t0
+            prof = {k: ctx.profile_get(k) for k in classes}
+            ctx.profile_enable([])
+            pms = time_precond(ctx, xin, xout)
+        fms = 1e3 * fel / calls
+        f = {"ms_per_matvec": fms, "matvec_per_s": calls / fel, "precond_apply_ms": pms,
+             "pcg_iterations_per_s": 1e3 / (fms + pms)}
+        if sparse:
+            # both sampled kernels at algorithmic HBM bytes (each operand read once)
+            for key, k in (("sampled_ye", L.SDP_K_SAMPLED_YE), ("sampled_dots", L.SDP_K_SAMPLED_DOTS)):
+                pk = prof[k]
+                gbs = pk["bytes"] / (pk["ms"] * 1e-3) / 1e9
+                f[key] = {"launches": pk["launches"], "avg_launch_ms": pk["ms"] / pk["launches"],
+                          "bytes_per_launch": pk["bytes"] / pk["launches"], "achieved_gbs": gbs,
+                          "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}
+            note = f"Y E {f['sampled_ye']['avg_launch_ms']:.3f} ms, dots {f['sampled_dots']['avg_launch_ms']:.3f} ms"
+        else:
+            pk = prof[L.SDP_K_SANDWICH]
+            tf = flops * pk["launches"] / (pk["ms"] * 1e-3) / 1e12
+            f["sandwich_gemm"] = {"launches": pk["launches"], "avg_launch_ms": pk["ms"] / pk["launches"],
+                                  "achieved_tflops": tf, "peak_tflops": MFMA_PEAK_TFLOPS[name],
+                                  "frac": tf / MFMA_PEAK_TFLOPS[name]}
+            note = f"E Y E GEMM {tf:.1f} TFLOP/s"
+        forms[name] = f
+        print(f"{name}: {fms:.3f} ms per operator product, {note}, preconditioner {pms:.3f} ms", file=sys.stderr,
+              flush=True)
+    del Xd, Sd, yd
+
+    line = {
+        "metric": METRIC,
+        "value": args.steps / el,
+        "unit": "matvec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": op_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": COMPLETION, "step": "one FP64 augmented-operator product, E Y E as two "
+                                                   "n x n x n FP64 MFMA GEMMs"},
+        "roofline": {
+            "kernel": "dgemm_kernel<false, false>: each n x n x n product of E Y E",
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": MFMA_PEAK_TFLOPS["f64"],
+            "unit": "TFLOP/s",
+            "frac": achieved / MFMA_PEAK_TFLOPS["f64"],
+            "traffic": None,
+            "flops_per_launch": flops,
+            "avg_launch_ms": avg_ms,
+            "launches": sw["launches"],
+        },
+        "forms": forms,
+    }
+
+    # ---- solves to the 1e-8 tolerances from the standard start ---------------------------
+    solves = {}
+    for name in [f for f in args.solve.split(",") if f]:
+        prec, sparse = SOLVE_FORMS[name]
+        with Context(p, inner_prec=prec, sparse_sandwich=sparse, verbose=1 if args.verbose else 0) as ctx:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = ctx.solve(raise_on_stall=False)
+            torch.cuda.synchronize()
+            solves[name] = {"time_to_gap_s": time.perf_counter() - t0, "status": res["status"],
+                            "iterations": res["iterations"], "pcg_iterations": res["pcg_iterations"],
+                            "fp64_matvecs": res["newton_matvecs"], "lowp_matvecs": res["lp_matvecs"],
+                            "relgap": res["relgap"], "pinf": res["pinf"], "dinf": res["dinf"], "pobj": res["pobj"]}
+        print(f"solve {name}: {solves[name]}", file=sys.stderr, flush=True)
+    if solves:
+        fp64 = [k for k in solves if k.startswith("f64")]
+        best = min(fp64, key=lambda k: solves[k]["time_to_gap_s"]) if fp64 else None
+        for k, v in solves.items():
+            if best and not k.startswith("f64"):
+                v["speedup_vs_best_fp64"] = solves[best]["time_to_gap_s"] / v["time_to_gap_s"]
+                v["pobj_rel_diff_vs_fp64"] = abs(v["pobj"] - solves[best]["pobj"]) / abs(solves[best]["pobj"])
+        line["ipm"] = {"best_fp64_form": best, **solves}
+
+    if not args.no_config1:
+        c1 = sensing_line(args, steps=3, warmup=1, with_cpu=False)
+        line["config1"] = c1
+        print(f"config 1: {c1['ms_per_step']:.1f} ms to the 1e-8 gap", file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = completion_cpu_baseline(p, x, s, V, r0)
+    return line
+
+
+def completion_cpu_baseline(p, x, s, V, r0, budget_s=15.0):
+    """The oracle's operator at n=4000 (same point) and its time to gap on a reduced instance, beside the GPU's."""
+    import torch
+
+    import workloads
+    from oracle import ipm, reform as rf
+    from paper_2407_14013_amd import Context
+
+    n, m = p["n"], p["m"]
+    w = np.sqrt(x / s)
+    order = np.argsort(-w, kind="stable")
+    lam, Vo = w[order], V[:, order]
+    sp = {"n": n, "r": r0, "tau": 0.5 * lam[r0], "lam": lam, "V": Vo, "Q": Vo[:, :r0], "Qp": Vo[:, r0:],
+          "lam_top": lam[:r0], "lam_perp": lam[r0:]}
+    E = rf.e_matrix(sp)
+    sig = rf.sigma_diag(sp)
+    xh = np.random.default_rng(0).standard_normal(m + rf.dim_d(n, r0))
+    calls = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        rf.aug_apply(p, sp, E, sig, xh[:m], xh[m:])
+        calls += 1
+    el = time.perf_counter() - t0
+    # time to gap: the oracle's direct method on a reduced instance of the same generator
+    nr, rr, mr = REDUCED
+    q = workloads.matrix_completion(nr, rr, mr, seed=2)
+    t0 = time.perf_counter()
+    ores = ipm.solve(q)
+    o_s = time.perf_counter() - t0
+    with Context(q) as ctx:
+        start = [t.clone() for t in ctx.get_point()]
+        ctx.solve()  # warm-up (first use of the kernels at this size)
+        ctx.set_point(*start)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gres = ctx.solve()
+        torch.cuda.synchronize()
+        g_s = time.perf_counter() - t0
+    return {
+        "value": calls / el,
+        "unit": "matvec/s",
+        "cores": host_threads(),
+        "kind": "oracle",
+        "sample": f"{calls} applications of the oracle's augmented operator (Section 5 products) on the same "
+                  f"workload and point, split supplied in closed form, {el:.1f} s",
+        "time_to_gap": {"instance": f"matrix completion n={nr} r={rr} m={mr} (same generator)",
+                        "oracle_s": o_s, "oracle_iterations": ores["iterations"],
+                        "oracle_pobj": ores["history"][-1]["pobj"], "gpu_fp64_s": g_s,
+                        "gpu_iterations": gres["iterations"], "gpu_pobj": gres["pobj"]},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--apply-loop", type=int, default=200, help="sensing: operator products in the tight loop")
+    ap.add_argument("--form-loop", type=int, default=50, help="completion: products timed per extra form")
+    ap.add_argument("--pmc-pass", action="store_true", help="only the short run profiled for HBM counters")
+    ap.add_argument("--no-mixed", action="store_true", help="sensing: skip the mixed-precision solves")
+    ap.add_argument("--no-config1", action="store_true", help="completion: skip the n=200 sensing solves")
+    ap.add_argument("--workload", choices=["completion", "sensing", "batched", "adjoint"], default="completion",
+                    help="completion: the headline line (n=4000 entry sampling); sensing: the n=200 dense line; "
+                         "batched: 1024 small SDPs in one launch; adjoint: n=1000 completion forward + backward")
+    ap.add_argument("--verbose", action="store_true", help="completion: one line per interior-point iteration")
+    ap.add_argument("--forms", default="f64,f64_sampled,f32,bf16",
+                    help="completion: operator forms to time (comma list of f64, f64_sampled, f32, bf16)")
+    ap.add_argument("--solve", default="f64_sampled,bf16",
+                    help="completion: solves to time to the 1e-8 tolerances (comma list of f64_sampled, f64, f32, "
+                         "bf16; empty for none)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: every instance of this workload fits one MI355X, "
+              "and the library has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    if args.pmc_pass:
+        pmc_pass()
+        return
+    if args.workload == "batched":
+        bench_batched(args)
+        return
+    if args.workload == "adjoint":
+        bench_adjoint(args)
+        return
+    if args.workload == "completion":
+        print(json.dumps(completion_line(args)))
+        return
+    line = sensing_line(args, args.steps, args.warmup, with_cpu=not args.no_cpu_baseline,
+                        with_mixed=not args.no_mixed)
+    line = {"metric": METRIC, "value": line.pop("value"), "unit": line.pop("unit"), "n_gpus": 1,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic", **line}
     print(json.dumps(line))
 
 

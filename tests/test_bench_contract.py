@@ -29,9 +29,7 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-@pytest.mark.gpu
-def test_default_bench_prints_one_json_line():
-    r = run_bench("--steps", "1", "--warmup", "0", "--no-cpu-baseline", "--no-mixed", "--apply-loop", "10")
+def one_line(r):
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [ln for ln in r.stdout.splitlines() if ln.strip()]
     assert len(lines) == 1
@@ -45,6 +43,29 @@ def test_default_bench_prints_one_json_line():
     roof = d["roofline"]
     for key in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert key in roof, key
-    assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
-    assert 0.0 < roof["frac"] < 1.0
+    assert 0.0 < roof["frac"] <= 1.0
     assert abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-12
+    return d
+
+
+@pytest.mark.gpu
+def test_default_bench_prints_one_json_line():
+    # the default workload (n = 4000 completion), cut to one step and no solves
+    r = run_bench("--steps", "1", "--warmup", "0", "--no-cpu-baseline", "--no-config1", "--solve", "",
+                  "--forms", "f64,f64_sampled", "--form-loop", "3")
+    d = one_line(r)
+    assert "n=4000" in d["config"]["workload"]
+    roof = d["roofline"]
+    assert roof["bound"] == "mfma" and roof["unit"] == "TFLOP/s" and roof["peak"] == 78.6
+    # the sampled kernels are reported at algorithmic HBM bytes: never above the peak
+    for key in ("sampled_ye", "sampled_dots"):
+        assert 0.0 < d["forms"]["f64_sampled"][key]["frac"] <= 1.0, key
+
+
+@pytest.mark.gpu
+def test_sensing_bench_prints_one_json_line():
+    r = run_bench("--workload", "sensing", "--steps", "1", "--warmup", "0", "--no-cpu-baseline", "--no-mixed",
+                  "--apply-loop", "10")
+    d = one_line(r)
+    roof = d["roofline"]
+    assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
