@@ -266,6 +266,162 @@ __global__ __launch_bounds__(256) void bgemm_sym_kernel(int M, int N, const unsi
             lp_store<OUT>(C, ldc, M, N, row0 + wm * 64 + x * 16, col0 + wn * 64 + y * 16, acc[x][y]);
 }
 
+// The same BF16 product for large n: 256 x 256 output tile per workgroup,
+// four waves in a 2 x 2 grid, each wave a 128 x 128 block of 8 x 8 MFMA tiles
+// (16 x 16 x 32) whose accumulators take 256 registers per lane -- twice the
+// flops per LDS byte of the 128 x 128 kernel.  With one wave per SIMD there
+// is nothing to hide load latency behind, so the operands go from global
+// memory straight into LDS (global_load_lds, 16 bytes per lane, no register
+// staging) through a ring of BS = 4 stages: the loads of step k + 3 are in
+// flight while step k multiplies, and each step ends with a wait for step
+// k + 1's own loads (vmcnt) and a barrier for everyone else's.  A stage holds
+// the step's 32 k-values of the 256 A rows and 256 B columns, 64 bytes per
+// row, with the four 16-byte pieces of row r stored at position
+// piece ^ ((r >> 1) & 3): the fragment reads (16 rows x 4 pieces per
+// instruction) are then free of bank conflicts.  Rows past the matrix edge
+// load a valid row (their outputs are not stored); a ragged K tail is
+// multiplied after the loop from fragments loaded straight from global
+// memory, zero past K.  Consecutive workgroups land on different XCDs (round
+// robin), so the launch index is remapped to give each XCD a compact block of
+// output tiles.  Requirements as for bgemm_sym_kernel.
+constexpr int BT = 256;
+constexpr int BS = 4;                 // stages in the LDS ring
+constexpr int BSTAGE = 2 * BT * 32;   // halves per stage (A rows, then B columns)
+
+__device__ __forceinline__ void xcd_tile(int tiles_m, int tiles_n, int& tm, int& tn) {
+    const int total = tiles_m * tiles_n, id = blockIdx.x;
+    int t = id;
+    if (total % 8 == 0) t = (id % 8) * (total / 8) + id / 8;  // workgroups of one XCD become consecutive
+    // walk the tiles in column panels of 4 tile rows (a compact block per XCD)
+    const int panel = 4;
+    const int full = tiles_m / panel * panel;
+    const int per_panel = panel * tiles_n;
+    if (t < full * tiles_n) {
+        const int pnl = t / per_panel, w = t % per_panel;
+        tm = pnl * panel + w % panel;
+        tn = w / panel;
+    } else {
+        const int rest = tiles_m - full, w = t - full * tiles_n;
+        tm = full + w % rest;
+        tn = w / rest;
+    }
+}
+
+// s_waitcnt vmcnt(n) for n in {0, 8, 16}, leaving expcnt and lgkmcnt alone (gfx9 encoding:
+// vmcnt bits [3:0] and [15:14], expcnt [6:4], lgkmcnt [11:8])
+__device__ __forceinline__ void wait_vmcnt(int n) {
+    if (n >= 16) __builtin_amdgcn_s_waitcnt((1 << 14) | 0x0F70);
+    else if (n >= 8) __builtin_amdgcn_s_waitcnt(0x0F70 | 8);
+    else __builtin_amdgcn_s_waitcnt(0x0F70);
+}
+// s_waitcnt lgkmcnt(0) with vmcnt and expcnt left alone
+__device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+template <LpOut OUT>
+__global__ __launch_bounds__(256) void bgemm_sym256_kernel(int M, int N, const unsigned short* __restrict__ A, long lda,
+                                                           const unsigned short* __restrict__ B, long ldb,
+                                                           void* __restrict__ C, long ldc, int tiles_m, int tiles_n) {
+    extern __shared__ __attribute__((aligned(16))) unsigned short hsm[];
+    const int K = M;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv & 1, wn = wv >> 1;
+    int tm, tn;
+    xcd_tile(tiles_m, tiles_n, tm, tn);
+    const int row0 = tm * BT, col0 = tn * BT;
+    const int full = K / 32;  // steps whose 32 k-values are all in range
+    // load instruction h of wave wv covers c = wv + 4 h: A rows (c < 16) or B columns
+    // 16 (c % 16) .. + 15; lane l fills row l / 4, stage position l % 4
+    const unsigned short* src[8];
+    {
+        const int lrow = lane >> 2, lpos = lane & 3;
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const int c = wv + 4 * h;
+            const int isB = c >> 4, r = 16 * (c & 15) + lrow;
+            const int piece = lpos ^ ((r >> 1) & 3);
+            int g = (isB ? col0 : row0) + r;
+            const int lim = isB ? N : M;
+            g = g < lim ? g : lim - 1;
+            src[h] = (isB ? B + (long)g * ldb : A + (long)g * lda) + 8 * piece;
+        }
+    }
+    auto issue = [&](int st) {
+        unsigned short* stage = hsm + (st % BS) * BSTAGE;
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const int c = wv + 4 * h;
+            __builtin_amdgcn_global_load_lds(src[h] + st * 32, stage + (c >> 4) * BT * 32 + (c & 15) * 16 * 32, 16,
+                                             0, 0);
+        }
+    };
+    v4f acc[8][8];
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+#pragma unroll
+        for (int y = 0; y < 8; ++y) acc[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int pos = (lane >> 4) ^ ((lane >> 1) & 3);
+    const int aoff = (wm * 128 + (lane & 15)) * 32 + 8 * pos;
+    const int boff = BT * 32 + (wn * 128 + (lane & 15)) * 32 + 8 * pos;
+    v8us a[8], b[8];
+    int issued = 0;
+    for (; issued < BS - 1 && issued < full; ++issued) issue(issued);
+    if (full > 0) {
+        wait_vmcnt(8 * (issued - 1));
+        __builtin_amdgcn_s_barrier();
+    }
+    for (int st = 0; st < full; ++st) {
+        // the stage about to be refilled was last read in step st - 1, before its barrier
+        if (issued < full) {
+            issue(issued);
+            ++issued;
+        }
+        const unsigned short* stage = hsm + (st % BS) * BSTAGE;
+#pragma unroll
+        for (int y = 0; y < 8; ++y) b[y] = *reinterpret_cast<const v8us*>(stage + boff + y * 16 * 32);
+#pragma unroll
+        for (int x = 0; x < 8; ++x) a[x] = *reinterpret_cast<const v8us*>(stage + aoff + x * 16 * 32);
+        __builtin_amdgcn_sched_barrier(0);  // every fragment load ahead of the first product
+#pragma unroll
+        for (int x = 0; x < 8; ++x)
+#pragma unroll
+            for (int y = 0; y < 8; ++y)
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a[x]),
+                                                                    __builtin_bit_cast(v8bf, b[y]), acc[x][y], 0, 0,
+                                                                    0);
+        // step st + 1's loads (this wave's) done, this step's fragment reads done, then everyone's
+        const int ahead = issued - st - 2;
+        wait_vmcnt(8 * (ahead > 0 ? ahead : 0));
+        wait_lgkm0();
+        __builtin_amdgcn_s_barrier();
+    }
+    if (K > 32 * full) {
+        // ragged K tail: fragments straight from global memory, zero past K
+        const int k = 32 * full + 8 * (lane >> 4);
+#pragma unroll
+        for (int y = 0; y < 8; ++y) {
+            const int g = col0 + wn * 128 + y * 16 + (lane & 15);
+            b[y] = g < N ? load8_guarded(B + (long)g * ldb + k, k, K) : v8us{0, 0, 0, 0, 0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            const int g = row0 + wm * 128 + x * 16 + (lane & 15);
+            a[x] = g < M ? load8_guarded(A + (long)g * lda + k, k, K) : v8us{0, 0, 0, 0, 0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int x = 0; x < 8; ++x)
+#pragma unroll
+            for (int y = 0; y < 8; ++y)
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a[x]),
+                                                                    __builtin_bit_cast(v8bf, b[y]), acc[x][y], 0, 0,
+                                                                    0);
+    }
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+#pragma unroll
+        for (int y = 0; y < 8; ++y)
+            lp_store<OUT>(C, ldc, M, N, row0 + wm * 128 + x * 16, col0 + wn * 128 + y * 16, acc[x][y]);
+}
+
 // FP32 form of the same product: 128 x 128 tiles, four waves of 4 x 4 MFMA
 // tiles (16 x 16 x 4, FP32).  Within a 32-deep K step, lane group g (= lane /
 // 16) owns the k-run 8g .. 8g + 7 and feeds k = 8g + j to MFMA step j, so the
@@ -388,6 +544,20 @@ bool lp_gemm_sym(hipStream_t st, Lp in, LpOut out, int M, int N, const void* A, 
     }
     const auto* a = static_cast<const unsigned short*>(A);
     const auto* b = static_cast<const unsigned short*>(B);
+    const int tm = cdiv(M, BT), tn = cdiv(N, BT);
+    if ((long)tm * tn >= 200) {
+        // enough 256 x 256 tiles to fill the chip (n >~ 3600)
+        const size_t lds = sizeof(unsigned short) * BS * BSTAGE;  // 128 KB
+        const dim3 g1(static_cast<unsigned>(tm * tn));
+        switch (out) {
+            case LpOut::F32: hipLaunchKernelGGL(bgemm_sym256_kernel<LpOut::F32>, g1, dim3(256), lds, st, M, N, a, lda, b, ldb, C, ldc, tm, tn); break;
+            case LpOut::BF16: hipLaunchKernelGGL(bgemm_sym256_kernel<LpOut::BF16>, g1, dim3(256), lds, st, M, N, a, lda, b, ldb, C, ldc, tm, tn); break;
+            case LpOut::F64: hipLaunchKernelGGL(bgemm_sym256_kernel<LpOut::F64>, g1, dim3(256), lds, st, M, N, a, lda, b, ldb, C, ldc, tm, tn); break;
+            case LpOut::ADD_F64: hipLaunchKernelGGL(bgemm_sym256_kernel<LpOut::ADD_F64>, g1, dim3(256), lds, st, M, N, a, lda, b, ldb, C, ldc, tm, tn); break;
+        }
+        WC_LAUNCH_CHECK();
+        return true;
+    }
     switch (out) {
         case LpOut::F32: hipLaunchKernelGGL(bgemm_sym_kernel<LpOut::F32>, grid, dim3(256), 0, st, M, N, a, lda, b, ldb, C, ldc); break;
         case LpOut::BF16: hipLaunchKernelGGL(bgemm_sym_kernel<LpOut::BF16>, grid, dim3(256), 0, st, M, N, a, lda, b, ldb, C, ldc); break;
@@ -424,6 +594,70 @@ void lp_gemm_nn(hipStream_t st, Lp in, LpOut out, int M, int N, int K, const voi
         case LpOut::F64: lp_gemm_launch<LpOut::F64>(st, in, M, N, K, A, lda, B, ldb, C, ldc); break;
         case LpOut::ADD_F64: lp_gemm_launch<LpOut::ADD_F64>(st, in, M, N, K, A, lda, B, ldb, C, ldc); break;
     }
+}
+
+// ---- entry-sampling pieces of the low-precision operator -----------------------------
+// Y = A^T(u) = sum_i u_i sym(e_j e_k^T) written straight into a zeroed
+// low-precision n x n matrix (the pairs are distinct, so every entry is one
+// u_i or u_i / 2, rounded as to_lowp would round it).
+template <Lp P>
+__global__ void entry_scatter_lp_kernel(int m, const int* __restrict__ jk, const double* __restrict__ u,
+                                        void* __restrict__ Y, long ldy) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int j = jk[2 * i], k = jk[2 * i + 1];
+    const float v = static_cast<float>(j == k ? u[i] : 0.5 * u[i]);
+    if constexpr (P == Lp::F32) {
+        static_cast<float*>(Y)[j + (long)k * ldy] = v;
+        static_cast<float*>(Y)[k + (long)j * ldy] = v;
+    } else {
+        const unsigned short h = bf16_rne(v);
+        static_cast<unsigned short*>(Y)[j + (long)k * ldy] = h;
+        static_cast<unsigned short*>(Y)[k + (long)j * ldy] = h;
+    }
+}
+void entry_scatter_lp(hipStream_t st, Lp p, int m, const int* jk, const double* u, void* Y, long ldy) {
+    if (m <= 0) return;
+    if (p == Lp::F32)
+        hipLaunchKernelGGL(entry_scatter_lp_kernel<Lp::F32>, dim3(cdiv(m, 256)), dim3(256), 0, st, m, jk, u, Y, ldy);
+    else
+        hipLaunchKernelGGL(entry_scatter_lp_kernel<Lp::BF16>, dim3(cdiv(m, 256)), dim3(256), 0, st, m, jk, u, Y, ldy);
+    WC_LAUNCH_CHECK();
+}
+
+// count elements of `bytes` bytes each set to zero (16-byte stores, then the tail)
+__global__ void zero_bytes_kernel(long n16, long nbytes, unsigned char* __restrict__ p) {
+    const long t = blockIdx.x * 256L + threadIdx.x;
+    if (t < n16) {
+        reinterpret_cast<uint4*>(p)[t] = uint4{0u, 0u, 0u, 0u};
+    } else if (t == n16) {
+        for (long b = 16 * n16; b < nbytes; ++b) p[b] = 0;
+    }
+}
+void zero_lowp(hipStream_t st, Lp p, long count, void* X) {
+    const long nbytes = count * lp_bytes(p);
+    if (nbytes <= 0) return;
+    require(reinterpret_cast<uintptr_t>(X) % 16 == 0, "zero_lowp: buffer must be 16-byte aligned");
+    const long n16 = nbytes / 16;
+    hipLaunchKernelGGL(zero_bytes_kernel, dim3(cdiv(n16 + 1, 256)), dim3(256), 0, st, n16, nbytes,
+                       static_cast<unsigned char*>(X));
+    WC_LAUNCH_CHECK();
+}
+
+// out_i = alpha (M_jk + M_kj) / 2 + beta out_i for an FP32 n x n M at the sampled pairs
+__global__ void entry_gather_f32_kernel(int m, const int* __restrict__ jk, const float* __restrict__ M, long ldm,
+                                        double* __restrict__ out, double alpha, double beta) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int j = jk[2 * i], k = jk[2 * i + 1];
+    const double v = 0.5 * (static_cast<double>(M[j + (long)k * ldm]) + static_cast<double>(M[k + (long)j * ldm]));
+    out[i] = (beta == 0.0) ? alpha * v : alpha * v + beta * out[i];
+}
+void entry_gather_f32(hipStream_t st, int m, const int* jk, const float* M, long ldm, double* out, double alpha,
+                      double beta) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(entry_gather_f32_kernel, dim3(cdiv(m, 256)), dim3(256), 0, st, m, jk, M, ldm, out, alpha, beta);
+    WC_LAUNCH_CHECK();
 }
 
 // ---- conversions ---------------------------------------------------------------------

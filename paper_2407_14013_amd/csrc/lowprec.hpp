@@ -32,6 +32,15 @@ void lp_gemm_nn(hipStream_t st, Lp in, LpOut out, int M, int N, int K, const voi
 bool lp_gemm_sym(hipStream_t st, Lp in, LpOut out, int M, int N, const void* A, long lda, const void* B, long ldb,
                  void* C, long ldc);
 
+// Entry sampling: Y = A^T(u) scattered into a zeroed low-precision n x n
+// matrix (each entry rounded as to_lowp rounds it); `count` elements of a
+// low-precision buffer (16-byte aligned) set to zero; out_i = alpha (M_jk +
+// M_kj) / 2 + beta out_i read from an FP32 matrix at the m sampled pairs.
+void entry_scatter_lp(hipStream_t st, Lp p, int m, const int* jk, const double* u, void* Y, long ldy);
+void zero_lowp(hipStream_t st, Lp p, long count, void* X);
+void entry_gather_f32(hipStream_t st, int m, const int* jk, const float* M, long ldm, double* out, double alpha,
+                      double beta);
+
 // B = A rounded to precision p (column-major, rows x cols).
 void to_lowp(hipStream_t st, Lp p, int rows, int cols, const double* A, long lda, void* B, long ldb);
 // y = x rounded to FP32 (count elements).

@@ -676,15 +676,31 @@ void newton_apply_lowp(sdp_ctx* c, const double* in, double* out) {
         gemv_rows(st, d, m, c->AQt, c->ldAQt, u, c->td3, 1.0, 0.0);
         aq_bottom(st, d, c->td3, c->sig, c->tau * c->tau, v, out + m);
     } else {
-        fill(st, (long)n * n, c->Y, 0.0);
-        entry_scatter(st, m, c->jk, u, c->Y, n);
-        to_lowp(st, c->lp, n, n, c->Y, n, c->Ylp, n);
+        // Only the m sampled entries of E Y E + sym(U Q^T) are needed: Y goes
+        // straight into its low-precision copy, E (Y E) is written in FP32 over
+        // that copy (dead once the first product has read it) and gathered,
+        // and the rank-r term and the bottom block come from the pattern at
+        // O(m r) -- no n x n FP64 pass at all.
+        const long nn = (long)n * n;
+        zero_lowp(st, c->lp, nn, c->Ylp);
+        entry_scatter_lp(st, c->lp, m, c->jk, u, c->Ylp, n);
+        hipEvent_t es;
+        const double bytes = (c->lp == Lp::F32 ? 4.0 : 2.0) * 3.0 * nn;
+        prof_begin(c, SDP_K_SANDWICH, &es);
+        if (!lp_gemm_sym(st, c->lp, tout, n, n, c->Ylp, n, c->Elp, n, c->Tlp, n))
+            lp_gemm_nn(st, c->lp, tout, n, n, n, c->Ylp, n, c->Elp, n, c->Tlp, n);
+        prof_end(c, SDP_K_SANDWICH, es, bytes);
+        float* Mf = c->Ylp.get();
+        prof_begin(c, SDP_K_SANDWICH, &es);
+        if (!lp_gemm_sym(st, c->lp, LpOut::F32, n, n, c->Elp, n, c->Tlp, n, Mf, n))
+            lp_gemm_nn(st, c->lp, LpOut::F32, n, n, n, c->Elp, n, c->Tlp, n, Mf, n);
+        prof_end(c, SDP_K_SANDWICH, es, bytes + 2.0 * nn);
+        entry_gather_f32(st, m, c->jk, Mf, n, out, 1.0, 0.0);
+        // top += script-A script-Q v;  bottom = (script-A script-Q)^T u - tau^2 Sigma v
         v_to_h(st, n, r, v, c->Hm);
         gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
-        symlr(st, n, r, c->U, c->Gw, n, c->Mm, n, 0.0);
-        sandwich_lp(c, tout, LpOut::ADD_F64);
-        entry_gather(st, m, c->jk, c->Mm, n, out, 1.0, 0.0);
-        gemm(c, false, false, n, r, n, 1.0, c->Y, n, c->Gw, n, 0.0, c->YQ, n);
+        aq_entry_apply(st, m, n, r, c->jk, c->U, c->Gw, n, out, 1.0, 1.0);
+        entry_yq(st, n, r, c->rptr, c->rcol, c->ridx, u, c->Gw, n, c->YQ);
         gemm(c, true, false, n, r, n, 1.0, c->Gw, n, c->YQ, n, 0.0, c->F, n);
         f_to_v(st, n, r, c->F, n, v, c->sig, c->tau * c->tau, out + m);
     }

@@ -96,13 +96,16 @@ def test_gemm_lp(prec, m, n, k):
     assert e.max() <= 0
 
 
-@pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("m,n", [(17, 5), (200, 200), (1032, 1032), (1100, 1030), (2056, 520)])
+@pytest.mark.parametrize("prec,m,n", [(p, m, n) for p in PRECS
+                                       for m, n in [(17, 5), (200, 200), (1032, 1032), (1100, 1030), (2056, 520)]]
+                         + [(L.SDP_PREC_BF16, 4000, 4000), (L.SDP_PREC_BF16, 3896, 3620)])
 def test_gemm_lp_sym(prec, m, n):
     # the product with a symmetric left operand (the E Y E products of the
     # operator), same bounds as test_gemm_lp with K = m; m = 17 (rows not
     # 16-byte aligned) and m = 200 (fewer than 64 tiles) take the general
-    # kernel, the others the 128 x 128 tiles with ragged row, column and K edges
+    # kernel, the others the 128 x 128 tiles with ragged row, column and K
+    # edges; in BF16 at m = 4000 and m = 3896 (ragged edges and K, 240 and 256
+    # tiles) the 256 x 256-tile kernel
     rng = np.random.default_rng(m * 5 + n)
     M0 = rng.standard_normal((m, m))
     A = 0.5 * (M0 + M0.T)
