@@ -395,11 +395,15 @@ def sensing_line(args, steps, warmup, with_cpu=True, with_mixed=True):
     return line
 
 
-SOLVE_FORMS = {  # name: (inner precision, sparse_sandwich)
-    "f64_sampled": (0, 1),
-    "f64": (0, 0),
-    "f32": (1, 0),
-    "bf16": (2, 0),
+# name: context options (inner precision, sampled A(E Y E) for the FP64 products, refinement mode)
+SOLVE_FORMS = {
+    "f64_sampled": {"inner_prec": 0, "sparse_sandwich": 1},
+    "f64": {"inner_prec": 0},
+    "f32": {"inner_prec": 1},
+    "bf16": {"inner_prec": 2},
+    "bf16_replace": {"inner_prec": 2, "refine_mode": 1},
+    "bf16_replace_sampled": {"inner_prec": 2, "refine_mode": 1, "sparse_sandwich": 1},
+    "f32_replace_sampled": {"inner_prec": 1, "refine_mode": 1, "sparse_sandwich": 1},
 }
 
 
@@ -469,7 +473,8 @@ def completion_line(args):
 
     # ---- the other forms of the same operator ---------------------------------------------
     for name in [f for f in args.forms.split(",") if f and f != "f64"]:
-        prec, sparse = SOLVE_FORMS[name]
+        fo = SOLVE_FORMS[name]
+        prec, sparse = fo["inner_prec"], fo.get("sparse_sandwich", 0)
         with Context(p, inner_prec=prec, sparse_sandwich=sparse) as ctx:
             ctx.set_point(Xd, yd, Sd)
             ctx.get_scaling()
@@ -548,8 +553,7 @@ def completion_line(args):
     # ---- solves to the 1e-8 tolerances from the standard start ---------------------------
     solves = {}
     for name in [f for f in args.solve.split(",") if f]:
-        prec, sparse = SOLVE_FORMS[name]
-        with Context(p, inner_prec=prec, sparse_sandwich=sparse, verbose=1 if args.verbose else 0) as ctx:
+        with Context(p, verbose=1 if args.verbose else 0, **SOLVE_FORMS[name]) as ctx:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             res = ctx.solve(raise_on_stall=False)
@@ -648,8 +652,8 @@ def main():
     ap.add_argument("--forms", default="f64,f64_sampled,f32,bf16",
                     help="completion: operator forms to time (comma list of f64, f64_sampled, f32, bf16)")
     ap.add_argument("--solve", default="f64_sampled,bf16",
-                    help="completion: solves to time to the 1e-8 tolerances (comma list of f64_sampled, f64, f32, "
-                         "bf16; empty for none)")
+                    help="completion: solves to time to the 1e-8 tolerances (comma list of "
+                         + ", ".join(SOLVE_FORMS) + "; empty for none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every instance of this workload fits one MI355X, "

@@ -60,6 +60,7 @@ enum {
 enum { SDP_A_DENSE = 0, SDP_A_ENTRY = 1 };
 enum { SDP_SOLVER_PCG = 0, SDP_SOLVER_MINRES = 1 };
 enum { SDP_PREC_F64 = 0, SDP_PREC_F32 = 1, SDP_PREC_BF16 = 2 };
+enum { SDP_REFINE_SWEEPS = 0, SDP_REFINE_REPLACE = 1 };
 
 /*
  * Problem data (Introduction, eq. sdp-pd).
@@ -106,18 +107,29 @@ typedef struct sdp_problem {
  *               point, its eigen-decomposition, the preconditioner, residuals
  *               and step lengths stay FP64.
  *  max_refine   FP64 refinement sweeps around a low-precision inner solve [8]
- *  refine_tol   relative residual reduction asked of each low-precision PCG
- *               run inside a refinement sweep (0: 1e-6 for FP32, 1e-3 for
- *               BF16); later sweeps ask only for the reduction still missing
- *               to inner_tol when that is larger [0]
+ *  refine_mode  how the FP64 refinement corrects the low-precision inner
+ *               solve [SDP_REFINE_SWEEPS]: SDP_REFINE_SWEEPS restarts a
+ *               low-precision PCG run on each FP64 residual (classic
+ *               iterative refinement); SDP_REFINE_REPLACE runs one PCG with
+ *               the low-precision operator and replaces its recursive
+ *               residual by the FP64 residual g - K x whenever it has dropped
+ *               by refine_tol since the last replacement, keeping the search
+ *               direction (the Krylov space survives the correction)
+ *  refine_tol   SWEEPS: relative residual reduction asked of each low-precision
+ *               PCG run (0: 1e-6 for FP32, 1e-3 for BF16); later sweeps ask
+ *               only for the reduction still missing to inner_tol when that is
+ *               larger.  REPLACE: reduction between two replacements (0: 1e-2
+ *               for FP32, 1e-1 for BF16) [0]
  *  gap_tol, feas_tol   stopping tolerances of the interior-point method [1e-8]
  *  max_ipm_iter [100]
  *  step_frac    fraction of the step to the boundary [0.98]
  *  verbose      0 silent, 1 one line per interior-point iteration and one per
  *               scaling setup with its phase timings (the stream is synchronised
  *               between phases), 2 also one line per Krylov iteration (stderr) [0]
- *  sparse_sandwich  entry-sampling constraints only, FP64 inner precision,
- *               n <= 16384: nonzero forms the A E A^T block of the operator
+ *  sparse_sandwich  entry-sampling constraints only, n <= 16384: nonzero
+ *               forms the A E A^T block of the FP64 operator (with a
+ *               low-precision inner_prec: of the FP64 products that the
+ *               refinement takes its residuals with)
  *               (Section 5) at the sampled pairs only, as Z = A^T(u) E (a
  *               sparse-dense product) followed by one length-n dot product
  *               per constraint, instead of the two dense n x n x n products
@@ -140,11 +152,12 @@ typedef struct sdp_options {
     int32_t verbose;
     double refine_tol;
     int32_t sparse_sandwich;
+    int32_t refine_mode;
 } sdp_options;
 
 typedef struct sdp_inner_stats {
     int32_t iterations;     /* Krylov iterations (summed over refinement sweeps) */
-    int32_t refinements;    /* FP64 refinement sweeps (0 in FP64 mode) */
+    int32_t refinements;    /* FP64 refinement sweeps, or FP64 residual replacements (0 in FP64 mode) */
     int32_t converged;      /* 1 if the tolerance was met */
     int32_t r;              /* rank parameter of the split */
     double tau;             /* lambda_{r+1}(W) / 2 */

@@ -18,6 +18,7 @@ SDP_ADJOINT_CENTER_TOL = 1e-6
 SDP_A_DENSE, SDP_A_ENTRY = 0, 1
 SDP_SOLVER_PCG, SDP_SOLVER_MINRES = 0, 1
 SDP_PREC_F64, SDP_PREC_F32, SDP_PREC_BF16 = 0, 1, 2
+SDP_REFINE_SWEEPS, SDP_REFINE_REPLACE = 0, 1
 SDP_K_A_APPLY, SDP_K_AT_APPLY, SDP_K_GEMM, SDP_K_NEWTON, SDP_K_SANDWICH = 0, 1, 2, 3, 4
 SDP_K_SAMPLED_YE, SDP_K_SAMPLED_DOTS = 5, 6
 SDP_K_COUNT = 7
@@ -64,6 +65,7 @@ class SdpOptions(C.Structure):
         ("verbose", C.c_int32),
         ("refine_tol", C.c_double),
         ("sparse_sandwich", C.c_int32),
+        ("refine_mode", C.c_int32),
     ]
 
 

@@ -67,6 +67,7 @@ void sdp_default_options(sdp_options* o) {
     o->verbose = 0;
     o->refine_tol = 0.0;
     o->sparse_sandwich = 0;
+    o->refine_mode = SDP_REFINE_SWEEPS;
 }
 
 sdp_status sdp_setup(const sdp_problem* prob, const sdp_options* opt, void* hip_stream, sdp_ctx** out) {
@@ -96,9 +97,10 @@ sdp_status sdp_setup(const sdp_problem* prob, const sdp_options* opt, void* hip_
                         "inner_prec must be SDP_PREC_F64, SDP_PREC_F32 or SDP_PREC_BF16");
             wc::require(opt->max_refine >= 0, "max_refine must be non-negative");
             wc::require(opt->refine_tol >= 0 && opt->refine_tol < 1, "refine_tol must lie in [0, 1)");
+            wc::require(opt->refine_mode == SDP_REFINE_SWEEPS || opt->refine_mode == SDP_REFINE_REPLACE,
+                        "refine_mode must be SDP_REFINE_SWEEPS or SDP_REFINE_REPLACE");
             if (opt->sparse_sandwich) {
                 wc::require(prob && prob->a_kind == SDP_A_ENTRY, "sparse_sandwich needs entry-sampling constraints");
-                wc::require(opt->inner_prec == SDP_PREC_F64, "sparse_sandwich runs with the FP64 operator only");
                 wc::require(prob->n <= 16384, "sparse_sandwich needs n <= 16384");
             }
         }

@@ -805,22 +805,37 @@ static void recover(sdp_ctx* c, const double* x, const double* Ct, double* dX, d
 // already in x, preconditioned as in Section 6, with the FP64 operator or its
 // low-precision form.  Stops when ||r_u|| <= tol_rel ||r_u(0)|| or after maxit
 // iterations.  Uses vr, vz, vp, vKp.
+//
+// replace > 0 (low-precision operator only): FP64 residual replacement.  The
+// starting residual is the FP64 one.  Once the recursive residual has dropped
+// by the factor `replace` since the last replacement (or meets the
+// tolerance), the next iteration replaces its updated residual by the FP64
+// residual g - K x before forming z = P^{-1} r, beta and the new search
+// direction -- the order of a reliable update, so the direction stays
+// consistent with the residual it came from.  If the FP64 residual shows no
+// progress since the previous replacement, the direction restarts at p = z.
+// The loop stops only on an FP64 residual that meets the tolerance.  Also
+// uses vres.
 struct PcgOut {
     int it = 0;
     double ref = 0, rr = 0;
+    int replacements = 0;
     bool conv = false;
 };
-static PcgOut pcg_loop(sdp_ctx* c, bool lowp, const double* g, double* x, double tol_rel, int maxit) {
+static PcgOut pcg_loop(sdp_ctx* c, bool lowp, const double* g, double* x, double tol_rel, int maxit,
+                       double replace = 0.0) {
     const int m = c->m, d = c->d;
     const long N = (long)m + d;
     hipStream_t st = c->st;
     double* sc = c->sc;
+    const bool rep = lowp && replace > 0.0;
     auto K = [&](const double* in, double* out) {
         if (lowp) newton_apply_lowp(c, in, out);
         else newton_apply(c, in, out);
     };
     // r = g - K x with its bottom block zero (Corollary pcg), z = P^{-1} r, p = z
-    K(x, c->vKp);
+    if (rep) newton_apply(c, x, c->vKp);
+    else K(x, c->vKp);
     axpbypcz(st, N, 1.0, g, -1.0, c->vKp, 0.0, c->vr);
     fill(st, d, c->vr + m, 0.0);
     precond_apply(c, c->vr, c->vz);
@@ -832,23 +847,45 @@ static PcgOut pcg_loop(sdp_ctx* c, bool lowp, const double* g, double* x, double
     o.ref = std::sqrt(c->pin[0]);
     o.rr = o.ref;
     const double tol = tol_rel * (o.ref > 0 ? o.ref : 1.0);
-    bool have_kp = false;  // vKp already holds K p for the current p
+    double last = o.ref;    // FP64 residual norm at the last replacement
+    bool is_true = true;    // o.rr is an FP64 residual norm
+    bool have_kp = false;   // vKp already holds K p for the current p
     while (true) {
-        if (!(o.rr > tol)) {
+        if (!(o.rr > tol) && (is_true || !rep)) {
             o.conv = std::isfinite(o.rr);
             break;
         }
         if (o.it >= maxit) break;
+        // o.rr is the residual this iteration starts from (recursive when replacing)
+        const bool do_rep = rep && !is_true && (!(o.rr > tol) || o.rr <= replace * last || !std::isfinite(o.rr));
         if (!have_kp) K(c->vp, c->vKp);
         have_kp = false;
         dot(st, N, c->vp, c->vKp, sc + 1, c->part);
         pcg_alpha(st, sc);
         pcg_xr(st, N, m, x, c->vr, c->vp, c->vKp, sc);
-        dot(st, m, c->vr, c->vr, sc + 4, c->part);
+        bool restart = false;
+        if (do_rep) {
+            // the updated residual replaced by g - K x in FP64 (bottom block zero)
+            newton_apply(c, x, c->vres);
+            axpbypcz(st, N, 1.0, g, -1.0, c->vres, 0.0, c->vr);
+            fill(st, d, c->vr + m, 0.0);
+            dot(st, m, c->vr, c->vr, sc + 4, c->part);
+            fetch(c, sc + 4, 1);
+            const double rt = std::sqrt(c->pin[0]);
+            restart = !(rt < last);
+            last = rt;
+            ++o.replacements;
+            if (c->opt.verbose >= 2)
+                fprintf(stderr, "[wcsdp]   replace %d at it %d: |r_u| / |r_u(0)| %.3e%s\n", o.replacements, o.it,
+                        o.ref > 0 ? rt / o.ref : 0.0, restart ? " (no progress: direction restarted)" : "");
+        } else {
+            dot(st, m, c->vr, c->vr, sc + 4, c->part);
+        }
         precond_apply(c, c->vr, c->vz);
         dot(st, N, c->vr, c->vz, sc + 5, c->part);
         pcg_beta(st, sc);
-        pcg_p(st, N, c->vp, c->vz, sc);
+        if (restart) copy(st, N, c->vz, c->vp);
+        else pcg_p(st, N, c->vp, c->vz, sc);
         ++o.it;
         if (c->opt.verbose >= 2) {
             dot(st, d, c->vr + m, c->vr + m, sc + 6, c->part);
@@ -868,6 +905,7 @@ static PcgOut pcg_loop(sdp_ctx* c, bool lowp, const double* g, double* x, double
         }
         WC_HIP(hipEventSynchronize(c->ev_rr));
         o.rr = std::sqrt(c->pin[0]);
+        is_true = !rep || do_rep;
     }
     // a product started for an iteration that did not run is not counted
     if (have_kp) {
@@ -993,6 +1031,18 @@ int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, doub
         ref = o.ref;
         rr = o.rr;
         conv = o.conv;
+    } else if (c->opt.refine_mode == SDP_REFINE_REPLACE) {
+        // one low-precision PCG run whose residual is replaced by the FP64 one
+        // after every reduction by `rep` (0 selects a factor that suits the
+        // precision: a BF16 operator keeps the recursive residual accurate to
+        // ~1e-3 of the residual at the last replacement)
+        const double rep = c->opt.refine_tol > 0 ? c->opt.refine_tol : (c->lp == Lp::BF16 ? 1e-1 : 1e-2);
+        PcgOut o = pcg_loop(c, true, c->vg, c->vx, c->opt.inner_tol, c->opt.inner_maxit, rep);
+        its = o.it;
+        ref = o.ref;
+        rr = o.rr;
+        conv = o.conv;
+        sweeps = o.replacements;
     } else {
         // 0 selects the reduction that suits the precision: BF16 GEMM operands
         // (u = 2^-8) make each sweep's correction accurate to ~1e-3 only

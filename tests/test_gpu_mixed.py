@@ -181,10 +181,16 @@ def test_newton_apply_lowp_close_to_oracle(prec, which):
     assert elp > 0  # the low-precision path really ran
 
 
+MODES = [L.SDP_REFINE_SWEEPS, L.SDP_REFINE_REPLACE]
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("which", ["cfg0", "entry"])
+@pytest.mark.parametrize("which", ["cfg0", "entry", "entry_sampled"])
 @pytest.mark.parametrize("iters", [2, 6])
-def test_inner_solve_mixed_meets_fp64_bars(prec, which, iters):
+def test_inner_solve_mixed_meets_fp64_bars(prec, which, iters, mode):
+    # both refinement modes (restarted sweeps, FP64 residual replacement);
+    # entry_sampled takes the FP64 residuals with the sampled A(E Y E)
     p = workloads.config(0) if which == "cfg0" else small_entry()
     X, y, S = ipm_point(p, iters)
     r = ipm.residuals(p, X, y, S)
@@ -192,7 +198,7 @@ def test_inner_solve_mixed_meets_fp64_bars(prec, which, iters):
     bt = r["rp"]
     G, d, Lf = nt.nt_factor(X, S)
     W = G @ G.T
-    with Context(p, inner_prec=prec) as ctx:
+    with Context(p, inner_prec=prec, refine_mode=mode, sparse_sandwich=int(which == "entry_sampled")) as ctx:
         ctx.set_point(dev(X), dev(y), dev(S))
         dX, dy, st = ctx.inner_solve(dev(bt), dev(Ct))
     dX, dy = host(dX), host(dy)
@@ -202,7 +208,7 @@ def test_inner_solve_mixed_meets_fp64_bars(prec, which, iters):
     Gi = np.linalg.inv(G)
     rhs = G.T @ (ops.at_op(p, dy) - Ct) @ G
     e_second = np.linalg.norm(Gi @ dX @ Gi.T - rhs) / np.linalg.norm(rhs)
-    print(f"{which} it {iters} prec {prec}: sweeps {st['refinements']} pcg {st['iterations']} "
+    print(f"{which} it {iters} prec {prec} mode {mode}: sweeps {st['refinements']} pcg {st['iterations']} "
           f"primal {e_primal:.1e} second {e_second:.1e}")
     assert e_primal <= 1e-9
     assert e_second <= 1e-8
@@ -215,11 +221,12 @@ def _solve(p, prec, **kw):
     return res, host(X), host(y), host(S)
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("prec", PRECS)
-def test_solve_mixed_config0_and_entry(prec):
+def test_solve_mixed_config0_and_entry(prec, mode):
     for p in (workloads.config(0), small_entry()):
         ref = ipm.solve(p)
-        res, X, y, S = _solve(p, prec)
+        res, X, y, S = _solve(p, prec, refine_mode=mode)
         assert res["status"] == 0 and res["lp_matvecs"] > 0
         c = certify.certificate(p, X, y, S)
         assert c["pinf"] <= 1.01e-8 and c["dinf"] <= 1.01e-8 and c["relgap"] <= 1.01e-8, c
@@ -230,19 +237,20 @@ def test_solve_mixed_config0_and_entry(prec):
         assert e_X <= 1e-6
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("prec", PRECS)
-def test_solve_mixed_config1_matches_oracle(prec):
+def test_solve_mixed_config1_matches_oracle(prec, mode):
     with open(GOLDEN1) as f:
         gold = json.load(f)
     p = workloads.config(1)
-    res, X, y, S = _solve(p, prec)
+    res, X, y, S = _solve(p, prec, refine_mode=mode)
     assert res["status"] == 0 and res["lp_matvecs"] > 0
     c = certify.certificate(p, X, y, S)
     assert c["pinf"] <= 1.01e-8 and c["dinf"] <= 1.01e-8 and c["relgap"] <= 1.01e-8, c
     e_obj = abs(c["pobj"] - gold["certificate"]["pobj"]) / abs(gold["certificate"]["pobj"])
     Xs = p["U"] @ p["U"].T
     e_rec = np.linalg.norm(X - Xs) / np.linalg.norm(Xs)
-    print(f"n=200 sensing, prec {prec}: objective error {e_obj:.1e}, planted recovery {e_rec:.1e}, "
+    print(f"n=200 sensing, prec {prec} mode {mode}: objective error {e_obj:.1e}, planted recovery {e_rec:.1e}, "
           f"fp64 matvecs {res['newton_matvecs']}, low-precision matvecs {res['lp_matvecs']}")
     assert e_obj <= 1e-8
     assert e_rec <= 1e-6

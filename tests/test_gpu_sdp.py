@@ -185,7 +185,9 @@ def test_sparse_sandwich_rejects_unsupported_options():
     with pytest.raises(SdpError):
         Context(workloads.config(0), sparse_sandwich=1)
     with pytest.raises(SdpError):
-        Context(small_entry(), sparse_sandwich=1, inner_prec=L.SDP_PREC_F32)
+        Context(small_entry(), refine_mode=2)
+    # with a low-precision inner operator the option selects the FP64 products' form
+    Context(small_entry(), sparse_sandwich=1, inner_prec=L.SDP_PREC_F32).close()
 
 
 @pytest.mark.parametrize("which", ["cfg0", "entry", "entry150"])
