@@ -2,7 +2,9 @@
 
 An uneven batch of Gaussian sensing problems (n from 18 to 30, r in {1,2,3},
 m = 3 n r, the generator of the batched workload at sizes the oracle solves
-in seconds) is solved in one launch and every instance is checked like the
+in seconds), and a sample spread over the workload's whole size range (n from
+16 to 128, r in {1,2,3}, including the m-capped n = 16, r = 3 case), are each
+solved in one launch and every instance is checked like the
 single-instance solver: objective within 1e-8 of the oracle's, relative gap
 and primal infeasibility <= 1e-8 recomputed on the CPU from the returned X
 and y, X positive definite and C - A^T(y) PSD to rounding, and the planted
@@ -65,3 +67,21 @@ def test_batched_autotune_and_single_instances_agree():
         assert r_all[i]["status"] == 0 and r_one[0]["status"] == 0
         e = abs(r_all[i]["pobj"] - r_one[0]["pobj"]) / abs(r_one[0]["pobj"])
         assert e <= 1e-10
+
+
+# (n, r) across the batched workload's range: n = 16 with r = 3 has m = 3 n r
+# = 144 capped at n (n + 1) / 2 = 136, the largest instances have n = 128
+SPREAD = [(16, 3), (40, 1), (64, 2), (96, 3), (128, 1), (128, 3)]
+
+
+def test_batched_size_spread_matches_oracle():
+    probs = [workloads.gaussian_sensing(n, r, min(3 * n * r, n * (n + 1) // 2), seed=100 + i)
+             for i, (n, r) in enumerate(SPREAD)]
+    assert probs[0]["m"] == 136
+    refs = [ipm.solve(p)["history"][-1]["pobj"] for p in probs]
+    results, Xs, ys = solve_batched(probs, want_y=True)
+    for i, p in enumerate(probs):
+        e_obj, e_rec = check_instance(p, results[i], Xs[i], ys[i], refs[i])
+        print(f"instance {i}: n {p['n']} r {p['r']} m {p['m']} its {results[i]['iterations']} "
+              f"pcg {results[i]['pcg_iterations']} objective error {e_obj:.1e} recovery {e_rec:.1e}")
+        assert e_rec <= 1e-6
