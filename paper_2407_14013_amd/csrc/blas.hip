@@ -5,6 +5,7 @@
 #include <cstdint>
 
 #include "common.hpp"
+#include "launch_plan.hpp"
 
 namespace wc {
 
@@ -18,11 +19,8 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 // supplies A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator element v of
 // lane l is D[l / 16 + 4 v][l % 16].
 // ---------------------------------------------------------------------------
-constexpr int GBM = 64, GBN = 64, GBK = 16;
 constexpr int GBIG = 128;  // tile edge for large products
 constexpr size_t dgemm_lds(int bm, int bn) { return sizeof(double) * 2 * GBK * (bm + 1 + bn + 1); }
-constexpr int GEMM_SPLITS = 8;        // most K-splits of a small product
-constexpr int GEMM_SPLIT_TILES = 64;  // split K only below this many output tiles
 
 // Block tile BM x BN (64 x 64 or 128 x 128), four waves in a 2 x 2 grid, each
 // wave (BM/2) x (BN/2) of 16 x 16 FP64 MFMA tiles.  K advances GBK at a time
@@ -34,19 +32,32 @@ constexpr int GEMM_SPLIT_TILES = 64;  // split K only below this many output til
 // accumulator through vector registers at once (the compiler schedules the
 // reads together), which halves the occupancy of the 128 x 128 form, so that
 // form is only instantiated with EPI = 0.
+// tri: 0 every tile; 1 only the lower triangle (row >= col) is written
+// (symmetric rank-k updates); 2 op(A) and op(B) are triangular with
+// op(A)_ik = 0 for k < i and op(B)_kj = 0 for k < j (C = Z^T Z with Z lower
+// triangular): only the tiles that touch the upper triangle run, each from
+// k = max(its first row, its first column), and they are written whole.
 template <bool TA, bool TB, int BM, int BN, int EPI>
 __global__ __launch_bounds__(256) void dgemm_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
                                                     long lda, const double* __restrict__ B, long ldb, double beta,
-                                                    double* __restrict__ C, long ldc, int lower_only, long sA,
+                                                    double* __restrict__ C, long ldc, int tri, long sA,
                                                     long sB, long sC, int klast) {
     // split-K launches give the last z-slice the remainder of K
     if (klast > 0 && blockIdx.z == gridDim.z - 1) K = klast;
     const int tile_m = blockIdx.x * BM;
     const int tile_n = blockIdx.y * BN;
-    if (lower_only && tile_n > tile_m + BM - 1) return;
+    if (tri == 1 && tile_n > tile_m + BM - 1) return;
     A += blockIdx.z * sA;
     B += blockIdx.z * sB;
     C += blockIdx.z * sC;
+    if (tri == 2) {
+        if (tile_m > tile_n + BN - 1) return;
+        // every term with k < max(i, j) vanishes; tile starts are multiples of GBK
+        const int ks = max(tile_m, tile_n);
+        A += TA ? (long)ks : (long)ks * lda;
+        B += TB ? (long)ks * ldb : (long)ks;
+        K -= ks;
+    }
 
     extern __shared__ double gsm[];
     double (*As)[GBK][BM + 1] = reinterpret_cast<double (*)[GBK][BM + 1]>(gsm);
@@ -142,7 +153,7 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int M, int N, int K, double 
             for (int v = 0; v < 4; ++v) {
                 const int gi = tile_m + wm * (BM / 2) + a * 16 + (lane >> 4) + 4 * v;
                 const int gj = tile_n + wn * (BN / 2) + b * 16 + (lane & 15);
-                if (gi < M && gj < N && (!lower_only || gi >= gj)) {
+                if (gi < M && gj < N && (tri != 1 || gi >= gj)) {
                     double* c = C + gi + (long)gj * ldc;
                     if constexpr (EPI == 0) *c = acc[a][b][v];
                     else if constexpr (EPI == 1) *c = alpha * acc[a][b][v];
@@ -224,28 +235,37 @@ void dgemm(hipStream_t st, bool ta, bool tb, int m, int n, int k, double alpha, 
     };
     // Few output tiles and a long K (the n = 200 products): split K over the
     // z dimension into partial products, then add them in a fixed order.
-    if (batch == 1 && !lower_only && ws != nullptr && tiles < GEMM_SPLIT_TILES && k >= 64) {
-        int splits = static_cast<int>(std::min<long>(GEMM_SPLITS, std::min<long>(cdiv(k, 32), cdiv(128, tiles))));
-        if (splits >= 2) {
-            const int kc = static_cast<int>(round_up(cdiv(k, splits), GBK));
-            splits = cdiv(k, kc);
-            if (splits >= 2 && (long)splits * m * n <= ws_len) {
-                const int klast = k - (splits - 1) * kc;
-                const long sa = ta ? kc : (long)kc * lda, sb = tb ? (long)kc * ldb : kc;
-                // each slice computes K = kc (the last one klast) from its offset operands
-                launch(dim3(cdiv(m, GBM), cdiv(n, GBN), splits), false, kc, 1.0, 0.0, ws, m, sa, sb, (long)m * n,
-                       klast);
-                hipLaunchKernelGGL(dgemm_reduce_kernel, dim3(cdiv((long)m * n, 256)), dim3(256), 0, st, m, n, splits,
-                                   ws, alpha, beta, C, ldc);
-                WC_LAUNCH_CHECK();
-                return;
-            }
+    if (batch == 1 && !lower_only && ws != nullptr) {
+        const SplitPlan sp = dgemm_split_plan(m, n, k, ws_len, GBM, GBN, GBK, GEMM_SPLITS, GEMM_SPLIT_TILES);
+        if (sp.splits >= 2) {
+            const int kc = sp.kc, splits = sp.splits;
+            const long sa = ta ? kc : (long)kc * lda, sb = tb ? (long)kc * ldb : kc;
+            // each slice computes K = kc (the last one klast) from its offset operands
+            launch(dim3(cdiv(m, GBM), cdiv(n, GBN), splits), false, kc, 1.0, 0.0, ws, m, sa, sb, (long)m * n,
+                   sp.klast);
+            hipLaunchKernelGGL(dgemm_reduce_kernel, dim3(cdiv((long)m * n, 256)), dim3(256), 0, st, m, n, splits,
+                               ws, alpha, beta, C, ldc);
+            WC_LAUNCH_CHECK();
+            return;
         }
     }
     // 128 x 128 tiles once they still give every CU several workgroups (plain C = A B only)
     const bool big = alpha == 1.0 && beta == 0.0 && (long)cdiv(m, GBIG) * cdiv(n, GBIG) * batch >= 4L * 256;
     if (big) launch(dim3(cdiv(m, GBIG), cdiv(n, GBIG), batch), true, k, alpha, beta, C, ldc, sA, sB, sC, 0);
     else launch(dim3(cdiv(m, GBM), cdiv(n, GBN), batch), false, k, alpha, beta, C, ldc, sA, sB, sC, 0);
+}
+
+// C = Z^T Z for a lower-triangular n x n Z (column-major, ldz): the tiles
+// touching the upper triangle of C, each summing only k >= max(row, col), so
+// n^3 / 3 flops instead of 2 n^3.  Entries below the diagonal outside the
+// diagonal tiles are not written.
+void dgemm_lauum_upper(hipStream_t st, int n, const double* Z, long ldz, double* C, long ldc) {
+    if (n <= 0) return;
+    const bool big = (long)cdiv(n, GBIG) * cdiv(n, GBIG) >= 4L * 256;
+    const int bt = big ? GBIG : GBM;
+    dgemm_launch<true, false>(st, dim3(cdiv(n, bt), cdiv(n, bt), 1), big, n, n, n, 1.0, Z, ldz, Z, ldz, 0.0, C, ldc,
+                              2, 0, 0, 0, 0);
+    WC_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------
@@ -256,8 +276,6 @@ void dgemm(hipStream_t st, bool ta, bool tb, int m, int n, int k, double alpha, 
 // over K, wave reduction.
 // ---------------------------------------------------------------------------
 constexpr int THIN_N = 16;
-constexpr int THIN_LDS = 4096;  // doubles of B staged in LDS
-constexpr int THIN_SPLITS = 32;  // most K-splits of the split-K form
 
 // 64 rows per workgroup; the four waves split K and their partial sums are
 // added in LDS in wave order.
@@ -495,12 +513,9 @@ bool dgemm_thin(hipStream_t st, bool ta, int m, int n, int k, double alpha, cons
     if (!ta) {
         // one workgroup per 64 rows covers the chip only for m >= 64 * #CUs;
         // otherwise split K as well (when a workspace is given)
-        int splits = std::max(1, cdiv((long)k * n, THIN_LDS));
-        // about 2048 workgroups (8 waves per SIMD) keep enough loads in flight
-        if (ws != nullptr) splits = std::max(splits, std::min(cdiv(k, 128), cdiv(2048, cdiv(m, 64))));
-        splits = std::min(splits, THIN_SPLITS);
-        const int kc = cdiv(k, splits);
-        splits = cdiv(k, kc);
+        // (about 2048 workgroups, 8 waves per SIMD, keep enough loads in flight)
+        const SplitPlan sp = thin_split_plan(m, n, k, ws != nullptr, THIN_LDS, THIN_SPLITS);
+        const int kc = sp.kc, splits = sp.splits;
         if (splits == 1) {
             const size_t lds = sizeof(double) * (size_t)k * n;
             if (n <= 4)

@@ -78,6 +78,10 @@ inline long round_up(long a, long b) { return ((a + b - 1) / b) * b; }
 // ---------------------------------------------------------------------------
 // blas.hip
 // ---------------------------------------------------------------------------
+// C = Z^T Z for a lower-triangular n x n Z: only the upper triangle of C is
+// guaranteed (n^3 / 3 flops); the symmetric product kernel reads no other.
+void dgemm_lauum_upper(hipStream_t st, int n, const double* Z, long ldz, double* C, long ldc);
+
 // C = alpha op(A) op(B) + beta C, column-major.  lower_only writes only the
 // entries with row >= col (used for symmetric rank-k updates).  Batched over
 // `batch` with element strides sA, sB, sC.

@@ -17,8 +17,11 @@ EPS = np.finfo(np.float64).eps
 @pytest.mark.parametrize("tb", ["N", "T"])
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1), (17, 33, 9), (64, 64, 64), (130, 67, 95), (200, 200, 200), (65, 1, 129),
                                    (200, 3, 200), (301, 16, 77), (5000, 2, 300), (4000, 4, 4000), (300, 10, 1000),
-                                   (77, 3, 20000)])
+                                   (77, 3, 20000), (130, 70, 1001), (200, 200, 333), (64, 64, 97)])
 def test_dgemm(ta, tb, m, n, k):
+    # (200, 200, 200) and the last three take the split-K path of few-tile
+    # products; the last three with a ragged last slice (K = 1001: 7 x 128 +
+    # 105; K = 333: 6 x 48 + 45; K = 97: 3 x 32 + 1)
     rng = np.random.default_rng(m * 1000 + n * 10 + k)
     A = rng.standard_normal((k, m) if ta == "T" else (m, k))
     B = rng.standard_normal((n, k) if tb == "T" else (k, n))
