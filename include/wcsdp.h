@@ -305,7 +305,13 @@ typedef struct sdp_batch_tune {
 /*
  * Solve `count` independent problems in one persistent launch: each
  * workgroup takes instances from a queue (largest first) and runs the whole
- * interior-point method of sdp_solve (FP64, PCG) for one instance at a time.
+ * interior-point method of sdp_solve (PCG) for one instance at a time.
+ * opt->inner_prec SDP_PREC_F64 (default) or SDP_PREC_F32: with FP32 the inner
+ * operator reads an FP32 copy of the packed rows in both constraint passes
+ * and forms E Y E on the FP32 matrix cores (off-diagonal blocks through the
+ * FP64 script-A script-Q), and FP64 refinement sweeps (max_refine, refine_tol
+ * with 0 meaning 1e-6) bring each Newton step to inner_tol; results count the
+ * FP64 and low-precision operator products.
  * Dense constraint data only (a_kind SDP_A_DENSE), host inputs (on_device 0),
  * n_i <= 128 recommended (every workgroup keeps O(n^2 + m d + d^2) doubles of
  * scratch).  results: count entries (time_ms is the whole launch).  X_out,

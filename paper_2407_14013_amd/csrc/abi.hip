@@ -194,6 +194,9 @@ sdp_status sdp_solve_batched(const sdp_problem* probs, int32_t count, const sdp_
                              const sdp_batch_tune* tune) {
     try {
         wc::require(probs && results && count >= 1, "solve_batched: NULL argument or count < 1");
+        wc::require(!opt || opt->inner_prec == SDP_PREC_F64 || opt->inner_prec == SDP_PREC_F32,
+                    "solve_batched: inner_prec must be SDP_PREC_F64 or SDP_PREC_F32");
+        wc::require(!opt || opt->solver == SDP_SOLVER_PCG, "solve_batched runs PCG only");
         wc::solve_batched(probs, count, opt, static_cast<hipStream_t>(hip_stream), results, X_out, y_out, tune);
         return SDP_OK;
     } catch (const wc::Error& e) {
@@ -209,6 +212,8 @@ sdp_status sdp_autotune_batched(const sdp_problem* probs, int32_t count, const s
                                 sdp_batch_tune* tune_out, double* bucket_ms) {
     try {
         wc::require(probs && tune_out && count >= 1, "autotune_batched: NULL argument or count < 1");
+        wc::require(!opt || opt->inner_prec == SDP_PREC_F64 || opt->inner_prec == SDP_PREC_F32,
+                    "autotune_batched: inner_prec must be SDP_PREC_F64 or SDP_PREC_F32");
         wc::autotune_batched(probs, count, opt, static_cast<hipStream_t>(hip_stream), tune_out, bucket_ms);
         return SDP_OK;
     } catch (const wc::Error& e) {

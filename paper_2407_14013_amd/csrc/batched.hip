@@ -38,8 +38,9 @@ typedef double bd2 __attribute__((ext_vector_type(2)));
 
 struct BInst {
     int n, m, rmax, rows_per_wave, aq_group, pad;
-    long N2, ldp;
+    long N2, ldp, ldp32;
     const double* P;  // m x ldp packed rows
+    const float* P32; // m x ldp32 packed rows rounded to FP32 (low-precision inner solves), else null
     const double* b;
     const double* C;  // n x n
     double xi, eta, mean_a2, bnorm, Cnorm;
@@ -49,7 +50,7 @@ struct BInst {
 
 struct BOut {
     int status, iterations;
-    long long pcg;
+    long long pcg, matvecs, lp_matvecs;
     double pobj, dobj, relgap, pinf, dinf, mu;
 };
 
@@ -59,6 +60,9 @@ struct BParams {
     long per_wg;  // doubles of scratch per workgroup
     double inner_tol, gap_tol, feas_tol, step_frac;
     int inner_maxit, max_ipm_iter;
+    int lowp;           // FP32 inner operator with FP64 refinement sweeps
+    int max_refine;
+    double refine_tol;  // residual reduction asked of each low-precision PCG run
 };
 
 // ---------------------------------------------------------------------------
@@ -199,6 +203,59 @@ __device__ void wg_gemm(bool ta, bool tb, int M, int N, int K, double alpha, con
                     if (i < M && j < N) {
                         double* c = C + i + (long)j * ldc;
                         const double val = alpha * acc[x][y][v];
+                        *c = (beta == 0.0) ? val : val + beta * (*c);
+                    }
+                }
+    }
+    bsync();
+}
+
+// C = alpha A B + beta C on the FP32 matrix cores (v_mfma_f32_16x16x4_f32):
+// the FP64 operands are rounded to FP32 as they are read, the products are
+// accumulated in FP32 and C is FP64.  Same wave tiling as wg_gemm; the FP32
+// instruction delivers D[4 (l / 16) + v][l % 16] in lane l, element v.
+typedef float bf4 __attribute__((ext_vector_type(4)));
+__device__ void wg_sgemm(int M, int N, int K, double alpha, const double* A, long lda, const double* B, long ldb,
+                         double beta, double* C, long ldc) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tm = (M + 31) / 32, tn = (N + 31) / 32;
+    for (int t = wave; t < tm * tn; t += BWV) {
+        const int r0 = (t % tm) * 32, c0 = (t / tm) * 32;
+        bf4 acc[2][2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) acc[x][y] = bf4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            const int k = k0 + (lane >> 4);
+            float a[2], bb[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const int i = r0 + x * 16 + (lane & 15);
+                a[x] = (i < M && k < K) ? static_cast<float>(A[i + (long)k * lda]) : 0.f;
+            }
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const int j = c0 + y * 16 + (lane & 15);
+                bb[y] = (j < N && k < K) ? static_cast<float>(B[k + (long)j * ldb]) : 0.f;
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x], bb[y], acc[x][y], 0, 0, 0);
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = r0 + x * 16 + 4 * (lane >> 4) + v;
+                    const int j = c0 + y * 16 + (lane & 15);
+                    if (i < M && j < N) {
+                        double* c = C + i + (long)j * ldc;
+                        const double val = alpha * static_cast<double>(acc[x][y][v]);
                         *c = (beta == 0.0) ? val : val + beta * (*c);
                     }
                 }
@@ -518,7 +575,8 @@ struct Work {
     double *X, *S, *L, *Linv, *R, *Rinv, *G, *Ginv, *Gw, *Gt, *E, *Y, *T1, *T2, *Mm, *Rd, *Ct, *dXa, *dSa, *dX, *dS,
         *Hc, *Vs, *Tp, *Q;
     double *y, *rp, *dya, *dy, *tm, *lam, *dnt, *evE, *srt, *nrm, *sig, *U, *Hm, *YQ, *F;
-    double *vx, *vr, *vz, *vp, *vKp, *vg, *vtmp, *rho, *dz, *td, *td2, *td3, *AQ, *Cm, *colk, *mw, *yp, *Taq, *ab;
+    double *vx, *vr, *vz, *vp, *vKp, *vg, *vtmp, *rho, *dz, *vres, *vdx, *td, *td2, *td3, *AQ, *Cm, *colk, *mw, *yp,
+        *Taq, *ab;
     int *pj, *pk, *rank;
     long ldaq;
 };
@@ -555,7 +613,7 @@ __device__ Work carve(double* base, const BParams& bp) {
     w.YQ = take(nr);
     w.F = take(nr);
     const long NV = bp.mmax + bp.dmax + 8;
-    double** vecs[] = {&w.vx, &w.vr, &w.vz, &w.vp, &w.vKp, &w.vg, &w.vtmp, &w.rho, &w.dz};
+    double** vecs[] = {&w.vx, &w.vr, &w.vz, &w.vp, &w.vKp, &w.vg, &w.vtmp, &w.rho, &w.dz, &w.vres, &w.vdx};
     for (double** v : vecs) *v = take(NV);
     w.td = take(bp.dmax);
     w.td2 = take(bp.dmax);
@@ -584,6 +642,7 @@ struct Inst {
     int n, m, r, d;
     long N2;
     double tau, beta;
+    long long mv = 0, lmv = 0;  // FP64 and low-precision operator products
 };
 
 // ---- constraint operator --------------------------------------------------------
@@ -660,6 +719,97 @@ __device__ void op_at(Inst& s, const double* u, double* Y) {
         }
         s.w.yp[2 * c] = a0;
         s.w.yp[2 * c + 1] = a1;
+    }
+    bsync();
+    for (long p = threadIdx.x; p < s.N2; p += BT) {
+        const int j = s.w.pj[p], k = s.w.pk[p];
+        Y[j + (long)k * n] = s.w.yp[p];
+        Y[k + (long)j * n] = s.w.yp[p];
+    }
+    bsync();
+}
+
+// The two passes over the FP32 copy of the packed rows (low-precision inner
+// operator): rows read as 16-byte quads of FP32 values, FP64 accumulation.
+// ldp32 is a multiple of 4 and mw / yp hold at least ldp32 entries.
+typedef float bf4u __attribute__((ext_vector_type(4)));
+__device__ void op_a_f32(Inst& s, const double* M, double* out, double alpha, double beta) {
+    const int n = s.n;
+    const long N2 = s.N2, ldp32 = s.I.ldp32;
+    for (long p = threadIdx.x; p < ldp32; p += BT) {
+        double v = 0.0;
+        if (p < N2) {
+            const int j = s.w.pj[p], k = s.w.pk[p];
+            v = (j == k) ? M[j + (long)j * n] : (M[j + (long)k * n] + M[k + (long)j * n]);
+        }
+        s.w.mw[p] = v;
+    }
+    bsync();
+    // each wave streams rows_per_wave rows at once (their loads in flight together)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rpw = s.I.rows_per_wave;
+    const long h4 = (N2 + 3) / 4;
+    for (int i0 = wave * rpw; i0 < s.m; i0 += BWV * rpw) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        const bf4u* rows[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rows[q] = reinterpret_cast<const bf4u*>(s.I.P32 + (long)min(i0 + q, s.m - 1) * ldp32);
+        for (long c = lane; c < h4; c += 64) {
+            const double* x = s.w.mw + 4 * c;
+            const double x0 = x[0], x1 = x[1], x2 = x[2], x3 = x[3];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q < rpw) {
+                    const bf4u av = __builtin_nontemporal_load(&rows[q][c]);
+                    acc[q] += ((double)av.x * x0 + (double)av.y * x1) + ((double)av.z * x2 + (double)av.w * x3);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double v = acc[q];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            const int i = i0 + q;
+            if (lane == 0 && q < rpw && i < s.m) out[i] = (beta == 0.0) ? alpha * v : alpha * v + beta * out[i];
+        }
+    }
+    bsync();
+}
+
+__device__ void op_at_f32(Inst& s, const double* u, double* Y) {
+    const int n = s.n;
+    const long h4 = (s.N2 + 3) / 4, ldp32 = s.I.ldp32;
+    for (long c = threadIdx.x; c < h4; c += BT) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int i = 0;
+        // eight rows' loads in flight before their products (same summation order)
+        for (; i + 8 <= s.m; i += 8) {
+            bf4u v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                v[q] = __builtin_nontemporal_load(reinterpret_cast<const bf4u*>(s.I.P32 + (long)(i + q) * ldp32) + c);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double ui = u[i + q];
+                a0 += (double)v[q].x * ui;
+                a1 += (double)v[q].y * ui;
+                a2 += (double)v[q].z * ui;
+                a3 += (double)v[q].w * ui;
+            }
+        }
+        for (; i < s.m; ++i) {
+            const bf4u v = __builtin_nontemporal_load(reinterpret_cast<const bf4u*>(s.I.P32 + (long)i * ldp32) + c);
+            const double ui = u[i];
+            a0 += (double)v.x * ui;
+            a1 += (double)v.y * ui;
+            a2 += (double)v.z * ui;
+            a3 += (double)v.w * ui;
+        }
+        s.w.yp[4 * c] = a0;
+        s.w.yp[4 * c + 1] = a1;
+        s.w.yp[4 * c + 2] = a2;
+        s.w.yp[4 * c + 3] = a3;
     }
     bsync();
     for (long p = threadIdx.x; p < s.N2; p += BT) {
@@ -749,6 +899,28 @@ __device__ void newton_apply(Inst& s, const double* in, double* out) {
     f_to_v(s, w.F, v, s.tau * s.tau, out + m);
 }
 
+// The operator with its A E A^T block in low precision (the refinement
+// sweeps' inner operator, as in the single-instance solver): A^T(u) and
+// A(E Y E) over the FP32 rows, E Y E on the FP32 matrix cores; the
+// off-diagonal blocks are FP64 products with the explicit script-A script-Q
+// that the preconditioner also uses, and the bottom-right block is FP64, so
+// only the top-left block differs from the FP64 operator.
+__device__ void newton_apply_lp(Inst& s, const double* in, double* out) {
+    const int n = s.n, m = s.m, d = s.d;
+    Work& w = s.w;
+    const double* u = in;
+    const double* v = in + m;
+    const double t2 = s.tau * s.tau;
+    op_at_f32(s, u, w.Y);
+    wg_sgemm(n, n, n, 1.0, w.Y, n, w.E, n, 0.0, w.T1, n);
+    wg_sgemm(n, n, n, 1.0, w.E, n, w.T1, n, 0.0, w.Mm, n);
+    op_a_f32(s, w.Mm, out, 1.0, 0.0);
+    wg_gemv_rows(m, d, w.AQ, w.ldaq, v, out, 1.0, 1.0);
+    wg_gemv_cols(m, d, w.AQ, w.ldaq, u, w.td, 1.0, 0.0);
+    for (int c = threadIdx.x; c < d; c += BT) out[m + c] = w.td[c] - t2 * w.sig[c] * v[c];
+    bsync();
+}
+
 // Block elimination with P = [beta I, AQ; AQ^T, -tau^2 Sigma] (Section 6).
 __device__ void precond_block(Inst& s, const double* f, const double* h, double* z1, double* zv) {
     const int m = s.m, d = s.d;
@@ -799,8 +971,67 @@ __device__ void recover(Inst& s, const double* x, const double* Ct, double* dX, 
     wg_symmetrize(n, dX);
 }
 
-// Indefinite PCG (Corollary pcg) started at [0; -Sigma^{-1} Q^T c]; returns the
-// iteration count (negative when inner_maxit was reached).
+// Indefinite PCG (Definition pcg, Corollary pcg) on K x = g from the x
+// given, with the FP64 operator or its low-precision form: stops when
+// ||r_u|| <= tol_rel ||r_u(0)||; returns the iteration count, negative
+// (-its - 1) when maxit was reached first.  ref and rr receive ||r_u(0)|| and
+// the final ||r_u||.  Uses vr, vz, vp, vKp and the preconditioner's buffers.
+__device__ int pcg(Inst& s, bool lowp, const double* g, double* x, double tol_rel, int maxit, double& ref,
+                   double& rr) {
+    const int m = s.m;
+    const long N = (long)m + s.d;
+    Work& w = s.w;
+    auto K = [&](const double* in, double* out) {
+        if (lowp) {
+            newton_apply_lp(s, in, out);
+            ++s.lmv;
+        } else {
+            newton_apply(s, in, out);
+            ++s.mv;
+        }
+    };
+    K(x, w.vKp);
+    for (long t = threadIdx.x; t < N; t += BT) w.vr[t] = (t < m) ? g[t] - w.vKp[t] : 0.0;
+    bsync();
+    precond_apply(s, w.vr, w.vz);
+    wg_copy(N, w.vz, w.vp);
+    double rz = wg_dot(N, w.vr, w.vz, s.red);
+    ref = sqrt(wg_dot(m, w.vr, w.vr, s.red));
+    rr = ref;
+    const double tol = tol_rel * (ref > 0.0 ? ref : 1.0);
+    int it = 0;
+    bool conv = false;
+    while (true) {
+        if (!(rr > tol)) {
+            conv = isfinite(rr);
+            break;
+        }
+        if (it >= maxit) break;
+        K(w.vp, w.vKp);
+        const double pkp = wg_dot(N, w.vp, w.vKp, s.red);
+        const double alpha = rz / pkp;
+        for (long t = threadIdx.x; t < N; t += BT) {
+            x[t] += alpha * w.vp[t];
+            w.vr[t] = (t < m) ? w.vr[t] - alpha * w.vKp[t] : 0.0;
+        }
+        bsync();
+        rr = sqrt(wg_dot(m, w.vr, w.vr, s.red));
+        precond_apply(s, w.vr, w.vz);
+        const double rzn = wg_dot(N, w.vr, w.vz, s.red);
+        const double bk = rzn / rz;
+        rz = rzn;
+        wg_axpby(N, 1.0, w.vz, bk, w.vp, w.vp);
+        ++it;
+    }
+    return conv ? it : -it - 1;
+}
+
+// The Newton system of eq. Newt-eps by eq. augsys started at [0; -Sigma^{-1}
+// Q^T c], then eq. recover; returns the Krylov iteration count (negative when
+// the tolerance was not met).  With the low-precision operator: FP64
+// refinement sweeps, each a low-precision PCG run on the FP64 residual g - K x
+// (bottom block zero) from zero to refine_tol, or to the reduction still
+// missing to inner_tol when that is larger.
 __device__ int inner_solve(Inst& s, const double* bt, const double* Ct, double* dX, double* dy) {
     const int n = s.n, m = s.m, r = s.r, d = s.d;
     const long N = (long)m + d;
@@ -820,41 +1051,39 @@ __device__ int inner_solve(Inst& s, const double* bt, const double* Ct, double* 
     }
     for (int i = threadIdx.x; i < m; i += BT) w.vx[i] = 0.0;
     bsync();
-    newton_apply(s, w.vx, w.vKp);
-    for (long t = threadIdx.x; t < N; t += BT) w.vr[t] = (t < m) ? w.vg[t] - w.vKp[t] : 0.0;
-    bsync();
-    precond_apply(s, w.vr, w.vz);
-    wg_copy(N, w.vz, w.vp);
-    double rz = wg_dot(N, w.vr, w.vz, s.red);
-    const double ref = sqrt(wg_dot(m, w.vr, w.vr, s.red));
-    double rr = ref;
-    const double tol = s.bp.inner_tol * (ref > 0.0 ? ref : 1.0);
-    int it = 0;
+    const double tol = s.bp.inner_tol;
+    int its = 0;
     bool conv = false;
-    while (true) {
-        if (!(rr > tol)) {
-            conv = isfinite(rr);
-            break;
+    if (!s.bp.lowp) {
+        double ref, rr;
+        const int it = pcg(s, false, w.vg, w.vx, tol, s.bp.inner_maxit, ref, rr);
+        conv = it >= 0;
+        its = conv ? it : -it - 1;
+    } else {
+        double ref = 0.0;
+        for (int sweep = 0;; ++sweep) {
+            newton_apply(s, w.vx, w.vKp);
+            ++s.mv;
+            for (long t = threadIdx.x; t < N; t += BT) w.vres[t] = (t < m) ? w.vg[t] - w.vKp[t] : 0.0;
+            bsync();
+            const double rr = sqrt(wg_dot(m, w.vres, w.vres, s.red));
+            if (sweep == 0) ref = rr;
+            if (!(rr > tol * (ref > 0.0 ? ref : 1.0))) {
+                conv = isfinite(rr);
+                break;
+            }
+            if (!isfinite(rr) || sweep >= s.bp.max_refine || its >= s.bp.inner_maxit) break;
+            wg_fill(N, w.vdx, 0.0);
+            const double need = 0.5 * tol * ref / (rr > 0.0 ? rr : 1.0);
+            double r0, r1;
+            const int it = pcg(s, true, w.vres, w.vdx, fmax(s.bp.refine_tol, need), s.bp.inner_maxit - its, r0, r1);
+            its += it >= 0 ? it : -it - 1;
+            if (!isfinite(r1)) break;
+            wg_axpby(N, 1.0, w.vdx, 1.0, w.vx, w.vx);
         }
-        if (it >= s.bp.inner_maxit) break;
-        newton_apply(s, w.vp, w.vKp);
-        const double pkp = wg_dot(N, w.vp, w.vKp, s.red);
-        const double alpha = rz / pkp;
-        for (long t = threadIdx.x; t < N; t += BT) {
-            w.vx[t] += alpha * w.vp[t];
-            w.vr[t] = (t < m) ? w.vr[t] - alpha * w.vKp[t] : 0.0;
-        }
-        bsync();
-        rr = sqrt(wg_dot(m, w.vr, w.vr, s.red));
-        precond_apply(s, w.vr, w.vz);
-        const double rzn = wg_dot(N, w.vr, w.vz, s.red);
-        const double bk = rzn / rz;
-        rz = rzn;
-        wg_axpby(N, 1.0, w.vz, bk, w.vp, w.vp);
-        ++it;
     }
     recover(s, w.vx, Ct, dX, dy);
-    return conv ? it : -it - 1;
+    return conv ? its : -its - 1;
 }
 
 // Largest alpha with L L^T + alpha D PSD, from lambda_min(L^{-1} D L^{-T}).
@@ -1131,6 +1360,8 @@ __device__ void solve_one(const BInst& I, const BParams& bp, Work& w, double* re
     if (threadIdx.x == 0) {
         o.iterations = its;
         o.pcg = pcg;
+        o.matvecs = s.mv;
+        o.lp_matvecs = s.lmv;
         o.pobj = R.pobj;
         o.dobj = R.dobj;
         o.relgap = R.relgap;
@@ -1170,6 +1401,7 @@ namespace {
 struct Staged {
     std::vector<BInst> insts;
     DevBuf<double> data;  // packed rows, b and C of every instance
+    DevBuf<float> data32; // FP32 copies of the packed rows (low-precision inner solves)
     BParams bp{};
 };
 
@@ -1197,8 +1429,20 @@ void stage(const sdp_problem* probs, int count, const sdp_options& o, hipStream_
         rcap = std::max(rcap, std::min(std::max(1, o.rank_max), p.n - 1));
     }
     S.data.alloc(total);
+    // low-precision inner solves: every instance's rows again in FP32, rows of
+    // ldp32 = round_up(N2, 4) floats so that they load as 16-byte quads
+    const bool lowp = o.inner_prec == SDP_PREC_F32;
+    long total32 = 0;
+    if (lowp) {
+        for (int i = 0; i < count; ++i) {
+            const long N2 = (long)probs[i].n * (probs[i].n + 1) / 2;
+            total32 += (long)probs[i].m * round_up(N2, 4);
+        }
+        S.data32.alloc(total32);
+    }
     std::vector<double> host;
-    long off = 0;
+    std::vector<float> host32;
+    long off = 0, off32 = 0;
     for (int i = 0; i < count; ++i) {
         const sdp_problem& p = probs[i];
         const int n = p.n, m = p.m;
@@ -1233,6 +1477,14 @@ void stage(const sdp_problem* probs, int count, const sdp_options& o, hipStream_
         }
         WC_HIP(hipMemcpyAsync(S.data.get() + off, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice,
                               st));
+        const long ldp32 = round_up(N2, 4);
+        if (lowp) {
+            host32.assign((long)m * ldp32, 0.0f);
+            for (int r = 0; r < m; ++r)
+                for (long q = 0; q < N2; ++q) host32[(long)r * ldp32 + q] = static_cast<float>(host[(long)r * ldp + q]);
+            WC_HIP(hipMemcpyAsync(S.data32.get() + off32, host32.data(), sizeof(float) * host32.size(),
+                                  hipMemcpyHostToDevice, st));
+        }
         WC_HIP(hipStreamSynchronize(st));
         BInst& I = S.insts[i];
         I.n = n;
@@ -1244,6 +1496,9 @@ void stage(const sdp_problem* probs, int count, const sdp_options& o, hipStream_
                 "batch tune out of range (rows_per_wave 1..4, aq_group 1..16)");
         I.N2 = N2;
         I.ldp = ldp;
+        I.ldp32 = ldp32;
+        I.P32 = lowp ? S.data32.get() + off32 : nullptr;
+        if (lowp) off32 += (long)m * ldp32;
         I.P = S.data.get() + off;
         I.b = S.data.get() + off + (long)m * ldp;
         I.C = S.data.get() + off + (long)m * ldp + round_up(m, 2);
@@ -1266,7 +1521,7 @@ void stage(const sdp_problem* probs, int count, const sdp_options& o, hipStream_
     const long NV = mmax + bp.dmax + 8;
     auto r8 = [](long c) { return (c + 7) & ~7L; };
     bp.per_wg = 24 * r8(nn) + r8((long)nmax * (BLZ + 1)) + 5 * r8(mmax + 8) + 5 * r8(nmax) + r8(2L * nmax) +
-                r8(bp.dmax) + 4 * r8((long)nmax * rcap) + 9 * r8(NV) + 3 * r8(bp.dmax) +
+                r8(bp.dmax) + 4 * r8((long)nmax * rcap) + 11 * r8(NV) + 3 * r8(bp.dmax) +
                 r8((long)mmax * bp.dmax) + r8((long)bp.dmax * bp.dmax) + r8(bp.dmax) + 2 * r8(N2max + 8) +
                 r8(16L * nmax * rcap) + r8(2L * BLZ) + 2 * r8(N2max / 2 + 8) + r8(nmax / 2 + 8);
     bp.inner_tol = o.inner_tol;
@@ -1275,6 +1530,9 @@ void stage(const sdp_problem* probs, int count, const sdp_options& o, hipStream_
     bp.feas_tol = o.feas_tol;
     bp.max_ipm_iter = o.max_ipm_iter;
     bp.step_frac = o.step_frac;
+    bp.lowp = lowp ? 1 : 0;
+    bp.max_refine = o.max_refine;
+    bp.refine_tol = o.refine_tol > 0 ? o.refine_tol : 1e-6;
 }
 
 // Launch the persistent kernel over `sel` (indices into S.insts) and wait.
@@ -1333,7 +1591,7 @@ void solve_batched(const sdp_problem* probs, int count, const sdp_options* opt, 
         r.status = b.status;
         r.iterations = b.iterations;
         r.pcg_iterations = b.pcg;
-        r.newton_matvecs = 0;
+        r.newton_matvecs = b.matvecs;
         r.pobj = b.pobj;
         r.dobj = b.dobj;
         r.relgap = b.relgap;
@@ -1341,7 +1599,7 @@ void solve_batched(const sdp_problem* probs, int count, const sdp_options* opt, 
         r.dinf = b.dinf;
         r.mu = b.mu;
         r.time_ms = ms;
-        r.lp_matvecs = 0;
+        r.lp_matvecs = b.lp_matvecs;
     }
 }
 

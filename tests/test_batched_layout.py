@@ -50,11 +50,11 @@ def layout(probs):
     nn = nmax * nmax
     NV = mmax + dmax + 8
     per_wg = (24 * r8(nn) + r8(nmax * (BLZ + 1)) + 5 * r8(mmax + 8) + 5 * r8(nmax) + r8(2 * nmax) + r8(dmax)
-              + 4 * r8(nmax * rcap) + 9 * r8(NV) + 3 * r8(dmax) + r8(mmax * dmax) + r8(dmax * dmax) + r8(dmax)
+              + 4 * r8(nmax * rcap) + 11 * r8(NV) + 3 * r8(dmax) + r8(mmax * dmax) + r8(dmax * dmax) + r8(dmax)
               + 2 * r8(N2max + 8) + r8(16 * nmax * rcap) + r8(2 * BLZ) + 2 * r8(N2max // 2 + 8) + r8(nmax // 2 + 8))
     # carve(): region sizes in order (doubles; the int regions hold twice as many ints)
     regions = ([("mat", nn)] * 24 + [("Q", nmax * (BLZ + 1))] + [("mvec", mmax + 8)] * 5 + [("nvec", nmax)] * 4
-               + [("nrm", 2 * nmax), ("sig", dmax)] + [("nr", nmax * rcap)] * 4 + [("NV", NV)] * 9
+               + [("nrm", 2 * nmax), ("sig", dmax)] + [("nr", nmax * rcap)] * 4 + [("NV", NV)] * 11
                + [("td", dmax)] * 3 + [("AQ", mmax * dmax), ("Cm", dmax * dmax), ("colk", dmax),
                                       ("mw", N2max + 8), ("yp", N2max + 8), ("Taq", 16 * nmax * rcap),
                                       ("ab", 2 * BLZ), ("pj", N2max // 2 + 8), ("pk", N2max // 2 + 8),
@@ -83,6 +83,12 @@ def check_batch(probs):
         # op_at: pairs c < h2 of rows i < m into yp[2c], yp[2c + 1]; then N2 scatters through pj / pk
         assert size["yp"] >= 2 * h2
         assert 2 * size["pj"] >= N2 and 2 * size["pk"] >= N2
+        # FP32 passes (low-precision inner solves): rows of ldp32 floats read as
+        # quads c < h4; mw / yp written up to ldp32
+        ldp32 = round_up(N2, 4)
+        h4 = (N2 + 3) // 4
+        assert 4 * h4 <= ldp32 and size["mw"] >= ldp32 and size["yp"] >= ldp32
+        assert (m - 1) * ldp32 + 4 * h4 - 1 < m * ldp32
         # b and C follow the rows inside the block
         assert m * ldp + round_up(m, 2) + n * n <= block
         off += block

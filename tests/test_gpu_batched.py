@@ -20,6 +20,8 @@ torch = pytest.importorskip("torch")
 
 import workloads  # noqa: E402
 from oracle import ipm, operators as ops  # noqa: E402
+from paper_2407_14013_amd import SdpError  # noqa: E402
+from paper_2407_14013_amd import _lib as L  # noqa: E402
 from paper_2407_14013_amd.batched import autotune, solve_batched  # noqa: E402
 
 
@@ -46,15 +48,24 @@ def check_instance(p, res, X, y, pobj_ref):
     return e_obj, np.linalg.norm(X - Xs) / np.linalg.norm(Xs)
 
 
-def test_batched_matches_oracle():
+PRECS = [L.SDP_PREC_F64, L.SDP_PREC_F32]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batched_matches_oracle(prec):
+    # prec F32: the inner operator over FP32 rows with E Y E on the FP32
+    # matrix cores, FP64 refinement of every Newton step -- the same bars
     probs = batch()
     refs = [ipm.solve(p)["history"][-1]["pobj"] for p in probs]
-    results, Xs, ys = solve_batched(probs, want_y=True)
+    results, Xs, ys = solve_batched(probs, want_y=True, inner_prec=prec)
     for i, p in enumerate(probs):
         e_obj, e_rec = check_instance(p, results[i], Xs[i], ys[i], refs[i])
-        print(f"instance {i}: n {p['n']} r {p['r']} m {p['m']} its {results[i]['iterations']} "
-              f"pcg {results[i]['pcg_iterations']} objective error {e_obj:.1e} recovery {e_rec:.1e}")
+        r = results[i]
+        print(f"instance {i} prec {prec}: n {p['n']} r {p['r']} m {p['m']} its {r['iterations']} "
+              f"pcg {r['pcg_iterations']} products fp64 {r['newton_matvecs']} low {r['lp_matvecs']} "
+              f"objective error {e_obj:.1e} recovery {e_rec:.1e}")
         assert e_rec <= 1e-6
+        assert (r["lp_matvecs"] > 0) == (prec == L.SDP_PREC_F32)
 
 
 def test_batched_autotune_and_single_instances_agree():
@@ -74,14 +85,27 @@ def test_batched_autotune_and_single_instances_agree():
 SPREAD = [(16, 3), (40, 1), (64, 2), (96, 3), (128, 1), (128, 3)]
 
 
-def test_batched_size_spread_matches_oracle():
+@pytest.fixture(scope="module")
+def spread():
     probs = [workloads.gaussian_sensing(n, r, min(3 * n * r, n * (n + 1) // 2), seed=100 + i)
              for i, (n, r) in enumerate(SPREAD)]
     assert probs[0]["m"] == 136
-    refs = [ipm.solve(p)["history"][-1]["pobj"] for p in probs]
-    results, Xs, ys = solve_batched(probs, want_y=True)
+    return probs, [ipm.solve(p)["history"][-1]["pobj"] for p in probs]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batched_size_spread_matches_oracle(spread, prec):
+    probs, refs = spread
+    results, Xs, ys = solve_batched(probs, want_y=True, inner_prec=prec)
     for i, p in enumerate(probs):
         e_obj, e_rec = check_instance(p, results[i], Xs[i], ys[i], refs[i])
-        print(f"instance {i}: n {p['n']} r {p['r']} m {p['m']} its {results[i]['iterations']} "
-              f"pcg {results[i]['pcg_iterations']} objective error {e_obj:.1e} recovery {e_rec:.1e}")
+        r = results[i]
+        print(f"instance {i} prec {prec}: n {p['n']} r {p['r']} m {p['m']} its {r['iterations']} "
+              f"pcg {r['pcg_iterations']} products fp64 {r['newton_matvecs']} low {r['lp_matvecs']} "
+              f"objective error {e_obj:.1e} recovery {e_rec:.1e}")
         assert e_rec <= 1e-6
+
+
+def test_batched_rejects_bf16_inner():
+    with pytest.raises(SdpError):
+        solve_batched(batch(count=2), inner_prec=L.SDP_PREC_BF16)
