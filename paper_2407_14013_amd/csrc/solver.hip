@@ -918,8 +918,13 @@ static PcgOut pcg_loop(sdp_ctx* c, bool lowp, const double* g, double* x, double
 
 // MINRES (Corollary minres: identity preconditioner, start at 0) on K x = g,
 // by the Lanczos three-term recurrence and Givens rotations of the
-// tridiagonal (the Paige-Saunders form of the method).  Stops when the
-// residual norm estimate |phibar| <= tol_rel ||g|| or after maxit steps.
+// tridiagonal, as published by C. C. Paige and M. A. Saunders, "Solution of
+// sparse indefinite systems of linear equations", SIAM J. Numer. Anal. 12
+// (1975) 617-629.  The scalar names (oldb, alfa, dbar, epsln, gbar, phibar,
+// cs, sn, oldeps, w/w2) are those of SciPy's minres (BSD-3-Clause licence,
+// Copyright the SciPy Developers), whose arrangement of the same recurrence
+// this loop follows.  Stops when the residual norm estimate
+// |phibar| <= tol_rel ||g|| or after maxit steps.
 static PcgOut minres_loop(sdp_ctx* c, const double* g, double* x, double tol_rel, int maxit) {
     const int m = c->m, d = c->d;
     const long N = (long)m + d;
