@@ -40,6 +40,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "packed_passes_gaussian_n200_m2400_hbm_traffic.json")
+GEMM_KERNEL = "dgemm_kernel<false, false, 128, 128, 0>"
+GEMM_COUNTERS_FILE = os.path.join(ROOT, "profiles", "operator_completion_n4000_m160000_counters.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2407_14013_amd", "csrc", "blas.hip")
 METRIC = "Newton-op matvecs/s and IPM time-to-1e-8 gap, FP64 vs mixed prec, 1 GPU"
 WORKLOAD = "gaussian sensing SDP n=200 r=3 m=2400 (dense A, FP64)"
@@ -103,7 +105,17 @@ def packed_source_digest():
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def measured_traffic(kernel):
+def gemm_source_digest():
+    """SHA-256 of the GEMM sources (the FP64 tiles, their launch plans, the low-precision tiles)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("blas.hip", "launch_plan.hpp", "lowprec.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2407_14013_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, record=TRAFFIC_FILE, digest=packed_source_digest):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter runs.
 
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are each divided by what the
@@ -111,36 +123,82 @@ def measured_traffic(kernel):
     None when no record exists or the kernel source changed since it was taken.
     """
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(record))
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha256") != packed_source_digest() or kernel not in rec.get("kernels", {}):
+    if rec.get("source_sha256") != digest() or kernel not in rec.get("kernels", {}):
         return None
     k = rec["kernels"][kernel]
     return 1024.0 * (k["fetch_kib"] / rec["copy"]["fetch_factor"] + k["write_kib"] / rec["copy"]["write_factor"])
 
 
-def pmc_pass():
-    """Short run for the rocprofv3 counter passes: operator applications plus a copy of known size."""
+def pmc_pass(workload):
+    """Short run for the rocprofv3 counter passes: operator products plus a device copy of known size.
+
+    sensing: ten FP64 products on the n=200 sensing workload (packed passes).
+    completion: five FP64 and five BF16 products at the centred n=4000
+    completion point (the E Y E GEMMs of the default line).
+    """
     import torch
 
     import workloads
     from paper_2407_14013_amd import Context
+    from paper_2407_14013_amd import _lib as L
 
     torch.cuda.set_device(0)
-    ctx = Context(workloads.config(1))
-    N = ctx.aug_dim()
-    xin = torch.randn(N, dtype=torch.float64, device="cuda")
-    xout = torch.empty_like(xin)
-    for _ in range(10):
-        ctx.newton_apply(xin, xout)
+    if workload == "sensing":
+        ctx = Context(workloads.config(1))
+        N = ctx.aug_dim()
+        xin = torch.randn(N, dtype=torch.float64, device="cuda")
+        xout = torch.empty_like(xin)
+        for _ in range(10):
+            ctx.newton_apply(xin, xout)
+        ctx.close()
+        what = "10 FP64 operator products"
+    else:
+        p = workloads.config(2)
+        X, S, _, _, _ = workloads.centred_pair(p["n"], 4, 1e-2, seed=21)
+        Xd, Sd = torch.from_numpy(X).cuda(), torch.from_numpy(S).cuda()
+        yd = torch.zeros(p["m"], dtype=torch.float64, device="cuda")
+        del X, S
+        for prec in (L.SDP_PREC_F64, L.SDP_PREC_BF16):
+            with Context(p, inner_prec=prec) as ctx:
+                ctx.set_point(Xd, yd, Sd)
+                N = ctx.aug_dim()
+                xin = torch.randn(N, dtype=torch.float64, device="cuda")
+                xout = torch.empty_like(xin)
+                for _ in range(5):
+                    ctx.newton_apply(xin, xout, prec=None if prec == L.SDP_PREC_F64 else prec)
+                torch.cuda.synchronize()
+        what = "5 FP64 and 5 BF16 operator products"
     src = torch.randn(64 << 20, dtype=torch.float64, device="cuda")  # 512 MiB
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
-    ctx.close()
-    print(f"pmc pass: 10 operator applications, 3 copies of {src.numel() * 8} bytes", flush=True)
+    print(f"pmc pass ({workload}): {what}, 3 copies of {src.numel() * 8} bytes", flush=True)
+
+
+def pmc_reduce(out_path, specs):
+    """Per-kernel averages (per dispatch) of rocprofv3 counter CSVs: specs are tag=directory pairs."""
+    import collections
+    import csv
+    import glob
+
+    out = {}
+    for tag, d in (a.split("=", 1) for a in specs):
+        agg = collections.defaultdict(lambda: collections.defaultdict(float))
+        disp = collections.defaultdict(set)
+        for f in glob.glob(f"{d}/**/*counter_collection.csv", recursive=True):
+            for row in csv.DictReader(open(f)):
+                key = (row["Kernel_Name"][:160], row["Grid_Size"], row["Workgroup_Size"])
+                agg[key][row["Counter_Name"]] += float(row["Counter_Value"])
+                disp[key].add(row["Dispatch_Id"])
+        out[tag] = [{"kernel": k[0], "grid": int(k[1]), "wg": int(k[2]), "dispatches": len(disp[k]),
+                     **{c: v / len(disp[k]) for c, v in cs.items()}} for k, cs in agg.items()]
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(f"reduced {', '.join(f'{k}: {len(v)} kernels' for k, v in out.items())}", flush=True)
 
 
 def bench_batched(args):
@@ -550,13 +608,13 @@ def completion_line(args):
         "config": {"workload": COMPLETION, "step": "one FP64 augmented-operator product, E Y E as two "
                                                    "n x n x n FP64 MFMA GEMMs"},
         "roofline": {
-            "kernel": "dgemm_kernel<false, false>: each n x n x n product of E Y E",
+            "kernel": GEMM_KERNEL + ": each n x n x n product of E Y E",
             "bound": "mfma",
             "achieved": achieved,
             "peak": MFMA_PEAK_TFLOPS["f64"],
             "unit": "TFLOP/s",
             "frac": achieved / MFMA_PEAK_TFLOPS["f64"],
-            "traffic": None,
+            "traffic": measured_traffic(GEMM_KERNEL, GEMM_COUNTERS_FILE, gemm_source_digest),
             "flops_per_launch": flops,
             "avg_launch_ms": avg_ms,
             "launches": sw["launches"],
@@ -656,7 +714,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-loop", type=int, default=200, help="sensing: operator products in the tight loop")
     ap.add_argument("--form-loop", type=int, default=50, help="completion: products timed per extra form")
-    ap.add_argument("--pmc-pass", action="store_true", help="only the short run profiled for HBM counters")
+    ap.add_argument("--pmc-pass", choices=["sensing", "completion"], default=None,
+                    help="only the short run profiled for hardware counters")
+    ap.add_argument("--pmc-reduce", nargs="+", metavar="ARG", default=None,
+                    help="OUT.json tag=dir ...: per-kernel averages of rocprofv3 counter CSVs (no GPU)")
     ap.add_argument("--no-mixed", action="store_true", help="sensing: skip the mixed-precision solves")
     ap.add_argument("--no-config1", action="store_true", help="completion: skip the n=200 sensing solves")
     ap.add_argument("--workload", choices=["completion", "sensing", "batched", "adjoint"], default="completion",
@@ -673,8 +734,11 @@ def main():
         print("bench.py measures one GPU only: every instance of this workload fits one MI355X, "
               "and the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.pmc_reduce:
+        pmc_reduce(args.pmc_reduce[0], args.pmc_reduce[1:])
+        return
     if args.pmc_pass:
-        pmc_pass()
+        pmc_pass(args.pmc_pass)
         return
     if args.workload == "batched":
         bench_batched(args)
