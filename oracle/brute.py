@@ -29,7 +29,7 @@ def lp_instance(n: int, m: int, seed: int):
     b = a @ x_feas
     c = rng.uniform(0.5, 2.0, size=n)
     A = np.stack([np.diag(a[i]).reshape(-1) for i in range(m)])
-    return {"kind": "dense", "n": n, "m": m, "A": A, "b": b, "C": np.diag(c), "lp": (a, b, c)}
+    return {"kind": "dense", "n": n, "m": m, "A": A, "b": b, "C": np.diag(c), "lp_data": (a, b, c)}
 
 
 def lp_optimum(a: np.ndarray, b: np.ndarray, c: np.ndarray):

@@ -9,6 +9,11 @@ A(X)_i = <A_i, X> and A^T(y) = sum_i y_i A_i.  Two data forms:
 
 The matrix form used by the paper, script-A = [svec(A_1) ... svec(A_m)]^T
 (Section 3), is built by ``amat`` for small instances.
+
+A problem may also carry a nonnegative-orthant (LP) block x >= 0 entering
+the constraints as A(X) + B x = b with cost c^T x (the cone of eq. rmc-sdp
+and eq. snl-sdp).  problem["lp"] holds B column by column (compressed
+sparse columns: ``ptr`` (l+1), ``row`` and ``val`` (nnz)) and ``c`` (l).
 """
 from __future__ import annotations
 
@@ -70,3 +75,34 @@ def frob_norms(problem) -> np.ndarray:
         return np.linalg.norm(problem["A"], axis=1)
     jk = problem["jk"]
     return np.where(jk[:, 0] == jk[:, 1], 1.0, np.sqrt(0.5))
+
+
+def has_lp(problem) -> bool:
+    return problem.get("lp") is not None
+
+
+def lp_len(problem) -> int:
+    return int(problem["lp"]["c"].size) if has_lp(problem) else 0
+
+
+def b_matrix(problem) -> np.ndarray:
+    """The dense m x l matrix B of the LP block, entry by entry from its columns (built once)."""
+    lp = problem["lp"]
+    if "_B" not in lp:
+        ell = lp["c"].size
+        B = np.zeros((problem["m"], ell))
+        for j in range(ell):
+            for q in range(lp["ptr"][j], lp["ptr"][j + 1]):
+                B[lp["row"][q], j] += lp["val"][q]
+        lp["_B"] = B
+    return lp["_B"]
+
+
+def b_op(problem, x: np.ndarray) -> np.ndarray:
+    """B x."""
+    return b_matrix(problem) @ x
+
+
+def bt_op(problem, y: np.ndarray) -> np.ndarray:
+    """B^T y."""
+    return b_matrix(problem).T @ y

@@ -19,6 +19,19 @@ Follows Section 3 of the paper:
 * Experiments section: rank rule r = argmax_{i <= rhat} lambda_i / lambda_{i+1}
   and beta = (median eigenvalue of E)^2.
 
+LP block (eq. rmc-sdp, eq. snl-sdp; the paper gives no formulas for it):
+each coordinate x_j >= 0 is a 1 x 1 block of the cone with scaling
+w_j = sqrt(x_j / s_j), so the Schur complement gains B diag(w^2) B^T.  The
+split treats w_j like an eigenvalue of W: the coordinates with w_j > 2 tau
+(above lambda_{r+1}) join the low-rank part, T = those indices (at most
+``cap``, the largest w_j), with script-E entry 1 and Sigma entry
+1/(w_j^2 - tau^2); the others stay in script-E with entry (w_j/tau)^2 <= 4.
+Then diag(w^2) = tau^2 script-E_lp + P_T Sigma_lp^{-1} P_T^T exactly, the
+LP analogue of W (x)_s W = tau^2 script-E + script-Q Sigma^{-1} script-Q^T,
+and the augmented system, right-hand side, recovery and preconditioner
+extend block by block: v = [v_sdp; v_lp], script-A script-Q gains the
+columns B[:, T], and dx = script-E_lp (B^T u - tau^2 c~) + P_T v_lp.
+
 Readings (documented in the design notes):
 * the v-coordinates are [svec(B) (r(r+1)/2); vec(N) ((n-r) x r, column-major)];
 * eigenvalues are sorted in decreasing order and every eigenvector column is
@@ -202,3 +215,65 @@ def precond_matrix(AQ: np.ndarray, sp, sig: np.ndarray, beta: float) -> np.ndarr
 def schur_c(AQ: np.ndarray, sp, sig: np.ndarray, beta: float) -> np.ndarray:
     """C = tau^2 Sigma + beta^{-1} (A Q)^T (A Q) (Section 6)."""
     return (sp["tau"] ** 2) * np.diag(sig) + (AQ.T @ AQ) / beta
+
+
+# ---- LP block (nonnegative orthant) ------------------------------------------
+
+
+def lp_split(sp, w: np.ndarray, cap: int | None = None):
+    """Split of the LP scaling w = sqrt(x/s) against the SDP split's tau."""
+    tau = sp["tau"]
+    T = np.flatnonzero(w > 2.0 * tau)
+    if cap is not None and T.size > cap:
+        order = np.argsort(-w[T], kind="stable")
+        T = np.sort(T[order[:cap]])
+    e2 = (w / tau) ** 2
+    e2[T] = 1.0
+    sig = 1.0 / (w[T] ** 2 - tau * tau)
+    return {"T": T, "e2": e2, "sig": sig, "w": w, "t": int(T.size)}
+
+
+def aug_apply_lp(problem, sp, lsp, E, sig, u, v):
+    """eq. augsys with the LP block: v = [v_sdp; v_lp]."""
+    d = sig.size
+    top, bot = aug_apply(problem, sp, E, sig, u, v[:d])
+    B = ops.b_matrix(problem)
+    T = lsp["T"]
+    t = B.T @ u
+    top = top + B @ (lsp["e2"] * t) + B[:, T] @ v[d:]
+    bot_lp = t[T] - sp["tau"] ** 2 * lsp["sig"] * v[d:]
+    return top, np.concatenate([bot, bot_lp])
+
+
+def aug_rhs_lp(problem, sp, lsp, E, bt, Ct, ct):
+    t2 = sp["tau"] ** 2
+    gu, gv = aug_rhs(problem, sp, E, bt, Ct)
+    B = ops.b_matrix(problem)
+    gu = gu + t2 * (B @ (lsp["e2"] * ct))
+    return gu, np.concatenate([gv, t2 * ct[lsp["T"]]])
+
+
+def recover_lp(problem, sp, lsp, E, u, v, Ct, ct):
+    """eq. recover with the LP block: returns (dX, dy, dx)."""
+    d = v.size - lsp["t"]
+    dX, dy = recover(problem, sp, E, u, v[:d], Ct)
+    t2 = sp["tau"] ** 2
+    dx = lsp["e2"] * (ops.bt_op(problem, u) - t2 * ct)
+    dx[lsp["T"]] += v[d:]
+    return dX, dy, dx
+
+
+def aq_matrix_lp(problem, sp, lsp) -> np.ndarray:
+    """[script-A script-Q, B[:, T]]."""
+    return np.hstack([aq_matrix(problem, sp), ops.b_matrix(problem)[:, lsp["T"]]])
+
+
+def aug_matrix_lp(problem, sp, lsp) -> np.ndarray:
+    """The augmented matrix with the LP block, from explicit blocks."""
+    Am = ops.amat(problem)
+    B = ops.b_matrix(problem)
+    AQ = np.hstack([Am @ q_bold(sp), B[:, lsp["T"]]])
+    sig = np.concatenate([sigma_diag(sp), lsp["sig"]])
+    top = np.hstack([Am @ e_bold(sp) @ Am.T + (B * lsp["e2"]) @ B.T, AQ])
+    bot = np.hstack([AQ.T, -(sp["tau"] ** 2) * np.diag(sig)])
+    return np.vstack([top, bot])

@@ -24,7 +24,7 @@ def main():
     lp = []
     for (n, m, seed) in [(4, 2, 0), (5, 2, 1), (6, 3, 2), (6, 2, 3)]:
         q = brute.lp_instance(n, m, seed)
-        val, x = brute.lp_optimum(*q["lp"])
+        val, x = brute.lp_optimum(*q["lp_data"])
         lp.append({"n": n, "m": m, "seed": seed, "optimum": val, "x": x.tolist()})
     out["lp_diagonal"] = {"citation": "eq. sdp-pd with diagonal data reduces to an LP on diag(X)", "cases": lp}
     tb = []

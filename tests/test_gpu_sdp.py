@@ -328,7 +328,7 @@ def test_solve_brute_force_cases():
         X, y, S = ctx.get_point()
     check_solution(q, res, X, y, S, val)
     q = brute.lp_instance(5, 2, 1)
-    val, _ = brute.lp_optimum(*q["lp"])
+    val, _ = brute.lp_optimum(*q["lp_data"])
     with Context(q) as ctx:
         res = ctx.solve()
         X, y, S = ctx.get_point()

@@ -34,7 +34,7 @@ from oracle import adjoint, brute, ipm
 def test_lp_vertex_gradient_closed_form():
     # the seed gives a nondegenerate optimal vertex (checked below)
     q = brute.lp_instance(5, 2, 3)
-    a, b, c = q["lp"]
+    a, b, c = q["lp_data"]
     val, x = brute.lp_optimum(a, b, c)
     basis = np.flatnonzero(x > 1e-9)
     assert basis.size == q["m"]

@@ -16,6 +16,10 @@ dense  : ``A`` is an (m, n*n) float64 array, row i = vec(A_i) (A_i is
 entry  : ``jk`` is an (m, 2) int32 array of 0-based pairs with j <= k,
          all distinct; A_i = (e_j e_k^T + e_k e_j^T) / 2 so <A_i, X> = X_jk.
 C      : (n, n) float64, symmetric.
+lp     : optional nonnegative-orthant block x >= 0 with A(X) + B x = b and
+         cost c^T x (eq. rmc-sdp, eq. snl-sdp): ``ptr`` (l+1, int64),
+         ``row`` (nnz, int32) and ``val`` (nnz, float64) hold B by columns,
+         ``c`` (l, float64) the cost.
 """
 from __future__ import annotations
 
@@ -27,6 +31,8 @@ __all__ = [
     "batched_sensing",
     "random_pd_pair",
     "centred_pair",
+    "robust_completion",
+    "sensor_localization",
     "config",
     "CONFIGS",
 ]
@@ -184,6 +190,124 @@ def matrix_completion(n: int, r: int, m: int, seed: int):
         "b": b,
         "C": np.eye(n),
         "U": U,
+        "seed": seed,
+    }
+
+
+def _slack_pairs(rows: np.ndarray, scale: np.ndarray, m: int):
+    """LP block of slack pairs: column t (< len(rows)) is +scale_t at row rows_t, column
+    len(rows) + t is -scale_t at the same row; unit costs."""
+    q = rows.size
+    return {
+        "ptr": np.arange(2 * q + 1, dtype=np.int64),
+        "row": np.concatenate([rows, rows]).astype(np.int32),
+        "val": np.concatenate([scale, -scale]).astype(np.float64),
+        "c": np.ones(2 * q),
+    }
+
+
+def robust_completion(n: int, m: int, m_o: int, seed: int, r: int = 2, lam: float = 1.0):
+    """Robust matrix completion (eq. rmc-sdp), generated as in the experiments section.
+
+    X* = G G^T with G (n x r) of N(0, 10^2) entries; m distinct entries of
+    svec(X) (j <= k) are observed, b = P_m svec(X*) + eps with m_o outliers
+    eps_i ~ N(0, 10^4) (zero elsewhere), and the problem is
+    min 1^T v + 1^T w + lam tr(X)  s.t.  v - w + P_m svec(X) = b,  X PSD, v, w >= 0.
+    Stored with entry-sampling rows A_i = sym(e_j e_k^T): the svec weight
+    kappa_i (1 on the diagonal, sqrt 2 off it) is divided out of row i, so
+    the LP columns of row i carry +-1/kappa_i and b_i becomes b_i / kappa_i
+    (the same feasible set and objective).
+    """
+    rng = np.random.default_rng(seed)
+    G = 10.0 * rng.standard_normal((n, r))
+    N2 = n * (n + 1) // 2
+    if m > N2:
+        raise ValueError("m exceeds the number of distinct entries")
+    p = np.sort(rng.choice(N2, size=m, replace=False))
+    jlo, khi = _packed_index_to_pair(p, n)
+    j = np.minimum(jlo, khi).astype(np.int32)
+    k = np.maximum(jlo, khi).astype(np.int32)
+    kappa = np.where(j == k, 1.0, np.sqrt(2.0))
+    eps = np.zeros(m)
+    out_idx = np.sort(rng.choice(m, size=m_o, replace=False)) if m_o > 0 else np.zeros(0, dtype=np.int64)
+    eps[out_idx] = 100.0 * rng.standard_normal(m_o)
+    Xstar = G @ G.T
+    b_svec = kappa * Xstar[j, k] + eps
+    return {
+        "kind": "entry",
+        "n": n,
+        "m": m,
+        "r": r,
+        "jk": np.ascontiguousarray(np.stack([j, k], axis=1)),
+        "b": b_svec / kappa,
+        "C": lam * np.eye(n),
+        "lp": _slack_pairs(np.arange(m), 1.0 / kappa, m),
+        "Xstar": Xstar,
+        "outliers": out_idx,
+        "seed": seed,
+    }
+
+
+def sensor_localization(n: int, m_y: int, m_a: int, m_yo: int, m_ao: int, seed: int, d: int = 2, k: int = 3):
+    """Sensor network localization with outliers (eq. snl-sdp), generated as in the experiments section.
+
+    Sensors y_1..y_n and anchors a_1..a_k uniform in [0, 1]^d; m_y of the
+    n(n-1)/2 sensor pairs and m_a of the n k anchor-sensor pairs are
+    measured; m_yo (m_ao) of them carry an outlier eps ~ N(0, I_d) inside
+    the norm.  X is (n + d) x (n + d) with X = [I_d, Y; Y^T, Z]: d(d+1)/2
+    rows fix the identity block (no slack), then one row per distance,
+    <[0; e_i - e_j][0; e_i - e_j]^T, X> + v - u = delta_ij^2 and
+    <[a_i; -e_j][a_i; -e_j]^T, X> + v - u = delta-bar_ij^2, with cost
+    sum (v + u) and C = 0.  Dense rows (vec of each A_i).
+    """
+    rng = np.random.default_rng(seed)
+    Ys = rng.uniform(0.0, 1.0, size=(d, n))
+    anc = rng.uniform(0.0, 1.0, size=(d, k))
+    N = n + d
+    iu, ju = np.triu_indices(n, 1)
+    py = np.sort(rng.choice(iu.size, size=m_y, replace=False))
+    pa = np.sort(rng.choice(n * k, size=m_a, replace=False))
+    rows, bs = [], []
+    for p in range(d):
+        for q in range(p, d):
+            M = np.zeros((N, N))
+            M[p, q] += 0.5
+            M[q, p] += 0.5
+            rows.append(M.reshape(-1))
+            bs.append(1.0 if p == q else 0.0)
+    oy = set(rng.choice(m_y, size=m_yo, replace=False).tolist()) if m_yo > 0 else set()
+    oa = set(rng.choice(m_a, size=m_a and m_ao, replace=False).tolist()) if m_ao > 0 else set()
+    for t, pidx in enumerate(py):
+        i, j = iu[pidx], ju[pidx]
+        vec = np.zeros(N)
+        vec[d + i], vec[d + j] = 1.0, -1.0
+        diff = Ys[:, i] - Ys[:, j]
+        if t in oy:
+            diff = diff + rng.standard_normal(d)
+        rows.append(np.outer(vec, vec).reshape(-1))
+        bs.append(float(diff @ diff))
+    for t, pidx in enumerate(pa):
+        i, j = divmod(int(pidx), n)  # anchor i, sensor j
+        vec = np.zeros(N)
+        vec[:d], vec[d + j] = anc[:, i], -1.0
+        diff = anc[:, i] - Ys[:, j]
+        if t in oa:
+            diff = diff + rng.standard_normal(d)
+        rows.append(np.outer(vec, vec).reshape(-1))
+        bs.append(float(diff @ diff))
+    m0 = d * (d + 1) // 2
+    m = m0 + m_y + m_a
+    return {
+        "kind": "dense",
+        "n": N,
+        "m": m,
+        "A": np.ascontiguousarray(np.stack(rows)),
+        "b": np.array(bs),
+        "C": np.zeros((N, N)),
+        "lp": _slack_pairs(np.arange(m0, m), np.ones(m - m0), m),
+        "Ystar": Ys,
+        "anchors": anc,
+        "d": d,
         "seed": seed,
     }
 
