@@ -87,6 +87,30 @@ typedef struct sdp_problem {
 } sdp_problem;
 
 /*
+ * A nonnegative-orthant (LP) block beside the PSD variable: the problem
+ * becomes  min <C, X> + c^T x  s.t.  A(X) + B x = b,  X PSD,  x >= 0  (the
+ * cone of eq. rmc-sdp and eq. snl-sdp in the experiments section), with the
+ * dual slack s = c - B^T y >= 0.
+ *  l           LP coordinates (>= 1)
+ *  col_ptr     l + 1 offsets into row / val, col_ptr[0] = 0, nondecreasing:
+ *              column j of B holds the entries col_ptr[j] .. col_ptr[j+1]-1
+ *  row, val    0-based constraint index (< m) and value of each entry; a
+ *              row may repeat within a column (the values add)
+ *  c           the cost, l entries
+ *  on_device   nonzero: the four arrays are device pointers (checked for shape
+ *              only), else host pointers (also checked for range and finite
+ *              values).  sdp_setup_lp copies what it needs.
+ */
+typedef struct sdp_lp_block {
+    int32_t l;
+    const int32_t* col_ptr;
+    const int32_t* row;
+    const double* val;
+    const double* c;
+    int32_t on_device;
+} sdp_lp_block;
+
+/*
  * Solver options.  sdp_default_options fills the defaults given in brackets.
  *  rank_max     rhat of the rank rule r = argmax_{i <= rhat} lambda_i/lambda_{i+1}
  *               (Experiments section) [10, clipped to n - 1]
@@ -106,7 +130,9 @@ typedef struct sdp_problem {
  *               brought to inner_tol by FP64 iterative refinement; the scaling
  *               point, its eigen-decomposition, the preconditioner, residuals
  *               and step lengths stay FP64.
- *  max_refine   FP64 refinement sweeps around a low-precision inner solve [8]
+ *  max_refine   most FP64 refinement sweeps around a low-precision inner
+ *               solve; SDP_REFINE_SWEEPS also stops once two sweeps in a row
+ *               fail to halve the FP64 residual [20]
  *  refine_mode  how the FP64 refinement corrects the low-precision inner
  *               solve [SDP_REFINE_SWEEPS]: SDP_REFINE_SWEEPS restarts a
  *               low-precision PCG run on each FP64 residual (classic
@@ -135,6 +161,11 @@ typedef struct sdp_problem {
  *               per constraint, instead of the two dense n x n x n products
  *               of E Y E.  Same operator up to rounding; it pays when m is far
  *               below n^2 [0]
+ *  lp_top_max   LP block only: most LP coordinates that join the low-rank
+ *               part T of the split (those with w_j = sqrt(x_j/s_j) above
+ *               2 tau; past the cap only the largest stay, a tied group as a
+ *               whole or not at all).  The augmented system and the
+ *               preconditioner's Schur complement grow by |T| [2048]
  */
 typedef struct sdp_options {
     int32_t rank_max;
@@ -153,6 +184,7 @@ typedef struct sdp_options {
     double refine_tol;
     int32_t sparse_sandwich;
     int32_t refine_mode;
+    int32_t lp_top_max;
 } sdp_options;
 
 typedef struct sdp_inner_stats {
@@ -195,6 +227,20 @@ void sdp_default_options(sdp_options* opt);
  * *out is NULL and the message is available from sdp_last_error(NULL).
  */
 sdp_status sdp_setup(const sdp_problem* prob, const sdp_options* opt, void* hip_stream, sdp_ctx** out);
+
+/*
+ * sdp_setup for a problem with an LP block (see sdp_lp_block; lp may be NULL,
+ * which is sdp_setup).  The starting point adds x = xi 1, s = eta 1 with the
+ * magnitudes of X0 and S0.  On such a context the augmented system gains one
+ * v-coordinate per LP coordinate in T after the SDP ones (sdp_aug_dim counts
+ * them); sdp_newton_apply, sdp_precond_apply, sdp_ipm_step, sdp_solve and
+ * sdp_get_point work as documented, with the LP block included; use
+ * sdp_set_point_lp, sdp_get_point_lp and sdp_inner_solve_lp for the parts that
+ * carry x, s or c~.  sdp_set_point, sdp_inner_solve, sdp_adjoint and
+ * sdp_solve_batched return SDP_EINVAL on it.
+ */
+sdp_status sdp_setup_lp(const sdp_problem* prob, const sdp_lp_block* lp, const sdp_options* opt, void* hip_stream,
+                        sdp_ctx** out);
 
 /* Release every device buffer the context owns.  NULL is allowed. */
 void sdp_destroy(sdp_ctx* ctx);
@@ -245,6 +291,23 @@ sdp_status sdp_precond_apply(sdp_ctx* ctx, const double* uv_in, double* uv_out);
  */
 sdp_status sdp_inner_solve(sdp_ctx* ctx, const double* b_tilde, const double* C_tilde, double* dX, double* dy,
                            sdp_inner_stats* stats);
+
+/*
+ * sdp_inner_solve on a context with an LP block: eq. Newt-eps extended by
+ * B dx with dx = w^2 (B^T dy - c~) (w = sqrt(x/s) elementwise) and
+ * A(dX) + B dx = b_tilde.  c_tilde_lp and dx_lp are device pointers of l
+ * entries; the other arguments as for sdp_inner_solve.
+ */
+sdp_status sdp_inner_solve_lp(sdp_ctx* ctx, const double* b_tilde, const double* C_tilde, const double* c_tilde_lp,
+                              double* dX, double* dy, double* dx_lp, sdp_inner_stats* stats);
+
+/*
+ * The LP split at the current scaling point (prepared first if needed):
+ * *t = |T|; top_idx (device, at least lp_top_max int32 entries, or NULL)
+ * receives T in increasing order; w (device, l doubles, or NULL) receives
+ * w = sqrt(x/s).  SDP_EINVAL without an LP block.
+ */
+sdp_status sdp_get_lp_split(sdp_ctx* ctx, int32_t* t, int32_t* top_idx, double* w);
 
 /*
  * One Mehrotra predictor-corrector iteration with the Nesterov-Todd
@@ -344,6 +407,16 @@ sdp_status sdp_get_point(sdp_ctx* ctx, double* X, double* y, double* S);
  * next computed, SDP_ENUMERIC otherwise).  Resets the iteration counter.
  */
 sdp_status sdp_set_point(sdp_ctx* ctx, const double* X, const double* y, const double* S);
+
+/* sdp_get_point with the LP block: x and s (device, l entries each; any may be NULL). */
+sdp_status sdp_get_point_lp(sdp_ctx* ctx, double* X, double* y, double* S, double* x, double* s);
+
+/*
+ * sdp_set_point with the LP block: x and s (device, l entries each) must be
+ * positive (checked when the scaling is next computed, SDP_ENUMERIC otherwise).
+ */
+sdp_status sdp_set_point_lp(sdp_ctx* ctx, const double* X, const double* y, const double* S, const double* x,
+                            const double* s);
 
 /*
  * The eigen-split of the scaling point (eq. EQSigdef) at the current

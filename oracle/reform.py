@@ -24,7 +24,8 @@ each coordinate x_j >= 0 is a 1 x 1 block of the cone with scaling
 w_j = sqrt(x_j / s_j), so the Schur complement gains B diag(w^2) B^T.  The
 split treats w_j like an eigenvalue of W: the coordinates with w_j > 2 tau
 (above lambda_{r+1}) join the low-rank part, T = those indices (at most
-``cap``, the largest w_j), with script-E entry 1 and Sigma entry
+``cap`` of them: j stays only when at most cap entries are >= w_j), with
+script-E entry 1 and Sigma entry
 1/(w_j^2 - tau^2); the others stay in script-E with entry (w_j/tau)^2 <= 4.
 Then diag(w^2) = tau^2 script-E_lp + P_T Sigma_lp^{-1} P_T^T exactly, the
 LP analogue of W (x)_s W = tau^2 script-E + script-Q Sigma^{-1} script-Q^T,
@@ -225,8 +226,11 @@ def lp_split(sp, w: np.ndarray, cap: int | None = None):
     tau = sp["tau"]
     T = np.flatnonzero(w > 2.0 * tau)
     if cap is not None and T.size > cap:
-        order = np.argsort(-w[T], kind="stable")
-        T = np.sort(T[order[:cap]])
+        # keep j when at most cap entries are >= w_j (a tied group that would
+        # overflow the cap stays out as a whole)
+        ws = np.sort(w)
+        at_least = w.size - np.searchsorted(ws, w[T], side="left")
+        T = T[at_least <= cap]
     e2 = (w / tau) ** 2
     e2[T] = 1.0
     sig = 1.0 / (w[T] ** 2 - tau * tau)

@@ -48,6 +48,17 @@ class SdpProblem(C.Structure):
     ]
 
 
+class SdpLpBlock(C.Structure):
+    _fields_ = [
+        ("l", C.c_int32),
+        ("col_ptr", C.c_void_p),
+        ("row", C.c_void_p),
+        ("val", C.c_void_p),
+        ("c", C.c_void_p),
+        ("on_device", C.c_int32),
+    ]
+
+
 class SdpOptions(C.Structure):
     _fields_ = [
         ("rank_max", C.c_int32),
@@ -66,6 +77,7 @@ class SdpOptions(C.Structure):
         ("refine_tol", C.c_double),
         ("sparse_sandwich", C.c_int32),
         ("refine_mode", C.c_int32),
+        ("lp_top_max", C.c_int32),
     ]
 
 
@@ -146,6 +158,8 @@ _lib = None
 _SIGNATURES = [
     ("sdp_default_options", None, [C.POINTER(SdpOptions)]),
     ("sdp_setup", C.c_int32, [C.POINTER(SdpProblem), C.POINTER(SdpOptions), C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("sdp_setup_lp", C.c_int32, [C.POINTER(SdpProblem), C.POINTER(SdpLpBlock), C.POINTER(SdpOptions), C.c_void_p,
+                                 C.POINTER(C.c_void_p)]),
     ("sdp_destroy", None, [C.c_void_p]),
     ("sdp_last_error", C.c_char_p, [C.c_void_p]),
     ("sdp_aug_dim", C.c_int64, [C.c_void_p]),
@@ -153,6 +167,9 @@ _SIGNATURES = [
     ("sdp_newton_apply_prec", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     ("sdp_precond_apply", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("sdp_inner_solve", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SdpInnerStats)]),
+    ("sdp_inner_solve_lp", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.POINTER(SdpInnerStats)]),
+    ("sdp_get_lp_split", C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p, C.c_void_p]),
     ("sdp_ipm_step", C.c_int32, [C.c_void_p, C.POINTER(SdpStepStats)]),
     ("sdp_solve_batched", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(SdpOptions), C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -162,6 +179,8 @@ _SIGNATURES = [
     ("sdp_solve", C.c_int32, [C.c_void_p, C.POINTER(SdpResult)]),
     ("sdp_get_point", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("sdp_set_point", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("sdp_get_point_lp", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("sdp_set_point_lp", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("sdp_get_scaling", C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p, C.POINTER(C.c_int32),
                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("sdp_profile_enable", C.c_int32, [C.c_void_p, C.c_int32]),

@@ -94,8 +94,22 @@ class Context:
                 p.A = host(problem["A"], np.float64)
             else:
                 p.jk = host(problem["jk"], np.int32)
+        # nonnegative-orthant block (problem["lp"]: B by columns and the cost c)
+        lpb = None
+        self.ell = 0
+        if problem.get("lp") is not None:
+            lp = problem["lp"]
+            self.ell = int(len(lp["c"]))
+            lpb = L.SdpLpBlock()
+            lpb.l = self.ell
+            lpb.on_device = 0
+            lpb.col_ptr = host(lp["ptr"], np.int32)
+            lpb.row = host(lp["row"], np.int32)
+            lpb.val = host(lp["val"], np.float64)
+            lpb.c = host(lp["c"], np.float64)
         ctx = C.c_void_p()
-        st = lib.sdp_setup(C.byref(p), C.byref(options), _stream_ptr(self.stream), C.byref(ctx))
+        st = lib.sdp_setup_lp(C.byref(p), C.byref(lpb) if lpb is not None else None, C.byref(options),
+                              _stream_ptr(self.stream), C.byref(ctx))
         if st != L.SDP_OK:
             raise SdpError(st, lib.sdp_last_error(None).decode())
         self._ctx = ctx
@@ -162,6 +176,31 @@ class Context:
             self._check(st)
         return dX, dy, L.struct_dict(s)
 
+    def inner_solve_lp(self, b_tilde: torch.Tensor, C_tilde: torch.Tensor, c_tilde: torch.Tensor,
+                       raise_on_notconv: bool = True):
+        """Newton step with the LP block: (dX, dy, dx, stats)."""
+        n, m, ell = self.n, self.m, self.ell
+        dX = torch.empty((n, n), dtype=torch.float64, device=b_tilde.device)
+        dy = torch.empty(m, dtype=torch.float64, device=b_tilde.device)
+        dx = torch.empty(ell, dtype=torch.float64, device=b_tilde.device)
+        s = L.SdpInnerStats()
+        st = self._lib.sdp_inner_solve_lp(self._ctx, _dptr(b_tilde, "b_tilde", m), _dptr(C_tilde, "C_tilde", n * n),
+                                          _dptr(c_tilde, "c_tilde", ell), _dptr(dX, "dX"), _dptr(dy, "dy"),
+                                          _dptr(dx, "dx"), C.byref(s))
+        if st != L.SDP_OK and (raise_on_notconv or st != L.SDP_ENOTCONV):
+            self._check(st)
+        return dX, dy, dx, L.struct_dict(s)
+
+    def lp_split(self) -> dict:
+        """The LP split at the current scaling: T (increasing) and w = sqrt(x/s)."""
+        dev = torch.device("cuda", torch.cuda.current_device())
+        t = C.c_int32()
+        cap = max(1, int(self.options.lp_top_max))
+        top = torch.empty(cap, dtype=torch.int32, device=dev)
+        w = torch.empty(self.ell, dtype=torch.float64, device=dev)
+        self._check(self._lib.sdp_get_lp_split(self._ctx, C.byref(t), C.c_void_p(top.data_ptr()), _dptr(w, "w")))
+        return {"t": t.value, "T": top[: t.value].clone(), "w": w}
+
     def adjoint(self, dL_dX: torch.Tensor, raise_off_centre: bool = True):
         """(dL/db, dL/dC, stats) for a loss gradient dL/dX at the current (re-centred) iterate.
 
@@ -203,9 +242,27 @@ class Context:
         self._check(self._lib.sdp_get_point(self._ctx, _dptr(X, "X"), _dptr(y, "y"), _dptr(S, "S")))
         return X, y, S
 
-    def set_point(self, X: torch.Tensor, y: torch.Tensor, S: torch.Tensor):
+    def set_point(self, X: torch.Tensor, y: torch.Tensor, S: torch.Tensor, x: torch.Tensor | None = None,
+                  s: torch.Tensor | None = None):
+        """Replace the iterate; x and s (the LP block) are required exactly when the problem has one."""
         n, m = self.n, self.m
-        self._check(self._lib.sdp_set_point(self._ctx, _dptr(X, "X", n * n), _dptr(y, "y", m), _dptr(S, "S", n * n)))
+        if self.ell == 0:
+            self._check(self._lib.sdp_set_point(self._ctx, _dptr(X, "X", n * n), _dptr(y, "y", m),
+                                                _dptr(S, "S", n * n)))
+        else:
+            if x is None or s is None:
+                raise ValueError("the problem has an LP block: pass x and s")
+            self._check(self._lib.sdp_set_point_lp(self._ctx, _dptr(X, "X", n * n), _dptr(y, "y", m),
+                                                   _dptr(S, "S", n * n), _dptr(x, "x", self.ell),
+                                                   _dptr(s, "s", self.ell)))
+
+    def get_lp_point(self):
+        """(x, s) of the LP block."""
+        dev = torch.device("cuda", torch.cuda.current_device())
+        x = torch.empty(self.ell, dtype=torch.float64, device=dev)
+        s = torch.empty(self.ell, dtype=torch.float64, device=dev)
+        self._check(self._lib.sdp_get_point_lp(self._ctx, None, None, None, _dptr(x, "x"), _dptr(s, "s")))
+        return x, s
 
     def get_scaling(self) -> dict:
         n = self.n

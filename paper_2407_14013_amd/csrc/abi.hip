@@ -59,7 +59,7 @@ void sdp_default_options(sdp_options* o) {
     o->inner_tol = 1e-10;
     o->inner_maxit = 2000;
     o->inner_prec = SDP_PREC_F64;
-    o->max_refine = 8;
+    o->max_refine = 20;
     o->gap_tol = 1e-8;
     o->feas_tol = 1e-8;
     o->max_ipm_iter = 100;
@@ -68,9 +68,15 @@ void sdp_default_options(sdp_options* o) {
     o->refine_tol = 0.0;
     o->sparse_sandwich = 0;
     o->refine_mode = SDP_REFINE_SWEEPS;
+    o->lp_top_max = 2048;
 }
 
 sdp_status sdp_setup(const sdp_problem* prob, const sdp_options* opt, void* hip_stream, sdp_ctx** out) {
+    return sdp_setup_lp(prob, nullptr, opt, hip_stream, out);
+}
+
+sdp_status sdp_setup_lp(const sdp_problem* prob, const sdp_lp_block* lp, const sdp_options* opt, void* hip_stream,
+                        sdp_ctx** out) {
     if (!out) {
         g_setup_error = "out is NULL";
         return SDP_EINVAL;
@@ -103,8 +109,9 @@ sdp_status sdp_setup(const sdp_problem* prob, const sdp_options* opt, void* hip_
                 wc::require(prob && prob->a_kind == SDP_A_ENTRY, "sparse_sandwich needs entry-sampling constraints");
                 wc::require(prob->n <= 16384, "sparse_sandwich needs n <= 16384");
             }
+            wc::require(opt->lp_top_max >= 0, "lp_top_max must be non-negative");
         }
-        wc::setup(c, prob, opt, static_cast<hipStream_t>(hip_stream));
+        wc::setup(c, prob, lp, opt, static_cast<hipStream_t>(hip_stream));
         return SDP_OK;
     });
     if (s != SDP_OK) {
@@ -128,7 +135,7 @@ int64_t sdp_aug_dim(sdp_ctx* ctx) {
     int64_t out = -1;
     sdp_status s = guarded(ctx, [&]() {
         wc::ensure_scaling(ctx);
-        out = (int64_t)ctx->m + ctx->d;
+        out = (int64_t)ctx->m + ctx->dv;
         return SDP_OK;
     });
     return s == SDP_OK ? out : (int64_t)s;
@@ -171,10 +178,38 @@ sdp_status sdp_inner_solve(sdp_ctx* ctx, const double* b_tilde, const double* C_
     if (!ctx) return SDP_EINVAL;
     return guarded(ctx, [&]() {
         wc::require(b_tilde && C_tilde && dX && dy, "inner_solve: NULL argument");
-        int rc = wc::inner_solve(ctx, b_tilde, C_tilde, dX, dy, stats);
+        wc::require(ctx->ell == 0, "the problem has an LP block: use sdp_inner_solve_lp");
+        int rc = wc::inner_solve(ctx, b_tilde, C_tilde, nullptr, dX, dy, nullptr, stats);
         WC_HIP(hipStreamSynchronize(ctx->st));
         if (rc != 0) ctx->last_error = "inner solve reached inner_maxit";
         return (sdp_status)rc;
+    });
+}
+
+sdp_status sdp_inner_solve_lp(sdp_ctx* ctx, const double* b_tilde, const double* C_tilde, const double* c_tilde_lp,
+                              double* dX, double* dy, double* dx_lp, sdp_inner_stats* stats) {
+    if (!ctx) return SDP_EINVAL;
+    return guarded(ctx, [&]() {
+        wc::require(b_tilde && C_tilde && c_tilde_lp && dX && dy && dx_lp, "inner_solve_lp: NULL argument");
+        wc::require(ctx->ell > 0, "the problem has no LP block: use sdp_inner_solve");
+        int rc = wc::inner_solve(ctx, b_tilde, C_tilde, c_tilde_lp, dX, dy, dx_lp, stats);
+        WC_HIP(hipStreamSynchronize(ctx->st));
+        if (rc != 0) ctx->last_error = "inner solve reached inner_maxit";
+        return (sdp_status)rc;
+    });
+}
+
+sdp_status sdp_get_lp_split(sdp_ctx* ctx, int32_t* t, int32_t* top_idx, double* w) {
+    if (!ctx) return SDP_EINVAL;
+    return guarded(ctx, [&]() {
+        wc::require(ctx->ell > 0, "the problem has no LP block");
+        wc::ensure_scaling(ctx);
+        if (t) *t = ctx->t;
+        if (top_idx && ctx->t > 0)
+            WC_HIP(hipMemcpyAsync(top_idx, ctx->Tl.get(), sizeof(int) * ctx->t, hipMemcpyDeviceToDevice, ctx->st));
+        if (w) wc::copy(ctx->st, ctx->ell, ctx->wl, w);
+        WC_HIP(hipStreamSynchronize(ctx->st));
+        return SDP_OK;
     });
 }
 
@@ -255,7 +290,33 @@ sdp_status sdp_set_point(sdp_ctx* ctx, const double* X, const double* y, const d
     if (!ctx) return SDP_EINVAL;
     return guarded(ctx, [&]() {
         wc::require(X && y && S, "set_point: X, y and S are required");
+        wc::require(ctx->ell == 0, "the problem has an LP block: use sdp_set_point_lp");
         wc::set_point(ctx, X, y, S);
+        return SDP_OK;
+    });
+}
+
+sdp_status sdp_get_point_lp(sdp_ctx* ctx, double* X, double* y, double* S, double* x, double* s) {
+    if (!ctx) return SDP_EINVAL;
+    sdp_status rc = sdp_get_point(ctx, X, y, S);
+    if (rc != SDP_OK) return rc;
+    return guarded(ctx, [&]() {
+        wc::require(ctx->ell > 0, "the problem has no LP block");
+        if (x) wc::copy(ctx->st, ctx->ell, ctx->xl, x);
+        if (s) wc::copy(ctx->st, ctx->ell, ctx->sl, s);
+        WC_HIP(hipStreamSynchronize(ctx->st));
+        return SDP_OK;
+    });
+}
+
+sdp_status sdp_set_point_lp(sdp_ctx* ctx, const double* X, const double* y, const double* S, const double* x,
+                            const double* s) {
+    if (!ctx) return SDP_EINVAL;
+    return guarded(ctx, [&]() {
+        wc::require(X && y && S && x && s, "set_point_lp: X, y, S, x and s are required");
+        wc::require(ctx->ell > 0, "the problem has no LP block: use sdp_set_point");
+        wc::set_point(ctx, X, y, S);
+        wc::set_point_lp(ctx, x, s);
         return SDP_OK;
     });
 }

@@ -8,6 +8,7 @@
 #include <limits>
 
 #include "lanczos.hpp"
+#include "lp_kernels.hpp"
 #include "sdp_kernels.hpp"
 #include "solver.hpp"
 
@@ -114,7 +115,8 @@ static void gemm(sdp_ctx* c, bool ta, bool tb, int m, int n, int k, double alpha
 static void alloc_work(sdp_ctx* c) {
     const int n = c->n, m = c->m;
     const long nn = (long)n * n;
-    const long dmax = dim_d(n, c->rmax);
+    // v-length bound: the SDP coordinates at the largest rank plus the LP ones in T
+    const long dmax = dim_d(n, c->rmax) + c->tcap;
     c->dmaxp = round_up(dmax + 1, 32);
     const long Nmax = m + c->dmaxp + 32;
     for (auto* b : {&c->L, &c->Rs, &c->Linv, &c->Rinv, &c->Mt, &c->Vs, &c->G, &c->Ginv, &c->Gt, &c->Gw, &c->E, &c->Y,
@@ -183,12 +185,21 @@ static void alloc_work(sdp_ctx* c) {
     fill(c->st, c->dmaxp, c->td2, 0.0);
     fill(c->st, c->dmaxp, c->td3, 0.0);
     fill(c->st, c->dmaxp, c->td4, 0.0);
+    if (c->ell > 0) {
+        const int ell = c->ell;
+        for (auto* b : {&c->wl, &c->e2l, &c->dxa_l, &c->dsa_l, &c->dx_l, &c->ds_l, &c->ct_l, &c->rd_l, &c->lz, &c->lbt}) {
+            b->alloc(ell);
+            fill(c->st, ell, b->get(), 0.0);
+        }
+        c->posl.alloc(ell);
+        c->Tl.alloc(std::max(1, c->tcap));
+    }
     c->dya.alloc(m + 32);
     c->dy.alloc(m + 32);
     c->rp.alloc(m + 32);
     c->sc.alloc(64);
     fill(c->st, 64, c->sc, 0.0);
-    c->info.alloc(4);
+    c->info.alloc(8);
     WC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->pin), 64 * sizeof(double), hipHostMallocDefault));
     WC_HIP(hipEventCreateWithFlags(&c->ev_rr, hipEventDisableTiming));
 }
@@ -234,7 +245,80 @@ static void validate_host(const sdp_problem* p) {
     }
 }
 
-void setup(sdp_ctx* c, const sdp_problem* p, const sdp_options* o, hipStream_t st) {
+// The LP block: validated on the host (host inputs), B stored by columns with
+// the rows of each column sorted and by rows, the cost c.
+static void setup_lp(sdp_ctx* c, const sdp_lp_block* lp, hipStream_t st) {
+    require(lp->l >= 1, "the LP block needs l >= 1");
+    require(lp->col_ptr && lp->row && lp->val && lp->c, "LP block arrays are required");
+    const int ell = lp->l, m = c->m;
+    const hipMemcpyKind kind = lp->on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+    std::vector<int> cptr(ell + 1);
+    WC_HIP(hipMemcpyAsync(cptr.data(), lp->col_ptr, sizeof(int) * (ell + 1), kind, st));
+    WC_HIP(hipStreamSynchronize(st));
+    require(cptr[0] == 0, "LP col_ptr[0] must be 0");
+    for (int j = 0; j < ell; ++j) require(cptr[j + 1] >= cptr[j], "LP col_ptr must be nondecreasing");
+    const int nnz = cptr[ell];
+    std::vector<int> row(std::max(1, nnz));
+    std::vector<double> val(std::max(1, nnz)), cost(ell);
+    WC_HIP(hipMemcpyAsync(row.data(), lp->row, sizeof(int) * nnz, kind, st));
+    WC_HIP(hipMemcpyAsync(val.data(), lp->val, sizeof(double) * nnz, kind, st));
+    WC_HIP(hipMemcpyAsync(cost.data(), lp->c, sizeof(double) * ell, kind, st));
+    WC_HIP(hipStreamSynchronize(st));
+    for (int q = 0; q < nnz; ++q) {
+        require(row[q] >= 0 && row[q] < m, "LP row index out of range");
+        if (!lp->on_device) require(std::isfinite(val[q]), "LP value is not finite");
+    }
+    double cn = 0;
+    for (int j = 0; j < ell; ++j) {
+        if (!lp->on_device) require(std::isfinite(cost[j]), "LP cost is not finite");
+        cn += cost[j] * cost[j];
+    }
+    c->lcnorm = std::sqrt(cn);
+    // sort the rows within each column (the LP-LP block of C merges columns)
+    std::vector<int> ord;
+    std::vector<int> srow(row.size());
+    std::vector<double> sval(val.size());
+    for (int j = 0; j < ell; ++j) {
+        ord.resize(cptr[j + 1] - cptr[j]);
+        for (size_t a = 0; a < ord.size(); ++a) ord[a] = cptr[j] + static_cast<int>(a);
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return row[a] < row[b]; });
+        for (size_t a = 0; a < ord.size(); ++a) {
+            srow[cptr[j] + a] = row[ord[a]];
+            sval[cptr[j] + a] = val[ord[a]];
+        }
+    }
+    // by rows
+    std::vector<int> rptr(m + 1, 0), rcol(std::max(1, nnz));
+    std::vector<double> rval(std::max(1, nnz));
+    for (int q = 0; q < nnz; ++q) ++rptr[srow[q] + 1];
+    for (int i = 0; i < m; ++i) rptr[i + 1] += rptr[i];
+    std::vector<int> at(rptr.begin(), rptr.end() - 1);
+    for (int j = 0; j < ell; ++j)
+        for (int q = cptr[j]; q < cptr[j + 1]; ++q) {
+            const int g = at[srow[q]]++;
+            rcol[g] = j;
+            rval[g] = sval[q];
+        }
+    c->ell = ell;
+    c->tcap = std::max(0, std::min(ell, c->opt.lp_top_max));
+    c->lcptr.alloc(ell + 1);
+    c->lcrow.alloc(std::max(1, nnz));
+    c->lcval.alloc(std::max(1, nnz));
+    c->lrptr.alloc(m + 1);
+    c->lrcol.alloc(std::max(1, nnz));
+    c->lrval.alloc(std::max(1, nnz));
+    c->lc.alloc(ell);
+    WC_HIP(hipMemcpyAsync(c->lcptr.get(), cptr.data(), sizeof(int) * (ell + 1), hipMemcpyHostToDevice, st));
+    WC_HIP(hipMemcpyAsync(c->lcrow.get(), srow.data(), sizeof(int) * srow.size(), hipMemcpyHostToDevice, st));
+    WC_HIP(hipMemcpyAsync(c->lcval.get(), sval.data(), sizeof(double) * sval.size(), hipMemcpyHostToDevice, st));
+    WC_HIP(hipMemcpyAsync(c->lrptr.get(), rptr.data(), sizeof(int) * (m + 1), hipMemcpyHostToDevice, st));
+    WC_HIP(hipMemcpyAsync(c->lrcol.get(), rcol.data(), sizeof(int) * rcol.size(), hipMemcpyHostToDevice, st));
+    WC_HIP(hipMemcpyAsync(c->lrval.get(), rval.data(), sizeof(double) * rval.size(), hipMemcpyHostToDevice, st));
+    WC_HIP(hipMemcpyAsync(c->lc.get(), cost.data(), sizeof(double) * ell, hipMemcpyHostToDevice, st));
+    WC_HIP(hipStreamSynchronize(st));
+}
+
+void setup(sdp_ctx* c, const sdp_problem* p, const sdp_lp_block* lp, const sdp_options* o, hipStream_t st) {
     require(p != nullptr, "problem is NULL");
     require(p->n >= 2, "n must be at least 2");
     require(p->m >= 1, "m must be at least 1");
@@ -418,6 +502,13 @@ void setup(sdp_ctx* c, const sdp_problem* p, const sdp_options* o, hipStream_t s
     set_identity(st, n, c->X, n, c->xi);
     set_identity(st, n, c->S, n, c->eta);
     fill(st, m + 32, c->y, 0.0);
+    if (lp != nullptr) {
+        setup_lp(c, lp, st);
+        c->xl.alloc(c->ell);
+        c->sl.alloc(c->ell);
+        fill(st, c->ell, c->xl, c->xi);
+        fill(st, c->ell, c->sl, c->eta);
+    }
     alloc_work(c);
     WC_HIP(hipStreamSynchronize(st));
 }
@@ -523,8 +614,22 @@ void ensure_scaling(sdp_ctx* c) {
     symmetrize(st, n, c->E, n);
     if (c->lowp) to_lowp(st, c->lp, n, n, c->E, n, c->Elp, n);
     sigma_diag(st, n, r, c->lam, c->tau, c->sig);
-    // script-A script-Q, row i = script-Q^T svec(A_i)
     const int d = c->d;
+    // the LP split against the same tau: T, its Sigma entries after the SDP
+    // ones in sig, and the script-E entries of the rest
+    c->t = 0;
+    if (c->ell > 0) {
+        lp_split(st, c->ell, c->xl, c->sl, c->tau, c->tcap, c->wl, c->e2l, c->posl, c->Tl, c->sig + d,
+                 c->info.get() + 3);
+        int ht[2] = {0, 0};
+        WC_HIP(hipMemcpyAsync(ht, c->info.get() + 3, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        WC_HIP(hipStreamSynchronize(st));
+        if (ht[1]) throw Error(kENumeric, "x or s of the LP block is not positive (" + std::to_string(ht[1]) + " entries)");
+        require(ht[0] >= 0 && ht[0] <= c->tcap, "LP split: |T| outside [0, lp_top_max]");
+        c->t = ht[0];
+    }
+    c->dv = d + c->t;
+    // script-A script-Q, row i = script-Q^T svec(A_i)
     if (c->kind == SDP_A_DENSE) {
         // T_i = A_i Q for every constraint (one batched GEMM), then
         // F = G_w^T [T_1 ... T_m] (one GEMM), so F_i = G_w^T A_i Q
@@ -550,17 +655,27 @@ void ensure_scaling(sdp_ctx* c) {
             }
         }
     }
+    if (c->t > 0) {
+        // the LP columns B[:, T] of script-A script-Q: C's blocks
+        // (AQ)^T B_T / beta and tau^2 Sigma_T + B_T^T B_T / beta
+        const bool dense = c->kind == SDP_A_DENSE;
+        lp_c12(st, n, r, d, c->t, c->Tl, c->lcptr, c->lcrow, c->lcval, dense ? c->AQ.get() : nullptr, c->dmaxp,
+               dense ? nullptr : c->jk.get(), c->Gw, n, 1.0 / c->beta, c->Cm, c->dmaxp);
+        lp_c22(st, d, c->t, c->Tl, c->lcptr, c->lcrow, c->lcval, c->sig + d, c->tau * c->tau, 1.0 / c->beta, c->Cm,
+               c->dmaxp);
+    }
+    const int dv = c->dv;
     mark(3);
     // C = L_C L_C^T, then C^{-1} = L_C^{-T} L_C^{-1}
-    potrf(st, d, c->Cm, c->dmaxp, c->info.get());
+    potrf(st, dv, c->Cm, c->dmaxp, c->info.get());
     WC_HIP(hipMemcpyAsync(hinfo, c->info.get(), sizeof(int), hipMemcpyDeviceToHost, st));
     WC_HIP(hipStreamSynchronize(st));
     if (hinfo[0]) throw Error(kENumeric, "the preconditioner's Schur complement is not positive definite");
     // Z = L_C^{-1}, then C^{-1} = Z^T Z: only its upper triangle, which is all
     // the symmetric product of the preconditioner reads (a third of the flops
     // of a full product, the triangular factors' zeros skipped)
-    trtri(st, d, c->Cm, c->dmaxp, c->Cinv, c->dmaxp, c->Zw);
-    dgemm_lauum_upper(st, d, c->Cinv, c->dmaxp, c->Cm, c->dmaxp);
+    trtri(st, dv, c->Cm, c->dmaxp, c->Cinv, c->dmaxp, c->Zw);
+    dgemm_lauum_upper(st, dv, c->Cinv, c->dmaxp, c->Cm, c->dmaxp);
     std::swap(c->Cm, c->Cinv);
     mark(4);
     if (tm)
@@ -572,6 +687,16 @@ void ensure_scaling(sdp_ctx* c) {
 }
 
 // ---- augmented operator (eq. augsys via the Section 5 products) --------------------------
+// The LP block's share of the operator (FP64 in every form): with
+// t = B^T u, top += B (E_lp t + P_T v_lp) and bottom_T = t_T - tau^2 Sigma_T v_lp.
+static void lp_operator(sdp_ctx* c, const double* u, const double* v, double* out) {
+    if (c->ell == 0) return;
+    const int m = c->m, d = c->d;
+    lp_apply_cols(c->st, c->ell, c->lcptr, c->lcrow, c->lcval, u, c->e2l, c->posl, v + d, c->sig + d,
+                  c->tau * c->tau, c->lz, out + m + d);
+    lp_b(c->st, m, c->lrptr, c->lrcol, c->lrval, c->lz, out, 1.0, 1.0);
+}
+
 void newton_apply(sdp_ctx* c, const double* in, double* out) {
     ensure_scaling(c);
     const int n = c->n, m = c->m, r = c->r;
@@ -600,6 +725,7 @@ void newton_apply(sdp_ctx* c, const double* in, double* out) {
         entry_yq(st, n, r, c->rptr, c->rcol, c->ridx, u, c->Gw, n, c->YQ);
         gemm(c, true, false, n, r, n, 1.0, c->Gw, n, c->YQ, n, 0.0, c->F, n);
         f_to_v(st, n, r, c->F, n, v, c->sig, c->tau * c->tau, out + m);
+        lp_operator(c, u, v, out);
         prof_end(c, SDP_K_NEWTON, e, 0.0);
         c->matvecs += 1;
         return;
@@ -625,6 +751,7 @@ void newton_apply(sdp_ctx* c, const double* in, double* out) {
     gemm(c, false, false, n, r, n, 1.0, c->Y, n, c->Gw, n, 0.0, c->YQ, n);
     gemm(c, true, false, n, r, n, 1.0, c->Gw, n, c->YQ, n, 0.0, c->F, n);
     f_to_v(st, n, r, c->F, n, v, c->sig, c->tau * c->tau, out + m);
+    lp_operator(c, u, v, out);
     prof_end(c, SDP_K_NEWTON, e, 0.0);
     c->matvecs += 1;
 }
@@ -705,6 +832,7 @@ void newton_apply_lowp(sdp_ctx* c, const double* in, double* out) {
         gemm(c, true, false, n, r, n, 1.0, c->Gw, n, c->YQ, n, 0.0, c->F, n);
         f_to_v(st, n, r, c->F, n, v, c->sig, c->tau * c->tau, out + m);
     }
+    lp_operator(c, u, v, out);
     c->lp_matvecs += 1;
 }
 
@@ -714,12 +842,14 @@ void newton_apply_lowp(sdp_ctx* c, const double* in, double* out) {
 static void aq_mul(sdp_ctx* c, const double* v, double* out, double alpha, double beta) {
     if (c->kind == SDP_A_DENSE) {
         gemv_rows(c->st, c->m, c->d, c->AQ, c->dmaxp, v, out, alpha, beta);
-        return;
+    } else {
+        const int n = c->n, r = c->r;
+        v_to_h(c->st, n, r, v, c->Hm);
+        gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
+        aq_entry_apply(c->st, c->m, n, r, c->jk, c->U, c->Gw, n, out, alpha, beta);
     }
-    const int n = c->n, r = c->r;
-    v_to_h(c->st, n, r, v, c->Hm);
-    gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
-    aq_entry_apply(c->st, c->m, n, r, c->jk, c->U, c->Gw, n, out, alpha, beta);
+    // the LP columns B[:, T]
+    if (c->t > 0) lp_b_top(c->st, c->m, c->lrptr, c->lrcol, c->lrval, c->posl, v + c->d, out, alpha);
 }
 
 // out = alpha (script-A script-Q)^T u + beta out (d).  Entry sampling:
@@ -727,13 +857,16 @@ static void aq_mul(sdp_ctx* c, const double* v, double* out, double alpha, doubl
 static void aqt_mul(sdp_ctx* c, const double* u, double* out, double alpha, double beta) {
     if (c->kind == SDP_A_DENSE) {
         gemv_rows(c->st, c->d, c->m, c->AQt, c->ldAQt, u, out, alpha, beta);
-        return;
+    } else {
+        const int n = c->n, r = c->r;
+        entry_yq(c->st, n, r, c->rptr, c->rcol, c->ridx, u, c->Gw, n, c->YQ);
+        gemm(c, true, false, n, r, n, 1.0, c->Gw, n, c->YQ, n, 0.0, c->F, n);
+        f_to_v(c->st, n, r, c->F, n, nullptr, c->sig, 0.0, c->td4);
+        axpby(c->st, c->d, alpha, c->td4, beta, out);
     }
-    const int n = c->n, r = c->r;
-    entry_yq(c->st, n, r, c->rptr, c->rcol, c->ridx, u, c->Gw, n, c->YQ);
-    gemm(c, true, false, n, r, n, 1.0, c->Gw, n, c->YQ, n, 0.0, c->F, n);
-    f_to_v(c->st, n, r, c->F, n, nullptr, c->sig, 0.0, c->td4);
-    axpby(c->st, c->d, alpha, c->td4, beta, out);
+    // the LP rows: (B^T u)_T
+    if (c->t > 0)
+        lp_bt_top(c->st, c->t, c->Tl, c->lcptr, c->lcrow, c->lcval, u, out + c->d, alpha, beta);
 }
 
 // Block elimination with P = [beta I, AQ; AQ^T, -tau^2 Sigma] (Section 6, with
@@ -742,7 +875,7 @@ static void aqt_mul(sdp_ctx* c, const double* u, double* out, double alpha, doub
 // gemv_rows reads its vector in 16-byte pairs, so zv must be an aligned,
 // zero-padded buffer (z + m is not 16-byte aligned for odd m).
 static void precond_block(sdp_ctx* c, const double* f, const double* h, double* z1, double* zv) {
-    const int m = c->m, d = c->d;
+    const int m = c->m, d = c->dv;  // the v-length, LP coordinates in T included
     hipStream_t st = c->st;
     const double ib = 1.0 / c->beta;
     aqt_mul(c, f, c->td, -ib, 0.0);                                      // td = -AQ^T f / beta
@@ -759,7 +892,7 @@ static void precond_block(sdp_ctx* c, const double* f, const double* h, double* 
 // AQ^T z1 - tau^2 Sigma zv = h that keeps the bottom residual of indefinite
 // PCG at zero (Section 6); one refinement step restores it to O(eps^2).
 static void precond_apply(sdp_ctx* c, const double* rv, double* z) {
-    const int m = c->m, d = c->d;
+    const int m = c->m, d = c->dv;
     hipStream_t st = c->st;
     const double* f = rv;
     const double* h = rv + m;
@@ -779,7 +912,7 @@ static void precond_apply(sdp_ctx* c, const double* rv, double* z) {
 // buffers that the row passes expect.
 void precond(sdp_ctx* c, const double* in, double* out) {
     ensure_scaling(c);
-    const long N = (long)c->m + c->d;
+    const long N = (long)c->m + c->dv;
     copy(c->st, N, in, c->vres);
     precond_apply(c, c->vres, c->vdx);
     copy(c->st, N, c->vdx, out);
@@ -825,7 +958,7 @@ struct PcgOut {
 };
 static PcgOut pcg_loop(sdp_ctx* c, bool lowp, const double* g, double* x, double tol_rel, int maxit,
                        double replace = 0.0) {
-    const int m = c->m, d = c->d;
+    const int m = c->m, d = c->dv;  // v-length, LP coordinates in T included
     const long N = (long)m + d;
     hipStream_t st = c->st;
     double* sc = c->sc;
@@ -926,7 +1059,7 @@ static PcgOut pcg_loop(sdp_ctx* c, bool lowp, const double* g, double* x, double
 // this loop follows.  Stops when the residual norm estimate
 // |phibar| <= tol_rel ||g|| or after maxit steps.
 static PcgOut minres_loop(sdp_ctx* c, const double* g, double* x, double tol_rel, int maxit) {
-    const int m = c->m, d = c->d;
+    const int m = c->m, d = c->dv;  // v-length, LP coordinates in T included
     const long N = (long)m + d;
     hipStream_t st = c->st;
     double* sc = c->sc;
@@ -1004,9 +1137,11 @@ static PcgOut minres_loop(sdp_ctx* c, const double* g, double* x, double tol_rel
 // bottom block with the FP64 one, so that residual is rounding noise, which
 // the tiny tau^2 Sigma block would amplify (indefinite PCG likewise keeps its
 // bottom residual at zero).
-int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, double* dy, sdp_inner_stats* stats) {
+int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, const double* ct_l, double* dX, double* dy,
+                double* dx_l, sdp_inner_stats* stats) {
     ensure_scaling(c);
-    const int n = c->n, m = c->m, r = c->r, d = c->d;
+    require((c->ell > 0) == (ct_l != nullptr && dx_l != nullptr), "inner solve: the LP block's c~ and dx go together");
+    const int n = c->n, m = c->m, r = c->r, d = c->dv;  // d: v-length, LP coordinates in T included
     const long N = (long)m + d;
     hipStream_t st = c->st;
     const double t2 = c->tau * c->tau;
@@ -1019,6 +1154,12 @@ int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, doub
     gemm(c, false, false, n, r, n, 1.0, Ct, n, c->Gw, n, 0.0, c->YQ, n);
     gemm(c, true, false, n, r, n, 1.0, c->Gw, n, c->YQ, n, 0.0, c->F, n);
     f_to_v(st, n, r, c->F, n, nullptr, c->sig, 0.0, c->vtmp);              // vtmp = Q^T c
+    if (c->ell > 0) {
+        // LP block: top += tau^2 B (E_lp c~); vtmp's LP part = c~_T
+        lp_scale_e2(st, c->ell, c->e2l, ct_l, t2, c->lz);
+        lp_b(st, m, c->lrptr, c->lrcol, c->lrval, c->lz, c->vg, 1.0, 1.0);
+        lp_gather_top(st, c->t, c->Tl, ct_l, c->vtmp + c->d);
+    }
     axpby(st, d, t2, c->vtmp, 0.0, c->vg + m);
     fill(st, m, c->vx, 0.0);
     neg_div(st, d, c->vtmp, c->sig, c->vx + m);
@@ -1053,6 +1194,8 @@ int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, doub
         // 0 selects the reduction that suits the precision: BF16 GEMM operands
         // (u = 2^-8) make each sweep's correction accurate to ~1e-3 only
         const double rtol = c->opt.refine_tol > 0 ? c->opt.refine_tol : (c->lp == Lp::BF16 ? 1e-3 : 1e-6);
+        double prev = 0.0;
+        int slow = 0;  // consecutive sweeps that did not halve the FP64 residual
         while (true) {
             newton_apply(c, c->vx, c->vKp);
             axpbypcz(st, N, 1.0, c->vg, -1.0, c->vKp, 0.0, c->vres);          // rho = g - K x (FP64)
@@ -1067,6 +1210,10 @@ int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, doub
                 break;
             }
             if (!std::isfinite(rr) || sweeps >= c->opt.max_refine || its >= c->opt.inner_maxit) break;
+            // stop once the sweeps no longer contract (two in a row below a factor 2)
+            slow = (sweeps > 0 && rr > 0.5 * prev) ? slow + 1 : 0;
+            if (slow >= 2) break;
+            prev = rr;
             fill(st, d, c->vres + m, 0.0);
             fill(st, N, c->vdx, 0.0);
             // ask each sweep only for the reduction still needed (with a factor 2
@@ -1080,6 +1227,11 @@ int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, doub
         }
     }
     recover(c, c->vx, Ct, dX, dy);
+    if (c->ell > 0) {
+        // dx = E_lp (B^T u - tau^2 c~) + P_T v_lp
+        lp_bt(st, c->ell, c->lcptr, c->lcrow, c->lcval, c->vx, c->lbt, 1.0, 0.0);
+        lp_recover(st, c->ell, c->e2l, c->posl, c->lbt, ct_l, t2, c->vx + m + c->d, dx_l);
+    }
     c->pcg_total += its;
     if (stats) {
         stats->iterations = its;
@@ -1178,19 +1330,34 @@ static Resid residuals(sdp_ctx* c) {
     axpby(st, nn, -1.0, c->S, 1.0, c->Rd);
     symmetrize(st, n, c->Rd, n);
     double* sc = c->sc;
+    const int ell = c->ell;
+    if (ell > 0) {
+        // r_p -= B x;  r_d = c - B^T y - s
+        lp_b(st, m, c->lrptr, c->lrcol, c->lrval, c->xl, c->rp, -1.0, 1.0);
+        lp_bt(st, ell, c->lcptr, c->lcrow, c->lcval, c->y, c->rd_l, -1.0, 0.0);
+        axpbypcz(st, ell, 1.0, c->lc, -1.0, c->sl, 1.0, c->rd_l);
+    }
     dot(st, nn, c->X, c->S, sc + 10, c->part);
     dot(st, nn, c->C, c->X, sc + 11, c->part);
     dot(st, m, c->b, c->y, sc + 12, c->part);
     dot(st, m, c->rp, c->rp, sc + 13, c->part);
     dot(st, nn, c->Rd, c->Rd, sc + 14, c->part);
-    fetch(c, sc + 10, 5);
+    if (ell > 0) {
+        dot(st, ell, c->xl, c->sl, sc + 15, c->part);
+        dot(st, ell, c->lc, c->xl, sc + 16, c->part);
+        dot(st, ell, c->rd_l, c->rd_l, sc + 17, c->part);
+    }
+    fetch(c, sc + 10, ell > 0 ? 8 : 5);
     Resid R;
-    R.mu = c->pin[0] / n;
-    R.pobj = c->pin[1];
-    R.dobj = c->pin[2];
+    const double* q = c->pin;
+    const double gap = q[0] + (ell > 0 ? q[5] : 0.0);
+    R.mu = gap / (n + ell);
+    R.pobj = q[1] + (ell > 0 ? q[6] : 0.0);
+    R.dobj = q[2];
     R.relgap = std::fabs(R.pobj - R.dobj) / (1.0 + std::fabs(R.pobj) + std::fabs(R.dobj));
-    R.pinf = std::sqrt(c->pin[3]) / (1.0 + c->bnorm);
-    R.dinf = std::sqrt(c->pin[4]) / (1.0 + c->Cnorm);
+    R.pinf = std::sqrt(q[3]) / (1.0 + c->bnorm);
+    R.dinf = std::sqrt(q[4] + (ell > 0 ? q[7] : 0.0)) /
+             (1.0 + std::sqrt(c->Cnorm * c->Cnorm + c->lcnorm * c->lcnorm));
     return R;
 }
 
@@ -1218,24 +1385,46 @@ int ipm_step(sdp_ctx* c, sdp_step_stats* stats) {
     WC_HIP(hipStreamSynchronize(st));
     const auto t2c = clk::now();
     s.r = c->r;
-    // predictor: b~ = r_p, C~ = R_d + S
+    const int ell = c->ell;
+    const bool lp = ell > 0;
+    double* sc = c->sc;
+    // predictor: b~ = r_p, C~ = R_d + S (LP block: c~ = r_d + s)
     axpbypcz(st, nn, 1.0, c->Rd, 1.0, c->S, 0.0, c->Ct);
+    if (lp) axpbypcz(st, ell, 1.0, c->rd_l, 1.0, c->sl, 0.0, c->ct_l);
     sdp_inner_stats is{};
-    int rc = inner_solve(c, c->rp, c->Ct, c->dXa, c->dya, &is);
+    int rc = inner_solve(c, c->rp, c->Ct, lp ? c->ct_l.get() : nullptr, c->dXa, c->dya, lp ? c->dxa_l.get() : nullptr,
+                         &is);
     if (rc != 0) throw Error(rc, "predictor inner solve did not converge");
     s.pcg_pred = is.iterations;
     at_apply(c, c->dya, c->Y);
     axpbypcz(st, nn, 1.0, c->Rd, -1.0, c->Y, 0.0, c->dSa);
+    if (lp) {
+        // ds = r_d - B^T dy
+        lp_bt(st, ell, c->lcptr, c->lcrow, c->lcval, c->dya, c->dsa_l, -1.0, 0.0);
+        axpby(st, ell, 1.0, c->rd_l, 1.0, c->dsa_l);
+    }
     double ap, ad;
     max_step2(c, c->dXa, c->dSa, &ap, &ad);
     ap = std::min(1.0, ap);
     ad = std::min(1.0, ad);
-    double* sc = c->sc;
+    if (lp) {
+        lp_ratio(st, ell, c->xl, c->dxa_l, c->sl, c->dsa_l, sc + 24);
+        fetch(c, sc + 24, 2);
+        ap = std::min(ap, c->pin[0]);
+        ad = std::min(ad, c->pin[1]);
+    }
     dot(st, nn, c->X, c->dSa, sc + 16, c->part);
     dot(st, nn, c->dXa, c->S, sc + 17, c->part);
     dot(st, nn, c->dXa, c->dSa, sc + 18, c->part);
-    fetch(c, sc + 16, 3);
-    const double mu_aff = (R.mu * n + ad * c->pin[0] + ap * c->pin[1] + ap * ad * c->pin[2]) / n;
+    if (lp) {
+        dot(st, ell, c->xl, c->dsa_l, sc + 19, c->part);
+        dot(st, ell, c->dxa_l, c->sl, sc + 20, c->part);
+        dot(st, ell, c->dxa_l, c->dsa_l, sc + 21, c->part);
+    }
+    fetch(c, sc + 16, lp ? 6 : 3);
+    const double* q = c->pin;
+    const double gx = q[0] + (lp ? q[3] : 0.0), gs = q[1] + (lp ? q[4] : 0.0), gg = q[2] + (lp ? q[5] : 0.0);
+    const double mu_aff = (R.mu * (n + ell) + ad * gx + ap * gs + ap * ad * gg) / (n + ell);
     double sig = std::min(1.0, std::max(0.0, mu_aff / R.mu));
     sig = sig * sig * sig;
     s.sigma = sig;
@@ -1250,18 +1439,36 @@ int ipm_step(sdp_ctx* c, sdp_step_stats* stats) {
     gemm(c, false, false, n, n, n, 1.0, c->T1, n, c->Ginv, n, 0.0, c->T2, n);
     axpbypcz(st, nn, 1.0, c->Rd, -1.0, c->T2, 0.0, c->Ct);
     symmetrize(st, n, c->Ct, n);
-    rc = inner_solve(c, c->rp, c->Ct, c->dX, c->dy, &is);
+    // LP block: c~ = r_d - h / w with h = (sigma mu - x s - dx_a ds_a) / sqrt(x s)
+    if (lp) lp_corrector(st, ell, c->xl, c->sl, c->dxa_l, c->dsa_l, sig * R.mu, c->rd_l, c->ct_l);
+    rc = inner_solve(c, c->rp, c->Ct, lp ? c->ct_l.get() : nullptr, c->dX, c->dy, lp ? c->dx_l.get() : nullptr, &is);
     if (rc != 0) throw Error(rc, "corrector inner solve did not converge");
     s.pcg_corr = is.iterations;
     at_apply(c, c->dy, c->Y);
     axpbypcz(st, nn, 1.0, c->Rd, -1.0, c->Y, 0.0, c->dS);
+    if (lp) {
+        lp_bt(st, ell, c->lcptr, c->lcrow, c->lcval, c->dy, c->ds_l, -1.0, 0.0);
+        axpby(st, ell, 1.0, c->rd_l, 1.0, c->ds_l);
+    }
     const double frac = c->opt.step_frac;
     max_step2(c, c->dX, c->dS, &ap, &ad);
-    ap = guard_step(c, c->X, c->dX, std::min(1.0, frac * ap));
-    ad = guard_step(c, c->S, c->dS, std::min(1.0, frac * ad));
+    ap = std::min(1.0, frac * ap);
+    ad = std::min(1.0, frac * ad);
+    if (lp) {
+        lp_ratio(st, ell, c->xl, c->dx_l, c->sl, c->ds_l, sc + 24);
+        fetch(c, sc + 24, 2);
+        ap = std::min(ap, frac * c->pin[0]);
+        ad = std::min(ad, frac * c->pin[1]);
+    }
+    ap = guard_step(c, c->X, c->dX, ap);
+    ad = guard_step(c, c->S, c->dS, ad);
     axpby(st, nn, ap, c->dX, 1.0, c->X);
     axpby(st, m, ad, c->dy, 1.0, c->y);
     axpby(st, nn, ad, c->dS, 1.0, c->S);
+    if (lp) {
+        axpby(st, ell, ap, c->dx_l, 1.0, c->xl);
+        axpby(st, ell, ad, c->ds_l, 1.0, c->sl);
+    }
     symmetrize(st, n, c->X, n);
     symmetrize(st, n, c->S, n);
     WC_HIP(hipStreamSynchronize(st));
@@ -1291,6 +1498,7 @@ int ipm_step(sdp_ctx* c, sdp_step_stats* stats) {
 // iterate is first moved onto that point by pure centring Newton steps
 // (sigma = 1, no second-order term), each an inner solve as in ipm_step.
 int adjoint(sdp_ctx* c, const double* GX, double* gb, double* gC, sdp_adjoint_stats* stats) {
+    require(c->ell == 0, "sdp_adjoint does not support problems with an LP block");
     const int n = c->n, m = c->m;
     const long nn = (long)n * n;
     hipStream_t st = c->st;
@@ -1331,7 +1539,7 @@ int adjoint(sdp_ctx* c, const double* GX, double* gb, double* gC, sdp_adjoint_st
         axpbypcz(st, nn, 1.0, c->Rd, -1.0, c->T2, 0.0, c->Ct);
         symmetrize(st, n, c->Ct, n);
         sdp_inner_stats is{};
-        int rc = inner_solve(c, c->rp, c->Ct, c->dX, c->dy, &is);
+        int rc = inner_solve(c, c->rp, c->Ct, nullptr, c->dX, c->dy, nullptr, &is);
         inner_its += is.iterations;
         if (rc != 0) break;  // keep the closest point so far
         at_apply(c, c->dy, c->Y);
@@ -1361,7 +1569,7 @@ int adjoint(sdp_ctx* c, const double* GX, double* gb, double* gC, sdp_adjoint_st
     symmetrize(st, n, c->Ct, n);
     fill(st, m, c->dya, 0.0);
     sdp_inner_stats is{};
-    int rc = inner_solve(c, c->dya, c->Ct, gC, gb, &is);
+    int rc = inner_solve(c, c->dya, c->Ct, nullptr, gC, gb, nullptr, &is);
     inner_its += is.iterations;
     WC_HIP(hipStreamSynchronize(st));
     if (stats) {
@@ -1441,6 +1649,14 @@ void set_point(sdp_ctx* c, const double* X, const double* y, const double* S) {
     // depend on what the context computed before
     c->have_prev = false;
     c->iter = 0;
+    WC_HIP(hipStreamSynchronize(c->st));
+}
+
+void set_point_lp(sdp_ctx* c, const double* x, const double* s) {
+    require(c->ell > 0, "the problem has no LP block");
+    if (x) copy(c->st, c->ell, x, c->xl);
+    if (s) copy(c->st, c->ell, s, c->sl);
+    c->scaling_valid = false;
     WC_HIP(hipStreamSynchronize(c->st));
 }
 

@@ -32,14 +32,23 @@ struct sdp_ctx {
     wc::DevBuf<double> b, C;    // m, n x n
     double bnorm = 0, Cnorm = 0, mean_a2 = 0, xi = 1, eta = 1;
 
+    // ---- LP block (nonnegative orthant, eq. rmc-sdp / eq. snl-sdp; ell == 0 when absent) ----
+    int ell = 0;                // LP coordinates
+    int tcap = 0;               // most LP coordinates in the low-rank part T
+    wc::DevBuf<int> lcptr, lcrow, lrptr, lrcol;  // B by columns (rows sorted) and by rows
+    wc::DevBuf<double> lcval, lrval, lc;         // their values; the cost c
+    double lcnorm = 0;
+
     // ---- iterate -------------------------------------------------------------
     wc::DevBuf<double> X, y, S;
+    wc::DevBuf<double> xl, sl;  // LP block of the primal and dual iterate
     int iter = 0;
 
     // ---- scaling point and its split (valid while scaling_valid) -------------
     bool scaling_valid = false;
     bool have_prev = false;     // Vs / Gw hold the previous scaling's vectors (warm start)
     int rmax = 1, r = 1, d = 0;
+    int t = 0, dv = 0;          // LP coordinates in T; v-length d + t of the augmented system
     int sweeps_nt = 0, sweeps_w = 0;  // Jacobi sweeps of the last NT SVD and eigen-decomposition of W
     long dmaxp = 0;             // padded row pitch for d-length rows
     double tau = 0, beta = 0;
@@ -50,6 +59,8 @@ struct sdp_ctx {
                                 // (entry-sampling problems apply script-A script-Q without forming it)
     wc::JacobiWork jw;
     wc::LanczosWork lw;
+    wc::DevBuf<double> wl, e2l;  // LP split: w = sqrt(x/s), script-E entries (Sigma at T sits in sig[d..d+t))
+    wc::DevBuf<int> posl, Tl;    // LP split: position of each coordinate in T (or -1); T in increasing order
 
     // ---- temporaries -------------------------------------------------------------
     wc::DevBuf<double> Y, T1, T2, T3, Mm, Hm, U, YQ, F, mw, yp, part, gpart, tm, td, td2, td3, td4, rho, dz;
@@ -72,6 +83,7 @@ struct sdp_ctx {
 
     // ---- Newton direction buffers ----------------------------------------------
     wc::DevBuf<double> dXa, dya, dSa, dX, dy, dS, Ct, Rd, rp, Hc, Dx, Ds;
+    wc::DevBuf<double> dxa_l, dsa_l, dx_l, ds_l, ct_l, rd_l, lz, lbt;  // LP block (l entries each)
 
     // ---- counters / profiling ------------------------------------------------------
     int64_t matvecs = 0, pcg_total = 0, lp_matvecs = 0;
@@ -88,16 +100,19 @@ struct sdp_ctx {
 
 namespace wc {
 
-void setup(sdp_ctx* c, const sdp_problem* p, const sdp_options* o, hipStream_t st);
+void setup(sdp_ctx* c, const sdp_problem* p, const sdp_lp_block* lp, const sdp_options* o, hipStream_t st);
 void ensure_scaling(sdp_ctx* c);
 void newton_apply(sdp_ctx* c, const double* in, double* out);
 void newton_apply_lowp(sdp_ctx* c, const double* in, double* out);
 void precond(sdp_ctx* c, const double* in, double* out);
-int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, double* dX, double* dy, sdp_inner_stats* stats);
+// ct_l / dx_l: the LP block's c~ and dx (l entries; nullptr without an LP block)
+int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, const double* ct_l, double* dX, double* dy,
+                double* dx_l, sdp_inner_stats* stats);
 int ipm_step(sdp_ctx* c, sdp_step_stats* stats);
 int solve(sdp_ctx* c, sdp_result* res);
 int adjoint(sdp_ctx* c, const double* GX, double* gb, double* gC, sdp_adjoint_stats* stats);
 void set_point(sdp_ctx* c, const double* X, const double* y, const double* S);
+void set_point_lp(sdp_ctx* c, const double* x, const double* s);
 void prof_begin(sdp_ctx* c, int k, hipEvent_t* e0);
 void prof_end(sdp_ctx* c, int k, hipEvent_t e0, double bytes);
 void prof_collect(sdp_ctx* c);

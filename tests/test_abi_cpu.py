@@ -37,7 +37,7 @@ def test_default_options():
     L.lib().sdp_default_options(C.byref(o))
     assert o.rank_max == 10 and o.inner_tol == 1e-10 and o.gap_tol == 1e-8 and o.step_frac == 0.98
     assert o.solver == L.SDP_SOLVER_PCG and o.inner_prec == L.SDP_PREC_F64
-    assert o.max_refine == 8 and o.refine_tol == 0.0
+    assert o.max_refine == 20 and o.refine_tol == 0.0 and o.lp_top_max == 2048
 
 
 def _setup_status(problem, opts=None):

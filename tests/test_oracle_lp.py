@@ -112,6 +112,14 @@ def test_lp_split_identity(cap):
         assert np.all(lsp["e2"][off] <= 4.0)
 
 
+def test_lp_split_cap_keeps_or_drops_tied_groups_whole():
+    sp = {"tau": 0.1}
+    w = np.array([5.0, 1.0, 5.0, 7.0, 5.0, 0.05])
+    assert list(rf.lp_split(sp, w, cap=3)["T"]) == [3]
+    assert list(rf.lp_split(sp, w, cap=4)["T"]) == [0, 2, 3, 4]
+    assert list(rf.lp_split(sp, w, cap=10)["T"]) == [0, 1, 2, 3, 4]
+
+
 def rmc_split(iters):
     p, res = rmc_point(iters)
     G, _, _ = nt.nt_factor(res["X"], res["S"])
