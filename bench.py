@@ -201,6 +201,30 @@ def pmc_reduce(out_path, specs):
     print(f"reduced {', '.join(f'{k}: {len(v)} kernels' for k, v in out.items())}", flush=True)
 
 
+def trace_reduce(out_path, trace_dir):
+    """Per (kernel, grid) call counts and durations from a rocprofv3 kernel-trace CSV directory."""
+    import collections
+    import csv
+    import glob
+
+    agg = collections.defaultdict(list)
+    for f in glob.glob(f"{trace_dir}/**/*kernel_trace.csv", recursive=True):
+        for row in csv.DictReader(open(f)):
+            dur = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
+            # total work-items: Grid_Size, or the product of its per-dimension columns
+            grid = 1
+            for k, v in row.items():
+                if k.startswith("Grid_Size") and v not in ("", None):
+                    grid *= int(v)
+            agg[(row["Kernel_Name"][:160], grid)].append(dur)
+    rows = [{"kernel": k, "grid": g, "calls": len(v), "total_ms": sum(v) / 1e6, "avg_us": sum(v) / len(v) / 1e3,
+             "min_us": min(v) / 1e3, "max_us": max(v) / 1e3} for (k, g), v in agg.items()]
+    rows.sort(key=lambda r: -r["total_ms"])
+    with open(out_path, "w") as fh:
+        json.dump(rows, fh, indent=1)
+    print(f"reduced {len(rows)} (kernel, grid) pairs", flush=True)
+
+
 def bench_batched(args):
     """The batched workload: 1024 Gaussian sensing SDPs (n in [16,128], r in {1,2,3}, m = 3nr) in one persistent launch.
 
@@ -788,6 +812,8 @@ def main():
                     help="only the short run profiled for hardware counters")
     ap.add_argument("--pmc-reduce", nargs="+", metavar="ARG", default=None,
                     help="OUT.json tag=dir ...: per-kernel averages of rocprofv3 counter CSVs (no GPU)")
+    ap.add_argument("--trace-reduce", nargs=2, metavar=("OUT", "DIR"), default=None,
+                    help="per (kernel, grid) durations from a rocprofv3 kernel-trace CSV directory (no GPU)")
     ap.add_argument("--no-mixed", action="store_true", help="sensing: skip the mixed-precision solves")
     ap.add_argument("--no-config1", action="store_true", help="completion: skip the n=200 sensing solves")
     ap.add_argument("--workload", choices=["completion", "sensing", "batched", "adjoint", "rmc", "snl"],
@@ -808,6 +834,9 @@ def main():
         sys.exit(2)
     if args.pmc_reduce:
         pmc_reduce(args.pmc_reduce[0], args.pmc_reduce[1:])
+        return
+    if args.trace_reduce:
+        trace_reduce(*args.trace_reduce)
         return
     if args.pmc_pass:
         pmc_pass(args.pmc_pass)
