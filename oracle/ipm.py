@@ -53,8 +53,9 @@ def scaled_rows(problem, G: np.ndarray) -> np.ndarray:
     n, m = problem["n"], problem["m"]
     jj, kk = np.tril_indices(n)
     w = np.where(jj == kk, 1.0, np.sqrt(2.0))
-    if problem["kind"] == "dense":
-        A = problem["A"].reshape(m, n, n)
+    if problem["kind"] in ("dense", "sparse"):
+        A = (problem["A"].reshape(m, n, n) if problem["kind"] == "dense"
+             else np.stack([ops.a_matrix(problem, i) for i in range(m)]))
         At = np.matmul(np.matmul(G.T[None], A), G[None])
     else:
         jk = problem["jk"]
@@ -66,7 +67,7 @@ def scaled_rows(problem, G: np.ndarray) -> np.ndarray:
 
 def schur_matrix(problem, G: np.ndarray, W: np.ndarray, w_lp=None) -> np.ndarray:
     """M_ij = <A_i, W A_j W> (+ (B diag(w_lp^2) B^T)_ij with an LP block) formed explicitly."""
-    if problem["kind"] == "dense":
+    if problem["kind"] in ("dense", "sparse"):
         Ap = scaled_rows(problem, G)
         M = Ap @ Ap.T
     else:

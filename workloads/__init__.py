@@ -248,7 +248,8 @@ def robust_completion(n: int, m: int, m_o: int, seed: int, r: int = 2, lam: floa
     }
 
 
-def sensor_localization(n: int, m_y: int, m_a: int, m_yo: int, m_ao: int, seed: int, d: int = 2, k: int = 3):
+def sensor_localization(n: int, m_y: int, m_a: int, m_yo: int, m_ao: int, seed: int, d: int = 2, k: int = 3,
+                        kind: str = "dense"):
     """Sensor network localization with outliers (eq. snl-sdp), generated as in the experiments section.
 
     Sensors y_1..y_n and anchors a_1..a_k uniform in [0, 1]^d; m_y of the
@@ -258,7 +259,9 @@ def sensor_localization(n: int, m_y: int, m_a: int, m_yo: int, m_ao: int, seed: 
     rows fix the identity block (no slack), then one row per distance,
     <[0; e_i - e_j][0; e_i - e_j]^T, X> + v - u = delta_ij^2 and
     <[a_i; -e_j][a_i; -e_j]^T, X> + v - u = delta-bar_ij^2, with cost
-    sum (v + u) and C = 0.  Dense rows (vec of each A_i).
+    sum (v + u) and C = 0.  kind "dense": rows vec(A_i); kind "sparse": the
+    entries of each A_i on and above the diagonal (at most (d + 1)(d + 2)/2
+    per row), the same matrices.
     """
     rng = np.random.default_rng(seed)
     Ys = rng.uniform(0.0, 1.0, size=(d, n))
@@ -267,41 +270,41 @@ def sensor_localization(n: int, m_y: int, m_a: int, m_yo: int, m_ao: int, seed: 
     iu, ju = np.triu_indices(n, 1)
     py = np.sort(rng.choice(iu.size, size=m_y, replace=False))
     pa = np.sort(rng.choice(n * k, size=m_a, replace=False))
-    rows, bs = [], []
+    ents = []  # per row: list of (row, col, val) with row <= col
+    bs = []
     for p in range(d):
         for q in range(p, d):
-            M = np.zeros((N, N))
-            M[p, q] += 0.5
-            M[q, p] += 0.5
-            rows.append(M.reshape(-1))
+            ents.append([(p, q, 1.0 if p == q else 0.5)])
             bs.append(1.0 if p == q else 0.0)
     oy = set(rng.choice(m_y, size=m_yo, replace=False).tolist()) if m_yo > 0 else set()
     oa = set(rng.choice(m_a, size=m_a and m_ao, replace=False).tolist()) if m_ao > 0 else set()
+
+    def outer_entries(idx, vals):
+        out = []
+        for s1 in range(len(idx)):
+            for s2 in range(s1, len(idx)):
+                out.append((idx[s1], idx[s2], vals[s1] * vals[s2]))
+        return out
+
     for t, pidx in enumerate(py):
         i, j = iu[pidx], ju[pidx]
-        vec = np.zeros(N)
-        vec[d + i], vec[d + j] = 1.0, -1.0
         diff = Ys[:, i] - Ys[:, j]
         if t in oy:
             diff = diff + rng.standard_normal(d)
-        rows.append(np.outer(vec, vec).reshape(-1))
+        ents.append(outer_entries([d + i, d + j], [1.0, -1.0]))
         bs.append(float(diff @ diff))
     for t, pidx in enumerate(pa):
         i, j = divmod(int(pidx), n)  # anchor i, sensor j
-        vec = np.zeros(N)
-        vec[:d], vec[d + j] = anc[:, i], -1.0
         diff = anc[:, i] - Ys[:, j]
         if t in oa:
             diff = diff + rng.standard_normal(d)
-        rows.append(np.outer(vec, vec).reshape(-1))
+        ents.append(outer_entries(list(range(d)) + [d + j], list(anc[:, i]) + [-1.0]))
         bs.append(float(diff @ diff))
     m0 = d * (d + 1) // 2
     m = m0 + m_y + m_a
-    return {
-        "kind": "dense",
+    out = {
         "n": N,
         "m": m,
-        "A": np.ascontiguousarray(np.stack(rows)),
         "b": np.array(bs),
         "C": np.zeros((N, N)),
         "lp": _slack_pairs(np.arange(m0, m), np.ones(m - m0), m),
@@ -310,6 +313,22 @@ def sensor_localization(n: int, m_y: int, m_a: int, m_yo: int, m_ao: int, seed: 
         "d": d,
         "seed": seed,
     }
+    if kind == "sparse":
+        ptr = np.zeros(m + 1, dtype=np.int64)
+        ptr[1:] = np.cumsum([len(e) for e in ents])
+        flat = [t for e in ents for t in e]
+        out.update({"kind": "sparse", "sp": {"ptr": ptr,
+                                             "row": np.array([t[0] for t in flat], dtype=np.int32),
+                                             "col": np.array([t[1] for t in flat], dtype=np.int32),
+                                             "val": np.array([t[2] for t in flat], dtype=np.float64)}})
+    else:
+        A = np.zeros((m, N * N))
+        for i, e in enumerate(ents):
+            for r, c, v in e:
+                A[i, r * N + c] = v
+                A[i, c * N + r] = v
+        out.update({"kind": "dense", "A": A})
+    return out
 
 
 def batched_sensing(count: int, seed: int, n_lo: int = 16, n_hi: int = 128):
