@@ -312,7 +312,8 @@ def bench_batched(args):
 # Table rmc and Table snl rows (n, m, m_o) with the paper's own times for its
 # method (CPU, another machine): context, not a target on this hardware
 RMC_ROWS = [(100, 3000, 12, 1.2), (300, 45000, 150, 32.1), (500, 125000, 300, 127.0), (1000, 500000, 450, 1106.0)]
-SNL_ROWS = [(50, 1000, 30, 1.0), (50, 1300, 50, 0.6), (100, 5000, 100, 4.1)]
+SNL_ROWS = [(50, 1000, 30, 1.0), (50, 1300, 50, 0.6), (100, 5000, 100, 4.1), (300, 45000, 300, 117.5),
+            (500, 100000, 420, 499.3), (550, 110000, 460, 559.4), (500, 120000, 500, 760.5)]
 
 
 def bench_lp(args, which):
@@ -320,8 +321,8 @@ def bench_lp(args, which):
 
     RMC: entry-sampling rows plus slack pairs (eq. rmc-sdp), m sampled svec
     entries of X* = G G^T (G n x 2, N(0, 10^2)), m_o outliers N(0, 10^4).
-    SNL: n sensors, 3 anchors in [0, 1]^2, distance rows plus slack pairs
-    (eq. snl-sdp), min(3n, m/8) anchor-sensor measurements and the rest
+    SNL: n sensors, 3 anchors in [0, 1]^2, distance rows (sparse constraint
+    kind) plus slack pairs (eq. snl-sdp), min(3n, m/8) anchor-sensor measurements and the rest
     between sensors, m_o outliers N(0, I) inside the norm, split in proportion.  One solve per row from the
     standard start, timed around sdp_solve; the recovery error is
     ||X - X*||_F / ||X*||_F (RMC) or ||Y - Y*||_F (SNL) on the host.
@@ -341,7 +342,7 @@ def bench_lp(args, which):
         else:
             m_a = min(3 * n, m // 8)  # anchor-sensor pairs (there are only 3 n of them)
             m_ao = m_o * m_a // m
-            p = workloads.sensor_localization(n, m - m_a, m_a, m_o - m_ao, m_ao, seed=100 + n)
+            p = workloads.sensor_localization(n, m - m_a, m_a, m_o - m_ao, m_ao, seed=100 + n + m, kind="sparse")
         gen_s = time.perf_counter() - t0
         with Context(p) as ctx:
             torch.cuda.synchronize()
@@ -373,7 +374,7 @@ def bench_lp(args, which):
         "config": {"workload": ("robust matrix completion (eq. rmc-sdp), rank 2, entry sampling + LP slack pairs"
                                 if which == "rmc" else
                                 "sensor network localization with outliers (eq. snl-sdp), d = 2, 3 anchors, "
-                                "dense rows + LP slack pairs")},
+                                "sparse distance rows + LP slack pairs")},
         "rows": rows,
     }
     print(json.dumps(line))

@@ -57,7 +57,7 @@ enum {
 /* Largest distance to the central path at which sdp_adjoint reports SDP_OK. */
 #define SDP_ADJOINT_CENTER_TOL 1e-6
 
-enum { SDP_A_DENSE = 0, SDP_A_ENTRY = 1 };
+enum { SDP_A_DENSE = 0, SDP_A_ENTRY = 1, SDP_A_SPARSE = 2 };
 enum { SDP_SOLVER_PCG = 0, SDP_SOLVER_MINRES = 1 };
 enum { SDP_PREC_F64 = 0, SDP_PREC_F32 = 1, SDP_PREC_BF16 = 2 };
 enum { SDP_REFINE_SWEEPS = 0, SDP_REFINE_REPLACE = 1 };
@@ -68,6 +68,8 @@ enum { SDP_REFINE_SWEEPS = 0, SDP_REFINE_REPLACE = 1 };
  *      A_i must be symmetric.
  *  a_kind == SDP_A_ENTRY: jk holds m pairs (j, k), 0-based, j <= k < n, all
  *      distinct; A_i = (e_j e_k^T + e_k e_j^T)/2, so <A_i, X> = X_jk.
+ *  a_kind == SDP_A_SPARSE: A and jk are unused; the entries come in an
+ *      sdp_sparse_rows given to sdp_setup_ex.
  *  b has m entries; C is n x n symmetric.
  *  on_device != 0 means A / jk / b / C are device pointers, else host
  *  pointers.  Validation of values (NaN, symmetry, index range, duplicates)
@@ -85,6 +87,22 @@ typedef struct sdp_problem {
     const double* C;
     int32_t on_device;
 } sdp_problem;
+
+/*
+ * Sparse constraint matrices (a_kind == SDP_A_SPARSE): constraint i owns the
+ * entries ptr[i] .. ptr[i+1]-1 of (row, col, val), 0-based, row <= col < n,
+ * with A_i[row][col] = A_i[col][row] = val (repeated positions add).
+ * ptr has m + 1 entries, ptr[0] = 0, nondecreasing.  on_device as in
+ * sdp_lp_block.  Suited to constraints with few nonzeros each, such as the
+ * distance rows a a^T of eq. snl-sdp.
+ */
+typedef struct sdp_sparse_rows {
+    const int32_t* ptr;
+    const int32_t* row;
+    const int32_t* col;
+    const double* val;
+    int32_t on_device;
+} sdp_sparse_rows;
 
 /*
  * A nonnegative-orthant (LP) block beside the PSD variable: the problem
@@ -116,7 +134,9 @@ typedef struct sdp_lp_block {
  *               (Experiments section) [10, clipped to n - 1]
  *  rank_fixed   > 0 forces r [0]
  *  beta         > 0 fixes the preconditioner's beta (Corollary pcg); <= 0 uses
- *               (median eigenvalue of E)^2 * mean ||A_i||_F^2 [0]
+ *               (median eigenvalue of E)^2 * mean ||A_i||_F^2, with an LP block
+ *               raised to max_i (B diag(e2) B^T)_ii when that is larger (e2 the
+ *               LP coordinates' script-E entries: 1 on T) [0]
  *  solver       SDP_SOLVER_PCG (Corollary pcg) or SDP_SOLVER_MINRES (Corollary minres) [PCG]
  *  inner_tol    PCG stops when ||r_u|| <= inner_tol * ||r_u(0)|| [1e-10]
  *  inner_maxit  [2000]
@@ -241,6 +261,16 @@ sdp_status sdp_setup(const sdp_problem* prob, const sdp_options* opt, void* hip_
  */
 sdp_status sdp_setup_lp(const sdp_problem* prob, const sdp_lp_block* lp, const sdp_options* opt, void* hip_stream,
                         sdp_ctx** out);
+
+/*
+ * sdp_setup_lp for any constraint kind: sparse carries the constraint entries
+ * when prob->a_kind == SDP_A_SPARSE (NULL otherwise); lp may be NULL.  The
+ * sparse kind forms script-A script-Q explicitly from the entries (as for
+ * dense rows) and runs with inner_prec SDP_PREC_F64; sdp_adjoint and
+ * sdp_solve_batched do not take it (SDP_EINVAL).
+ */
+sdp_status sdp_setup_ex(const sdp_problem* prob, const sdp_sparse_rows* sparse, const sdp_lp_block* lp,
+                        const sdp_options* opt, void* hip_stream, sdp_ctx** out);
 
 /* Release every device buffer the context owns.  NULL is allowed. */
 void sdp_destroy(sdp_ctx* ctx);

@@ -117,7 +117,7 @@ def solve_newton_pcg_lp(problem, sp, lsp, bt, Ct, ct, beta=None, tol=1e-10, maxi
     sig = rf.sigma_diag(sp)
     sig_all = np.concatenate([sig, lsp["sig"]])
     if beta is None:
-        beta = rf.beta_rule(sp, problem)
+        beta = rf.beta_rule_lp(sp, lsp, problem)
     gu, gv = rf.aug_rhs_lp(problem, sp, lsp, E, bt, Ct, ct)
     g = np.concatenate([gu, gv])
     v0 = -np.concatenate([rf.qt_apply(sp, Ct), ct[lsp["T"]]]) / sig_all

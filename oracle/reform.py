@@ -42,7 +42,9 @@ Readings (documented in the design notes):
 * beta is the squared median eigenvalue of E multiplied by the mean of
   ||A_i||_F^2, so that it stays inside [lambda_min, lambda_max] of
   A E A^T for constraint matrices that are not unit-norm; the median of an
-  even count is the mean of the two middle values.
+  even count is the mean of the two middle values.  With the LP block it is
+  raised to the largest diagonal entry of B diag(e2) B^T when that is
+  larger (beta_rule_lp).
 """
 from __future__ import annotations
 
@@ -118,6 +120,17 @@ def beta_rule(sp, problem) -> float:
     med = float(np.median(e_eigenvalues(sp)))
     scale = float(np.mean(ops.frob_norms(problem) ** 2))
     return med * med * scale
+
+
+def beta_rule_lp(sp, lsp, problem) -> float:
+    """beta with the LP block: the (1,1) block of eq. augsys becomes
+    A E A^T + B diag(e2) B^T, and beta is the SDP rule's value raised to the
+    largest diagonal entry of B diag(e2) B^T when that is larger.  A diagonal
+    entry of that positive semidefinite term is at most lambda_max of the
+    whole block, so beta stays inside the bracket of Corollary pcg."""
+    B = ops.b_matrix(problem)
+    diag = (B * B) @ lsp["e2"]
+    return max(beta_rule(sp, problem), float(diag.max()) if diag.size else 0.0)
 
 
 # ---- explicit matrices (small n only) ---------------------------------------

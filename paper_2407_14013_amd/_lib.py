@@ -15,7 +15,7 @@ SDP_OK, SDP_EINVAL, SDP_ENOMEM, SDP_EDEVICE, SDP_ENOTCONV, SDP_ENUMERIC, SDP_EST
 SDP_ECENTER = -7
 WC_DSYMV_NOALLOC_MAX_D = 16384
 SDP_ADJOINT_CENTER_TOL = 1e-6
-SDP_A_DENSE, SDP_A_ENTRY = 0, 1
+SDP_A_DENSE, SDP_A_ENTRY, SDP_A_SPARSE = 0, 1, 2
 SDP_SOLVER_PCG, SDP_SOLVER_MINRES = 0, 1
 SDP_PREC_F64, SDP_PREC_F32, SDP_PREC_BF16 = 0, 1, 2
 SDP_REFINE_SWEEPS, SDP_REFINE_REPLACE = 0, 1
@@ -44,6 +44,16 @@ class SdpProblem(C.Structure):
         ("jk", C.c_void_p),
         ("b", C.c_void_p),
         ("C", C.c_void_p),
+        ("on_device", C.c_int32),
+    ]
+
+
+class SdpSparseRows(C.Structure):
+    _fields_ = [
+        ("ptr", C.c_void_p),
+        ("row", C.c_void_p),
+        ("col", C.c_void_p),
+        ("val", C.c_void_p),
         ("on_device", C.c_int32),
     ]
 
@@ -160,6 +170,8 @@ _SIGNATURES = [
     ("sdp_setup", C.c_int32, [C.POINTER(SdpProblem), C.POINTER(SdpOptions), C.c_void_p, C.POINTER(C.c_void_p)]),
     ("sdp_setup_lp", C.c_int32, [C.POINTER(SdpProblem), C.POINTER(SdpLpBlock), C.POINTER(SdpOptions), C.c_void_p,
                                  C.POINTER(C.c_void_p)]),
+    ("sdp_setup_ex", C.c_int32, [C.POINTER(SdpProblem), C.POINTER(SdpSparseRows), C.POINTER(SdpLpBlock),
+                                 C.POINTER(SdpOptions), C.c_void_p, C.POINTER(C.c_void_p)]),
     ("sdp_destroy", None, [C.c_void_p]),
     ("sdp_last_error", C.c_char_p, [C.c_void_p]),
     ("sdp_aug_dim", C.c_int64, [C.c_void_p]),

@@ -65,7 +65,7 @@ class Context:
         keep = []
         p = L.SdpProblem()
         p.n, p.m = self.n, self.m
-        p.a_kind = L.SDP_A_DENSE if self.kind == "dense" else L.SDP_A_ENTRY
+        p.a_kind = {"dense": L.SDP_A_DENSE, "entry": L.SDP_A_ENTRY, "sparse": L.SDP_A_SPARSE}[self.kind]
 
         def host(arr, dtype):
             a = np.ascontiguousarray(arr, dtype=dtype)
@@ -74,7 +74,20 @@ class Context:
 
         on_device = isinstance(problem["b"], torch.Tensor)
         p.on_device = 1 if on_device else 0
-        if on_device:
+        spr = None
+        if self.kind == "sparse":
+            # entries on and above the diagonal per constraint (host arrays)
+            sp = problem["sp"]
+            spr = L.SdpSparseRows()
+            spr.ptr = host(sp["ptr"], np.int32)
+            spr.row = host(sp["row"], np.int32)
+            spr.col = host(sp["col"], np.int32)
+            spr.val = host(sp["val"], np.float64)
+            spr.on_device = 0
+            p.b = host(problem["b"].cpu().numpy() if on_device else problem["b"], np.float64)
+            p.C = host(problem["C"].cpu().numpy() if on_device else problem["C"], np.float64)
+            p.on_device = 0
+        elif on_device:
             for key in ("b", "C") + (("A",) if self.kind == "dense" else ("jk",)):
                 t = problem[key]
                 if not t.is_contiguous() or not t.is_cuda:
@@ -108,7 +121,8 @@ class Context:
             lpb.val = host(lp["val"], np.float64)
             lpb.c = host(lp["c"], np.float64)
         ctx = C.c_void_p()
-        st = lib.sdp_setup_lp(C.byref(p), C.byref(lpb) if lpb is not None else None, C.byref(options),
+        st = lib.sdp_setup_ex(C.byref(p), C.byref(spr) if spr is not None else None,
+                              C.byref(lpb) if lpb is not None else None, C.byref(options),
                               _stream_ptr(self.stream), C.byref(ctx))
         if st != L.SDP_OK:
             raise SdpError(st, lib.sdp_last_error(None).decode())

@@ -77,6 +77,11 @@ sdp_status sdp_setup(const sdp_problem* prob, const sdp_options* opt, void* hip_
 
 sdp_status sdp_setup_lp(const sdp_problem* prob, const sdp_lp_block* lp, const sdp_options* opt, void* hip_stream,
                         sdp_ctx** out) {
+    return sdp_setup_ex(prob, nullptr, lp, opt, hip_stream, out);
+}
+
+sdp_status sdp_setup_ex(const sdp_problem* prob, const sdp_sparse_rows* sparse, const sdp_lp_block* lp,
+                        const sdp_options* opt, void* hip_stream, sdp_ctx** out) {
     if (!out) {
         g_setup_error = "out is NULL";
         return SDP_EINVAL;
@@ -110,8 +115,10 @@ sdp_status sdp_setup_lp(const sdp_problem* prob, const sdp_lp_block* lp, const s
                 wc::require(prob->n <= 16384, "sparse_sandwich needs n <= 16384");
             }
             wc::require(opt->lp_top_max >= 0, "lp_top_max must be non-negative");
+            wc::require(!prob || prob->a_kind != SDP_A_SPARSE || opt->inner_prec == SDP_PREC_F64,
+                        "sparse constraint rows run with inner_prec SDP_PREC_F64");
         }
-        wc::setup(c, prob, lp, opt, static_cast<hipStream_t>(hip_stream));
+        wc::setup(c, prob, sparse, lp, opt, static_cast<hipStream_t>(hip_stream));
         return SDP_OK;
     });
     if (s != SDP_OK) {

@@ -238,6 +238,35 @@ void lp_ratio(hipStream_t st, int ell, const double* x, const double* dx, const 
     WC_LAUNCH_CHECK();
 }
 
+// out[0] = max_i sum_j B_ij^2 e2_j, the largest diagonal entry of B diag(e2) B^T
+// (rows of B in CSR).  One workgroup.
+__global__ __launch_bounds__(kSplitThreads) void lp_row_diag_max_kernel(int m, const int* __restrict__ rptr,
+                                                                        const int* __restrict__ rcol,
+                                                                        const double* __restrict__ rval,
+                                                                        const double* __restrict__ e2,
+                                                                        double* __restrict__ out) {
+    __shared__ double red[kSplitThreads];
+    const int t = threadIdx.x;
+    double a = 0.0;
+    for (int i = t; i < m; i += kSplitThreads) {
+        double acc = 0.0;
+        for (int k = rptr[i]; k < rptr[i + 1]; ++k) acc += rval[k] * rval[k] * e2[rcol[k]];
+        a = fmax(a, acc);
+    }
+    red[t] = a;
+    __syncthreads();
+    for (int off = kSplitThreads / 2; off > 0; off >>= 1) {
+        if (t < off) red[t] = fmax(red[t], red[t + off]);
+        __syncthreads();
+    }
+    if (t == 0) out[0] = red[0];
+}
+void lp_row_diag_max(hipStream_t st, int m, const int* rptr, const int* rcol, const double* rval, const double* e2,
+                     double* out) {
+    hipLaunchKernelGGL(lp_row_diag_max_kernel, dim3(1), dim3(kSplitThreads), 0, st, m, rptr, rcol, rval, e2, out);
+    WC_LAUNCH_CHECK();
+}
+
 // The LP split, one workgroup: w = sqrt(x / s); T = {j : w_j > 2 tau and
 // #{i : w_i >= w_j} <= cap} in increasing j; pos_j = position of j in T or
 // -1; e2_j = 1 on T and (w_j / tau)^2 elsewhere; sig_lp[k] = 1 / (w^2 - tau^2)

@@ -34,6 +34,9 @@ void lp_corrector(hipStream_t st, int ell, const double* x, const double* s, con
 // out[0], out[1]: the ratio tests of (x, dx) and (s, ds)
 void lp_ratio(hipStream_t st, int ell, const double* x, const double* dx, const double* s, const double* ds,
               double* out);
+// out[0] = max_i sum_j B_ij^2 e2_j (rows of B in CSR)
+void lp_row_diag_max(hipStream_t st, int m, const int* rptr, const int* rcol, const double* rval, const double* e2,
+                     double* out);
 // the split of the LP scaling w = sqrt(x/s) against tau (at most cap entries in T); info[0] = |T|,
 // info[1] = entries with x or s not positive
 void lp_split(hipStream_t st, int ell, const double* x, const double* s, double tau, int cap, double* w, double* e2,

@@ -337,6 +337,102 @@ void f_to_aq(hipStream_t st, int m, int n, int r, const double* F, long si, long
     WC_LAUNCH_CHECK();
 }
 
+// ---- sparse constraint kind: the entries of each A_i on and above the diagonal ----------
+// Constraint i owns entries ptr[i] .. ptr[i+1]-1 of (row, col, val), row <= col, and
+// A_i[row, col] = A_i[col, row] = val.
+
+// out_i = alpha <A_i, M> + beta out_i (M[r, c] + M[c, r] off the diagonal)
+__global__ void sparse_gather_kernel(int m, const int* __restrict__ ptr, const int* __restrict__ row,
+                                     const int* __restrict__ col, const double* __restrict__ val,
+                                     const double* __restrict__ M, long ldm, double* __restrict__ out, double alpha,
+                                     double beta) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    double s = 0.0;
+    for (int q = ptr[i]; q < ptr[i + 1]; ++q) {
+        const int r = row[q], c = col[q];
+        const double mrc = M[r + (long)c * ldm];
+        s += val[q] * (r == c ? mrc : mrc + M[c + (long)r * ldm]);
+    }
+    const double v = alpha * s;
+    out[i] = (beta == 0.0) ? v : v + beta * out[i];
+}
+void sparse_gather(hipStream_t st, int m, const int* ptr, const int* row, const int* col, const double* val,
+                   const double* M, long ldm, double* out, double alpha, double beta) {
+    hipLaunchKernelGGL(sparse_gather_kernel, g1(m), dim3(256), 0, st, m, ptr, row, col, val, M, ldm, out, alpha, beta);
+    WC_LAUNCH_CHECK();
+}
+
+// Y = A^T(u) at the pattern's positions (Y zero elsewhere, set by the caller):
+// position p = (pr[p], pc[p]), pr <= pc, sums u[pidx[q]] pval[q] over its entries
+// in a fixed order and writes both triangles (no atomics: the sum is deterministic).
+__global__ void sparse_scatter_kernel(long npos, const int* __restrict__ pr, const int* __restrict__ pc,
+                                      const int* __restrict__ pptr, const int* __restrict__ pidx,
+                                      const double* __restrict__ pval, const double* __restrict__ u,
+                                      double* __restrict__ Y, long ldy) {
+    const long p = blockIdx.x * 256L + threadIdx.x;
+    if (p >= npos) return;
+    double s = 0.0;
+    for (int q = pptr[p]; q < pptr[p + 1]; ++q) s += pval[q] * u[pidx[q]];
+    const int r = pr[p], c = pc[p];
+    Y[r + (long)c * ldy] = s;
+    if (r != c) Y[c + (long)r * ldy] = s;
+}
+void sparse_scatter(hipStream_t st, long npos, const int* pr, const int* pc, const int* pptr, const int* pidx,
+                    const double* pval, const double* u, double* Y, long ldy) {
+    if (npos <= 0) return;
+    hipLaunchKernelGGL(sparse_scatter_kernel, g1(npos), dim3(256), 0, st, npos, pr, pc, pptr, pidx, pval, u, Y, ldy);
+    WC_LAUNCH_CHECK();
+}
+
+// Row i of script-A script-Q (row-major, pitch ldaq, zero past d) from
+// F_i = G_w^T A_i Q = sum_q val_q (g_r q_c^T + [r != c] g_c q_r^T), g_r the r-th
+// row of G_w and q_r its first r entries, read in v-coordinates as f_to_aq does.
+__global__ void sparse_aq_kernel(int m, int n, int rk, const int* __restrict__ ptr, const int* __restrict__ row,
+                                 const int* __restrict__ col, const double* __restrict__ val,
+                                 const double* __restrict__ Gw, long ldg, double* __restrict__ AQ, long ldaq) {
+    const long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)m * ldaq) return;
+    const int coord = static_cast<int>(t % ldaq);
+    const int i = static_cast<int>(t / ldaq);
+    const int nb = rk * (rk + 1) / 2;
+    const int d = nb + (n - rk) * rk;
+    double v = 0.0;
+    if (coord < d) {
+        int a, b;
+        bool pair = false;
+        if (coord < nb) {
+            svec_pair(coord, rk, a, b);
+            pair = a != b;
+        } else {
+            const int s2 = coord - nb;
+            a = rk + s2 % (n - rk);
+            b = s2 / (n - rk);
+        }
+        // F(x, y) summed over the constraint's entries
+        double fab = 0.0, fba = 0.0;
+        for (int q = ptr[i]; q < ptr[i + 1]; ++q) {
+            const int r = row[q], c = col[q];
+            const double w = val[q];
+            fab += w * Gw[r + (long)a * ldg] * Gw[c + (long)b * ldg];
+            if (r != c) fab += w * Gw[c + (long)a * ldg] * Gw[r + (long)b * ldg];
+            if (pair) {
+                fba += w * Gw[r + (long)b * ldg] * Gw[c + (long)a * ldg];
+                if (r != c) fba += w * Gw[c + (long)b * ldg] * Gw[r + (long)a * ldg];
+            }
+        }
+        if (coord < nb) v = pair ? kSqrt2 * 0.5 * (fab + fba) : fab;
+        else v = kSqrt2 * fab;
+    }
+    AQ[(long)i * ldaq + coord] = v;
+}
+void sparse_aq(hipStream_t st, int m, int n, int rk, const int* ptr, const int* row, const int* col, const double* val,
+               const double* Gw, long ldg, double* AQ, long ldaq) {
+    hipLaunchKernelGGL(sparse_aq_kernel, g1((long)m * ldaq), dim3(256), 0, st, m, n, rk, ptr, row, col, val, Gw, ldg,
+                       AQ, ldaq);
+    WC_LAUNCH_CHECK();
+}
+
 // ---- entry-sampling script-A script-Q without forming it (Section 6) -----------------
 // For A_i = sym(e_j e_k^T) the i-th row of script-A script-Q, read in the
 // n x r coordinates H = [B; sqrt2 N] of v, is F_i = (g_j q_k^T + g_k q_j^T) / 2

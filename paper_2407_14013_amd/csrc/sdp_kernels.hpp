@@ -28,6 +28,13 @@ void f_to_v(hipStream_t st, int n, int r, const double* F, long ldf, const doubl
 void symlr(hipStream_t st, int n, int r, const double* U, const double* Q, long ldq, double* M, long ldm, double beta);
 // AQ rows from F_i = G_w^T A_i Q stored at F[i * si + (a + n b) * sab].
 void f_to_aq(hipStream_t st, int m, int n, int r, const double* F, long si, long sab, double* AQ, long ldaq);
+// Sparse constraint kind (entries on and above the diagonal per constraint): A(M), A^T(u) by positions, AQ rows.
+void sparse_gather(hipStream_t st, int m, const int* ptr, const int* row, const int* col, const double* val,
+                   const double* M, long ldm, double* out, double alpha, double beta);
+void sparse_scatter(hipStream_t st, long npos, const int* pr, const int* pc, const int* pptr, const int* pidx,
+                    const double* pval, const double* u, double* Y, long ldy);
+void sparse_aq(hipStream_t st, int m, int n, int rk, const int* ptr, const int* row, const int* col, const double* val,
+               const double* Gw, long ldg, double* AQ, long ldaq);
 // Entry-sampling script-A script-Q products and Schur-complement blocks (implicit, see sdp_kernels.hip).
 void aq_entry_apply(hipStream_t st, int m, int n, int r, const int* jk, const double* U, const double* Q, long ldq,
                     double* out, double alpha, double beta);

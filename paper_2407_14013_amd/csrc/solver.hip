@@ -82,8 +82,10 @@ static void a_apply(sdp_ctx* c, const double* M, double* out, double alpha, doub
         prof_kernel_events(c, SDP_K_A_APPLY, &e0, &e1);
         packed_rows(c->st, c->m, static_cast<int>(c->N2), c->P, c->ldP, c->mw, out, alpha, beta, e0, e1);
         prof_kernel_done(c, SDP_K_A_APPLY, e0, e1, 8.0 * c->m * c->N2 + 8.0 * c->N2 + 8.0 * c->m);  // P, x, y
-    } else {
+    } else if (c->kind == SDP_A_ENTRY) {
         entry_gather(c->st, c->m, c->jk, M, c->n, out, alpha, beta);
+    } else {
+        sparse_gather(c->st, c->m, c->spptr, c->sprow, c->spcol, c->spval, M, c->n, out, alpha, beta);
     }
 }
 
@@ -95,9 +97,12 @@ static void at_apply(sdp_ctx* c, const double* u, double* Y) {
         packed_cols_partial(c->st, c->m, static_cast<int>(c->N2), c->P, c->ldP, u, c->gpart, e0, e1);
         prof_kernel_done(c, SDP_K_AT_APPLY, e0, e1, 8.0 * c->m * c->N2 + 8.0 * c->m);
         at_reduce_unpack(c->st, c->N2, packed_cols_parts(c->m), c->gpart, round_up(c->N2, 2), c->pj, c->pk, Y, c->n);
-    } else {
+    } else if (c->kind == SDP_A_ENTRY) {
         fill(c->st, (long)c->n * c->n, Y, 0.0);
         entry_scatter(c->st, c->m, c->jk, u, Y, c->n);
+    } else {
+        fill(c->st, (long)c->n * c->n, Y, 0.0);
+        sparse_scatter(c->st, c->npos, c->ppr, c->ppc, c->pptr, c->pidx, c->pval, u, Y, c->n);
     }
 }
 
@@ -130,7 +135,7 @@ static void alloc_work(sdp_ctx* c) {
     c->U.alloc((long)n * c->rmax);
     c->YQ.alloc((long)n * c->rmax);
     c->F.alloc((long)n * c->rmax);
-    if (c->kind == SDP_A_DENSE) {
+    if (c->kind != SDP_A_ENTRY) {  // dense and sparse rows: script-A script-Q explicit
         c->AQ.alloc((long)m * c->dmaxp);
         c->ldAQt = round_up(m, 32);
         c->AQt.alloc(c->ldAQt * c->dmaxp);
@@ -219,6 +224,7 @@ static void validate_host(const sdp_problem* p) {
             require(std::fabs(p->C[i + (long)j * n] - p->C[j + (long)i * n]) <= 1e-12 * std::max(cn, 1e-300),
                     "C is not symmetric");
     for (int i = 0; i < m; ++i) require(finite(p->b[i]), "b has a non-finite entry");
+    if (p->a_kind == SDP_A_SPARSE) return;  // the entries are checked by setup_sparse
     if (p->a_kind == SDP_A_DENSE) {
         for (int i = 0; i < m; ++i) {
             const double* Ai = p->A + (long)i * nn;
@@ -318,13 +324,117 @@ static void setup_lp(sdp_ctx* c, const sdp_lp_block* lp, hipStream_t st) {
     WC_HIP(hipStreamSynchronize(st));
 }
 
-void setup(sdp_ctx* c, const sdp_problem* p, const sdp_lp_block* lp, const sdp_options* o, hipStream_t st) {
+// Sparse constraint entries: checked (host inputs also for finite values),
+// repeated positions within a constraint merged, norms ||A_i||_F^2, and the
+// position-major copy for A^T(u) (positions sorted by (row, col), entries of a
+// position by constraint).
+static void setup_sparse(sdp_ctx* c, const sdp_sparse_rows* sp, hipStream_t st, std::vector<double>& norms2) {
+    require(sp != nullptr && sp->ptr && sp->row && sp->col && sp->val, "the sparse constraint entries are required");
+    const int m = c->m, n = c->n;
+    const hipMemcpyKind kind = sp->on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+    std::vector<int> ptr(m + 1);
+    WC_HIP(hipMemcpyAsync(ptr.data(), sp->ptr, sizeof(int) * (m + 1), kind, st));
+    WC_HIP(hipStreamSynchronize(st));
+    require(ptr[0] == 0, "sparse ptr[0] must be 0");
+    for (int i = 0; i < m; ++i) require(ptr[i + 1] >= ptr[i], "sparse ptr must be nondecreasing");
+    const int nnz = ptr[m];
+    std::vector<int> row(std::max(1, nnz)), col(std::max(1, nnz));
+    std::vector<double> val(std::max(1, nnz));
+    WC_HIP(hipMemcpyAsync(row.data(), sp->row, sizeof(int) * nnz, kind, st));
+    WC_HIP(hipMemcpyAsync(col.data(), sp->col, sizeof(int) * nnz, kind, st));
+    WC_HIP(hipMemcpyAsync(val.data(), sp->val, sizeof(double) * nnz, kind, st));
+    WC_HIP(hipStreamSynchronize(st));
+    struct Ent {
+        int r, c, i;
+        double v;
+    };
+    std::vector<Ent> ents;
+    ents.reserve(nnz);
+    for (int i = 0; i < m; ++i) {
+        const size_t first = ents.size();
+        for (int q = ptr[i]; q < ptr[i + 1]; ++q) {
+            require(row[q] >= 0 && row[q] <= col[q] && col[q] < n, "sparse entry must satisfy 0 <= row <= col < n");
+            if (!sp->on_device) require(std::isfinite(val[q]), "sparse entry value is not finite");
+            ents.push_back({row[q], col[q], i, val[q]});
+        }
+        // merge repeated positions of constraint i
+        std::sort(ents.begin() + first, ents.end(),
+                  [](const Ent& a, const Ent& b) { return a.r != b.r ? a.r < b.r : a.c < b.c; });
+        size_t w = first;
+        for (size_t e = first; e < ents.size(); ++e) {
+            if (w > first && ents[w - 1].r == ents[e].r && ents[w - 1].c == ents[e].c) ents[w - 1].v += ents[e].v;
+            else ents[w++] = ents[e];
+        }
+        ents.resize(w);
+        double nrm = 0.0;
+        for (size_t e = first; e < w; ++e) nrm += ents[e].v * ents[e].v * (ents[e].r == ents[e].c ? 1.0 : 2.0);
+        norms2[i] = nrm;
+        ptr[i + 1] = static_cast<int>(w);
+    }
+    const int nz = static_cast<int>(ents.size());
+    std::vector<int> erow(std::max(1, nz)), ecol(std::max(1, nz));
+    std::vector<double> eval(std::max(1, nz));
+    for (int q = 0; q < nz; ++q) {
+        erow[q] = ents[q].r;
+        ecol[q] = ents[q].c;
+        eval[q] = ents[q].v;
+    }
+    // position-major copy
+    std::vector<int> ord(nz);
+    for (int q = 0; q < nz; ++q) ord[q] = q;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+        return ents[a].r != ents[b].r ? ents[a].r < ents[b].r : ents[a].c < ents[b].c;
+    });
+    std::vector<int> ppr, ppc, pptr{0}, pidx(std::max(1, nz));
+    std::vector<double> pval(std::max(1, nz));
+    for (int k = 0; k < nz; ++k) {
+        const Ent& e = ents[ord[k]];
+        if (k == 0 || e.r != ents[ord[k - 1]].r || e.c != ents[ord[k - 1]].c) {
+            if (k > 0) pptr.push_back(k);
+            ppr.push_back(e.r);
+            ppc.push_back(e.c);
+        }
+        pidx[k] = e.i;
+        pval[k] = e.v;
+    }
+    pptr.push_back(nz);
+    c->npos = static_cast<long>(ppr.size());
+    if (ppr.empty()) {
+        ppr.push_back(0);
+        ppc.push_back(0);
+    }
+    c->spptr.alloc(m + 1);
+    c->sprow.alloc(erow.size());
+    c->spcol.alloc(ecol.size());
+    c->spval.alloc(eval.size());
+    c->ppr.alloc(ppr.size());
+    c->ppc.alloc(ppc.size());
+    c->pptr.alloc(pptr.size());
+    c->pidx.alloc(pidx.size());
+    c->pval.alloc(pval.size());
+    WC_HIP(hipMemcpyAsync(c->spptr.get(), ptr.data(), sizeof(int) * (m + 1), hipMemcpyHostToDevice, st));
+    WC_HIP(hipMemcpyAsync(c->sprow.get(), erow.data(), sizeof(int) * erow.size(), hipMemcpyHostToDevice, st));
+    WC_HIP(hipMemcpyAsync(c->spcol.get(), ecol.data(), sizeof(int) * ecol.size(), hipMemcpyHostToDevice, st));
+    WC_HIP(hipMemcpyAsync(c->spval.get(), eval.data(), sizeof(double) * eval.size(), hipMemcpyHostToDevice, st));
+    WC_HIP(hipMemcpyAsync(c->ppr.get(), ppr.data(), sizeof(int) * ppr.size(), hipMemcpyHostToDevice, st));
+    WC_HIP(hipMemcpyAsync(c->ppc.get(), ppc.data(), sizeof(int) * ppc.size(), hipMemcpyHostToDevice, st));
+    WC_HIP(hipMemcpyAsync(c->pptr.get(), pptr.data(), sizeof(int) * pptr.size(), hipMemcpyHostToDevice, st));
+    WC_HIP(hipMemcpyAsync(c->pidx.get(), pidx.data(), sizeof(int) * pidx.size(), hipMemcpyHostToDevice, st));
+    WC_HIP(hipMemcpyAsync(c->pval.get(), pval.data(), sizeof(double) * pval.size(), hipMemcpyHostToDevice, st));
+    WC_HIP(hipStreamSynchronize(st));
+}
+
+void setup(sdp_ctx* c, const sdp_problem* p, const sdp_sparse_rows* sp, const sdp_lp_block* lp, const sdp_options* o,
+           hipStream_t st) {
     require(p != nullptr, "problem is NULL");
     require(p->n >= 2, "n must be at least 2");
     require(p->m >= 1, "m must be at least 1");
-    require(p->a_kind == SDP_A_DENSE || p->a_kind == SDP_A_ENTRY, "unknown a_kind");
+    require(p->a_kind == SDP_A_DENSE || p->a_kind == SDP_A_ENTRY || p->a_kind == SDP_A_SPARSE, "unknown a_kind");
     require(p->b && p->C, "b and C are required");
-    require(p->a_kind == SDP_A_DENSE ? p->A != nullptr : p->jk != nullptr, "constraint data is NULL");
+    require(p->a_kind == SDP_A_DENSE    ? p->A != nullptr
+            : p->a_kind == SDP_A_ENTRY ? p->jk != nullptr
+                                       : sp != nullptr,
+            "constraint data is NULL");
     const int n = p->n, m = p->m;
     const long N2 = (long)n * (n + 1) / 2;
     require(m <= N2, "m exceeds n(n+1)/2: the constraints cannot be linearly independent");
@@ -375,6 +485,8 @@ void setup(sdp_ctx* c, const sdp_problem* p, const sdp_lp_block* lp, const sdp_o
         packed_row_norm2(st, m, N2, c->ldP, c->P, c->pj, c->pk, nrm);
         WC_HIP(hipMemcpyAsync(norms2.data(), nrm.get(), sizeof(double) * m, hipMemcpyDeviceToHost, st));
         WC_HIP(hipStreamSynchronize(st));
+    } else if (c->kind == SDP_A_SPARSE) {
+        setup_sparse(c, sp, st, norms2);
     } else {
         c->jk.alloc(2L * m);
         WC_HIP(hipMemcpyAsync(c->jk.get(), p->jk, sizeof(int) * 2 * m, kind, st));
@@ -621,12 +733,19 @@ void ensure_scaling(sdp_ctx* c) {
     if (c->ell > 0) {
         lp_split(st, c->ell, c->xl, c->sl, c->tau, c->tcap, c->wl, c->e2l, c->posl, c->Tl, c->sig + d,
                  c->info.get() + 3);
+        // the LP part of the (1,1) block, B diag(e2) B^T, and its largest diagonal entry
+        lp_row_diag_max(st, m, c->lrptr, c->lrcol, c->lrval, c->e2l, c->sc + 32);
         int ht[2] = {0, 0};
+        double bl = 0.0;
         WC_HIP(hipMemcpyAsync(ht, c->info.get() + 3, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        WC_HIP(hipMemcpyAsync(&bl, c->sc + 32, sizeof(double), hipMemcpyDeviceToHost, st));
         WC_HIP(hipStreamSynchronize(st));
         if (ht[1]) throw Error(kENumeric, "x or s of the LP block is not positive (" + std::to_string(ht[1]) + " entries)");
         require(ht[0] >= 0 && ht[0] <= c->tcap, "LP split: |T| outside [0, lp_top_max]");
         c->t = ht[0];
+        // beta stays in the bracket of Corollary pcg for the (1,1) block with the
+        // LP part: that diagonal entry is at most its largest eigenvalue
+        if (!(c->opt.beta > 0)) c->beta = std::max(c->beta, bl);
     }
     c->dv = d + c->t;
     // script-A script-Q, row i = script-Q^T svec(A_i)
@@ -640,6 +759,12 @@ void ensure_scaling(sdp_ctx* c) {
         // row-major copy of (AQ)^T: the products (AQ)^T f become row passes
         transpose(st, d, m, c->AQ, c->dmaxp, c->AQt, c->ldAQt);
         // Schur complement of the preconditioner: C = tau^2 Sigma + (AQ)^T (AQ) / beta
+        gemm(c, false, true, d, d, m, 1.0 / c->beta, c->AQ, c->dmaxp, c->AQ, c->dmaxp, 0.0, c->Cm, c->dmaxp);
+        add_diag_vec(st, d, c->Cm, c->dmaxp, c->sig, c->tau * c->tau);
+    } else if (c->kind == SDP_A_SPARSE) {
+        // AQ rows straight from the entries (F_i = G_w^T A_i Q in closed form), then as for dense rows
+        sparse_aq(st, m, n, r, c->spptr, c->sprow, c->spcol, c->spval, c->Gw, n, c->AQ, c->dmaxp);
+        transpose(st, d, m, c->AQ, c->dmaxp, c->AQt, c->ldAQt);
         gemm(c, false, true, d, d, m, 1.0 / c->beta, c->AQ, c->dmaxp, c->AQ, c->dmaxp, 0.0, c->Cm, c->dmaxp);
         add_diag_vec(st, d, c->Cm, c->dmaxp, c->sig, c->tau * c->tau);
     } else {
@@ -658,7 +783,7 @@ void ensure_scaling(sdp_ctx* c) {
     if (c->t > 0) {
         // the LP columns B[:, T] of script-A script-Q: C's blocks
         // (AQ)^T B_T / beta and tau^2 Sigma_T + B_T^T B_T / beta
-        const bool dense = c->kind == SDP_A_DENSE;
+        const bool dense = c->kind != SDP_A_ENTRY;  // AQ explicit for dense and sparse rows
         lp_c12(st, n, r, d, c->t, c->Tl, c->lcptr, c->lcrow, c->lcval, dense ? c->AQ.get() : nullptr, c->dmaxp,
                dense ? nullptr : c->jk.get(), c->Gw, n, 1.0 / c->beta, c->Cm, c->dmaxp);
         lp_c22(st, d, c->t, c->Tl, c->lcptr, c->lcrow, c->lcval, c->sig + d, c->tau * c->tau, 1.0 / c->beta, c->Cm,
@@ -840,7 +965,7 @@ void newton_apply_lowp(sdp_ctx* c, const double* in, double* out) {
 // matrix (v in an aligned, zero-padded buffer).  Entry sampling: U = G_w H(v),
 // then one gather per constraint.  Uses Hm and U.
 static void aq_mul(sdp_ctx* c, const double* v, double* out, double alpha, double beta) {
-    if (c->kind == SDP_A_DENSE) {
+    if (c->kind != SDP_A_ENTRY) {
         gemv_rows(c->st, c->m, c->d, c->AQ, c->dmaxp, v, out, alpha, beta);
     } else {
         const int n = c->n, r = c->r;
@@ -855,7 +980,7 @@ static void aq_mul(sdp_ctx* c, const double* v, double* out, double alpha, doubl
 // out = alpha (script-A script-Q)^T u + beta out (d).  Entry sampling:
 // F = G_w^T (A^T(u) Q) with the sparse product row by row.  Uses YQ, F, td4.
 static void aqt_mul(sdp_ctx* c, const double* u, double* out, double alpha, double beta) {
-    if (c->kind == SDP_A_DENSE) {
+    if (c->kind != SDP_A_ENTRY) {
         gemv_rows(c->st, c->d, c->m, c->AQt, c->ldAQt, u, out, alpha, beta);
     } else {
         const int n = c->n, r = c->r;
@@ -1482,9 +1607,9 @@ int ipm_step(sdp_ctx* c, sdp_step_stats* stats) {
     s.t_inner_ms = s.t_total_ms - s.t_scaling_ms;
     if (c->opt.verbose)
         fprintf(stderr,
-                "[wcsdp] it %d mu %.3e relgap %.3e pinf %.3e dinf %.3e r %d pcg %d/%d ap %.3f ad %.3f "
+                "[wcsdp] it %d mu %.3e relgap %.3e pinf %.3e dinf %.3e r %d |T| %d pcg %d/%d ap %.3f ad %.3f "
                 "sweeps %d/%d t_scaling %.2f t_total %.2f ms\n",
-                c->iter, s.mu, s.relgap, s.pinf, s.dinf, s.r, s.pcg_pred, s.pcg_corr, ap, ad, c->sweeps_nt,
+                c->iter, s.mu, s.relgap, s.pinf, s.dinf, s.r, c->t, s.pcg_pred, s.pcg_corr, ap, ad, c->sweeps_nt,
                 c->sweeps_w, s.t_scaling_ms, s.t_total_ms);
     if (stats) *stats = s;
     return 0;
@@ -1499,6 +1624,7 @@ int ipm_step(sdp_ctx* c, sdp_step_stats* stats) {
 // (sigma = 1, no second-order term), each an inner solve as in ipm_step.
 int adjoint(sdp_ctx* c, const double* GX, double* gb, double* gC, sdp_adjoint_stats* stats) {
     require(c->ell == 0, "sdp_adjoint does not support problems with an LP block");
+    require(c->kind != SDP_A_SPARSE, "sdp_adjoint does not support sparse constraint rows");
     const int n = c->n, m = c->m;
     const long nn = (long)n * n;
     hipStream_t st = c->st;

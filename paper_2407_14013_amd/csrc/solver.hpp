@@ -29,6 +29,11 @@ struct sdp_ctx {
     wc::DevBuf<uint16_t> ecol;         // sliced pattern: column of each slot
     wc::DevBuf<int> dptr, dpart, didx; // constraints grouped by their smaller index j: partner k, constraint
     wc::DevBuf<double> sval;    // slot values of Y = A^T(u) in the sliced pattern
+    wc::DevBuf<int> spptr, sprow, spcol;  // sparse: entries per constraint (row <= col)
+    wc::DevBuf<double> spval;
+    long npos = 0;                        // sparse: distinct positions of the pattern
+    wc::DevBuf<int> ppr, ppc, pptr, pidx; // sparse: per position (row, col), its entries' constraints
+    wc::DevBuf<double> pval;              //         and values, in a fixed order
     wc::DevBuf<double> b, C;    // m, n x n
     double bnorm = 0, Cnorm = 0, mean_a2 = 0, xi = 1, eta = 1;
 
@@ -100,7 +105,8 @@ struct sdp_ctx {
 
 namespace wc {
 
-void setup(sdp_ctx* c, const sdp_problem* p, const sdp_lp_block* lp, const sdp_options* o, hipStream_t st);
+void setup(sdp_ctx* c, const sdp_problem* p, const sdp_sparse_rows* sp, const sdp_lp_block* lp, const sdp_options* o,
+           hipStream_t st);
 void ensure_scaling(sdp_ctx* c);
 void newton_apply(sdp_ctx* c, const double* in, double* out);
 void newton_apply_lowp(sdp_ctx* c, const double* in, double* out);

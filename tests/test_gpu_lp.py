@@ -85,6 +85,8 @@ def test_split_and_operator_match_oracle(which, iters):
         assert np.allclose(w, np.sqrt(res["x"] / res["s"]), rtol=1e-14)
         lsp = rf.lp_split(sp, w, cap=int(ctx.options.lp_top_max))
         assert np.array_equal(host(ls["T"]), lsp["T"]), (host(ls["T"]), lsp["T"])
+        beta = rf.beta_rule_lp(sp, lsp, p)
+        assert abs(g["beta"] - beta) <= 1e-10 * beta, (g["beta"], beta)
         N = ctx.aug_dim()
         assert N == m + rf.dim_d(n, sp["r"]) + lsp["t"]
         E = rf.e_matrix(sp)

@@ -9,6 +9,8 @@
   exactly, with or without the cap on |T|.
 * The augmented operator with the LP block equals its explicit matrix, and
   solving that system exactly and recovering gives the direct Newton step.
+* beta with the LP block stays inside the bracket of Corollary pcg for the
+  (1,1) block A E A^T + B diag(e2) B^T.
 * The whole method: the PCG-based IPM reaches the direct IPM's point; RMC
   recovers X* (the paper's Table rmc reports exact recovery) and its LP
   part equals the l1 misfit of eq. rmc; SNL recovers the sensor positions
@@ -155,6 +157,30 @@ def test_augrec_lp_equals_direct_newton(iters):
     dX, dy, dx = rf.recover_lp(p, sp, lsp, E, sol[: p["m"]], sol[p["m"]:], Ct, ct)
     for a, b_ in ((dX, dX0), (dy, dy0), (dx, dx0)):
         assert np.allclose(a, b_, rtol=1e-7, atol=1e-8 * np.abs(b_).max())
+
+
+@pytest.mark.parametrize("which", ["rmc", "snl"])
+def test_beta_rule_lp_in_bracket(which):
+    # Corollary pcg asks for lambda_min <= beta <= lambda_max of the (1,1) block
+    # of eq. augsys, which with the LP block is A E A^T + B diag(e2) B^T.
+    if which == "rmc":
+        p = workloads.robust_completion(12, 60, 3, seed=6)
+    else:
+        p = workloads.sensor_localization(8, 20, 6, 2, 1, seed=5, kind="sparse")
+    Am, B = ops.amat(p), ops.b_matrix(p)
+    raised = 0
+    for iters in (2, 6, 10, 14):
+        res = ipm.solve(p, maxit=iters)
+        G, _, _ = nt.nt_factor(res["X"], res["S"])
+        sp = rf.eig_split(sym(G @ G.T), rank_max=3)
+        lsp = rf.lp_split(sp, np.sqrt(res["x"] / res["s"]))
+        H = Am @ rf.e_bold(sp) @ Am.T + B @ np.diag(lsp["e2"]) @ B.T
+        ev = np.linalg.eigvalsh(H)
+        beta = rf.beta_rule_lp(sp, lsp, p)
+        assert ev[0] <= beta <= ev[-1] * (1 + 1e-12)
+        assert beta >= rf.beta_rule(sp, p)
+        raised += beta > rf.beta_rule(sp, p)
+    assert raised > 0  # the LP term decides beta somewhere on the path
 
 
 def pcg_newton(problem, X, S, G, d, W, bt, Ct, Rd, lp=None):
