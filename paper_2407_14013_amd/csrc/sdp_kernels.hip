@@ -365,23 +365,85 @@ void sparse_gather(hipStream_t st, int m, const int* ptr, const int* row, const 
 
 // Y = A^T(u) at the pattern's positions (Y zero elsewhere, set by the caller):
 // position p = (pr[p], pc[p]), pr <= pc, sums u[pidx[q]] pval[q] over its entries
-// in a fixed order and writes both triangles (no atomics: the sum is deterministic).
+// and writes both triangles (no atomics: every sum has one writer and a fixed
+// order).  Positions with at most kScatterLong entries take one thread each;
+// the longer ones (the diagonal, and entries that many constraints share) are
+// listed in plong and take one wave each, its lanes striding over the list and
+// the partial sums reduced in a fixed tree.
 __global__ void sparse_scatter_kernel(long npos, const int* __restrict__ pr, const int* __restrict__ pc,
                                       const int* __restrict__ pptr, const int* __restrict__ pidx,
                                       const double* __restrict__ pval, const double* __restrict__ u,
                                       double* __restrict__ Y, long ldy) {
     const long p = blockIdx.x * 256L + threadIdx.x;
     if (p >= npos) return;
+    const int q0 = pptr[p], q1 = pptr[p + 1];
+    if (q1 - q0 > kScatterLong) return;  // a wave of sparse_scatter_long writes it
     double s = 0.0;
-    for (int q = pptr[p]; q < pptr[p + 1]; ++q) s += pval[q] * u[pidx[q]];
+    for (int q = q0; q < q1; ++q) s += pval[q] * u[pidx[q]];
     const int r = pr[p], c = pc[p];
     Y[r + (long)c * ldy] = s;
     if (r != c) Y[c + (long)r * ldy] = s;
 }
+__global__ __launch_bounds__(256) void sparse_scatter_long_kernel(int nlong, const int* __restrict__ plong,
+                                                                  const int* __restrict__ pr,
+                                                                  const int* __restrict__ pc,
+                                                                  const int* __restrict__ pptr,
+                                                                  const int* __restrict__ pidx,
+                                                                  const double* __restrict__ pval,
+                                                                  const double* __restrict__ u,
+                                                                  double* __restrict__ Y, long ldy) {
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= nlong) return;  // whole waves leave together
+    const int p = plong[k];
+    double s = 0.0;
+    for (int q = pptr[p] + lane; q < pptr[p + 1]; q += 64) s += pval[q] * u[pidx[q]];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+        const int r = pr[p], c = pc[p];
+        Y[r + (long)c * ldy] = s;
+        if (r != c) Y[c + (long)r * ldy] = s;
+    }
+}
 void sparse_scatter(hipStream_t st, long npos, const int* pr, const int* pc, const int* pptr, const int* pidx,
-                    const double* pval, const double* u, double* Y, long ldy) {
+                    const double* pval, const double* u, double* Y, long ldy, const int* plong, int nlong) {
     if (npos <= 0) return;
     hipLaunchKernelGGL(sparse_scatter_kernel, g1(npos), dim3(256), 0, st, npos, pr, pc, pptr, pidx, pval, u, Y, ldy);
+    WC_LAUNCH_CHECK();
+    if (nlong > 0) {
+        hipLaunchKernelGGL(sparse_scatter_long_kernel, dim3(cdiv(nlong, 4)), dim3(256), 0, st, nlong, plong, pr, pc,
+                           pptr, pidx, pval, u, Y, ldy);
+        WC_LAUNCH_CHECK();
+    }
+}
+
+// out_i = alpha (script-A script-Q v)_i + beta out_i without script-A script-Q:
+// with U = G_w H(v) (n x r) and Q the first r columns of G_w, an entry
+// (r, c, val) of A_i adds val (U_r . Q_c + U_c . Q_r), halved when r = c.
+__global__ void sparse_aq_apply_kernel(int m, int n, int rk, const int* __restrict__ ptr, const int* __restrict__ row,
+                                       const int* __restrict__ col, const double* __restrict__ val,
+                                       const double* __restrict__ U, const double* __restrict__ Q, long ldq,
+                                       double* __restrict__ out, double alpha, double beta) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    double s = 0.0;
+    for (int q = ptr[i]; q < ptr[i + 1]; ++q) {
+        const int r = row[q], c = col[q];
+        double t = 0.0;
+        for (int b = 0; b < rk; ++b)
+            t += U[r + (long)b * n] * Q[c + (long)b * ldq] + U[c + (long)b * n] * Q[r + (long)b * ldq];
+        s += (r == c ? 0.5 : 1.0) * val[q] * t;
+    }
+    const double v = alpha * s;
+    out[i] = (beta == 0.0) ? v : v + beta * out[i];
+}
+void sparse_aq_apply(hipStream_t st, int m, int n, int rk, const int* ptr, const int* row, const int* col,
+                     const double* val, const double* U, const double* Q, long ldq, double* out, double alpha,
+                     double beta) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(sparse_aq_apply_kernel, g1(m), dim3(256), 0, st, m, n, rk, ptr, row, col, val, U, Q, ldq, out,
+                       alpha, beta);
     WC_LAUNCH_CHECK();
 }
 

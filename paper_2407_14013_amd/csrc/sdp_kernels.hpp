@@ -31,10 +31,16 @@ void f_to_aq(hipStream_t st, int m, int n, int r, const double* F, long si, long
 // Sparse constraint kind (entries on and above the diagonal per constraint): A(M), A^T(u) by positions, AQ rows.
 void sparse_gather(hipStream_t st, int m, const int* ptr, const int* row, const int* col, const double* val,
                    const double* M, long ldm, double* out, double alpha, double beta);
+// positions with more entries than this are listed in plong and scattered one wave each
+constexpr int kScatterLong = 32;
 void sparse_scatter(hipStream_t st, long npos, const int* pr, const int* pc, const int* pptr, const int* pidx,
-                    const double* pval, const double* u, double* Y, long ldy);
+                    const double* pval, const double* u, double* Y, long ldy, const int* plong, int nlong);
 void sparse_aq(hipStream_t st, int m, int n, int rk, const int* ptr, const int* row, const int* col, const double* val,
                const double* Gw, long ldg, double* AQ, long ldaq);
+// out = alpha (script-A script-Q) v + beta out from U = G_w H(v) and Q = G_w[:, :rk], no explicit rows
+void sparse_aq_apply(hipStream_t st, int m, int n, int rk, const int* ptr, const int* row, const int* col,
+                     const double* val, const double* U, const double* Q, long ldq, double* out, double alpha,
+                     double beta);
 // Entry-sampling script-A script-Q products and Schur-complement blocks (implicit, see sdp_kernels.hip).
 void aq_entry_apply(hipStream_t st, int m, int n, int r, const int* jk, const double* U, const double* Q, long ldq,
                     double* out, double alpha, double beta);

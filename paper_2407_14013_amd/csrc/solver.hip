@@ -102,7 +102,7 @@ static void at_apply(sdp_ctx* c, const double* u, double* Y) {
         entry_scatter(c->st, c->m, c->jk, u, Y, c->n);
     } else {
         fill(c->st, (long)c->n * c->n, Y, 0.0);
-        sparse_scatter(c->st, c->npos, c->ppr, c->ppc, c->pptr, c->pidx, c->pval, u, Y, c->n);
+        sparse_scatter(c->st, c->npos, c->ppr, c->ppc, c->pptr, c->pidx, c->pval, u, Y, c->n, c->plong, c->nlong);
     }
 }
 
@@ -135,11 +135,13 @@ static void alloc_work(sdp_ctx* c) {
     c->U.alloc((long)n * c->rmax);
     c->YQ.alloc((long)n * c->rmax);
     c->F.alloc((long)n * c->rmax);
-    if (c->kind != SDP_A_ENTRY) {  // dense and sparse rows: script-A script-Q explicit
+    if (c->kind != SDP_A_ENTRY) {  // dense and sparse rows: script-A script-Q explicit (for C) ...
         c->AQ.alloc((long)m * c->dmaxp);
-        c->ldAQt = round_up(m, 32);
-        c->AQt.alloc(c->ldAQt * c->dmaxp);
-        fill(c->st, c->ldAQt * c->dmaxp, c->AQt, 0.0);
+        if (c->kind == SDP_A_DENSE) {  // ... and, for dense rows, row-major (AQ)^T for the preconditioner
+            c->ldAQt = round_up(m, 32);
+            c->AQt.alloc(c->ldAQt * c->dmaxp);
+            fill(c->st, c->ldAQt * c->dmaxp, c->AQt, 0.0);
+        }
     }
     c->Cm.alloc(c->dmaxp * c->dmaxp);
     c->Cinv.alloc(c->dmaxp * c->dmaxp);
@@ -399,6 +401,13 @@ static void setup_sparse(sdp_ctx* c, const sdp_sparse_rows* sp, hipStream_t st, 
     }
     pptr.push_back(nz);
     c->npos = static_cast<long>(ppr.size());
+    std::vector<int> plong;
+    for (long p = 0; p < c->npos; ++p)
+        if (pptr[p + 1] - pptr[p] > kScatterLong) plong.push_back(static_cast<int>(p));
+    c->nlong = static_cast<int>(plong.size());
+    c->plong.alloc(std::max<size_t>(1, plong.size()));
+    if (!plong.empty())
+        WC_HIP(hipMemcpyAsync(c->plong.get(), plong.data(), sizeof(int) * plong.size(), hipMemcpyHostToDevice, st));
     if (ppr.empty()) {
         ppr.push_back(0);
         ppc.push_back(0);
@@ -764,7 +773,6 @@ void ensure_scaling(sdp_ctx* c) {
     } else if (c->kind == SDP_A_SPARSE) {
         // AQ rows straight from the entries (F_i = G_w^T A_i Q in closed form), then as for dense rows
         sparse_aq(st, m, n, r, c->spptr, c->sprow, c->spcol, c->spval, c->Gw, n, c->AQ, c->dmaxp);
-        transpose(st, d, m, c->AQ, c->dmaxp, c->AQt, c->ldAQt);
         gemm(c, false, true, d, d, m, 1.0 / c->beta, c->AQ, c->dmaxp, c->AQ, c->dmaxp, 0.0, c->Cm, c->dmaxp);
         add_diag_vec(st, d, c->Cm, c->dmaxp, c->sig, c->tau * c->tau);
     } else {
@@ -962,29 +970,41 @@ void newton_apply_lowp(sdp_ctx* c, const double* in, double* out) {
 }
 
 // out = alpha (script-A script-Q) v + beta out (m).  Dense A: the explicit
-// matrix (v in an aligned, zero-padded buffer).  Entry sampling: U = G_w H(v),
-// then one gather per constraint.  Uses Hm and U.
+// matrix (v in an aligned, zero-padded buffer).  Entry sampling and sparse
+// rows: U = G_w H(v), then one closed-form gather per constraint (O(nnz r)
+// instead of a pass over the m x d rows).  Uses Hm and U.
 static void aq_mul(sdp_ctx* c, const double* v, double* out, double alpha, double beta) {
-    if (c->kind != SDP_A_ENTRY) {
+    const int n = c->n, r = c->r;
+    if (c->kind == SDP_A_DENSE) {
         gemv_rows(c->st, c->m, c->d, c->AQ, c->dmaxp, v, out, alpha, beta);
     } else {
-        const int n = c->n, r = c->r;
         v_to_h(c->st, n, r, v, c->Hm);
         gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
-        aq_entry_apply(c->st, c->m, n, r, c->jk, c->U, c->Gw, n, out, alpha, beta);
+        if (c->kind == SDP_A_ENTRY)
+            aq_entry_apply(c->st, c->m, n, r, c->jk, c->U, c->Gw, n, out, alpha, beta);
+        else
+            sparse_aq_apply(c->st, c->m, n, r, c->spptr, c->sprow, c->spcol, c->spval, c->U, c->Gw, n, out, alpha,
+                            beta);
     }
     // the LP columns B[:, T]
     if (c->t > 0) lp_b_top(c->st, c->m, c->lrptr, c->lrcol, c->lrval, c->posl, v + c->d, out, alpha);
 }
 
-// out = alpha (script-A script-Q)^T u + beta out (d).  Entry sampling:
-// F = G_w^T (A^T(u) Q) with the sparse product row by row.  Uses YQ, F, td4.
+// out = alpha (script-A script-Q)^T u + beta out (d): F = G_w^T (A^T(u) Q) read
+// in v-coordinates.  Entry sampling forms A^T(u) Q with the sparse product row
+// by row; sparse rows scatter A^T(u) into Y and multiply.  Uses YQ, F, td4
+// (and Y for sparse rows).
 static void aqt_mul(sdp_ctx* c, const double* u, double* out, double alpha, double beta) {
-    if (c->kind != SDP_A_ENTRY) {
+    const int n = c->n, r = c->r;
+    if (c->kind == SDP_A_DENSE) {
         gemv_rows(c->st, c->d, c->m, c->AQt, c->ldAQt, u, out, alpha, beta);
     } else {
-        const int n = c->n, r = c->r;
-        entry_yq(c->st, n, r, c->rptr, c->rcol, c->ridx, u, c->Gw, n, c->YQ);
+        if (c->kind == SDP_A_ENTRY) {
+            entry_yq(c->st, n, r, c->rptr, c->rcol, c->ridx, u, c->Gw, n, c->YQ);
+        } else {
+            at_apply(c, u, c->Y);
+            gemm(c, false, false, n, r, n, 1.0, c->Y, n, c->Gw, n, 0.0, c->YQ, n);
+        }
         gemm(c, true, false, n, r, n, 1.0, c->Gw, n, c->YQ, n, 0.0, c->F, n);
         f_to_v(c->st, n, r, c->F, n, nullptr, c->sig, 0.0, c->td4);
         axpby(c->st, c->d, alpha, c->td4, beta, out);

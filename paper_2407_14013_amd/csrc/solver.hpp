@@ -32,6 +32,8 @@ struct sdp_ctx {
     wc::DevBuf<int> spptr, sprow, spcol;  // sparse: entries per constraint (row <= col)
     wc::DevBuf<double> spval;
     long npos = 0;                        // sparse: distinct positions of the pattern
+    int nlong = 0;                        // sparse: positions with more than kScatterLong entries ...
+    wc::DevBuf<int> plong;                //         ... and their indices
     wc::DevBuf<int> ppr, ppc, pptr, pidx; // sparse: per position (row, col), its entries' constraints
     wc::DevBuf<double> pval;              //         and values, in a fixed order
     wc::DevBuf<double> b, C;    // m, n x n
