@@ -91,6 +91,16 @@ int32_t wc_djacobi_svd(void* stream, int32_t n, double* A, int32_t lda, double* 
                        double tol, int32_t max_sweeps, int32_t* sweeps_host);
 
 /*
+ * Smallest Ritz value of the symmetric n x n matrix T (device, column-major,
+ * leading dimension ldt >= n, 1 <= n <= 4096) after at most kmax (<= 64)
+ * Lanczos steps with full reorthogonalisation.  It is an upper bound on
+ * lambda_min(T), equal to it once converged, and it is the estimate the
+ * interior-point step length max{alpha : X + alpha dX PSD} is taken from.
+ * The value is written to *out_host; T is not modified.
+ */
+int32_t wc_dlanczos_min_eig(void* stream, int32_t n, const double* T, int32_t ldt, int32_t kmax, double* out_host);
+
+/*
  * Low-precision GEMM of the mixed-precision inner operator: C = A B for
  * column-major A (m x k) and B (k x n) given in FP32 (prec_in = 1) or as BF16
  * bit patterns (prec_in = 2, uint16 per element), multiplied on the matrix

@@ -202,6 +202,8 @@ _SIGNATURES = [
                              C.c_int32, C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_int32]),
     ("wc_dpotrf", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     ("wc_dtrtri", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
+    ("wc_dlanczos_min_eig", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32,
+                                         C.POINTER(C.c_double)]),
     ("wc_djacobi_svd", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                    C.c_double, C.c_int32, C.POINTER(C.c_int32)]),
     ("wc_dsymv", C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_int32, C.c_void_p, C.c_double,

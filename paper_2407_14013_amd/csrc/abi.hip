@@ -5,6 +5,7 @@
 
 #include "../../include/wcsdp.h"
 #include "../../include/wcsdp_linalg.h"
+#include "lanczos.hpp"
 #include "sdp_kernels.hpp"
 #include "lowprec.hpp"
 #include "batched.hpp"
@@ -489,6 +490,17 @@ int32_t wc_dtrtri(void* stream, int32_t n, const double* L, int32_t ldl, double*
         wc::DevBuf<double> work((size_t)n * n);
         wc::trtri(st, n, L, ldl, Linv, ldi, work);
         WC_HIP(hipStreamSynchronize(st));
+        return (int32_t)0;
+    });
+}
+
+int32_t wc_dlanczos_min_eig(void* stream, int32_t n, const double* T, int32_t ldt, int32_t kmax, double* out_host) {
+    return guarded_la([&]() {
+        wc::require(n >= 1 && n <= wc::LZ_MAX_N && ldt >= n && kmax >= 1 && T != nullptr && out_host != nullptr,
+                    "bad arguments");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        wc::LanczosWork w;
+        *out_host = wc::lanczos_min_eig(st, n, T, ldt, kmax, w);
         return (int32_t)0;
     });
 }

@@ -31,6 +31,9 @@ __device__ inline double lz_block_sum(double v, double* red) {
     return s;
 }
 
+// The start vector: deterministic, with no special structure.
+__device__ inline double lz_start(int i) { return 1.0 + 0.5 * sin(1.0 + 0.7071067811865476 * i) + 0.25 * cos(0.3 * i * i); }
+
 // Dynamic LDS layout: q (n), w (n), partial products of the matrix-vector
 // product (LZ_THREADS, only when rows are split into chunks), and, when it
 // fits (qlds != 0), the Lanczos basis (n x (kmax + 1)).  Otherwise the basis
@@ -67,7 +70,7 @@ __global__ __launch_bounds__(LZ_THREADS) void lanczos_kernel(int n, const double
     // deterministic start vector with no special structure
     double loc = 0.0;
     for (int i = tid; i < n; i += LZ_THREADS) {
-        double v = 1.0 + 0.5 * sin(1.0 + 0.7071067811865476 * i) + 0.25 * cos(0.3 * i * i);
+        const double v = lz_start(i);
         w[i] = v;
         loc += v * v;
     }
@@ -194,11 +197,188 @@ __global__ __launch_bounds__(LZ_THREADS) void lanczos_kernel(int n, const double
     if (tid == 0) *kout = k;
 }
 
+// ---- large n: each step as two launches ------------------------------------
+// Past a few hundred rows one workgroup streams T too slowly (n = 1000: 8 MB
+// per step through one CU).  Then a step is a matrix-vector product over the
+// whole chip (one wave per row of T, which is symmetric, so its contiguous
+// column i gives w_i) followed by one workgroup per run for the rest of the
+// step: alpha, the three-term update, two passes of reorthogonalisation
+// against the basis, beta, the stopping tests of lanczos_kernel and the next
+// vector.  Run b keeps its state in st[4 b ..]: beta of the previous step,
+// the norm estimate, the previous Ritz value; done[b] ends its later launches.
+__global__ __launch_bounds__(LZ_THREADS) void lanczos_start_kernel(int n, double* __restrict__ Qg,
+                                                                   int* __restrict__ kout, int* __restrict__ done,
+                                                                   double* __restrict__ st) {
+    const int b = blockIdx.x, tid = threadIdx.x;
+    Qg += (long)b * n * (LZ_MAX_K + 1);
+    __shared__ double red[LZ_WAVES];
+    double loc = 0.0;
+    for (int i = tid; i < n; i += LZ_THREADS) {
+        const double v = lz_start(i);
+        loc += v * v;
+    }
+    const double nrm = sqrt(lz_block_sum(loc, red));
+    for (int i = tid; i < n; i += LZ_THREADS) Qg[i] = lz_start(i) / nrm;
+    if (tid == 0) {
+        kout[b] = 0;
+        done[b] = 0;
+        st[4 * b] = 0.0;
+        st[4 * b + 1] = 0.0;
+        st[4 * b + 2] = 0.0;
+    }
+}
+
+// W[b][i] = (T_b q_j)_i: one wave per row, its lanes striding over the row
+__global__ __launch_bounds__(256) void lanczos_matvec_kernel(int n, int j, const double* __restrict__ T0,
+                                                             const double* __restrict__ T1, long ldt,
+                                                             const double* __restrict__ Qg, double* __restrict__ W,
+                                                             const int* __restrict__ done) {
+    const int b = blockIdx.y;
+    if (done[b]) return;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;  // whole waves leave together
+    const double* __restrict__ Ti = (b == 0 ? T0 : T1) + (long)i * ldt;
+    const double* __restrict__ q = Qg + (long)b * n * (LZ_MAX_K + 1) + (long)j * n;
+    double s0 = 0.0, s1 = 0.0;
+    int l = lane;
+    for (; l + 64 < n; l += 128) {
+        s0 += Ti[l] * q[l];
+        s1 += Ti[l + 64] * q[l + 64];
+    }
+    if (l < n) s0 += Ti[l] * q[l];
+    double s = s0 + s1;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) W[(long)b * n + i] = s;
+}
+
+__global__ __launch_bounds__(LZ_THREADS) void lanczos_orth_kernel(int n, int j, int kmax, const double* __restrict__ W,
+                                                                  double* __restrict__ Qg, double* __restrict__ ab,
+                                                                  int* __restrict__ kout, int* __restrict__ done,
+                                                                  double* __restrict__ st) {
+    const int b = blockIdx.x;
+    if (done[b]) return;
+    W += (long)b * n;
+    double* __restrict__ Q = Qg + (long)b * n * (LZ_MAX_K + 1);
+    ab += b * 2 * LZ_MAX_K;
+    st += 4 * b;
+    extern __shared__ double sm[];
+    double* w = sm;
+    double* q = sm + n;
+    __shared__ double red[LZ_WAVES];
+    __shared__ double h[LZ_MAX_K + 1];
+    __shared__ double ta[LZ_MAX_K], tb[LZ_MAX_K];
+    __shared__ int first_hit;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const double beta_prev = st[0], tnorm_prev = st[1], theta_prev = st[2];
+    for (int i = tid; i < n; i += LZ_THREADS) {
+        w[i] = W[i];
+        q[i] = Q[i + (long)j * n];
+    }
+    __syncthreads();
+    double loc = 0.0;
+    for (int i = tid; i < n; i += LZ_THREADS) loc += q[i] * w[i];
+    const double alpha = lz_block_sum(loc, red);
+    for (int i = tid; i < n; i += LZ_THREADS) {
+        double v = w[i] - alpha * q[i];
+        if (j > 0) v -= beta_prev * Q[i + (long)(j - 1) * n];
+        w[i] = v;
+    }
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int l = wv; l <= j; l += LZ_WAVES) {
+            double s = 0.0;
+            for (int i = lane; i < n; i += 64) s += Q[i + (long)l * n] * w[i];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+            if (lane == 0) h[l] = s;
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += LZ_THREADS) {
+            double v = w[i];
+            for (int l = 0; l <= j; ++l) v -= h[l] * Q[i + (long)l * n];
+            w[i] = v;
+        }
+        __syncthreads();
+    }
+    loc = 0.0;
+    for (int i = tid; i < n; i += LZ_THREADS) loc += w[i] * w[i];
+    const double beta = sqrt(lz_block_sum(loc, red));
+    const int k = j + 1;
+    if (tid == 0) {
+        ab[j] = alpha;
+        ab[kmax + j] = beta;
+        kout[b] = k;
+    }
+    if (!(beta > 1e-13 * (fabs(alpha) + beta_prev)) || k == kmax) {  // invariant subspace or done
+        if (tid == 0) done[b] = 1;
+        return;
+    }
+    const double tnorm = fmax(tnorm_prev, fabs(alpha) + beta + beta_prev);
+    double theta = theta_prev;
+    if (k >= 16 && (k & 7) == 0) {
+        // smallest eigenvalue of the tridiagonal so far, as in lanczos_kernel
+        // the earlier steps' entries from the launches that wrote them, this step's from registers
+        for (int i = tid; i < j; i += LZ_THREADS) {
+            ta[i] = ab[i];
+            tb[i] = ab[kmax + i];
+        }
+        if (tid == 0) {
+            ta[j] = alpha;
+            tb[j] = beta;
+        }
+        __syncthreads();
+        double lo = ta[0], hi = ta[0];
+        for (int i = 0; i < k; ++i) {
+            const double rr = (i > 0 ? fabs(tb[i - 1]) : 0.0) + (i + 1 < k ? fabs(tb[i]) : 0.0);
+            lo = fmin(lo, ta[i] - rr);
+            hi = fmax(hi, ta[i] + rr);
+        }
+        for (int round = 0; round < 6; ++round) {
+            const double step = (hi - lo) / (LZ_THREADS + 1);
+            const double x = lo + (tid + 1) * step;
+            int cnt = 0;
+            double dd = 1.0;
+            for (int i = 0; i < k; ++i) {
+                const double bb = i > 0 ? tb[i - 1] * tb[i - 1] : 0.0;
+                dd = ta[i] - x - (i > 0 ? bb / dd : 0.0);
+                if (dd == 0.0) dd = -1e-300;
+                if (dd < 0.0) ++cnt;
+            }
+            if (tid == 0) first_hit = LZ_THREADS;
+            __syncthreads();
+            if (cnt >= 1) atomicMin(&first_hit, tid);
+            __syncthreads();
+            const int t = first_hit;
+            __syncthreads();
+            const double nlo = lo + t * step, nhi = (t < LZ_THREADS) ? lo + (t + 1) * step : hi;
+            lo = nlo;
+            hi = nhi;
+        }
+        theta = 0.5 * (lo + hi);
+        const bool settled = k >= 24 && fabs(theta - theta_prev) <= 1e-10 * tnorm;
+        if (settled) {
+            if (tid == 0) done[b] = 1;
+            return;
+        }
+    }
+    for (int i = tid; i < n; i += LZ_THREADS) Q[i + (long)(j + 1) * n] = w[i] / beta;
+    if (tid == 0) {
+        st[0] = beta;
+        st[1] = tnorm;
+        st[2] = theta;
+    }
+}
+
 void LanczosWork::ensure(int n) {
     if (n <= cap) return;
     Q.alloc(2 * (size_t)n * (LZ_MAX_K + 1));  // two runs side by side
     ab.alloc(4 * LZ_MAX_K);
     kout.alloc(2);
+    W.alloc(2 * (size_t)n);
+    done.alloc(2);
+    st.alloc(8);
     if (!pinned) WC_HIP(hipHostMalloc(reinterpret_cast<void**>(&pinned), (4 * LZ_MAX_K + 2) * sizeof(double),
                                       hipHostMallocDefault));
     cap = n;
@@ -251,17 +431,39 @@ void lanczos_min_eig2(hipStream_t st, int n, const double* T0, const double* T1,
             v = 64 << 10;
         return static_cast<size_t>(v);
     }();
-    const bool split = n <= LZ_THREADS / 2;
-    size_t shm = (2 * (size_t)n + (split ? LZ_THREADS : 0)) * sizeof(double);
-    const size_t qbytes = (size_t)n * (kmax + 1) * sizeof(double);
-    const size_t static_lds = (LZ_WAVES + LZ_MAX_K + 1) * sizeof(double) + 1024;  // red, h, slack
-    const int qlds = shm + qbytes + static_lds <= lds_max ? 1 : 0;
-    if (qlds) shm += qbytes;
-    require(shm + static_lds <= lds_max, "lanczos: n too large for the workgroup's LDS");
     const int runs = T1 ? 2 : 1;
-    hipLaunchKernelGGL(lanczos_kernel, dim3(runs), dim3(LZ_THREADS), shm, st, n, T0, T1 ? T1 : T0, ldt, kmax,
-                       w.Q.get(), qlds, w.ab.get(), w.kout.get());
-    WC_LAUNCH_CHECK();
+    if (n > LZ_SPLIT_N) {
+        const size_t shm2 = 2 * (size_t)n * sizeof(double);
+        hipLaunchKernelGGL(lanczos_start_kernel, dim3(runs), dim3(LZ_THREADS), 0, st, n, w.Q.get(), w.kout.get(),
+                           w.done.get(), w.st.get());
+        WC_LAUNCH_CHECK();
+        for (int j = 0; j < kmax; ++j) {
+            hipLaunchKernelGGL(lanczos_matvec_kernel, dim3(cdiv(n, 4), runs), dim3(256), 0, st, n, j, T0,
+                               T1 ? T1 : T0, ldt, w.Q.get(), w.W.get(), w.done.get());
+            WC_LAUNCH_CHECK();
+            hipLaunchKernelGGL(lanczos_orth_kernel, dim3(runs), dim3(LZ_THREADS), shm2, st, n, j, kmax, w.W.get(),
+                               w.Q.get(), w.ab.get(), w.kout.get(), w.done.get(), w.st.get());
+            WC_LAUNCH_CHECK();
+            // the runs can stop from step 24 on (every 8 steps): stop launching once both have
+            if (j + 1 >= 24 && (j + 1) % 8 == 0 && j + 1 < kmax) {
+                int dn[2] = {1, 1};
+                WC_HIP(hipMemcpyAsync(dn, w.done.get(), runs * sizeof(int), hipMemcpyDeviceToHost, st));
+                WC_HIP(hipStreamSynchronize(st));
+                if (dn[0] && (runs == 1 || dn[1])) break;
+            }
+        }
+    } else {
+        const bool split = n <= LZ_THREADS / 2;
+        size_t shm = (2 * (size_t)n + (split ? LZ_THREADS : 0)) * sizeof(double);
+        const size_t qbytes = (size_t)n * (kmax + 1) * sizeof(double);
+        const size_t static_lds = (LZ_WAVES + LZ_MAX_K + 1) * sizeof(double) + 1024;  // red, h, slack
+        const int qlds = shm + qbytes + static_lds <= lds_max ? 1 : 0;
+        if (qlds) shm += qbytes;
+        require(shm + static_lds <= lds_max, "lanczos: n too large for the workgroup's LDS");
+        hipLaunchKernelGGL(lanczos_kernel, dim3(runs), dim3(LZ_THREADS), shm, st, n, T0, T1 ? T1 : T0, ldt, kmax,
+                           w.Q.get(), qlds, w.ab.get(), w.kout.get());
+        WC_LAUNCH_CHECK();
+    }
     WC_HIP(hipMemcpyAsync(w.pinned, w.ab.get(), 2 * LZ_MAX_K * runs * sizeof(double), hipMemcpyDeviceToHost, st));
     int k[2] = {0, 0};
     WC_HIP(hipMemcpyAsync(k, w.kout.get(), runs * sizeof(int), hipMemcpyDeviceToHost, st));

@@ -7,11 +7,15 @@ namespace wc {
 
 constexpr int LZ_MAX_K = 64;     // Lanczos steps at most
 constexpr int LZ_MAX_N = 4096;   // two n-vectors live in LDS
+constexpr int LZ_SPLIT_N = 640;  // above this the steps run as chip-wide products plus one workgroup per run
 
 struct LanczosWork {
     DevBuf<double> Q;   // n x (LZ_MAX_K + 1) Lanczos vectors
     DevBuf<double> ab;  // alpha[LZ_MAX_K], beta[LZ_MAX_K]
     DevBuf<int> kout;
+    DevBuf<double> W;   // T q per run (n each; large n only)
+    DevBuf<int> done;   // per run: no further steps (large n only)
+    DevBuf<double> st;  // per run: previous beta, norm estimate, previous Ritz value (large n only)
     double* pinned = nullptr;
     int cap = 0;
     void ensure(int n);

@@ -80,6 +80,13 @@ def dtrtri(Lm: torch.Tensor) -> torch.Tensor:
     return out
 
 
+def dlanczos_min_eig(T: torch.Tensor, kmax: int = 64) -> float:
+    n = T.shape[0]
+    out = C.c_double()
+    _chk(L.lib().wc_dlanczos_min_eig(_stream_ptr(), n, _p(T), n, kmax, C.byref(out)))
+    return out.value
+
+
 def djacobi_svd(A: torch.Tensor, want_v: bool = True, tol: float = 0.0, max_sweeps: int = 60):
     n = A.shape[0]
     V = torch.empty_like(A) if want_v else None

@@ -125,6 +125,24 @@ def test_jacobi_svd(n):
     assert np.all(Vg[idx, np.arange(n)] > 0)
 
 
+@pytest.mark.parametrize("n", [150, 600, 641, 1000, 4000])
+def test_lanczos_min_eig(n):
+    # n <= 640: one workgroup per run (basis in LDS up to ~240); above: each
+    # step as a chip-wide product plus one workgroup.  T = V diag(lam) V^T with
+    # a smallest eigenvalue -3 set apart from the rest, in [-1, 1]: the Ritz
+    # value is an upper bound on it and converges to it within the 64 steps.
+    rng = np.random.default_rng(n + 5)
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = rng.uniform(-1.0, 1.0, n)
+    lam[rng.integers(n)] = -3.0
+    T = (V * lam) @ V.T
+    T = 0.5 * (T + T.T)
+    ref = np.linalg.eigvalsh(T)[0]
+    got = la.dlanczos_min_eig(la.to_dev(T))
+    assert got >= ref - 1e-12 * 3.0
+    assert abs(got - ref) <= 1e-9 * 3.0
+
+
 @pytest.mark.parametrize("n", [48, 300])
 def test_jacobi_graded_columns_relative_accuracy(n):
     # A = B D with B well conditioned: one-sided Jacobi resolves every singular
