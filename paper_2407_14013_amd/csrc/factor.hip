@@ -81,13 +81,18 @@ __global__ __launch_bounds__(256) void trsm_rows_kernel(int rows, int nb, const 
     double x[PNB];
 #pragma unroll
     for (int c = 0; c < PNB; ++c) x[c] = (c < nb) ? P[r + (long)c * lda] : 0.0;
+    // the divisions off the dependent chain: one reciprocal per column, taken
+    // by every thread from the same LDS entries
+    double rd[PNB];
+#pragma unroll
+    for (int c = 0; c < PNB; ++c) rd[c] = (c < nb) ? 1.0 / Ls[c][c] : 0.0;
 #pragma unroll
     for (int c = 0; c < PNB; ++c) {
         if (c < nb) {
             double s = x[c];
 #pragma unroll
             for (int l = 0; l < c; ++l) s -= x[l] * Ls[c][l];
-            x[c] = s / Ls[c][c];
+            x[c] = s * rd[c];
         }
     }
 #pragma unroll
