@@ -1,9 +1,9 @@
 // Blocked Cholesky factorisation and triangular inversion (FP64, gfx950).
 //
-// potrf: right-looking, 32-column panels.  The diagonal block is factored
-// by one workgroup in LDS, the panel below it is solved row by row against
-// the block's transpose, and the trailing lower triangle is updated with
-// the MFMA GEMM.
+// potrf: right-looking, 32-column panels (inside 256-column outer panels for
+// large n).  The diagonal block is factored by one workgroup in LDS, the
+// panel below it is solved row by row against the block's transpose, and the
+// trailing lower triangle is updated with the MFMA GEMM.
 // trtri: recursive 2 x 2 blocking, inv([L11 0; L21 L22]) =
 // [L11^{-1} 0; -L22^{-1} L21 L11^{-1} L22^{-1}], with a one-workgroup
 // forward substitution at the leaves.
@@ -102,21 +102,42 @@ __global__ __launch_bounds__(256) void trsm_rows_kernel(int rows, int nb, const 
 
 __global__ void zero_int(int* p) { *p = 0; }
 
+// Right-looking with two levels for large n: the 32-column steps update only
+// the columns of their PNB_OUTER-wide outer panel, and the rest of the
+// trailing matrix takes one rank-PNB_OUTER update per outer panel -- the
+// trailing lower triangle is streamed n / PNB_OUTER times instead of n / 32.
+constexpr int PNB_OUTER = 256;
 void potrf(hipStream_t st, int n, double* A, long lda, int* info) {
     hipLaunchKernelGGL(zero_int, dim3(1), dim3(1), 0, st, info);
     WC_LAUNCH_CHECK();
-    for (int k = 0; k < n; k += PNB) {
-        int kb = std::min(PNB, n - k);
-        double* Akk = A + k + (long)k * lda;
-        hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(256), 0, st, kb, Akk, lda, info, k);
-        WC_LAUNCH_CHECK();
-        int rest = n - k - kb;
-        if (rest > 0) {
-            double* P = A + (k + kb) + (long)k * lda;
-            hipLaunchKernelGGL(trsm_rows_kernel, dim3(cdiv(rest, 256)), dim3(256), 0, st, rest, kb, Akk, lda, P);
+    const int outer = n > 2 * PNB_OUTER ? PNB_OUTER : n;
+    for (int k0 = 0; k0 < n; k0 += outer) {
+        const int kend = std::min(n, k0 + outer);  // columns [k0, kend) form the outer panel
+        for (int k = k0; k < kend; k += PNB) {
+            int kb = std::min(PNB, kend - k);
+            double* Akk = A + k + (long)k * lda;
+            hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(256), 0, st, kb, Akk, lda, info, k);
             WC_LAUNCH_CHECK();
-            double* A22 = A + (k + kb) + (long)(k + kb) * lda;
-            dgemm(st, false, true, rest, rest, kb, -1.0, P, lda, P, lda, 1.0, A22, lda, /*lower_only=*/true);
+            int rest = n - k - kb;
+            if (rest > 0) {
+                double* P = A + (k + kb) + (long)k * lda;
+                hipLaunchKernelGGL(trsm_rows_kernel, dim3(cdiv(rest, 256)), dim3(256), 0, st, rest, kb, Akk, lda,
+                                   P);
+                WC_LAUNCH_CHECK();
+                // the rest of the outer panel's columns (all rows below them)
+                const int cols = kend - k - kb;
+                if (cols > 0) {
+                    double* A22 = A + (k + kb) + (long)(k + kb) * lda;
+                    dgemm(st, false, true, rest, cols, kb, -1.0, P, lda, P, lda, 1.0, A22, lda, /*lower_only=*/true);
+                }
+            }
+        }
+        const int rest = n - kend;
+        if (rest > 0) {
+            // the trailing matrix past the outer panel, in one update of rank kend - k0
+            const double* Pb = A + kend + (long)k0 * lda;
+            double* A22 = A + kend + (long)kend * lda;
+            dgemm(st, false, true, rest, rest, kend - k0, -1.0, Pb, lda, Pb, lda, 1.0, A22, lda, /*lower_only=*/true);
         }
     }
     zero_upper(st, n, A, lda);

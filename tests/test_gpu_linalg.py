@@ -65,8 +65,9 @@ def test_dsymv(d):
     assert np.abs(y.cpu().numpy() - ref).max() <= bound
 
 
-@pytest.mark.parametrize("n", [1, 5, 31, 32, 33, 64, 100, 200, 597])
+@pytest.mark.parametrize("n", [1, 5, 31, 32, 33, 64, 100, 200, 512, 513, 597, 800, 1537, 3000])
 def test_dpotrf(n):
+    # n > 512 takes the two-level form (256-column outer panels, the last one ragged)
     rng = np.random.default_rng(n)
     M = rng.standard_normal((n, n))
     A = M @ M.T + n * np.eye(n)
@@ -87,6 +88,13 @@ def test_dpotrf_reports_bad_pivot():
     A[35, 35] = -1e6
     st, info = la.dpotrf(la.to_dev(A))
     assert st == -5 and info == 36
+    # the same inside a later outer panel of the two-level form
+    n = 700
+    M = rng.standard_normal((n, n))
+    A = M @ M.T + np.eye(n)
+    A[600, 600] = -1e9
+    st, info = la.dpotrf(la.to_dev(A))
+    assert st == -5 and info == 601
 
 
 @pytest.mark.parametrize("n", [1, 7, 32, 33, 64, 100, 200])
