@@ -145,7 +145,13 @@ void potrf(hipStream_t st, int n, double* A, long lda, int* info) {
 
 // Leaf inverse of a lower-triangular block of order nb <= PNB: thread j
 // computes column j of L^{-1} by forward substitution.
-__global__ __launch_bounds__(64) void trtri_leaf_kernel(int nb, const double* L, long ldl, double* X, long ldx) {
+// Workgroup b inverts the diagonal block [PNB b, min(PNB b + PNB, n)): every
+// leaf of the recursion below, in one launch.
+__global__ __launch_bounds__(64) void trtri_leaf_kernel(int n, const double* L, long ldl, double* X, long ldx) {
+    const int b0 = blockIdx.x * PNB;
+    const int nb = min(PNB, n - b0);
+    L += b0 + (long)b0 * ldl;
+    X += b0 + (long)b0 * ldx;
     __shared__ double Ls[PNB][PNB + 1];
     {  // all of a thread's loads in flight before the LDS stores
         constexpr int NL = PNB * PNB / 64;
@@ -182,12 +188,10 @@ __global__ __launch_bounds__(64) void trtri_leaf_kernel(int nb, const double* L,
         if (i < nb) X[i + (long)j * ldx] = (i >= j) ? x[i] : 0.0;
 }
 
+// Every split is at a multiple of PNB from the start of the matrix, so the
+// leaves (n <= PNB) are the PNB-aligned diagonal blocks, already inverted.
 static void trtri_rec(hipStream_t st, int n, const double* L, long ldl, double* X, long ldx, double* work) {
-    if (n <= PNB) {
-        hipLaunchKernelGGL(trtri_leaf_kernel, dim3(1), dim3(64), 0, st, n, L, ldl, X, ldx);
-        WC_LAUNCH_CHECK();
-        return;
-    }
+    if (n <= PNB) return;
     int n1 = static_cast<int>(round_up(n / 2, PNB));
     if (n1 >= n) n1 = n - PNB;
     int n2 = n - n1;
@@ -204,6 +208,8 @@ void trtri(hipStream_t st, int n, const double* L, long ldl, double* Linv, long 
     fill(st, 0, Linv, 0.0);
     // the strict upper triangle of Linv must be zero for the recursive GEMMs
     zero_upper(st, n, Linv, ldi);
+    hipLaunchKernelGGL(trtri_leaf_kernel, dim3(cdiv(n, PNB)), dim3(64), 0, st, n, L, ldl, Linv, ldi);
+    WC_LAUNCH_CHECK();
     trtri_rec(st, n, L, ldl, Linv, ldi, work);
 }
 

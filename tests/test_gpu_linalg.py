@@ -97,7 +97,7 @@ def test_dpotrf_reports_bad_pivot():
     assert st == -5 and info == 601
 
 
-@pytest.mark.parametrize("n", [1, 7, 32, 33, 64, 100, 200])
+@pytest.mark.parametrize("n", [1, 7, 32, 33, 64, 100, 200, 1000, 2049])
 def test_dtrtri(n):
     rng = np.random.default_rng(n + 7)
     M = rng.standard_normal((n, n))
