@@ -285,7 +285,7 @@ def bench_batched(args):
         "solved": head["solved"],
         "runs": runs,
         "speedup_f32_inner_vs_f64": runs["f64"]["launch_ms"] / head["launch_ms"],
-        "autotune": {"bucket_ms": bucket_ms, "configs": sorted({(t.rows_per_wave, t.aq_group) for t in tune})},
+        "autotune": {"bucket_ms": bucket_ms, "configs": sorted({(t.rows_per_wave, t.aq_group, t.gemm_tile) for t in tune})},
         "generate_s": gen_s,
     }
     if not args.no_cpu_baseline:

@@ -387,12 +387,15 @@ sdp_status sdp_adjoint(sdp_ctx* ctx, const double* dL_dX, double* dL_db, double*
 /*
  * Pass configuration of the batched solver, chosen per size bucket by
  * sdp_autotune_batched: packed constraint rows each wave streams at once in
- * the A(M) pass (1 to 4) and constraints per group when script-A script-Q is
- * formed (1 to 16).
+ * the A(M) pass (1 to 4), constraints per group when script-A script-Q is
+ * formed (1 to 16), and the edge of the output tile each wave computes in the
+ * workgroup's MFMA products (16 or 32; 0 selects 32): 16 keeps more of the
+ * workgroup's waves busy on small products.
  */
 typedef struct sdp_batch_tune {
     int32_t rows_per_wave;
     int32_t aq_group;
+    int32_t gemm_tile;
 } sdp_batch_tune;
 
 /*

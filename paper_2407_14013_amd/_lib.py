@@ -138,6 +138,7 @@ class SdpBatchTune(C.Structure):
     _fields_ = [
         ("rows_per_wave", C.c_int32),
         ("aq_group", C.c_int32),
+        ("gemm_tile", C.c_int32),
     ]
 
 

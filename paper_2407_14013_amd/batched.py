@@ -28,7 +28,7 @@ def _problems(problems, keep):
 
 
 def autotune(problems, stream=None, **opts):
-    """Per-instance pass configurations (list of (rows_per_wave, aq_group)) and the buckets' winning times."""
+    """Per-instance configurations (rows_per_wave, aq_group, gemm_tile) and the buckets' winning times."""
     keep = []
     probs = _problems(problems, keep)
     o = default_options(**opts)

@@ -37,7 +37,7 @@ typedef double bd4 __attribute__((ext_vector_type(4)));
 typedef double bd2 __attribute__((ext_vector_type(2)));
 
 struct BInst {
-    int n, m, rmax, rows_per_wave, aq_group, pad;
+    int n, m, rmax, rows_per_wave, aq_group, gemm_tile;
     long N2, ldp, ldp32;
     const double* P;  // m x ldp packed rows
     const float* P32; // m x ldp32 packed rows rounded to FP32 (low-precision inner solves), else null
@@ -157,45 +157,52 @@ __device__ void wg_scale_rows(int n, const double* A, const double* s, double pw
     bsync();
 }
 
-// C = alpha op(A) op(B) + beta C, column-major.  Each wave computes 32 x 32
-// output tiles as 2 x 2 v_mfma_f64_16x16x4 blocks with the operands read
-// straight from cache (lane l supplies A[l % 16][l / 16], B[l / 16][l % 16];
-// accumulator element v of lane l is D[l / 16 + 4 v][l % 16]).  C must not
-// alias A or B.
-__device__ void wg_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, long lda,
-                        const double* B, long ldb, double beta, double* C, long ldc) {
+// Wave tile edge of the workgroup's MFMA products for the instance it is
+// solving (16 or 32, the instance's gemm_tile), set at the start of each instance.
+__shared__ int wg_tile;
+
+// C = alpha op(A) op(B) + beta C, column-major.  Each wave computes TS x TS
+// output tiles (TS = 32: 2 x 2 v_mfma_f64_16x16x4 blocks; TS = 16: one, so
+// that small products keep more of the workgroup's waves busy) with the
+// operands read straight from cache (lane l supplies A[l % 16][l / 16],
+// B[l / 16][l % 16]; accumulator element v of lane l is D[l / 16 + 4 v][l % 16]).
+// C must not alias A or B.
+template <int TS>
+__device__ void wg_gemm_t(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, long lda,
+                          const double* B, long ldb, double beta, double* C, long ldc) {
+    constexpr int NB = TS / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int tm = (M + 31) / 32, tn = (N + 31) / 32;
+    const int tm = (M + TS - 1) / TS, tn = (N + TS - 1) / TS;
     for (int t = wave; t < tm * tn; t += BWV) {
-        const int r0 = (t % tm) * 32, c0 = (t / tm) * 32;
-        bd4 acc[2][2];
+        const int r0 = (t % tm) * TS, c0 = (t / tm) * TS;
+        bd4 acc[NB][NB];
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < NB; ++x)
 #pragma unroll
-            for (int y = 0; y < 2; ++y) acc[x][y] = bd4{0.0, 0.0, 0.0, 0.0};
+            for (int y = 0; y < NB; ++y) acc[x][y] = bd4{0.0, 0.0, 0.0, 0.0};
         for (int k0 = 0; k0 < K; k0 += 4) {
             const int k = k0 + (lane >> 4);
-            double a[2], bb[2];
+            double a[NB], bb[NB];
 #pragma unroll
-            for (int x = 0; x < 2; ++x) {
+            for (int x = 0; x < NB; ++x) {
                 const int i = r0 + x * 16 + (lane & 15);
                 a[x] = (i < M && k < K) ? (ta ? A[k + (long)i * lda] : A[i + (long)k * lda]) : 0.0;
             }
 #pragma unroll
-            for (int y = 0; y < 2; ++y) {
+            for (int y = 0; y < NB; ++y) {
                 const int j = c0 + y * 16 + (lane & 15);
                 bb[y] = (j < N && k < K) ? (tb ? B[j + (long)k * ldb] : B[k + (long)j * ldb]) : 0.0;
             }
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
+            for (int x = 0; x < NB; ++x)
 #pragma unroll
-                for (int y = 0; y < 2; ++y)
+                for (int y = 0; y < NB; ++y)
                     acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], bb[y], acc[x][y], 0, 0, 0);
         }
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < NB; ++x)
 #pragma unroll
-            for (int y = 0; y < 2; ++y)
+            for (int y = 0; y < NB; ++y)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int i = r0 + x * 16 + (lane >> 4) + 4 * v;
@@ -209,46 +216,53 @@ __device__ void wg_gemm(bool ta, bool tb, int M, int N, int K, double alpha, con
     }
     bsync();
 }
+__device__ void wg_gemm(bool ta, bool tb, int M, int N, int K, double alpha, const double* A, long lda,
+                        const double* B, long ldb, double beta, double* C, long ldc) {
+    if (wg_tile == 16) wg_gemm_t<16>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else wg_gemm_t<32>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+}
 
 // C = alpha A B + beta C on the FP32 matrix cores (v_mfma_f32_16x16x4_f32):
 // the FP64 operands are rounded to FP32 as they are read, the products are
 // accumulated in FP32 and C is FP64.  Same wave tiling as wg_gemm; the FP32
 // instruction delivers D[4 (l / 16) + v][l % 16] in lane l, element v.
 typedef float bf4 __attribute__((ext_vector_type(4)));
-__device__ void wg_sgemm(int M, int N, int K, double alpha, const double* A, long lda, const double* B, long ldb,
-                         double beta, double* C, long ldc) {
+template <int TS>
+__device__ void wg_sgemm_t(int M, int N, int K, double alpha, const double* A, long lda, const double* B, long ldb,
+                           double beta, double* C, long ldc) {
+    constexpr int NB = TS / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int tm = (M + 31) / 32, tn = (N + 31) / 32;
+    const int tm = (M + TS - 1) / TS, tn = (N + TS - 1) / TS;
     for (int t = wave; t < tm * tn; t += BWV) {
-        const int r0 = (t % tm) * 32, c0 = (t / tm) * 32;
-        bf4 acc[2][2];
+        const int r0 = (t % tm) * TS, c0 = (t / tm) * TS;
+        bf4 acc[NB][NB];
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < NB; ++x)
 #pragma unroll
-            for (int y = 0; y < 2; ++y) acc[x][y] = bf4{0.f, 0.f, 0.f, 0.f};
+            for (int y = 0; y < NB; ++y) acc[x][y] = bf4{0.f, 0.f, 0.f, 0.f};
         for (int k0 = 0; k0 < K; k0 += 4) {
             const int k = k0 + (lane >> 4);
-            float a[2], bb[2];
+            float a[NB], bb[NB];
 #pragma unroll
-            for (int x = 0; x < 2; ++x) {
+            for (int x = 0; x < NB; ++x) {
                 const int i = r0 + x * 16 + (lane & 15);
                 a[x] = (i < M && k < K) ? static_cast<float>(A[i + (long)k * lda]) : 0.f;
             }
 #pragma unroll
-            for (int y = 0; y < 2; ++y) {
+            for (int y = 0; y < NB; ++y) {
                 const int j = c0 + y * 16 + (lane & 15);
                 bb[y] = (j < N && k < K) ? static_cast<float>(B[k + (long)j * ldb]) : 0.f;
             }
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
+            for (int x = 0; x < NB; ++x)
 #pragma unroll
-                for (int y = 0; y < 2; ++y)
+                for (int y = 0; y < NB; ++y)
                     acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x], bb[y], acc[x][y], 0, 0, 0);
         }
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < NB; ++x)
 #pragma unroll
-            for (int y = 0; y < 2; ++y)
+            for (int y = 0; y < NB; ++y)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int i = r0 + x * 16 + 4 * (lane >> 4) + v;
@@ -262,8 +276,12 @@ __device__ void wg_sgemm(int M, int N, int K, double alpha, const double* A, lon
     }
     bsync();
 }
+__device__ void wg_sgemm(int M, int N, int K, double alpha, const double* A, long lda, const double* B, long ldb,
+                         double beta, double* C, long ldc) {
+    if (wg_tile == 16) wg_sgemm_t<16>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else wg_sgemm_t<32>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+}
 
-// y = alpha A x + beta y for row-major A (rows x cols, pitch lda): one wave per row.
 __device__ void wg_gemv_rows(int rows, int cols, const double* A, long lda, const double* x, double* y, double alpha,
                              double beta) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1257,6 +1275,8 @@ __device__ int scaling(Inst& s) {
 
 // The interior-point method of solver.hip for one instance.
 __device__ void solve_one(const BInst& I, const BParams& bp, Work& w, double* red, double* h, int* ired, BOut* out) {
+    if (threadIdx.x == 0) wg_tile = I.gemm_tile;
+    bsync();
     Inst s{I, bp, w, red, h, ired, I.n, I.m, 1, 1, 0, 0.0, 0.0};
     const int n = I.n, m = I.m;
     s.N2 = I.N2;
@@ -1492,8 +1512,10 @@ void stage(const sdp_problem* probs, int count, const sdp_options& o, hipStream_
         I.rmax = std::max(1, std::min(o.rank_max, n - 1));
         I.rows_per_wave = tune ? tune[i].rows_per_wave : 2;
         I.aq_group = tune ? tune[i].aq_group : 8;
-        require(I.rows_per_wave >= 1 && I.rows_per_wave <= 4 && I.aq_group >= 1 && I.aq_group <= 16,
-                "batch tune out of range (rows_per_wave 1..4, aq_group 1..16)");
+        I.gemm_tile = (tune && tune[i].gemm_tile) ? tune[i].gemm_tile : 32;
+        require(I.rows_per_wave >= 1 && I.rows_per_wave <= 4 && I.aq_group >= 1 && I.aq_group <= 16 &&
+                    (I.gemm_tile == 16 || I.gemm_tile == 32),
+                "batch tune out of range (rows_per_wave 1..4, aq_group 1..16, gemm_tile 0, 16 or 32)");
         I.N2 = N2;
         I.ldp = ldp;
         I.ldp32 = ldp32;
@@ -1609,8 +1631,13 @@ void autotune_batched(const sdp_problem* probs, int count, const sdp_options* op
     if (opt) o = *opt;
     else sdp_default_options(&o);
     o.max_ipm_iter = 2;  // time the first iterations only
-    const BatchTune cands[] = {{1, 4}, {2, 8}, {4, 8}, {4, 16}};
-    const int ncand = sizeof(cands) / sizeof(cands[0]);
+    // pass settings x the wave tile of the workgroup's MFMA products; 16 x 16
+    // wave tiles are tried only where 32 x 32 ones leave waves idle (n < 48:
+    // at most four tiles for the four waves), since elsewhere they only add
+    // operand reads
+    const BatchTune cands[] = {{1, 4, 32}, {2, 8, 32}, {4, 8, 32}, {4, 16, 32},
+                               {1, 4, 16}, {2, 8, 16}, {4, 8, 16}, {4, 16, 16}};
+    const int ncand_all = sizeof(cands) / sizeof(cands[0]);
     auto bucket = [](int n) { return n < 48 ? 0 : (n < 96 ? 1 : 2); };
     for (int i = 0; i < count; ++i) out[i] = cands[1];
     for (int bk = 0; bk < 3; ++bk) {
@@ -1623,6 +1650,7 @@ void autotune_batched(const sdp_problem* probs, int count, const sdp_options* op
         for (int i : idx) sample.push_back(probs[i]);
         int best = 1;
         double best_ms = 1e300;
+        const int ncand = bk == 0 ? ncand_all : 4;
         for (int c = 0; c < ncand; ++c) {
             std::vector<BatchTune> tt(sample.size(), cands[c]);
             Staged S;

@@ -71,7 +71,7 @@ def test_batched_matches_oracle(prec):
 def test_batched_autotune_and_single_instances_agree():
     probs = batch(count=6, seed=8)
     tune, ms = autotune(probs)
-    assert all(t.rows_per_wave in (1, 2, 4) and t.aq_group in (4, 8, 16) for t in tune)
+    assert all(t.rows_per_wave in (1, 2, 4) and t.aq_group in (4, 8, 16) and t.gemm_tile in (16, 32) for t in tune)
     r_all, X_all, _ = solve_batched(probs, tune=tune)
     for i, p in enumerate(probs):
         r_one, X_one, _ = solve_batched([p])
@@ -104,6 +104,17 @@ def test_batched_size_spread_matches_oracle(spread, prec):
               f"pcg {r['pcg_iterations']} products fp64 {r['newton_matvecs']} low {r['lp_matvecs']} "
               f"objective error {e_obj:.1e} recovery {e_rec:.1e}")
         assert e_rec <= 1e-6
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batched_16_wide_wave_tiles_match_oracle(spread, prec):
+    # the workgroup's MFMA products with 16 x 16 wave tiles (gemm_tile 16)
+    probs, refs = spread
+    tune = (L.SdpBatchTune * len(probs))(*[L.SdpBatchTune(2, 8, 16) for _ in probs])
+    results, Xs, ys = solve_batched(probs, tune=tune, want_y=True, inner_prec=prec)
+    for i, p in enumerate(probs):
+        e_obj, e_rec = check_instance(p, results[i], Xs[i], ys[i], refs[i])
+        assert e_rec <= 1e-6, (i, e_obj, e_rec)
 
 
 def test_batched_rejects_bf16_inner():
