@@ -204,23 +204,27 @@ void lp_corrector(hipStream_t st, int ell, const double* x, const double* s, con
 }
 
 // Ratio tests: out[0] = min over dx_j < 0 of -x_j / dx_j, out[1] the same for
-// (s, ds); +inf when no entry decreases.  One workgroup.
-__global__ __launch_bounds__(kSplitThreads) void lp_ratio_kernel(int ell, const double* __restrict__ x,
-                                                                 const double* __restrict__ dx,
-                                                                 const double* __restrict__ s,
-                                                                 const double* __restrict__ ds,
-                                                                 double* __restrict__ out) {
-    __shared__ double red[2][kSplitThreads];
+// (s, ds); +inf when no entry decreases.  Two stages: kRedBlocks workgroups
+// stride over the coordinates and write their minima to part[b] and
+// part[kRedBlocks + b]; one workgroup takes the minimum of those (min is exact,
+// so the result does not depend on the split).
+constexpr int kRedBlocks = 256;
+__global__ __launch_bounds__(256) void lp_ratio_part_kernel(int ell, const double* __restrict__ x,
+                                                            const double* __restrict__ dx,
+                                                            const double* __restrict__ s,
+                                                            const double* __restrict__ ds,
+                                                            double* __restrict__ part) {
+    __shared__ double red[2][256];
     const int t = threadIdx.x;
     double a = INFINITY, b = INFINITY;
-    for (int j = t; j < ell; j += kSplitThreads) {
+    for (long j = blockIdx.x * 256L + t; j < ell; j += (long)gridDim.x * 256) {
         if (dx[j] < 0.0) a = fmin(a, -x[j] / dx[j]);
         if (ds[j] < 0.0) b = fmin(b, -s[j] / ds[j]);
     }
     red[0][t] = a;
     red[1][t] = b;
     __syncthreads();
-    for (int off = kSplitThreads / 2; off > 0; off >>= 1) {
+    for (int off = 128; off > 0; off >>= 1) {
         if (t < off) {
             red[0][t] = fmin(red[0][t], red[0][t + off]);
             red[1][t] = fmin(red[1][t], red[1][t + off]);
@@ -228,42 +232,71 @@ __global__ __launch_bounds__(kSplitThreads) void lp_ratio_kernel(int ell, const 
         __syncthreads();
     }
     if (t == 0) {
-        out[0] = red[0][0];
-        out[1] = red[1][0];
+        part[blockIdx.x] = red[0][0];
+        part[kRedBlocks + blockIdx.x] = red[1][0];
     }
 }
+// out[k] = min (max when take_max) of part[k * kRedBlocks + b] over b < nb, for k < nout
+__global__ __launch_bounds__(256) void lp_red_finish_kernel(int nb, int nout, bool take_max,
+                                                            const double* __restrict__ part,
+                                                            double* __restrict__ out) {
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    for (int k = 0; k < nout; ++k) {
+        double v = take_max ? 0.0 : INFINITY;
+        for (int b = t; b < nb; b += 256) {
+            const double p = part[k * kRedBlocks + b];
+            v = take_max ? fmax(v, p) : fmin(v, p);
+        }
+        red[t] = v;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if (t < off) red[t] = take_max ? fmax(red[t], red[t + off]) : fmin(red[t], red[t + off]);
+            __syncthreads();
+        }
+        if (t == 0) out[k] = red[0];
+        __syncthreads();
+    }
+}
+static int red_blocks(long n) { return static_cast<int>(std::max(1L, std::min<long>(kRedBlocks, (n + 1023) / 1024))); }
 void lp_ratio(hipStream_t st, int ell, const double* x, const double* dx, const double* s, const double* ds,
-              double* out) {
-    hipLaunchKernelGGL(lp_ratio_kernel, dim3(1), dim3(kSplitThreads), 0, st, ell, x, dx, s, ds, out);
+              double* out, double* part) {
+    const int nb = red_blocks(ell);
+    hipLaunchKernelGGL(lp_ratio_part_kernel, dim3(nb), dim3(256), 0, st, ell, x, dx, s, ds, part);
+    WC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(lp_red_finish_kernel, dim3(1), dim3(256), 0, st, nb, 2, false, part, out);
     WC_LAUNCH_CHECK();
 }
 
 // out[0] = max_i sum_j B_ij^2 e2_j, the largest diagonal entry of B diag(e2) B^T
-// (rows of B in CSR).  One workgroup.
-__global__ __launch_bounds__(kSplitThreads) void lp_row_diag_max_kernel(int m, const int* __restrict__ rptr,
-                                                                        const int* __restrict__ rcol,
-                                                                        const double* __restrict__ rval,
-                                                                        const double* __restrict__ e2,
-                                                                        double* __restrict__ out) {
-    __shared__ double red[kSplitThreads];
+// (rows of B in CSR), in the two stages of lp_ratio (the sums are >= 0).
+__global__ __launch_bounds__(256) void lp_row_diag_max_part_kernel(int m, const int* __restrict__ rptr,
+                                                                   const int* __restrict__ rcol,
+                                                                   const double* __restrict__ rval,
+                                                                   const double* __restrict__ e2,
+                                                                   double* __restrict__ part) {
+    __shared__ double red[256];
     const int t = threadIdx.x;
     double a = 0.0;
-    for (int i = t; i < m; i += kSplitThreads) {
+    for (long i = blockIdx.x * 256L + t; i < m; i += (long)gridDim.x * 256) {
         double acc = 0.0;
         for (int k = rptr[i]; k < rptr[i + 1]; ++k) acc += rval[k] * rval[k] * e2[rcol[k]];
         a = fmax(a, acc);
     }
     red[t] = a;
     __syncthreads();
-    for (int off = kSplitThreads / 2; off > 0; off >>= 1) {
+    for (int off = 128; off > 0; off >>= 1) {
         if (t < off) red[t] = fmax(red[t], red[t + off]);
         __syncthreads();
     }
-    if (t == 0) out[0] = red[0];
+    if (t == 0) part[blockIdx.x] = red[0];
 }
 void lp_row_diag_max(hipStream_t st, int m, const int* rptr, const int* rcol, const double* rval, const double* e2,
-                     double* out) {
-    hipLaunchKernelGGL(lp_row_diag_max_kernel, dim3(1), dim3(kSplitThreads), 0, st, m, rptr, rcol, rval, e2, out);
+                     double* out, double* part) {
+    const int nb = red_blocks(m);
+    hipLaunchKernelGGL(lp_row_diag_max_part_kernel, dim3(nb), dim3(256), 0, st, m, rptr, rcol, rval, e2, part);
+    WC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(lp_red_finish_kernel, dim3(1), dim3(256), 0, st, nb, 1, true, part, out);
     WC_LAUNCH_CHECK();
 }
 

@@ -31,12 +31,12 @@ void lp_recover(hipStream_t st, int ell, const double* e2, const int* pos, const
 // c~ = r_d + s - (smu - dx_a ds_a) / x
 void lp_corrector(hipStream_t st, int ell, const double* x, const double* s, const double* dxa, const double* dsa,
                   double smu, const double* rd, double* ct);
-// out[0], out[1]: the ratio tests of (x, dx) and (s, ds)
+// out[0], out[1]: the ratio tests of (x, dx) and (s, ds); part: 512 doubles of scratch
 void lp_ratio(hipStream_t st, int ell, const double* x, const double* dx, const double* s, const double* ds,
-              double* out);
-// out[0] = max_i sum_j B_ij^2 e2_j (rows of B in CSR)
+              double* out, double* part);
+// out[0] = max_i sum_j B_ij^2 e2_j (rows of B in CSR); part: 256 doubles of scratch
 void lp_row_diag_max(hipStream_t st, int m, const int* rptr, const int* rcol, const double* rval, const double* e2,
-                     double* out);
+                     double* out, double* part);
 // the split of the LP scaling w = sqrt(x/s) against tau (at most cap entries in T); info[0] = |T|,
 // info[1] = entries with x or s not positive
 void lp_split(hipStream_t st, int ell, const double* x, const double* s, double tau, int cap, double* w, double* e2,

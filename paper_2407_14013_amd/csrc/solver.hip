@@ -743,7 +743,7 @@ void ensure_scaling(sdp_ctx* c) {
         lp_split(st, c->ell, c->xl, c->sl, c->tau, c->tcap, c->wl, c->e2l, c->posl, c->Tl, c->sig + d,
                  c->info.get() + 3);
         // the LP part of the (1,1) block, B diag(e2) B^T, and its largest diagonal entry
-        lp_row_diag_max(st, m, c->lrptr, c->lrcol, c->lrval, c->e2l, c->sc + 32);
+        lp_row_diag_max(st, m, c->lrptr, c->lrcol, c->lrval, c->e2l, c->sc + 32, c->part);
         int ht[2] = {0, 0};
         double bl = 0.0;
         WC_HIP(hipMemcpyAsync(ht, c->info.get() + 3, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1553,7 +1553,7 @@ int ipm_step(sdp_ctx* c, sdp_step_stats* stats) {
     ap = std::min(1.0, ap);
     ad = std::min(1.0, ad);
     if (lp) {
-        lp_ratio(st, ell, c->xl, c->dxa_l, c->sl, c->dsa_l, sc + 24);
+        lp_ratio(st, ell, c->xl, c->dxa_l, c->sl, c->dsa_l, sc + 24, c->part);
         fetch(c, sc + 24, 2);
         ap = std::min(ap, c->pin[0]);
         ad = std::min(ad, c->pin[1]);
@@ -1600,7 +1600,7 @@ int ipm_step(sdp_ctx* c, sdp_step_stats* stats) {
     ap = std::min(1.0, frac * ap);
     ad = std::min(1.0, frac * ad);
     if (lp) {
-        lp_ratio(st, ell, c->xl, c->dx_l, c->sl, c->ds_l, sc + 24);
+        lp_ratio(st, ell, c->xl, c->dx_l, c->sl, c->ds_l, sc + 24, c->part);
         fetch(c, sc + 24, 2);
         ap = std::min(ap, frac * c->pin[0]);
         ad = std::min(ad, frac * c->pin[1]);
