@@ -380,10 +380,217 @@ __global__ __launch_bounds__(kSplitThreads) void lp_split_kernel(int ell, const 
         info[1] = static_cast<int>(bad);
     }
 }
+// ---- the same split over the whole chip (large l) ------------------------------
+// Workgroup b of nb owns the contiguous range [b chunk, (b + 1) chunk).  The
+// cut, when more than cap entries exceed 2 tau, is the (cap + 1)-th largest w:
+// the smallest bit pattern B with #{w > B} <= cap, as the bisection above
+// finds.  It is selected by MSD radix select over the eight bytes of the bit
+// patterns: per-workgroup histograms of the next byte among the entries that
+// match the bytes fixed so far, summed in workgroup order by one workgroup,
+// which fixes the byte.  Integer sums, so the result does not depend on nb.
+// Workspace ws (int64), K = kSplitBlocks: [0, nb) counts above 2 tau,
+// [K, K + nb) nonpositive counts, [2 K, 2 K + nb) members per workgroup,
+// [4 K, 4 K + 256 nb) histograms, then the select state: ws[LPS_STATE] = prefix bits, + 1 = bytes fixed,
+// + 2 = rank still wanted, + 3 = total above, + 4 = total nonpositive, + 5 = cut.
+constexpr int kSplitBlocks = 256;
+constexpr long LPS_HIST = 4L * kSplitBlocks;
+constexpr long LPS_STATE = LPS_HIST + 256L * kSplitBlocks;
+long lp_split_ws_len() { return LPS_STATE + 8; }
+
+__device__ inline unsigned long long wbits(double v) { return static_cast<unsigned long long>(__double_as_longlong(v)); }
+
+__global__ __launch_bounds__(256) void lp_split_w_kernel(int ell, int chunk, const double* __restrict__ x,
+                                                         const double* __restrict__ s, double thr,
+                                                         double* __restrict__ w, long* __restrict__ ws) {
+    __shared__ long red[256];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int j0 = min(ell, b * chunk), j1 = min(ell, j0 + chunk);
+    long above = 0, bad = 0;
+    for (int j = j0 + t; j < j1; j += 256) {
+        const double xj = x[j], sj = s[j];
+        const bool ok = xj > 0.0 && sj > 0.0 && isfinite(xj) && isfinite(sj);
+        const double wj = ok ? sqrt(xj / sj) : 0.0;
+        w[j] = wj;
+        above += (wj > thr) ? 1 : 0;
+        bad += ok ? 0 : 1;
+    }
+    red[t] = above;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) red[t] += red[t + off];
+        __syncthreads();
+    }
+    if (t == 0) ws[b] = red[0];
+    __syncthreads();
+    red[t] = bad;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) red[t] += red[t + off];
+        __syncthreads();
+    }
+    if (t == 0) ws[kSplitBlocks + b] = red[0];
+}
+
+// one thread: totals, and the start of the select (the cut stays at 2 tau when at most cap exceed it)
+__global__ void lp_split_totals_kernel(int nb, int cap, double thr, long* __restrict__ ws) {
+    long above = 0, bad = 0;
+    for (int b = 0; b < nb; ++b) {
+        above += ws[b];
+        bad += ws[kSplitBlocks + b];
+    }
+    long* sv = ws + LPS_STATE;
+    sv[0] = 0;              // prefix bits
+    sv[1] = above > cap ? 0 : 8;  // bytes fixed (8: no select needed)
+    sv[2] = cap + 1;        // rank (from the top) of the cut among all entries
+    sv[3] = above;
+    sv[4] = bad;
+    sv[5] = static_cast<long>(wbits(thr));
+}
+
+// histogram of byte `pass` (from the top) of w's bit pattern among the entries whose higher bytes match the prefix
+__global__ __launch_bounds__(256) void lp_split_hist_kernel(int ell, int chunk, int pass,
+                                                            const double* __restrict__ w, long* __restrict__ ws) {
+    __shared__ int hist[256];
+    const long* sv = ws + LPS_STATE;
+    if (sv[1] >= 8) return;  // no select (uniform)
+    const int b = blockIdx.x, t = threadIdx.x;
+    hist[t] = 0;
+    __syncthreads();
+    const unsigned long long prefix = static_cast<unsigned long long>(sv[0]);
+    const int shift = 56 - 8 * pass;
+    const unsigned long long hmask = pass == 0 ? 0ull : (~0ull << (64 - 8 * pass));
+    const int j0 = min(ell, b * chunk), j1 = min(ell, j0 + chunk);
+    for (int j = j0 + t; j < j1; j += 256) {
+        const unsigned long long v = wbits(w[j]);
+        if ((v & hmask) == prefix) atomicAdd(&hist[(v >> shift) & 0xFF], 1);
+    }
+    __syncthreads();
+    ws[LPS_HIST + (long)b * 256 + t] = hist[t];
+}
+
+// one workgroup: fix byte `pass` -- walking the byte values downwards, the one at
+// which the count of larger-or-equal entries reaches the wanted rank
+__global__ __launch_bounds__(256) void lp_split_select_kernel(int nb, int pass, long* __restrict__ ws) {
+    __shared__ long cnt[256];
+    long* sv = ws + LPS_STATE;
+    if (sv[1] >= 8) return;
+    const int t = threadIdx.x;
+    long c = 0;
+    for (int b = 0; b < nb; ++b) c += ws[LPS_HIST + (long)b * 256 + t];
+    cnt[t] = c;
+    __syncthreads();
+    if (t == 0) {
+        long want = sv[2];
+        int digit = 0;
+        for (int d = 255; d >= 0; --d) {
+            if (cnt[d] >= want) {
+                digit = d;
+                break;
+            }
+            want -= cnt[d];
+        }
+        const int shift = 56 - 8 * pass;
+        sv[0] = static_cast<long>(static_cast<unsigned long long>(sv[0]) |
+                                  (static_cast<unsigned long long>(digit) << shift));
+        sv[2] = want;
+        sv[1] = pass + 1;
+        if (pass == 7) sv[5] = sv[0];  // the (cap + 1)-th largest bit pattern
+    }
+}
+
+// members (w > cut) per workgroup
+__global__ __launch_bounds__(256) void lp_split_count_kernel(int ell, int chunk, const double* __restrict__ w,
+                                                             long* __restrict__ ws) {
+    __shared__ long red[256];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const unsigned long long cut = static_cast<unsigned long long>(ws[LPS_STATE + 5]);
+    const int j0 = min(ell, b * chunk), j1 = min(ell, j0 + chunk);
+    long c = 0;
+    for (int j = j0 + t; j < j1; j += 256) c += (wbits(w[j]) > cut) ? 1 : 0;
+    red[t] = c;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) red[t] += red[t + off];
+        __syncthreads();
+    }
+    if (t == 0) ws[2 * kSplitBlocks + b] = red[0];
+}
+
+// order-preserving compaction: workgroup b starts at the members of the workgroups before it;
+// each thread owns a contiguous segment of the workgroup's range
+__global__ __launch_bounds__(256) void lp_split_write_kernel(int ell, int chunk, int nb, double tau,
+                                                             const double* __restrict__ w, double* __restrict__ e2,
+                                                             int* __restrict__ pos, int* __restrict__ Tl,
+                                                             double* __restrict__ sig_lp, const long* __restrict__ ws,
+                                                             int* __restrict__ info) {
+    __shared__ long red[256];
+    __shared__ long base;
+    const int b = blockIdx.x, t = threadIdx.x;
+    if (t == 0) {
+        long o = 0;
+        for (int q = 0; q < b; ++q) o += ws[2 * kSplitBlocks + q];
+        base = o;
+        if (b == nb - 1) {
+            info[0] = static_cast<int>(o + ws[2 * kSplitBlocks + b]);
+            info[1] = static_cast<int>(ws[LPS_STATE + 4]);
+        }
+    }
+    const unsigned long long cut = static_cast<unsigned long long>(ws[LPS_STATE + 5]);
+    const int j0 = min(ell, b * chunk), j1 = min(ell, j0 + chunk);
+    const int seg = (j1 - j0 + 255) / 256;
+    const int s0 = min(j1, j0 + t * seg), s1 = min(j1, s0 + seg);
+    long mine = 0;
+    for (int j = s0; j < s1; ++j) mine += (wbits(w[j]) > cut) ? 1 : 0;
+    red[t] = mine;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const long add = (t >= off) ? red[t - off] : 0;
+        __syncthreads();
+        red[t] += add;
+        __syncthreads();
+    }
+    long k = base + red[t] - mine;
+    const double t2 = tau * tau;
+    for (int j = s0; j < s1; ++j) {
+        const double wj = w[j];
+        if (wbits(wj) > cut) {
+            pos[j] = static_cast<int>(k);
+            Tl[k] = j;
+            sig_lp[k] = 1.0 / (wj * wj - t2);
+            e2[j] = 1.0;
+            ++k;
+        } else {
+            pos[j] = -1;
+            e2[j] = (wj / tau) * (wj / tau);
+        }
+    }
+}
+
 void lp_split(hipStream_t st, int ell, const double* x, const double* s, double tau, int cap, double* w, double* e2,
-              int* pos, int* Tl, double* sig_lp, int* info) {
-    hipLaunchKernelGGL(lp_split_kernel, dim3(1), dim3(kSplitThreads), 0, st, ell, x, s, tau, cap, w, e2, pos, Tl,
-                       sig_lp, info);
+              int* pos, int* Tl, double* sig_lp, int* info, long* ws) {
+    if (ell <= 4 * kSplitThreads || ws == nullptr) {
+        hipLaunchKernelGGL(lp_split_kernel, dim3(1), dim3(kSplitThreads), 0, st, ell, x, s, tau, cap, w, e2, pos, Tl,
+                           sig_lp, info);
+        WC_LAUNCH_CHECK();
+        return;
+    }
+    const int nb = std::min<int>(kSplitBlocks, (ell + 2047) / 2048);
+    const int chunk = (ell + nb - 1) / nb;
+    const double thr = 2.0 * tau;
+    hipLaunchKernelGGL(lp_split_w_kernel, dim3(nb), dim3(256), 0, st, ell, chunk, x, s, thr, w, ws);
+    WC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(lp_split_totals_kernel, dim3(1), dim3(1), 0, st, nb, cap, thr, ws);
+    WC_LAUNCH_CHECK();
+    for (int pass = 0; pass < 8; ++pass) {  // return at once when no select is needed
+        hipLaunchKernelGGL(lp_split_hist_kernel, dim3(nb), dim3(256), 0, st, ell, chunk, pass, w, ws);
+        WC_LAUNCH_CHECK();
+        hipLaunchKernelGGL(lp_split_select_kernel, dim3(1), dim3(256), 0, st, nb, pass, ws);
+        WC_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(lp_split_count_kernel, dim3(nb), dim3(256), 0, st, ell, chunk, w, ws);
+    WC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(lp_split_write_kernel, dim3(nb), dim3(256), 0, st, ell, chunk, nb, tau, w, e2, pos, Tl,
+                       sig_lp, ws, info);
     WC_LAUNCH_CHECK();
 }
 

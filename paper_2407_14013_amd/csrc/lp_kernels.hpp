@@ -39,8 +39,10 @@ void lp_row_diag_max(hipStream_t st, int m, const int* rptr, const int* rcol, co
                      double* out, double* part);
 // the split of the LP scaling w = sqrt(x/s) against tau (at most cap entries in T); info[0] = |T|,
 // info[1] = entries with x or s not positive
+// ws: lp_split_ws_len() int64 of scratch (large l runs over the whole chip; NULL: one workgroup)
 void lp_split(hipStream_t st, int ell, const double* x, const double* s, double tau, int cap, double* w, double* e2,
-              int* pos, int* Tl, double* sig_lp, int* info);
+              int* pos, int* Tl, double* sig_lp, int* info, long* ws);
+long lp_split_ws_len();
 // C's SDP-LP and LP-LP blocks (column-major, pitch ldc)
 void lp_c12(hipStream_t st, int n, int r, int d, int t, const int* Tl, const int* cptr, const int* crow,
             const double* cval, const double* AQ, long ldaq, const int* jk, const double* Gw, long ldg, double ib,

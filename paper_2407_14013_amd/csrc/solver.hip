@@ -200,6 +200,7 @@ static void alloc_work(sdp_ctx* c) {
         }
         c->posl.alloc(ell);
         c->Tl.alloc(std::max(1, c->tcap));
+        c->lpsw.alloc(lp_split_ws_len());
     }
     c->dya.alloc(m + 32);
     c->dy.alloc(m + 32);
@@ -741,7 +742,7 @@ void ensure_scaling(sdp_ctx* c) {
     c->t = 0;
     if (c->ell > 0) {
         lp_split(st, c->ell, c->xl, c->sl, c->tau, c->tcap, c->wl, c->e2l, c->posl, c->Tl, c->sig + d,
-                 c->info.get() + 3);
+                 c->info.get() + 3, c->lpsw);
         // the LP part of the (1,1) block, B diag(e2) B^T, and its largest diagonal entry
         lp_row_diag_max(st, m, c->lrptr, c->lrcol, c->lrval, c->e2l, c->sc + 32, c->part);
         int ht[2] = {0, 0};

@@ -67,6 +67,7 @@ struct sdp_ctx {
     wc::JacobiWork jw;
     wc::LanczosWork lw;
     wc::DevBuf<double> wl, e2l;  // LP split: w = sqrt(x/s), script-E entries (Sigma at T sits in sig[d..d+t))
+    wc::DevBuf<long> lpsw;       // LP split: workspace of the chip-wide form
     wc::DevBuf<int> posl, Tl;    // LP split: position of each coordinate in T (or -1); T in increasing order
 
     // ---- temporaries -------------------------------------------------------------

@@ -255,3 +255,50 @@ def test_lp_entry_points_reject_misuse():
         with pytest.raises(SdpError) as ei:
             ctx.aug_dim()
         assert ei.value.status == L.SDP_ENUMERIC
+
+
+def test_chip_wide_split_matches_the_rule():
+    # l = 20 000 LP coordinates take the chip-wide split (workgroup counts,
+    # radix select of the cut, order-preserving compaction).  At a point whose
+    # w spans many decades and holds a tied group of 41, T must equal the rule
+    # (w > 2 tau, at most cap entries >= w_j, a tied group in or out as a whole)
+    # for caps above |{w > 2 tau}|, below it, and with the cut inside the tie.
+    p = workloads.robust_completion(150, 10000, 40, seed=21)
+    n = p["n"]
+    with Context(p) as ctx:
+        for _ in range(3):
+            ctx.ipm_step()
+        X, y, S = ctx.get_point()
+        x, _ = ctx.get_lp_point()
+    ell = x.numel()
+    assert ell == 20000
+    rng = np.random.default_rng(3)
+    w = np.exp(rng.uniform(-12.0, 12.0, ell))
+    s2 = np.ones(ell)
+    with Context(p) as ctx:  # tau comes from the SDP part of the point alone
+        ctx.set_point(X, y, S, dev(w * w), dev(s2))
+        _, sp = gpu_split(ctx, n)
+    # a tied group of 41 above 2 tau, at a value no other entry has
+    w[4999:5040] = np.median(w[w > 2.0 * sp["tau"]]) * (1.0 + 1e-7)
+    assert int((w == w[4999]).sum()) == 41
+    x2 = w * w
+    above = int((w > 2.0 * sp["tau"]).sum())
+    ws = np.sort(w)[::-1]
+    tie_rank = int(np.argmax(ws == w[4999]))  # entries larger than the tied value
+    assert 0 < tie_rank and tie_rank + 41 < above
+    caps = [above + 5, above - 1, above // 3, tie_rank + 20, tie_rank + 41, tie_rank]
+    for cap in caps:
+        with Context(p, lp_top_max=cap) as ctx:
+            ctx.set_point(X, y, S, dev(x2), dev(s2))
+            _, sp = gpu_split(ctx, n)
+            ls = ctx.lp_split()
+            wg = host(ls["w"])
+            lsp = rf.lp_split(sp, wg, cap=cap)
+            got = host(ls["T"])
+        assert np.allclose(wg, w, rtol=1e-15)
+        assert ls["t"] == lsp["t"] and np.array_equal(got, lsp["T"]), (cap, ls["t"], lsp["t"])
+        if cap in (tie_rank + 20, tie_rank):
+            assert ls["t"] == tie_rank  # the cut falls in the tied group: it stays out whole
+        if cap == tie_rank + 41:
+            assert ls["t"] == tie_rank + 41  # just room for the whole group
+        print(f"cap {cap}: |T| {ls['t']} (above 2 tau: {above}, tied group of 41 after rank {tie_rank})")
