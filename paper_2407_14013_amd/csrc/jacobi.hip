@@ -39,17 +39,28 @@ __device__ inline void tournament_pair(int round, int w, int N, int& a, int& b) 
 // [app apq; apq aqq] (J[p][p] = J[q][q] = c, J[p][q] = s, J[q][p] = -s);
 // the identity when the entry is already negligible.
 // With x = aqq - app and y = 2 apq, the smaller root of t^2 + 2 (x / y) t - 1
-// is t = sgn(x) y / (|x| + sqrt(x^2 + y^2)), so |t| <= 1 (one square root,
-// one division and one reciprocal square root on the dependent chain).
+// is t = sgn(x) y / (|x| + sqrt(x^2 + y^2)), so |t| <= 1.
 __device__ inline bool jacobi_angle(double app, double aqq, double apq, double& c, double& s) {
     c = 1.0;
     s = 0.0;
     // negligible when |apq| <= eps sqrt(|app aqq|), tested on the squares
     if (!(apq * apq > 4.930380657631324e-32 * fabs(app * aqq)) || apq == 0.0) return false;
     const double x = aqq - app, y = 2.0 * apq;
-    const double h = sqrt(fma(x, x, y * y));
-    const double t = (x >= 0.0 ? y : -y) / (fabs(x) + h);
-    c = rsqrt(fma(t, t, 1.0));
+    // the hardware reciprocal and reciprocal square root refined by Newton
+    // steps on the dependent chain: t only steers the rotation (one step), but
+    // c must satisfy c^2 (1 + t^2) = 1 to working precision (two steps)
+    const double r2 = fma(x, x, y * y);
+    double rs = __builtin_amdgcn_rsq(r2);
+    rs = rs * fma(-0.5 * r2 * rs, rs, 1.5);
+    const double den = fabs(x) + r2 * rs;  // |x| + sqrt(x^2 + y^2)
+    double rd = __builtin_amdgcn_rcp(den);
+    rd = rd * fma(-den, rd, 2.0);
+    const double t = (x >= 0.0 ? y : -y) * rd;
+    const double u = fma(t, t, 1.0);
+    double rc = __builtin_amdgcn_rsq(u);
+    rc = rc * fma(-0.5 * u * rc, rc, 1.5);
+    rc = rc * fma(-0.5 * u * rc, rc, 1.5);  // two steps: c^2 u = 1 to rounding
+    c = rc;
     s = t * c;
     return true;
 }
