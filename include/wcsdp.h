@@ -478,7 +478,12 @@ enum {
                                bytes = E and Z read once each, 16 per constraint for the pair
                                index and the result; the per-constraint re-reads of Z's
                                columns are cache traffic and not counted) */
-    SDP_K_COUNT = 7
+    SDP_K_SANDWICH_LOWER = 7, /* FP64 operator at large n: the second product of E Y E as its lower
+                                 triangle (plus the ragged strip of rows below the last full
+                                 128-row block), E Y E being symmetric; n^2 (n + 1) flops and
+                                 the entries it writes as bytes.  The first product stays in
+                                 SDP_K_SANDWICH */
+    SDP_K_COUNT = 8
 };
 
 /*

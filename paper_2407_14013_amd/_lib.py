@@ -20,8 +20,8 @@ SDP_SOLVER_PCG, SDP_SOLVER_MINRES = 0, 1
 SDP_PREC_F64, SDP_PREC_F32, SDP_PREC_BF16 = 0, 1, 2
 SDP_REFINE_SWEEPS, SDP_REFINE_REPLACE = 0, 1
 SDP_K_A_APPLY, SDP_K_AT_APPLY, SDP_K_GEMM, SDP_K_NEWTON, SDP_K_SANDWICH = 0, 1, 2, 3, 4
-SDP_K_SAMPLED_YE, SDP_K_SAMPLED_DOTS = 5, 6
-SDP_K_COUNT = 7
+SDP_K_SAMPLED_YE, SDP_K_SAMPLED_DOTS, SDP_K_SANDWICH_LOWER = 5, 6, 7
+SDP_K_COUNT = 8
 
 STATUS_NAMES = {
     0: "SDP_OK",

@@ -36,7 +36,13 @@ constexpr size_t dgemm_lds(int bm, int bn) { return sizeof(double) * 2 * GBK * (
 // (symmetric rank-k updates); 2 op(A) and op(B) are triangular with
 // op(A)_ik = 0 for k < i and op(B)_kj = 0 for k < j (C = Z^T Z with Z lower
 // triangular): only the tiles that touch the upper triangle run, each from
-// k = max(its first row, its first column), and they are written whole.
+// k = max(its first row, its first column), and they are written whole;
+// 3 as 1 (BM == BN) from a 1-D grid of exactly the tiles on or below the
+// diagonal.  Workgroups go to the eight XCDs in turn by linear index, so
+// the 2-D grid of mode 1 hands the XCDs unequal shares of the working tiles
+// (76 against 48 for 31 x 31 tiles); mode 3 gives XCD j = id % 8 the
+// contiguous run of tiles starting at j P / 8 (row-major over the triangle),
+// which also keeps tiles that share an A panel on one XCD's L2.
 template <bool TA, bool TB, int BM, int BN, int EPI>
 __global__ __launch_bounds__(256) void dgemm_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
                                                     long lda, const double* __restrict__ B, long ldb, double beta,
@@ -44,8 +50,19 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int M, int N, int K, double 
                                                     long sB, long sC, int klast) {
     // split-K launches give the last z-slice the remainder of K
     if (klast > 0 && blockIdx.z == gridDim.z - 1) K = klast;
-    const int tile_m = blockIdx.x * BM;
-    const int tile_n = blockIdx.y * BN;
+    int bx = blockIdx.x, by = blockIdx.y;
+    if (tri == 3) {
+        const int P = gridDim.x, id = blockIdx.x, x8 = id & 7;
+        const int base = P >> 3, rem = P & 7;
+        const int t = x8 * base + min(x8, rem) + (id >> 3);
+        int x = static_cast<int>((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while (x * (x + 1) / 2 > t) --x;
+        while ((x + 1) * (x + 2) / 2 <= t) ++x;
+        bx = x;
+        by = t - x * (x + 1) / 2;
+    }
+    const int tile_m = bx * BM;
+    const int tile_n = by * BN;
     if (tri == 1 && tile_n > tile_m + BM - 1) return;
     A += blockIdx.z * sA;
     B += blockIdx.z * sB;
@@ -153,7 +170,7 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int M, int N, int K, double 
             for (int v = 0; v < 4; ++v) {
                 const int gi = tile_m + wm * (BM / 2) + a * 16 + (lane >> 4) + 4 * v;
                 const int gj = tile_n + wn * (BN / 2) + b * 16 + (lane & 15);
-                if (gi < M && gj < N && (tri != 1 || gi >= gj)) {
+                if (gi < M && gj < N && ((tri != 1 && tri != 3) || gi >= gj)) {
                     double* c = C + gi + (long)gj * ldc;
                     if constexpr (EPI == 0) *c = acc[a][b][v];
                     else if constexpr (EPI == 1) *c = alpha * acc[a][b][v];
@@ -266,6 +283,47 @@ void dgemm_lauum_upper(hipStream_t st, int n, const double* Z, long ldz, double*
     dgemm_launch<true, false>(st, dim3(cdiv(n, bt), cdiv(n, bt), 1), big, n, n, n, 1.0, Z, ldz, Z, ldz, 0.0, C, ldc,
                               2, 0, 0, 0, 0);
     WC_LAUNCH_CHECK();
+}
+
+bool dgemm_lower_pays(int n) { return (long)cdiv(n, GBIG) * cdiv(n, GBIG) >= 4L * 256; }
+
+// C = A B (n x n, plain operands) whose result is symmetric.  When the full
+// product would take 128 x 128 tiles, the first m0 = 128 floor(n / 128) rows
+// are computed as the T (T + 1) / 2 tiles on or below the diagonal of a T x T
+// tile grid, spread evenly over the XCDs (one pass over the CUs at n = 4000,
+// 62 tiles per XCD, where the full product takes two), writing row >= col
+// only; the ragged strip of rows m0 .. n-1 is a
+// separate product over all n columns, split over K since it has few tiles.
+void dgemm_lower(hipStream_t st, int n, int k, const double* A, long lda, const double* B, long ldb, double* C,
+                 long ldc, double* ws, long ws_len) {
+    if (n <= 0) return;
+    if (!dgemm_lower_pays(n) || k <= 0) {
+        dgemm(st, false, false, n, n, k, 1.0, A, lda, B, ldb, 0.0, C, ldc, false, 1, 0, 0, 0, ws, ws_len);
+        return;
+    }
+    const int T = n / GBIG, m0 = T * GBIG, ms = n - m0;
+    dgemm_launch<false, false>(st, dim3(T * (T + 1) / 2, 1, 1), true, m0, m0, k, 1.0, A, lda, B, ldb, 0.0, C, ldc, 3,
+                               0, 0, 0, 0);
+    WC_LAUNCH_CHECK();
+    if (ms == 0) return;
+    // the strip: splits K-slices of kc (the last klast), partial products in ws
+    int splits = static_cast<int>(std::min<long>(GEMM_SPLITS, ws != nullptr ? ws_len / ((long)ms * n) : 0));
+    if (k < 64) splits = 1;
+    if (splits >= 2) {
+        const int kc = static_cast<int>(round_up(cdiv(k, splits), GBK));
+        splits = cdiv(k, kc);
+        if (splits >= 2) {
+            dgemm_launch<false, false>(st, dim3(cdiv(ms, GBM), cdiv(n, GBN), splits), false, ms, n, kc, 1.0, A + m0,
+                                       lda, B, ldb, 0.0, ws, ms, 0, (long)kc * lda, kc, (long)ms * n,
+                                       k - (splits - 1) * kc);
+            WC_LAUNCH_CHECK();
+            hipLaunchKernelGGL(dgemm_reduce_kernel, dim3(cdiv((long)ms * n, 256)), dim3(256), 0, st, ms, n, splits, ws,
+                               1.0, 0.0, C + m0, ldc);
+            WC_LAUNCH_CHECK();
+            return;
+        }
+    }
+    dgemm(st, false, false, ms, n, k, 1.0, A + m0, lda, B, ldb, 0.0, C + m0, ldc);
 }
 
 // ---------------------------------------------------------------------------

@@ -92,6 +92,13 @@ void dgemm(hipStream_t st, bool ta, bool tb, int m, int n, int k, double alpha, 
            const double* B, long ldb, double beta, double* C, long ldc, bool lower_only = false, int batch = 1,
            long sA = 0, long sB = 0, long sC = 0, double* ws = nullptr, long ws_len = 0);
 long dgemm_splitk_ws();
+// C = A B for a product known to be symmetric (n x n, op = identity): the
+// entries with row >= col are written, others may or may not be.  Computes
+// only the lower triangle's tiles when dgemm_lower_pays(n) (large n), the
+// full product otherwise.  ws as for dgemm.
+bool dgemm_lower_pays(int n);
+void dgemm_lower(hipStream_t st, int n, int k, const double* A, long lda, const double* B, long ldb, double* C,
+                 long ldc, double* ws, long ws_len);
 
 // C = alpha op(A) B + beta C for a thin B (n <= 16 columns); returns false
 // (nothing launched) when the shape is not handled.  With a workspace of

@@ -309,6 +309,56 @@ void symlr(hipStream_t st, int n, int r, const double* U, const double* Q, long 
     WC_LAUNCH_CHECK();
 }
 
+// M <- L + L^T - diag(L) + sym(U Q^T) with L the lower triangle of M: one
+// workgroup per 32 x 32 tile on or below the diagonal (a linear index over the
+// tile triangle).  The tile's lower entries are updated in place (coalesced
+// down columns) and staged in LDS; their transposes go to the mirror tile
+// above the diagonal, again down columns.  A diagonal tile writes its strict
+// upper part from its own lower part, so no entry is written twice.
+__global__ __launch_bounds__(256) void symlr_lower_kernel(int n, int r, const double* __restrict__ U,
+                                                          const double* __restrict__ Q, long ldq,
+                                                          double* __restrict__ M, long ldm) {
+    __shared__ double tile[32][33];
+    const long t = blockIdx.x;
+    // tile row ti >= tile column tj with t = ti (ti + 1) / 2 + tj
+    int ti = static_cast<int>((sqrt(8.0 * static_cast<double>(t) + 1.0) - 1.0) * 0.5);
+    while ((long)ti * (ti + 1) / 2 > t) --ti;
+    while ((long)(ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    const int tj = static_cast<int>(t - (long)ti * (ti + 1) / 2);
+    const int i0 = ti * 32, j0 = tj * 32;
+    const int li = threadIdx.x & 31, lc = threadIdx.x >> 5;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int lj = lc + 8 * q;
+        const int gi = i0 + li, gj = j0 + lj;
+        double v = 0.0;
+        if (gi < n && gj <= gi) {
+            double s = 0.0;
+            for (int b = 0; b < r; ++b)
+                s += U[gi + (long)b * n] * Q[gj + (long)b * ldq] + Q[gi + (long)b * ldq] * U[gj + (long)b * n];
+            v = M[gi + (long)gj * ldm] + 0.5 * s;
+            M[gi + (long)gj * ldm] = v;
+        }
+        tile[lj][li] = v;  // tile[c][a]: the entry (i0 + a, j0 + c)
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int lj = lc + 8 * q;
+        // entry (j0 + li, i0 + lj) above the diagonal = entry (i0 + lj, j0 + li)
+        const int ro = j0 + li, co = i0 + lj;
+        if (co < n && ro < co) M[ro + (long)co * ldm] = tile[li][lj];
+    }
+}
+
+void symlr_lower(hipStream_t st, int n, int r, const double* U, const double* Q, long ldq, double* M, long ldm) {
+    if (n <= 0) return;
+    const long T = cdiv(n, 32);
+    hipLaunchKernelGGL(symlr_lower_kernel, dim3(static_cast<unsigned>(T * (T + 1) / 2)), dim3(256), 0, st, n, r, U, Q,
+                       ldq, M, ldm);
+    WC_LAUNCH_CHECK();
+}
+
 // AQ[i, c] (row-major, pitch ldaq) from F_i = G_w^T A_i Q (n x r, read with strides):
 // row i of script-A script-Q is script-Q^T svec(A_i) = [svec(F_top); sqrt2 vec(F_bot)].
 __global__ void f_to_aq_kernel(int m, int n, int r, const double* __restrict__ F, long si, long sab,

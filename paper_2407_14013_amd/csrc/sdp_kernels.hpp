@@ -26,6 +26,8 @@ void v_to_h(hipStream_t st, int n, int r, const double* v, double* Hm);
 void f_to_v(hipStream_t st, int n, int r, const double* F, long ldf, const double* vin, const double* sig, double t2,
             double* out);
 void symlr(hipStream_t st, int n, int r, const double* U, const double* Q, long ldq, double* M, long ldm, double beta);
+// M = the symmetric matrix whose lower triangle M holds, plus sym(U Q^T) (r may be 0)
+void symlr_lower(hipStream_t st, int n, int r, const double* U, const double* Q, long ldq, double* M, long ldm);
 // AQ rows from F_i = G_w^T A_i Q stored at F[i * si + (a + n b) * sab].
 void f_to_aq(hipStream_t st, int m, int n, int r, const double* F, long si, long sab, double* AQ, long ldaq);
 // Sparse constraint kind (entries on and above the diagonal per constraint): A(M), A^T(u) by positions, AQ rows.

@@ -116,6 +116,22 @@ static void gemm(sdp_ctx* c, bool ta, bool tb, int m, int n, int k, double alpha
     prof_end(c, SDP_K_GEMM, e, 8.0 * ((double)m * k + (double)k * n + 2.0 * (double)m * n));
 }
 
+// M = E T for the symmetric E Y E (T = Y E): at large n only the lower
+// triangle (sym_finish completes it), else the full product.
+static void gemm_sym(sdp_ctx* c, const double* E, const double* T, double* M) {
+    const int n = c->n;
+    hipEvent_t e;
+    prof_begin(c, SDP_K_GEMM, &e);
+    dgemm_lower(c->st, n, n, E, n, T, n, M, n, c->gemm_ws, static_cast<long>(c->gemm_ws.n));
+    prof_end(c, SDP_K_GEMM, e, 8.0 * 3.0 * (double)n * n);
+}
+// M += sym(U Q^T) (rank r, U n x r, Q = G_w[:, :r]; r may be 0) after gemm_sym,
+// mirroring its lower triangle when that is all it wrote.
+static void sym_finish(sdp_ctx* c, int r, const double* U, double* M) {
+    if (dgemm_lower_pays(c->n)) symlr_lower(c->st, c->n, r, U, c->Gw, c->n, M, c->n);
+    else if (r > 0) symlr(c->st, c->n, r, U, c->Gw, c->n, M, c->n, 1.0);
+}
+
 // ---- setup ---------------------------------------------------------------------------------
 static void alloc_work(sdp_ctx* c) {
     const int n = c->n, m = c->m;
@@ -872,13 +888,15 @@ void newton_apply(sdp_ctx* c, const double* in, double* out) {
     prof_begin(c, SDP_K_SANDWICH, &es);
     gemm(c, false, false, n, n, n, 1.0, c->Y, n, c->E, n, 0.0, c->T1, n);
     prof_end(c, SDP_K_SANDWICH, es, sw_bytes);
-    prof_begin(c, SDP_K_SANDWICH, &es);
-    gemm(c, false, false, n, n, n, 1.0, c->E, n, c->T1, n, 0.0, c->Mm, n);
-    prof_end(c, SDP_K_SANDWICH, es, sw_bytes);
+    // E (Y E) is symmetric: at large n only its lower triangle is computed
+    const bool lower = dgemm_lower_pays(n);
+    prof_begin(c, lower ? SDP_K_SANDWICH_LOWER : SDP_K_SANDWICH, &es);
+    gemm_sym(c, c->E, c->T1, c->Mm);
+    prof_end(c, lower ? SDP_K_SANDWICH_LOWER : SDP_K_SANDWICH, es, lower ? 8.0 * 0.5 * nn : sw_bytes);
     // Mm += sym(U Q^T) (after the products, which then need not read Mm)
     v_to_h(st, n, r, v, c->Hm);
     gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
-    symlr(st, n, r, c->U, c->Gw, n, c->Mm, n, 1.0);
+    sym_finish(c, r, c->U, c->Mm);
     // top = A(Mm)
     a_apply(c, c->Mm, out, 1.0, 0.0);
     // bottom = Q^T svec(Y) - tau^2 Sigma v, with Q^T svec(Y) read from F = G_w^T Y Q
@@ -1074,11 +1092,11 @@ static void recover(sdp_ctx* c, const double* x, const double* Ct, double* dX, d
     at_apply(c, x, c->Y);
     axpby(st, nn, -t2, Ct, 1.0, c->Y);
     gemm(c, false, false, n, n, n, 1.0, c->Y, n, c->E, n, 0.0, c->T1, n);
-    gemm(c, false, false, n, n, n, 1.0, c->E, n, c->T1, n, 0.0, dX, n);
+    gemm_sym(c, c->E, c->T1, dX);
     v_to_h(st, n, r, x + m, c->Hm);
     gemm(c, false, false, n, r, n, 1.0, c->Gw, n, c->Hm, n, 0.0, c->U, n);
-    symlr(st, n, r, c->U, c->Gw, n, dX, n, 1.0);
-    symmetrize(st, n, dX, n);
+    sym_finish(c, r, c->U, dX);
+    if (!dgemm_lower_pays(n)) symmetrize(st, n, dX, n);
 }
 
 // Indefinite PCG (Definition pcg, Corollary pcg) on K x = g from the iterate
@@ -1294,7 +1312,8 @@ int inner_solve(sdp_ctx* c, const double* bt, const double* Ct, const double* ct
     double* sc = c->sc;
     // right-hand side g = [b~ + tau^2 A(E C~ E); tau^2 Q^T c]
     gemm(c, false, false, n, n, n, 1.0, Ct, n, c->E, n, 0.0, c->T1, n);
-    gemm(c, false, false, n, n, n, 1.0, c->E, n, c->T1, n, 0.0, c->Mm, n);
+    gemm_sym(c, c->E, c->T1, c->Mm);
+    sym_finish(c, 0, nullptr, c->Mm);
     a_apply(c, c->Mm, c->vg, t2, 0.0);
     axpby(st, m, 1.0, bt, 1.0, c->vg);
     gemm(c, false, false, n, r, n, 1.0, Ct, n, c->Gw, n, 0.0, c->YQ, n);

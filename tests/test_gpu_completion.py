@@ -9,7 +9,9 @@ eigensolver at this size:
 * the GPU's eigen-split (Jacobi on n = 4000): every eigenvalue, r, tau and
   beta (eq. EQSigdef and the rank and median rules);
 * the operator of eq. augsys on u alone, sampled at 256 constraints, against
-  A(E A^T(u) E) evaluated from the closed-form E column by column;
+  A(E A^T(u) E) evaluated from the closed-form E column by column, and again
+  at constraints picked at the tile edges of the dense products (the lower
+  triangle of E (Y E), its ragged strip and its mirror);
 * the preconditioner of Section 6 (never formed as AQ on the GPU for this
   constraint kind) by the residual of P z = x, with P z computed as
   K z - [A(E A^T(z_u) E) - beta z_u; 0] from the GPU's K and the closed-form E.
@@ -101,6 +103,44 @@ def test_operator_top_block_sampled(full):
     ref = np.array([Ecols[:, where[j]] @ YE[:, where[k]] for j, k in jk[pick]])
     err = np.abs(got[pick] - ref).max() / np.abs(ref).max()
     print(f"sampled top block: max relative error {err:.1e}")
+    assert err <= 1e-10
+
+
+def test_operator_top_block_at_tile_edges(full):
+    """The dense products compute E (Y E) as its lower triangle in 128-row tiles
+    plus a ragged strip of rows 3968..3999, then mirror it in 32 x 32 tiles.
+    The pattern lists j <= k, so every off-diagonal constraint reads the
+    mirrored half.  Constraints in that strip, inside diagonal tiles, on the
+    diagonal and across the mirror's tile edges, against the closed form."""
+    p, sp, e, jk, ctx = full
+    n, m = p["n"], p["m"]
+    N = ctx.aug_dim()
+    rng = np.random.default_rng(7)
+    xin = np.zeros(N)
+    xin[:m] = rng.standard_normal(m)
+    got = host(ctx.newton_apply(dev(xin)))[:m]
+    j, k = jk[:, 0], jk[:, 1]
+    m0 = (n // 128) * 128
+    groups = {
+        "strip": np.flatnonzero(np.maximum(j, k) >= m0),
+        "diag128": np.flatnonzero((j // 128 == k // 128) & (j != k)),
+        "diagonal": np.flatnonzero(j == k),
+        "tile32_edge": np.flatnonzero((np.abs(j // 32 - k // 32) == 1)),
+    }
+    pick = []
+    for name, idx in groups.items():
+        assert idx.size > 0, name
+        pick.append(rng.choice(idx, size=min(120, idx.size), replace=False))
+    pick = np.unique(np.concatenate(pick))
+    Y = sparse_at(n, jk, xin[:m])
+    Vo = sp["V"]
+    cols = np.unique(jk[pick].ravel())
+    Ecols = Vo @ (e[:, None] * Vo[cols, :].T)
+    where = {c: i for i, c in enumerate(cols)}
+    YE = Y @ Ecols
+    ref = np.array([Ecols[:, where[a]] @ YE[:, where[b]] for a, b in jk[pick]])
+    err = np.abs(got[pick] - ref).max() / np.abs(ref).max()
+    print(f"top block at tile edges ({pick.size} constraints): max relative error {err:.1e}")
     assert err <= 1e-10
 
 
