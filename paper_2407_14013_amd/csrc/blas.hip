@@ -307,7 +307,7 @@ void dgemm_lower(hipStream_t st, int n, int k, const double* A, long lda, const 
     WC_LAUNCH_CHECK();
     if (ms == 0) return;
     // the strip: splits K-slices of kc (the last klast), partial products in ws
-    int splits = static_cast<int>(std::min<long>(GEMM_SPLITS, ws != nullptr ? ws_len / ((long)ms * n) : 0));
+    int splits = static_cast<int>(std::min<long>(2 * GEMM_SPLITS, ws != nullptr ? ws_len / ((long)ms * n) : 0));
     if (k < 64) splits = 1;
     if (splits >= 2) {
         const int kc = static_cast<int>(round_up(cdiv(k, splits), GBK));

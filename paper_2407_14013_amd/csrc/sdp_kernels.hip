@@ -311,14 +311,18 @@ void symlr(hipStream_t st, int n, int r, const double* U, const double* Q, long 
 
 // M <- L + L^T - diag(L) + sym(U Q^T) with L the lower triangle of M: one
 // workgroup per 32 x 32 tile on or below the diagonal (a linear index over the
-// tile triangle).  The tile's lower entries are updated in place (coalesced
-// down columns) and staged in LDS; their transposes go to the mirror tile
-// above the diagonal, again down columns.  A diagonal tile writes its strict
-// upper part from its own lower part, so no entry is written twice.
+// tile triangle).  The tile's lower entries are read first (four per thread,
+// in flight together), the rank columns of U and Q at the tile's rows and
+// columns are staged in LDS eight at a time, then the entries are updated in
+// place (coalesced down columns) and staged in LDS; their transposes go to
+// the mirror tile above the diagonal, again down columns.  A diagonal tile
+// writes its strict upper part from its own lower part, so no entry is
+// written twice.
 __global__ __launch_bounds__(256) void symlr_lower_kernel(int n, int r, const double* __restrict__ U,
                                                           const double* __restrict__ Q, long ldq,
                                                           double* __restrict__ M, long ldm) {
     __shared__ double tile[32][33];
+    __shared__ double rk[4][8][32];  // U rows, Q rows, U columns, Q columns of the tile
     const long t = blockIdx.x;
     // tile row ti >= tile column tj with t = ti (ti + 1) / 2 + tj
     int ti = static_cast<int>((sqrt(8.0 * static_cast<double>(t) + 1.0) - 1.0) * 0.5);
@@ -327,19 +331,45 @@ __global__ __launch_bounds__(256) void symlr_lower_kernel(int n, int r, const do
     const int tj = static_cast<int>(t - (long)ti * (ti + 1) / 2);
     const int i0 = ti * 32, j0 = tj * 32;
     const int li = threadIdx.x & 31, lc = threadIdx.x >> 5;
+    const int gi = i0 + li;
+    double v[4], s[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int gj = j0 + lc + 8 * q;
+        v[q] = (gi < n && gj <= gi) ? M[gi + (long)gj * ldm] : 0.0;
+        s[q] = 0.0;
+    }
+    for (int b0 = 0; b0 < r; b0 += 8) {
+        const int nb = min(8, r - b0);
+#pragma unroll
+        for (int e4 = 0; e4 < 4; ++e4) {
+            const int e = threadIdx.x + 256 * e4;  // e4 = which array, e>>5 & 7 = rank column, e & 31 = offset
+            const int b = (e >> 5) & 7, l = e & 31;
+            const int g = (e4 < 2 ? i0 : j0) + l;
+            double val = 0.0;
+            if (b < nb && g < n) val = (e4 & 1) ? Q[g + (long)(b0 + b) * ldq] : U[g + (long)(b0 + b) * n];
+            rk[e4][b][l] = val;
+        }
+        __syncthreads();
+        for (int b = 0; b < nb; ++b) {
+            const double ur = rk[0][b][li], qr = rk[1][b][li];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int lj = lc + 8 * q;
+                s[q] += ur * rk[3][b][lj] + qr * rk[2][b][lj];
+            }
+        }
+        __syncthreads();
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int lj = lc + 8 * q;
-        const int gi = i0 + li, gj = j0 + lj;
-        double v = 0.0;
+        const int gj = j0 + lj;
         if (gi < n && gj <= gi) {
-            double s = 0.0;
-            for (int b = 0; b < r; ++b)
-                s += U[gi + (long)b * n] * Q[gj + (long)b * ldq] + Q[gi + (long)b * ldq] * U[gj + (long)b * n];
-            v = M[gi + (long)gj * ldm] + 0.5 * s;
-            M[gi + (long)gj * ldm] = v;
+            v[q] += 0.5 * s[q];
+            M[gi + (long)gj * ldm] = v[q];
         }
-        tile[lj][li] = v;  // tile[c][a]: the entry (i0 + a, j0 + c)
+        tile[lj][li] = v[q];  // tile[c][a]: the entry (i0 + a, j0 + c)
     }
     __syncthreads();
 #pragma unroll
