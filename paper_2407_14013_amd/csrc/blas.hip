@@ -3,6 +3,7 @@
 #include <hip/hip_ext.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "common.hpp"
 #include "launch_plan.hpp"
@@ -99,6 +100,26 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int M, int N, int K, double 
         else { j = idx % BN; k = idx / BN; }
     };
     double ra[QA], rb[QB];
+    // Interior tiles with whole K steps load without bounds checks.  Element
+    // q of a thread sits a fixed multiple of q leading dimensions past its
+    // element 0 (256 is a multiple of BM, BN and GBK), so each load is a
+    // uniform base (step base plus that multiple) plus one per-thread offset
+    // fixed for the whole loop; the checked form puts every load behind its
+    // own branch.
+    static_assert(256 % BM == 0 && 256 % BN == 0 && 256 % GBK == 0, "tile edges must divide 256");
+    const bool interior = tile_m + BM <= M && tile_n + BN <= N && K % GBK == 0 &&
+                          (long)GBK * (lda > ldb ? lda : ldb) + 256 < (1L << 27);
+    const long qsa = (TA ? 256 / GBK : 256 / BM) * lda, qsb = (TB ? 256 / BN : 256 / GBK) * ldb;
+    const int offa = TA ? tid % GBK + (tid / GBK) * static_cast<int>(lda) : tid % BM + (tid / BM) * static_cast<int>(lda);
+    const int offb = TB ? tid % BN + (tid / BN) * static_cast<int>(ldb) : tid % GBK + (tid / GBK) * static_cast<int>(ldb);
+    auto load_interior = [&](int k0) {
+        const double* a0 = TA ? A + k0 + (long)tile_m * lda : A + tile_m + (long)k0 * lda;
+        const double* b0 = TB ? B + tile_n + (long)k0 * ldb : B + k0 + (long)tile_n * ldb;
+#pragma unroll
+        for (int q = 0; q < QA; ++q) ra[q] = (a0 + q * qsa)[offa];
+#pragma unroll
+        for (int q = 0; q < QB; ++q) rb[q] = (b0 + q * qsb)[offb];
+    };
     auto load = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
@@ -136,31 +157,41 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int M, int N, int K, double 
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-    load(0);
-    store(0);
-    __syncthreads();
-    int buf = 0;
-    for (int k0 = 0; k0 < K; k0 += GBK) {
-        const bool more = k0 + GBK < K;
-        if (more) load(k0 + GBK);
-#pragma unroll
-        for (int kk = 0; kk < GBK; kk += 4) {
-            const int kr = kk + (lane >> 4);
-            double av[TM], bv[TN];
-#pragma unroll
-            for (int a = 0; a < TM; ++a) av[a] = As[buf][kr][wm * (BM / 2) + a * 16 + (lane & 15)];
-#pragma unroll
-            for (int b = 0; b < TN; ++b) bv[b] = Bs[buf][kr][wn * (BN / 2) + b * 16 + (lane & 15)];
-#pragma unroll
-            for (int a = 0; a < TM; ++a)
-#pragma unroll
-                for (int b = 0; b < TN; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-        }
-        if (more) store(buf ^ 1);
+    // the K loop, instantiated once per load form so that each keeps only its
+    // own loop-invariant addresses in registers
+    auto k_loop = [&](auto fast) {
+        if constexpr (decltype(fast)::value) load_interior(0);
+        else load(0);
+        store(0);
         __syncthreads();
-        buf ^= 1;
-    }
+        int buf = 0;
+        for (int k0 = 0; k0 < K; k0 += GBK) {
+            const bool more = k0 + GBK < K;
+            if (more) {
+                if constexpr (decltype(fast)::value) load_interior(k0 + GBK);
+                else load(k0 + GBK);
+            }
+#pragma unroll
+            for (int kk = 0; kk < GBK; kk += 4) {
+                const int kr = kk + (lane >> 4);
+                double av[TM], bv[TN];
+#pragma unroll
+                for (int a = 0; a < TM; ++a) av[a] = As[buf][kr][wm * (BM / 2) + a * 16 + (lane & 15)];
+#pragma unroll
+                for (int b = 0; b < TN; ++b) bv[b] = Bs[buf][kr][wn * (BN / 2) + b * 16 + (lane & 15)];
+#pragma unroll
+                for (int a = 0; a < TM; ++a)
+#pragma unroll
+                    for (int b = 0; b < TN; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+            }
+            if (more) store(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    };
+    if (interior) k_loop(std::true_type{});
+    else k_loop(std::false_type{});
 
 #pragma unroll
     for (int a = 0; a < TM; ++a)

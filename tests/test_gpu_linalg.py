@@ -17,11 +17,14 @@ EPS = np.finfo(np.float64).eps
 @pytest.mark.parametrize("tb", ["N", "T"])
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1), (17, 33, 9), (64, 64, 64), (130, 67, 95), (200, 200, 200), (65, 1, 129),
                                    (200, 3, 200), (301, 16, 77), (5000, 2, 300), (4000, 4, 4000), (300, 10, 1000),
-                                   (77, 3, 20000), (130, 70, 1001), (200, 200, 333), (64, 64, 97)])
+                                   (77, 3, 20000), (130, 70, 1001), (200, 200, 333), (64, 64, 97),
+                                   (1000, 700, 512), (129, 200, 48)])
 def test_dgemm(ta, tb, m, n, k):
-    # (200, 200, 200) and the last three take the split-K path of few-tile
-    # products; the last three with a ragged last slice (K = 1001: 7 x 128 +
-    # 105; K = 333: 6 x 48 + 45; K = 97: 3 x 32 + 1)
+    # (200, 200, 200), (64, 64, 97), (130, 70, 1001) and (200, 200, 333) take
+    # the split-K path of few-tile products, the last three with a ragged last
+    # slice (K = 1001: 7 x 128 + 105; K = 333: 6 x 48 + 45; K = 97: 3 x 32 +
+    # 1); (1000, 700, 512) and (129, 200, 48) mix interior tiles (whole K
+    # steps, loads without bounds checks) with ragged edge tiles
     rng = np.random.default_rng(m * 1000 + n * 10 + k)
     A = rng.standard_normal((k, m) if ta == "T" else (m, k))
     B = rng.standard_normal((n, k) if tb == "T" else (k, n))
@@ -37,10 +40,11 @@ def test_dgemm(ta, tb, m, n, k):
 
 @pytest.mark.parametrize("ta", ["N", "T"])
 @pytest.mark.parametrize("tb", ["N", "T"])
-@pytest.mark.parametrize("m,n,k", [(4096, 4096, 64), (4100, 4097, 129)])
+@pytest.mark.parametrize("m,n,k", [(4096, 4096, 64), (4100, 4097, 129), (4100, 4097, 160)])
 def test_dgemm_large_tiles(ta, tb, m, n, k):
     # C = A B with alpha = 1, beta = 0 and at least 1024 tiles of 128 x 128:
-    # the large-tile kernel, including ragged row, column and K edges
+    # the large-tile kernel, including ragged row, column and K edges; with
+    # K = 64 or 160 the interior tiles load without bounds checks
     rng = np.random.default_rng(m + n + k)
     A = rng.standard_normal((k, m) if ta == "T" else (m, k))
     B = rng.standard_normal((n, k) if tb == "T" else (k, n))
