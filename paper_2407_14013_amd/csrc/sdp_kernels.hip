@@ -935,42 +935,40 @@ void aq_bottom(hipStream_t st, int d, const double* a, const double* sig, double
 
 // ---- PCG scalars (device-resident) ------------------------------------------
 // sc[0] = <r,z>, sc[1] = <p,Kp>, sc[2] = alpha, sc[3] = beta, sc[4] = ||r_u||^2, sc[5] = <r,z>_new
-__global__ void pcg_alpha_kernel(double* sc) { sc[2] = sc[0] / sc[1]; }
-__global__ void pcg_beta_kernel(double* sc) {
-    sc[3] = sc[5] / sc[0];
-    sc[0] = sc[5];
-}
+// PCG scalars in sc: [0] <r, z> of the previous iterate, [1] <p, K p>,
+// [2] alpha, [3] beta, [5] <r, z> of the current iterate.  The scalar steps
+// run inside the vector updates: every thread forms alpha (beta) from sc, and
+// thread 0 records it; the x / r update also moves [5] to [0], which none of
+// its threads reads, before the next <r, z> overwrites [5].
 // x += alpha p; r_u -= alpha (Kp)_u; r_v = 0.  The bottom block of the residual
 // is identically zero in exact arithmetic (Proposition indefpcg / Section 6);
 // keeping it at zero stops its rounding noise from entering <r, z>.
 __global__ void pcg_xr_kernel(long N, long m, double* __restrict__ x, double* __restrict__ r,
-                              const double* __restrict__ p, const double* __restrict__ Kp,
-                              const double* __restrict__ sc) {
+                              const double* __restrict__ p, const double* __restrict__ Kp, double* __restrict__ sc) {
     long i = blockIdx.x * 256L + threadIdx.x;
+    const double rz = sc[5];
+    const double a = rz / sc[1];
+    if (i == 0) {
+        sc[2] = a;
+        sc[0] = rz;
+    }
     if (i >= N) return;
-    double a = sc[2];
     x[i] += a * p[i];
     r[i] = (i < m) ? r[i] - a * Kp[i] : 0.0;
 }
-__global__ void pcg_p_kernel(long N, double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ sc) {
+// p = z + beta p with beta = <r, z>_new / <r, z>_old
+__global__ void pcg_p_kernel(long N, double* __restrict__ p, const double* __restrict__ z, double* __restrict__ sc) {
     long i = blockIdx.x * 256L + threadIdx.x;
+    const double b = sc[5] / sc[0];
+    if (i == 0) sc[3] = b;
     if (i >= N) return;
-    p[i] = z[i] + sc[3] * p[i];
+    p[i] = z[i] + b * p[i];
 }
-void pcg_alpha(hipStream_t st, double* sc) {
-    hipLaunchKernelGGL(pcg_alpha_kernel, dim3(1), dim3(1), 0, st, sc);
-    WC_LAUNCH_CHECK();
-}
-void pcg_beta(hipStream_t st, double* sc) {
-    hipLaunchKernelGGL(pcg_beta_kernel, dim3(1), dim3(1), 0, st, sc);
-    WC_LAUNCH_CHECK();
-}
-void pcg_xr(hipStream_t st, long N, long m, double* x, double* r, const double* p, const double* Kp,
-            const double* sc) {
+void pcg_xr(hipStream_t st, long N, long m, double* x, double* r, const double* p, const double* Kp, double* sc) {
     hipLaunchKernelGGL(pcg_xr_kernel, g1(N), dim3(256), 0, st, N, m, x, r, p, Kp, sc);
     WC_LAUNCH_CHECK();
 }
-void pcg_p(hipStream_t st, long N, double* p, const double* z, const double* sc) {
+void pcg_p(hipStream_t st, long N, double* p, const double* z, double* sc) {
     hipLaunchKernelGGL(pcg_p_kernel, g1(N), dim3(256), 0, st, N, p, z, sc);
     WC_LAUNCH_CHECK();
 }

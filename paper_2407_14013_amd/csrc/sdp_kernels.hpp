@@ -67,10 +67,8 @@ void corrector_h(hipStream_t st, int n, const double* Pm, const double* dv, doub
 void rho_bottom(hipStream_t st, int d, const double* h, const double* a, const double* sig, double t2,
                 const double* zv, double* out);
 void aq_bottom(hipStream_t st, int d, const double* a, const double* sig, double t2, const double* v, double* out);
-void pcg_alpha(hipStream_t st, double* sc);
-void pcg_beta(hipStream_t st, double* sc);
-void pcg_xr(hipStream_t st, long N, long m, double* x, double* r, const double* p, const double* Kp,
-            const double* sc);
-void pcg_p(hipStream_t st, long N, double* p, const double* z, const double* sc);
+// PCG updates with their scalar steps folded in (sc layout in sdp_kernels.hip)
+void pcg_xr(hipStream_t st, long N, long m, double* x, double* r, const double* p, const double* Kp, double* sc);
+void pcg_p(hipStream_t st, long N, double* p, const double* z, double* sc);
 
 }  // namespace wc

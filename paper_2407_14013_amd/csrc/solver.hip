@@ -1138,7 +1138,7 @@ static PcgOut pcg_loop(sdp_ctx* c, bool lowp, const double* g, double* x, double
     fill(st, d, c->vr + m, 0.0);
     precond_apply(c, c->vr, c->vz);
     copy(st, N, c->vz, c->vp);
-    dot(st, N, c->vr, c->vz, sc + 0, c->part);
+    dot(st, N, c->vr, c->vz, sc + 5, c->part);
     dot(st, m, c->vr, c->vr, sc + 4, c->part);
     fetch(c, sc + 4, 1);
     PcgOut o;
@@ -1159,8 +1159,7 @@ static PcgOut pcg_loop(sdp_ctx* c, bool lowp, const double* g, double* x, double
         if (!have_kp) K(c->vp, c->vKp);
         have_kp = false;
         dot(st, N, c->vp, c->vKp, sc + 1, c->part);
-        pcg_alpha(st, sc);
-        pcg_xr(st, N, m, x, c->vr, c->vp, c->vKp, sc);
+        pcg_xr(st, N, m, x, c->vr, c->vp, c->vKp, sc);  // alpha = sc[5] / sc[1]; sc[0] = sc[5]
         bool restart = false;
         if (do_rep) {
             // the updated residual replaced by g - K x in FP64 (bottom block zero)
@@ -1181,16 +1180,15 @@ static PcgOut pcg_loop(sdp_ctx* c, bool lowp, const double* g, double* x, double
         }
         precond_apply(c, c->vr, c->vz);
         dot(st, N, c->vr, c->vz, sc + 5, c->part);
-        pcg_beta(st, sc);
         if (restart) copy(st, N, c->vz, c->vp);
-        else pcg_p(st, N, c->vp, c->vz, sc);
+        else pcg_p(st, N, c->vp, c->vz, sc);  // beta = sc[5] / sc[0]
         ++o.it;
         if (c->opt.verbose >= 2) {
             dot(st, d, c->vr + m, c->vr + m, sc + 6, c->part);
             fetch(c, sc, 7);
             fprintf(stderr, "[wcsdp]   pcg%s %d |r_u| %.3e |r_v| %.3e rz %.3e pKp %.3e alpha %.3e beta %.3e\n",
-                    lowp ? "(lp)" : "", o.it, std::sqrt(c->pin[4]), std::sqrt(c->pin[6]), c->pin[0], c->pin[1],
-                    c->pin[2], c->pin[3]);
+                    lowp ? "(lp)" : "", o.it, std::sqrt(c->pin[4]), std::sqrt(c->pin[6]), c->pin[5], c->pin[1],
+                    c->pin[2], restart ? 0.0 : c->pin[3]);
         }
         // |r_u|^2 to the host; while it travels and the host waits, the GPU
         // already runs the next iteration's operator product on the new p (it
