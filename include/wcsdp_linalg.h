@@ -36,6 +36,20 @@ int32_t wc_dgemm(void* stream, char transa, char transb, int32_t m, int32_t n, i
                  const double* A, int32_t lda, const double* B, int32_t ldb, double beta, double* C, int32_t ldc);
 
 /*
+ * C = A B (n x n; A n x k, B k x n, column-major, no transposes) where the
+ * caller knows the product to be symmetric -- the second product E (Y E) of
+ * the augmented operator's E Y E (Section 5), with E and Y symmetric.  Every
+ * entry with row >= col is written; entries above the diagonal may or may not
+ * be.  For n >= 3969 only the 128 x 128 tiles on or below the diagonal of the
+ * first 128 floor(n / 128) rows are computed (spread evenly over the XCDs),
+ * plus the rows below them; smaller n take the full product.  A temporary
+ * workspace; the stream is synchronised before returning.  Returns 0, or -1
+ * with the reason in sdp_last_error() for bad sizes.
+ */
+int32_t wc_dgemm_sym_lower(void* stream, int32_t n, int32_t k, const double* A, int32_t lda, const double* B,
+                           int32_t ldb, double* C, int32_t ldc);
+
+/*
  * y = alpha A x + beta y for a symmetric d x d matrix A held in full
  * (column-major, lda even, A 16-byte aligned): only one triangle is read,
  * half the bytes of a general product -- the preconditioner applies C^{-1}

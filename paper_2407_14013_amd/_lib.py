@@ -201,6 +201,8 @@ _SIGNATURES = [
                                     C.POINTER(C.c_double)]),
     ("wc_dgemm", C.c_int32, [C.c_void_p, C.c_char, C.c_char, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_void_p,
                              C.c_int32, C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_int32]),
+    ("wc_dgemm_sym_lower", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                       C.c_int32, C.c_void_p, C.c_int32]),
     ("wc_dpotrf", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     ("wc_dtrtri", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
     ("wc_dlanczos_min_eig", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32,

@@ -398,6 +398,20 @@ int32_t wc_dgemm(void* stream, char transa, char transb, int32_t m, int32_t n, i
     });
 }
 
+int32_t wc_dgemm_sym_lower(void* stream, int32_t n, int32_t k, const double* A, int32_t lda, const double* B,
+                           int32_t ldb, double* C, int32_t ldc) {
+    return guarded_la([&]() {
+        wc::require(n >= 0 && k >= 0, "negative dimension");
+        wc::require(lda >= std::max(1, n) && ldb >= std::max(1, k) && ldc >= std::max(1, n), "leading dimension too small");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        wc::DevBuf<double> ws;
+        ws.alloc(wc::dgemm_splitk_ws());
+        wc::dgemm_lower(st, n, k, A, lda, B, ldb, C, ldc, ws.get(), static_cast<long>(ws.n));
+        WC_HIP(hipStreamSynchronize(st));
+        return (int32_t)0;
+    });
+}
+
 int32_t wc_dsymv(void* stream, int32_t d, double alpha, const double* A, int32_t lda, const double* x, double beta,
                  double* y) {
     return guarded_la([&]() {

@@ -66,6 +66,17 @@ def dgemm(transa: str, transb: str, alpha, A: torch.Tensor, B: torch.Tensor, bet
     return Cm
 
 
+def dgemm_sym_lower(A: torch.Tensor, B: torch.Tensor, Cm: torch.Tensor | None = None):
+    """The entries with row >= col of C = A B (n x n, column-major buffers as in to_dev), for products known
+    to be symmetric; entries above the diagonal are left as they are or overwritten."""
+    k, n = A.shape  # A is n x k column-major
+    assert tuple(B.shape) == (n, k), "B must be k x n"
+    if Cm is None:
+        Cm = torch.zeros((n, n), dtype=torch.float64, device=A.device)
+    _chk(L.lib().wc_dgemm_sym_lower(_stream_ptr(), n, k, _p(A), n, _p(B), k, _p(Cm), n))
+    return Cm
+
+
 def dpotrf(A: torch.Tensor):
     n = A.shape[0]
     info = C.c_int32()

@@ -55,6 +55,26 @@ def test_dgemm_large_tiles(ta, tb, m, n, k):
     assert err <= 4 * k * EPS * np.abs(A).max() * np.abs(B).max()
 
 
+@pytest.mark.parametrize("n,k", [(1000, 200), (3969, 96), (4000, 160), (4096, 64), (4100, 300), (4500, 128)])
+def test_dgemm_sym_lower(n, k):
+    # every entry with row >= col of A B: the full product below n = 3969;
+    # above it the tiles on or below the diagonal of the first 128 floor(n/128)
+    # rows from the XCD-balanced 1-D grid (496 tiles at n = 3969 and 4000, 528
+    # at 4096 with no ragged strip, 630 at 4500: more than one pass) and the
+    # strip of the remaining rows (1 row at 3969, 32 at 4000, 4 at 4100)
+    rng = np.random.default_rng(n + k)
+    A = rng.standard_normal((n, k))
+    B = rng.standard_normal((k, n))
+    ref = A @ B
+    Cd = la.to_dev(np.full((n, n), np.nan))
+    la.dgemm_sym_lower(la.to_dev(A), la.to_dev(B), Cd)
+    got = la.from_dev(Cd)
+    low = np.tril_indices(n)
+    err = np.abs(got[low] - ref[low]).max()
+    assert np.isfinite(got[low]).all()
+    assert err <= 4 * k * EPS * np.abs(A).max() * np.abs(B).max()
+
+
 @pytest.mark.parametrize("d", [1, 5, 64, 65, 130, 597, 2049])
 def test_dsymv(d):
     # one triangle read (64 x 64 tiles, partial sums per tile), against the full product
