@@ -162,7 +162,7 @@ typedef struct sdp_lp_block {
  *               by refine_tol since the last replacement, keeping the search
  *               direction (the Krylov space survives the correction)
  *  refine_tol   SWEEPS: relative residual reduction asked of each low-precision
- *               PCG run (0: 1e-6 for FP32, 1e-3 for BF16); later sweeps ask
+ *               PCG run (0: 1e-6 for FP32, 1e-2 for BF16); later sweeps ask
  *               only for the reduction still missing to inner_tol when that is
  *               larger.  REPLACE: reduction between two replacements (0: 1e-2
  *               for FP32, 1e-1 for BF16) [0]
