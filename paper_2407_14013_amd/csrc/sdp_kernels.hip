@@ -293,6 +293,37 @@ void f_to_v(hipStream_t st, int n, int r, const double* F, long ldf, const doubl
     WC_LAUNCH_CHECK();
 }
 
+// out = alpha v(F) + beta out (+ add): the v-coordinates of F as f_to_v reads
+// them, scaled into out in the same pass (out is not read when beta == 0;
+// add may be null).
+__global__ void f_to_v_axpby_kernel(int n, int r, const double* __restrict__ F, long ldf, double alpha, double beta,
+                                    const double* __restrict__ add, double* __restrict__ out) {
+    const int nb = r * (r + 1) / 2;
+    const int d = nb + (n - r) * r;
+    int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= d) return;
+    double val;
+    if (c < nb) {
+        int i, jj;
+        svec_pair(c, r, i, jj);
+        val = (i == jj) ? F[i + (long)i * ldf] : kSqrt2 * 0.5 * (F[i + (long)jj * ldf] + F[jj + (long)i * ldf]);
+    } else {
+        int t = c - nb;
+        int k = t % (n - r), b = t / (n - r);
+        val = kSqrt2 * F[(r + k) + (long)b * ldf];
+    }
+    double o = alpha * val;
+    if (beta != 0.0) o += beta * out[c];
+    if (add != nullptr) o += add[c];
+    out[c] = o;
+}
+void f_to_v_axpby(hipStream_t st, int n, int r, const double* F, long ldf, double alpha, double beta,
+                  const double* add, double* out) {
+    int d = r * (r + 1) / 2 + (n - r) * r;
+    hipLaunchKernelGGL(f_to_v_axpby_kernel, g1(d), dim3(256), 0, st, n, r, F, ldf, alpha, beta, add, out);
+    WC_LAUNCH_CHECK();
+}
+
 // M = (U Q^T + Q U^T) / 2 (+ beta M), U and Q n x r with leading dimension n.
 __global__ void symlr_kernel(int n, int r, const double* __restrict__ U, const double* __restrict__ Q, long ldq,
                              double* __restrict__ M, long ldm, double beta) {

@@ -25,6 +25,9 @@ void e_eigenvalues(hipStream_t st, int n, int r, const double* lam, double tau, 
 void v_to_h(hipStream_t st, int n, int r, const double* v, double* Hm);
 void f_to_v(hipStream_t st, int n, int r, const double* F, long ldf, const double* vin, const double* sig, double t2,
             double* out);
+// out = alpha v(F) + beta out (+ add, may be null), v(F) as f_to_v forms it
+void f_to_v_axpby(hipStream_t st, int n, int r, const double* F, long ldf, double alpha, double beta,
+                  const double* add, double* out);
 void symlr(hipStream_t st, int n, int r, const double* U, const double* Q, long ldq, double* M, long ldm, double beta);
 // M = the symmetric matrix whose lower triangle M holds, plus sym(U Q^T) (r may be 0)
 void symlr_lower(hipStream_t st, int n, int r, const double* U, const double* Q, long ldq, double* M, long ldm);

@@ -1009,14 +1009,17 @@ static void aq_mul(sdp_ctx* c, const double* v, double* out, double alpha, doubl
     if (c->t > 0) lp_b_top(c->st, c->m, c->lrptr, c->lrcol, c->lrval, c->posl, v + c->d, out, alpha);
 }
 
-// out = alpha (script-A script-Q)^T u + beta out (d): F = G_w^T (A^T(u) Q) read
-// in v-coordinates.  Entry sampling forms A^T(u) Q with the sparse product row
-// by row; sparse rows scatter A^T(u) into Y and multiply.  Uses YQ, F, td4
-// (and Y for sparse rows).
-static void aqt_mul(sdp_ctx* c, const double* u, double* out, double alpha, double beta) {
+// out = alpha (script-A script-Q)^T u + beta out (+ add, may be null; d plus
+// the LP coordinates in T): F = G_w^T (A^T(u) Q) read in v-coordinates and
+// scaled into out in one pass.  Entry sampling forms A^T(u) Q with the sparse
+// product row by row; sparse rows scatter A^T(u) into Y and multiply.  Uses
+// YQ, F (and Y for sparse rows).
+static void aqt_mul(sdp_ctx* c, const double* u, double* out, double alpha, double beta,
+                    const double* add = nullptr) {
     const int n = c->n, r = c->r;
     if (c->kind == SDP_A_DENSE) {
         gemv_rows(c->st, c->d, c->m, c->AQt, c->ldAQt, u, out, alpha, beta);
+        if (add) axpby(c->st, c->d, 1.0, add, 1.0, out);
     } else {
         if (c->kind == SDP_A_ENTRY) {
             entry_yq(c->st, n, r, c->rptr, c->rcol, c->ridx, u, c->Gw, n, c->YQ);
@@ -1025,12 +1028,13 @@ static void aqt_mul(sdp_ctx* c, const double* u, double* out, double alpha, doub
             gemm(c, false, false, n, r, n, 1.0, c->Y, n, c->Gw, n, 0.0, c->YQ, n);
         }
         gemm(c, true, false, n, r, n, 1.0, c->Gw, n, c->YQ, n, 0.0, c->F, n);
-        f_to_v(c->st, n, r, c->F, n, nullptr, c->sig, 0.0, c->td4);
-        axpby(c->st, c->d, alpha, c->td4, beta, out);
+        f_to_v_axpby(c->st, n, r, c->F, n, alpha, beta, add, out);
     }
     // the LP rows: (B^T u)_T
-    if (c->t > 0)
+    if (c->t > 0) {
         lp_bt_top(c->st, c->t, c->Tl, c->lcptr, c->lcrow, c->lcval, u, out + c->d, alpha, beta);
+        if (add) axpby(c->st, c->t, 1.0, add + c->d, 1.0, out + c->d);
+    }
 }
 
 // Block elimination with P = [beta I, AQ; AQ^T, -tau^2 Sigma] (Section 6, with
@@ -1042,8 +1046,7 @@ static void precond_block(sdp_ctx* c, const double* f, const double* h, double* 
     const int m = c->m, d = c->dv;  // the v-length, LP coordinates in T included
     hipStream_t st = c->st;
     const double ib = 1.0 / c->beta;
-    aqt_mul(c, f, c->td, -ib, 0.0);                                      // td = -AQ^T f / beta
-    axpby(st, d, 1.0, h, 1.0, c->td);                                    // td += h
+    aqt_mul(c, f, c->td, -ib, 0.0, h);                                   // td = h - AQ^T f / beta
     symv(st, d, c->Cinv, c->dmaxp, c->td, zv, -1.0, 0.0, c->sy_ws);      // zv = -C^{-1} td
     aq_mul(c, zv, c->tm, 1.0, 0.0);                                      // tm = AQ zv
     axpbypcz(st, m, ib, f, -ib, c->tm, 0.0, z1);                          // z1 = (f - tm) / beta
