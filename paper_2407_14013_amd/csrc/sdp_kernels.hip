@@ -966,6 +966,38 @@ void aq_bottom(hipStream_t st, int d, const double* a, const double* sig, double
 
 // ---- PCG scalars (device-resident) ------------------------------------------
 // sc[0] = <r,z>, sc[1] = <p,Kp>, sc[2] = alpha, sc[3] = beta, sc[4] = ||r_u||^2, sc[5] = <r,z>_new
+// The preconditioner's top-block updates (Section 6 block elimination):
+// z1 = (f - tm) / beta as ib f - ib tm, and, when rho is given, the top of the
+// refinement residual rho_u = (f - tm) - beta z1 in the same pass.
+__global__ void precond_top_kernel(long m, double ib, double beta, const double* __restrict__ f,
+                                   const double* __restrict__ tm, double* __restrict__ z1, double* __restrict__ rho) {
+    const long i = blockIdx.x * 256L + threadIdx.x;
+    if (i >= m) return;
+    const double fi = f[i], ti = tm[i];
+    const double z = ib * fi + (-ib) * ti;
+    z1[i] = z;
+    if (rho != nullptr) rho[i] = (-beta) * z + (fi - ti);
+}
+void precond_top(hipStream_t st, long m, double ib, double beta, const double* f, const double* tm, double* z1,
+                 double* rho) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(precond_top_kernel, g1(m), dim3(256), 0, st, m, ib, beta, f, tm, z1, rho);
+    WC_LAUNCH_CHECK();
+}
+// z = z + [dz; 0] on the top m entries, z_v = a + b on the d below them (the
+// refinement step's correction of both blocks in one pass).
+__global__ void precond_final_kernel(long m, long d, double* __restrict__ z, const double* __restrict__ dz,
+                                     const double* __restrict__ a, const double* __restrict__ b) {
+    const long i = blockIdx.x * 256L + threadIdx.x;
+    if (i < m) z[i] = dz[i] + z[i];
+    else if (i < m + d) z[i] = a[i - m] + b[i - m];
+}
+void precond_final(hipStream_t st, long m, long d, double* z, const double* dz, const double* a, const double* b) {
+    if (m + d <= 0) return;
+    hipLaunchKernelGGL(precond_final_kernel, g1(m + d), dim3(256), 0, st, m, d, z, dz, a, b);
+    WC_LAUNCH_CHECK();
+}
+
 // PCG scalars in sc: [0] <r, z> of the previous iterate, [1] <p, K p>,
 // [2] alpha, [3] beta, [5] <r, z> of the current iterate.  The scalar steps
 // run inside the vector updates: every thread forms alpha (beta) from sc, and

@@ -70,6 +70,11 @@ void corrector_h(hipStream_t st, int n, const double* Pm, const double* dv, doub
 void rho_bottom(hipStream_t st, int d, const double* h, const double* a, const double* sig, double t2,
                 const double* zv, double* out);
 void aq_bottom(hipStream_t st, int d, const double* a, const double* sig, double t2, const double* v, double* out);
+// Preconditioner top-block updates: z1 = (f - tm) / beta (and rho_u = f - tm - beta z1 when rho is
+// given); the refinement's final correction z[:m] += dz, z[m:m+d] = a + b
+void precond_top(hipStream_t st, long m, double ib, double beta, const double* f, const double* tm, double* z1,
+                 double* rho);
+void precond_final(hipStream_t st, long m, long d, double* z, const double* dz, const double* a, const double* b);
 // PCG updates with their scalar steps folded in (sc layout in sdp_kernels.hip)
 void pcg_xr(hipStream_t st, long N, long m, double* x, double* r, const double* p, const double* Kp, double* sc);
 void pcg_p(hipStream_t st, long N, double* p, const double* z, double* sc);

@@ -1042,14 +1042,15 @@ static void aqt_mul(sdp_ctx* c, const double* u, double* out, double alpha, doub
 // aligned buffer zv, z1 = (f - AQ zv) / beta, and tm = AQ zv is left behind.
 // gemv_rows reads its vector in 16-byte pairs, so zv must be an aligned,
 // zero-padded buffer (z + m is not 16-byte aligned for odd m).
-static void precond_block(sdp_ctx* c, const double* f, const double* h, double* z1, double* zv) {
+static void precond_block(sdp_ctx* c, const double* f, const double* h, double* z1, double* zv,
+                          double* rho_u = nullptr) {
     const int m = c->m, d = c->dv;  // the v-length, LP coordinates in T included
     hipStream_t st = c->st;
     const double ib = 1.0 / c->beta;
     aqt_mul(c, f, c->td, -ib, 0.0, h);                                   // td = h - AQ^T f / beta
     symv(st, d, c->Cinv, c->dmaxp, c->td, zv, -1.0, 0.0, c->sy_ws);      // zv = -C^{-1} td
     aq_mul(c, zv, c->tm, 1.0, 0.0);                                      // tm = AQ zv
-    axpbypcz(st, m, ib, f, -ib, c->tm, 0.0, z1);                          // z1 = (f - tm) / beta
+    precond_top(st, m, ib, c->beta, f, c->tm, z1, rho_u);                // z1 = (f - tm) / beta [, rho_u]
 }
 
 // z = P^{-1} rv: block elimination followed by one step of iterative
@@ -1064,15 +1065,12 @@ static void precond_apply(sdp_ctx* c, const double* rv, double* z) {
     const double* f = rv;
     const double* h = rv + m;
     double* z1 = z;
-    precond_block(c, f, h, z1, c->td2);
-    // rho = rv - P z:  rho_u = f - tm - beta z1,  rho_v = h - AQ^T z1 + tau^2 Sigma zv
-    axpbypcz(st, m, 1.0, f, -1.0, c->tm, 0.0, c->rho);
-    axpby(st, m, -c->beta, z1, 1.0, c->rho);
+    // rho = rv - P z:  rho_u = f - tm - beta z1 (formed with z1),  rho_v = h - AQ^T z1 + tau^2 Sigma zv
+    precond_block(c, f, h, z1, c->td2, c->rho);
     aqt_mul(c, z1, c->td3, 1.0, 0.0);                                      // td3 = AQ^T z1
     rho_bottom(st, d, h, c->td3, c->sig, c->tau * c->tau, c->td2, c->rho + m);
     precond_block(c, c->rho, c->rho + m, c->dz, c->td3);
-    axpby(st, m, 1.0, c->dz, 1.0, z1);
-    axpbypcz(st, d, 1.0, c->td2, 1.0, c->td3, 0.0, z + m);
+    precond_final(st, m, d, z, c->dz, c->td2, c->td3);                     // z1 += dz; zv = td2 + td3
 }
 
 // P^{-1} on caller buffers: staged through the aligned, zero-padded Krylov
